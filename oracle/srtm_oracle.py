@@ -1,0 +1,212 @@
+"""Sequential float64 reference for the SRTM filter and smoother (test infrastructure).
+
+Written from Yaghoobi & Sarkka, arXiv 2410.00627, Sec. III, in the paper's order
+and notation, with B = 0 (no inputs). Every function is a plain transcription of
+the stated equations using dense matrices; nothing is blocked, fused or reduced.
+
+Readings taken where the paper is silent (each also listed in the design notes):
+  * Q~ = E[w_bar w_bar^T] = I_L (x) Q, because the w_t are iid N(0, Q) (eq. prediction).
+  * Measurement window k holds x_{k,1..l}; x_{0,l} = x_0 is not measured (Sec. III).
+  * "Fast-rate filter" means p(x_{k,i} | y_{1:k}), i.e. it includes the window's own
+    measurement (eq. update-fast).
+  * Covariances are symmetrised, P <- (P + P^T)/2, after each update (rounding only).
+  * The log-likelihood is sum_k log N(y_k; C_bar m^f_{k-1,l}, C_bar P C_bar^T + R_x),
+    the normaliser of the IMKF update (eq. m-h-k-l).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _sym(P):
+    return 0.5 * (P + P.T)
+
+
+def _mpow(A, i):
+    return np.linalg.matrix_power(A, i)
+
+
+def slow_rate_model(A, Q, C, L):
+    """Slow-rate dynamic and measurement model of Sec. III-A.
+
+    eq. h-k-l-2:  x_{k,l} = A_bar x_{k-1,l} + G_bar w_bar_k,
+                  A_bar = A^l, G_bar = [A^{l-1} ... A I], Q_bar = G_bar Q~ G_bar^T.
+    eq. y-k-l-2:  y_k = C_bar x_{k-1,l} + M_bar w_bar_k + v_k,
+                  C_bar = (C/l) sum_{i=1..l} A^i,
+                  M_bar = (C/l) [sum_{i=0}^{l-1} A^i, sum_{i=0}^{l-2} A^i, ..., I].
+    """
+    nx = A.shape[0]
+    Abar = _mpow(A, L)
+    Gbar = np.hstack([_mpow(A, L - 1 - j) for j in range(L)])
+    Qtilde = np.kron(np.eye(L), Q)
+    Qbar = Gbar @ Qtilde @ Gbar.T
+    Cbar = (C / L) @ sum(_mpow(A, i) for i in range(1, L + 1))
+    Mbar = (C / L) @ np.hstack([sum(_mpow(A, i) for i in range(0, L - j)) for j in range(L)])
+    return dict(Abar=Abar, Gbar=Gbar, Qtilde=Qtilde, Qbar=Qbar, Cbar=Cbar, Mbar=Mbar,
+                nx=nx, L=L)
+
+
+def batch_model(A, Q, C, L):
+    """Stacked fast-rate window model of Sec. III-B.
+
+    eq. params-fast:   calA = [A; A^2; ...; A^l] (l nx x nx),
+                       calG = lower block-triangular Toeplitz with blocks A^{r-c}.
+    eq. y-k-l-2-H:     calH = (1/l) [C ... C] (ny x l nx).
+    """
+    nx = A.shape[0]
+    calA = np.vstack([_mpow(A, i) for i in range(1, L + 1)])
+    calG = np.zeros((L * nx, L * nx))
+    for r in range(L):
+        for c in range(r + 1):
+            calG[r * nx:(r + 1) * nx, c * nx:(c + 1) * nx] = _mpow(A, r - c)
+    calH = np.hstack([C] * L) / L
+    Qtilde = np.kron(np.eye(L), Q)
+    return dict(calA=calA, calG=calG, calH=calH, Qtilde=Qtilde, nx=nx, L=L)
+
+
+def imkf(A, Q, C, R, L, m0, P0, y):
+    """Sequential slow-rate IMKF, eq. prediction and eq. m-h-k-l (Sec. III-A).
+
+    Returns (m, P, loglik) with m[k-1] = m^f_{k,l}, P[k-1] = P^f_{k,l} for k = 1..N.
+    """
+    sr = slow_rate_model(A, Q, C, L)
+    Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[k] for k in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
+    N = y.shape[0]
+    nx, ny = A.shape[0], C.shape[0]
+    ms = np.zeros((N, nx))
+    Ps = np.zeros((N, nx, nx))
+    m, P = np.array(m0, dtype=float), np.array(P0, dtype=float)
+    ll = 0.0
+    for k in range(N):
+        # prediction (eq. prediction)
+        m_pred = Abar @ m
+        P_pred = Abar @ P @ Abar.T + Qbar
+        # update (eq. m-h-k-l): gain from the cross-covariance with the correlated noise term
+        cross = Abar @ P @ Cbar.T + Gbar @ Qt @ Mbar.T
+        S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + R
+        innov = y[k] - Cbar @ m
+        gain = np.linalg.solve(S.T, cross.T).T
+        m = m_pred + gain @ innov
+        P = _sym(P_pred - gain @ cross.T)
+        ms[k], Ps[k] = m, P
+        _, logdet = np.linalg.slogdet(S)
+        ll += -0.5 * (innov @ np.linalg.solve(S, innov) + logdet + ny * np.log(2 * np.pi))
+    return ms, Ps, ll
+
+
+def fast_filter_window(bm, R, m_prev, P_prev, yk):
+    """Window posterior p(X_{k,1:l} | y_{1:k}), eq. predict-fast and eq. update-fast.
+
+    (m_prev, P_prev) = (m^f_{k-1,l}, P^f_{k-1,l}); returns the dense (l nx) mean and
+    (l nx) x (l nx) covariance of the stacked window states.
+    """
+    calA, calG, calH, Qt = bm["calA"], bm["calG"], bm["calH"], bm["Qtilde"]
+    M_pred = calA @ m_prev
+    P_pred = calA @ P_prev @ calA.T + calG @ Qt @ calG.T
+    S = calH @ P_pred @ calH.T + R
+    gain = np.linalg.solve(S.T, (P_pred @ calH.T).T).T
+    M_f = M_pred + gain @ (yk - calH @ M_pred)
+    P_f = _sym(P_pred - gain @ calH @ P_pred)
+    return M_f, P_f
+
+
+def _blocks(M, P, nx, L):
+    m = M.reshape(L, nx)
+    Pd = np.stack([P[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] for i in range(L)])
+    return m, Pd
+
+
+def srtm_filter(A, Q, C, R, L, m0, P0, y):
+    """Fast- and slow-rate filtering marginals (Sec. III-A, III-B and Remark fast-par-filter).
+
+    Returns dict with
+      m_fast[k-1, i-1] = E[x_{k,i} | y_{1:k}],  P_fast[k-1, i-1] = Cov[x_{k,i} | y_{1:k}],
+      m_slow[k-1] = m^f_{k,l},  P_slow[k-1] = P^f_{k,l}  (the IMKF carry), and loglik.
+    """
+    nx, N = A.shape[0], y.shape[0]
+    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y)
+    bm = batch_model(A, Q, C, L)
+    m_fast = np.zeros((N, L, nx))
+    P_fast = np.zeros((N, L, nx, nx))
+    for k in range(N):
+        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
+        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k])
+        m_fast[k], P_fast[k] = _blocks(M_f, P_f, nx, L)
+    return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
+
+
+def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
+    """Fast- and slow-rate smoothing marginals by the proposed sequential smoother.
+
+    eq. smoothing-dynamic / eq. seq-smoothing-all (Sec. III-C): for k = N-1..1,
+      m^-_{k+1,1} = A_hat M^f_k,  P^-_{k+1,1} = A_hat P^f_k A_hat^T + Q,
+      G_k = P^f_k A_hat^T [P^-_{k+1,1}]^{-1},
+      M^s_k = M^f_k + G_k (m^s_{k+1,1} - m^-_{k+1,1}),
+      P^s_k = P^f_k + G_k (P^s_{k+1,1} - P^-_{k+1,1}) G_k^T,
+    with A_hat = [0 ... 0 A]; window N is smoothed = filtered. The window filter
+    (M^f_k, P^f_k) is recomputed from the stored slow carry (Remark fast-par-filter).
+
+    Returns dict with ms_fast/Ps_fast [N, L, ...] = p(x_{k,i} | y_{1:N}) and
+    ms_slow/Ps_slow [N, ...] = p(x_{k,1} | y_{1:N}) (the smoother's slow state).
+    """
+    nx, N = A.shape[0], y.shape[0]
+    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y)
+    bm = batch_model(A, Q, C, L)
+    Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A])
+    ms_fast = np.zeros((N, L, nx))
+    Ps_fast = np.zeros((N, L, nx, nx))
+    out = {}
+    if with_filter:
+        out["m_fast"] = np.zeros((N, L, nx))
+        out["P_fast"] = np.zeros((N, L, nx, nx))
+    ms1 = Ps1 = None
+    for k in range(N - 1, -1, -1):
+        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
+        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k])
+        if with_filter:
+            out["m_fast"][k], out["P_fast"][k] = _blocks(M_f, P_f, nx, L)
+        if k == N - 1:
+            M_s, P_s = M_f, P_f
+        else:
+            m_pred = Ahat @ M_f
+            P_pred = Ahat @ P_f @ Ahat.T + Q
+            G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
+            M_s = M_f + G @ (ms1 - m_pred)
+            P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)
+        ms_fast[k], Ps_fast[k] = _blocks(M_s, P_s, nx, L)
+        ms1, Ps1 = ms_fast[k, 0].copy(), Ps_fast[k, 0].copy()
+    out.update(ms_fast=ms_fast, Ps_fast=Ps_fast, ms_slow=ms_fast[:, 0].copy(),
+               Ps_slow=Ps_fast[:, 0].copy(), m_slow=m_slow, P_slow=P_slow, loglik=ll)
+    return out
+
+
+def slow_rate_smoother(A, Q, C, R, L, m0, P0, y):
+    """Slow-rate smoother for x_{k,1}, eq. seq-smoothing-1 (Sec. III-C).
+
+      G_{k,1} = P^f_{k,1,l} A^T [P^-_{k+1,1}]^{-1},
+      m^s_{k,1} = m^f_{k,1} + G_{k,1} (m^s_{k+1,1} - m^-_{k+1,1}),
+      P^s_{k,1} = P^f_{k,1} + G_{k,1} (P^s_{k+1,1} - P^-_{k+1,1}) G_{k,1}^T,
+    with m^-_{k+1,1} = A m^f_{k,l}, P^-_{k+1,1} = A P^f_{k,l} A^T + Q, and the
+    first/last cross-covariance P^f_{k,1,l} read from the window filter
+    (Remark pf-k-1-l). Returns (ms, Ps) with ms[k-1] = m^s_{k,1}.
+    """
+    nx, N = A.shape[0], y.shape[0]
+    m_slow, P_slow, _ = imkf(A, Q, C, R, L, m0, P0, y)
+    bm = batch_model(A, Q, C, L)
+    ms = np.zeros((N, nx))
+    Ps = np.zeros((N, nx, nx))
+    for k in range(N - 1, -1, -1):
+        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
+        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k])
+        mf1 = M_f[:nx]
+        Pf1 = P_f[:nx, :nx]
+        if k == N - 1:
+            ms[k], Ps[k] = mf1, Pf1
+            continue
+        Pf1L = P_f[:nx, (L - 1) * nx:]
+        m_pred = A @ m_slow[k]
+        P_pred = A @ P_slow[k] @ A.T + Q
+        G1 = np.linalg.solve(P_pred.T, (Pf1L @ A.T).T).T
+        ms[k] = mf1 + G1 @ (ms[k + 1] - m_pred)
+        Ps[k] = _sym(Pf1 + G1 @ (Ps[k + 1] - P_pred) @ G1.T)
+    return ms, Ps

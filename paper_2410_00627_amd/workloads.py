@@ -1,0 +1,148 @@
+"""Seeded synthetic SRTM workloads (model matrices and simulated measurements).
+
+This module is shared by the tests, the benchmark and the CPU reference. It holds
+no filtering or smoothing arithmetic: it only draws a linear Gaussian model of the
+form of Sec. III (eq. original-linear-SSM, with B = 0) and simulates data from it.
+
+Conventions (the paper's, Sec. III):
+  x_t = A x_{t-1} + w_{t-1},   w ~ N(0, Q)
+  y_k = (C / L) * sum_{i=1..L} x_{k,i} + v_k,  v ~ N(0, R)
+  window k holds fast steps (k-1)L+1 .. kL; x_0 ~ N(m0, P0) belongs to no window.
+The C-ABI names the matrices (F, Q, H, R); F is the paper's A and H the paper's C.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    """A time-invariant linear Gaussian SRTM model (all float64)."""
+    A: np.ndarray          # (nx, nx) fast-rate transition
+    Q: np.ndarray          # (nx, nx) process-noise covariance
+    C: np.ndarray          # (ny, nx) measurement matrix; y averages C x over a window
+    R: np.ndarray          # (ny, ny) measurement-noise covariance
+    L: int                 # window length (fast steps per measurement)
+    m0: np.ndarray         # (nx,) initial mean
+    P0: np.ndarray         # (nx, nx) initial covariance
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nx(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def ny(self) -> int:
+        return self.C.shape[0]
+
+
+def _haar_orthogonal(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Haar-distributed orthogonal matrix: QR of an N(0,1) matrix, columns sign-fixed."""
+    g = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(g)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def wna_model(dt: float = 0.01, q: float = 1.0, L: int = 10, r: float = 0.1) -> Model:
+    """Position/velocity model with white-noise acceleration (the tiny FP64 case).
+
+    The measurement is dt * sum_{window} [1, 0] x, i.e. in the paper's (C/L) sum
+    convention C = L * dt * [1, 0].
+    """
+    A = np.array([[1.0, dt], [0.0, 1.0]])
+    Q = q * np.array([[dt ** 3 / 3.0, dt ** 2 / 2.0], [dt ** 2 / 2.0, dt]])
+    C = np.array([[L * dt, 0.0]])
+    R = np.array([[r]])
+    return Model(A, Q, C, R, L, np.zeros(2), np.eye(2), name="wna",
+                 meta=dict(dt=dt, q=q))
+
+
+def random_stable_model(nx: int, ny: int, L: int, seed: int, *, rho: float = 0.99,
+                        q: float = 0.01, r: float = 0.05) -> Model:
+    """A = rho * U (U Haar orthogonal), Q = q I, C ~ N(0,1)^{ny x nx}, R = r I, m0 = 0, P0 = I."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rho * _haar_orthogonal(rng, nx)
+    C = rng.standard_normal((ny, nx))
+    return Model(A, q * np.eye(nx), C, r * np.eye(ny), L, np.zeros(nx), np.eye(nx),
+                 name=f"rand_nx{nx}_ny{ny}_L{L}_s{seed}", meta=dict(seed=seed))
+
+
+def random_spd(rng: np.random.Generator, n: int, scale: float = 1.0, floor: float = 0.1) -> np.ndarray:
+    g = rng.standard_normal((n, n))
+    return scale * (g @ g.T / n + floor * np.eye(n))
+
+
+def random_general_model(nx: int, ny: int, L: int, seed: int) -> Model:
+    """Non-orthogonal A, full Q, R, P0 and nonzero m0 (for pins that must not rely on structure)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = rng.standard_normal((nx, nx))
+    A *= 0.95 / max(abs(np.linalg.eigvals(A)))
+    Q = random_spd(rng, nx, 0.05)
+    C = rng.standard_normal((ny, nx))
+    R = random_spd(rng, ny, 0.2)
+    m0 = rng.standard_normal(nx)
+    P0 = random_spd(rng, nx, 1.0)
+    return Model(A, Q, C, R, L, m0, P0, name=f"gen_nx{nx}_ny{ny}_L{L}_s{seed}",
+                 meta=dict(seed=seed))
+
+
+def headline_model(seed: int = 2024) -> Model:
+    """One long sequence: nx=4, ny=2, L=20, A = 0.99 U, Q = 0.01 I, C Gaussian, R = 0.05 I."""
+    return random_stable_model(4, 2, 20, seed, rho=0.99, q=0.01, r=0.05)
+
+
+HEADLINE_N = 1 << 17
+WNA_N = 100
+
+
+def _chol_psd(S: np.ndarray) -> np.ndarray:
+    w, V = np.linalg.eigh(S)
+    return V * np.sqrt(np.clip(w, 0.0, None))[None, :]
+
+
+def simulate(model: Model, N: int, seed: int, *, return_states: bool = False):
+    """Draw x_0..x_{NL} and y_1..y_N from the model (float64).
+
+    The fast-rate recursion is evaluated blockwise: within blocks of b steps it runs
+    vectorised over all blocks from a zero start, then block-start states are chained
+    and their free responses A^j x_start added back. This is plain linear algebra on
+    the generative model, exact up to rounding.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, L = model.nx, model.ny, model.L
+    T = N * L
+    x0 = model.m0 + _chol_psd(model.P0) @ rng.standard_normal(nx)
+    w = rng.standard_normal((T, nx)) @ _chol_psd(model.Q).T      # w_{t-1} drives x_t
+    v = rng.standard_normal((N, ny)) @ _chol_psd(model.R).T
+    A = model.A
+    b = max(1, min(T, int(np.sqrt(T)) + 1))
+    nb = -(-T // b)
+    wp = np.zeros((nb * b, nx))
+    wp[:T] = w
+    wp = wp.reshape(nb, b, nx)
+    loc = np.zeros((nb, b, nx))            # zero-start response inside each block
+    cur = np.zeros((nb, nx))
+    for j in range(b):
+        cur = cur @ A.T + wp[:, j]
+        loc[:, j] = cur
+    starts = np.zeros((nb, nx))            # state just before each block
+    s = x0.copy()
+    Ab = np.linalg.matrix_power(A, b)
+    for k in range(nb):
+        starts[k] = s
+        s = Ab @ s + loc[k, b - 1]
+    Apows = np.empty((b, nx, nx))
+    P = np.eye(nx)
+    for j in range(b):
+        P = A @ P
+        Apows[j] = P
+    x = loc + np.einsum("jab,kb->kja", Apows, starts)
+    x = x.reshape(nb * b, nx)[:T]                     # x_1 .. x_T
+    xw = x.reshape(N, L, nx)
+    y = (xw.sum(axis=1) @ model.C.T) / L + v
+    if return_states:
+        return y, xw, x0
+    return y

@@ -1,0 +1,101 @@
+"""Brute-force posteriors of the SRTM model by conditioning one dense joint Gaussian.
+
+Independent of the recursive filters: the prior over all stacked fast states
+Z = [x_0; x_1; ...; x_{NL}] is written from x_t = A^t x_0 + sum_{s<=t} A^{t-s} w_{s-1},
+the measurements as Y = Psi Z + v with y_k = (C/L) sum_{i} x_{(k-1)L+i} (Sec. III,
+eq. original-linear-SSM), and marginals follow from the Gaussian conditioning rule.
+Only usable for tiny problems (dimension (N L + 1) nx).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def joint_prior(A, Q, C, R, L, m0, P0, N):
+    nx, ny = A.shape[0], C.shape[0]
+    T = N * L
+    dim = (T + 1) * nx
+    Phi = np.zeros((dim, nx))
+    Gam = np.zeros((dim, T * nx))
+    powers = [np.eye(nx)]
+    for _ in range(T):
+        powers.append(A @ powers[-1])
+    for t in range(T + 1):
+        Phi[t * nx:(t + 1) * nx] = powers[t]
+        for s in range(1, t + 1):          # w_{s-1} enters x_s
+            Gam[t * nx:(t + 1) * nx, (s - 1) * nx:s * nx] = powers[t - s]
+    muZ = Phi @ m0
+    SZ = Phi @ P0 @ Phi.T + Gam @ np.kron(np.eye(T), Q) @ Gam.T
+    Psi = np.zeros((N * ny, dim))
+    for k in range(N):
+        for i in range(1, L + 1):
+            t = k * L + i
+            Psi[k * ny:(k + 1) * ny, t * nx:(t + 1) * nx] = C / L
+    SY = Psi @ SZ @ Psi.T + np.kron(np.eye(N), R)
+    return muZ, SZ, Psi, SY
+
+
+def _condition(muZ, SZ, Psi, SY, y, rows):
+    """Mean and covariance of Z given the measurement rows `rows` of Y."""
+    SZY = (SZ @ Psi.T)[:, rows]
+    Syy = SY[np.ix_(rows, rows)]
+    r = y.reshape(-1)[rows] - (Psi @ muZ)[rows]
+    K = np.linalg.solve(Syy, SZY.T).T
+    return muZ + K @ r, SZ - K @ SZY.T
+
+
+def posteriors(A, Q, C, R, L, m0, P0, y):
+    """Exact filter and smoother marginals of every fast state x_{k,i}.
+
+    Returns dict: m_fast/P_fast = p(x_{k,i} | y_{1:k}), ms_fast/Ps_fast = p(x_{k,i} | y_{1:N}),
+    and loglik = log N(Y; Psi mu_Z, Psi S_Z Psi^T + I (x) R).
+    """
+    nx, ny = A.shape[0], C.shape[0]
+    N = y.shape[0]
+    muZ, SZ, Psi, SY = joint_prior(A, Q, C, R, L, m0, P0, N)
+    m_fast = np.zeros((N, L, nx))
+    P_fast = np.zeros((N, L, nx, nx))
+    for k in range(N):
+        mu, S = _condition(muZ, SZ, Psi, SY, y, np.arange((k + 1) * ny))
+        for i in range(L):
+            t = k * L + i + 1
+            m_fast[k, i] = mu[t * nx:(t + 1) * nx]
+            P_fast[k, i] = S[t * nx:(t + 1) * nx, t * nx:(t + 1) * nx]
+    mu, S = _condition(muZ, SZ, Psi, SY, y, np.arange(N * ny))
+    ms_fast = np.zeros((N, L, nx))
+    Ps_fast = np.zeros((N, L, nx, nx))
+    for k in range(N):
+        for i in range(L):
+            t = k * L + i + 1
+            ms_fast[k, i] = mu[t * nx:(t + 1) * nx]
+            Ps_fast[k, i] = S[t * nx:(t + 1) * nx, t * nx:(t + 1) * nx]
+    r = y.reshape(-1) - Psi @ muZ
+    _, logdet = np.linalg.slogdet(SY)
+    ll = -0.5 * (r @ np.linalg.solve(SY, r) + logdet + len(r) * np.log(2 * np.pi))
+    return dict(m_fast=m_fast, P_fast=P_fast, ms_fast=ms_fast, Ps_fast=Ps_fast, loglik=ll)
+
+
+def one_window_moments(A, Q, C, R, L):
+    """Moments of one window given x_{k-1,l} = 0, read off the joint prior of a single window.
+
+    Returns (Abar, Cbar, Qbar, Syx, Rx): the map x_{k-1,l} -> E[x_{k,l}], the map
+    x_{k-1,l} -> E[y_k], Cov(x_{k,l}), Cov(x_{k,l}, y_k) and Cov(y_k), obtained by
+    brute-force conditioning rather than by the slow-rate formulas.
+    """
+    nx, ny = A.shape[0], C.shape[0]
+    zero = np.zeros(nx)
+    muZ, SZ, Psi, SY = joint_prior(A, Q, C, R, L, zero, np.zeros((nx, nx)), 1)
+    last = slice(L * nx, (L + 1) * nx)
+    Qbar = SZ[last, last]
+    Syx = (SZ @ Psi.T)[last]
+    Rx = SY
+    # mean maps: propagate unit initial states without noise
+    Abar = np.zeros((nx, nx))
+    Cbar = np.zeros((ny, nx))
+    for j in range(nx):
+        e = np.zeros(nx)
+        e[j] = 1.0
+        mu, _, Psi1, _ = joint_prior(A, Q, C, R, L, e, np.zeros((nx, nx)), 1)
+        Abar[:, j] = mu[last]
+        Cbar[:, j] = Psi1 @ mu
+    return Abar, Cbar, Qbar, Syx, Rx
