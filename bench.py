@@ -1,0 +1,176 @@
+"""Benchmark: fast-rate smoothed states per second of one long SRTM sequence on one GPU.
+
+Workload: nx=4, ny=2, L=20, N=2^17 windows (2,621,440 fast states), A = 0.99 U (U Haar
+orthogonal), Q = 0.01 I, C Gaussian 2x4, R = 0.05 I, m0 = 0, P0 = I; measurements
+simulated from the model with a fixed seed. One step = one srtm_smooth call (filter
+scan, smoother scan, fast-rate recovery) producing smoothed fast- and slow-rate means
+and covariances, inputs already resident in HBM.
+
+Prints one JSON line. `roofline` is computed for the kernel with the largest measured
+time from HIP events recorded around every kernel on the launch stream; `cpu_baseline`
+times the float64 CPU reference (single BLAS thread) on a bounded prefix of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(nx, ny, L, N, esz):
+    """Bytes the method must move per call, by kernel and in total.
+
+    Whole path: read y; write and read the slow-filter carry (m, P) once; write smoothed
+    slow (m, P) and fast (m, P) outputs. Final smoother kernel: read y and the carry
+    (both neighbours come from the same array), write slow and fast outputs.
+    """
+    st = nx + nx * nx
+    total = N * (ny + 2 * st + st + L * st) * esz
+    final = N * (ny + st + st + L * st) * esz
+    return dict(total=total, k_bwd_final=final, fwd_final=N * (ny + st) * esz)
+
+
+def cpu_baseline(model, y, n_windows, max_seconds=30.0):
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_limits
+    import oracle
+    n = min(n_windows, y.shape[0])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.srtm_smoother(model.A, model.Q, model.C, model.R, model.L, model.m0, model.P0, y[:n])
+        dt = time.perf_counter() - t0
+    return dict(value=n * model.L / dt, unit="fast-rate smoothed states/s", cores=1, kind="oracle",
+                sample=f"first {n} of {y.shape[0]} windows of the same workload (float64 sequential smoother "
+                       f"with dense windows, one BLAS thread), {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--N", type=int, default=None, help="override the number of windows")
+    ap.add_argument("--cpu-windows", type=int, default=40000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-events", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's multi-GPU sharding is "
+                                   "described in the design notes but not built (use --gpus 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2410_00627_amd import srtm, workloads as wl
+    from paper_2410_00627_amd.hip_events import EventArray
+
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if dtype == torch.float64 else 4
+    model = wl.headline_model()
+    N = args.N or wl.HEADLINE_N
+    y = wl.simulate(model, N, seed=2024)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(model, dev, dtype)
+    yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dtype)
+    nx, ny, L = model.nx, model.ny, model.L
+    out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dtype),
+           "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dtype),
+           "ms_slow": torch.empty((N, nx), device=dev, dtype=dtype),
+           "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dtype)}
+    ws = torch.empty(srtm.workspace_size(nx, ny, L, N, dtype, True), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+
+    def step(events=None):
+        srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, events=events)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if int(info.item()) != 0:
+        raise RuntimeError(f"numerical failure during warmup: info={int(info.item())}")
+    print(f"[bench] warmup done: N={N} dtype={args.dtype}", file=sys.stderr, flush=True)
+
+    # timed region: plain calls
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = t0.elapsed_time(t1) / args.steps
+    fast_states = N * L
+    value = fast_states / (ms_per_step * 1e-3)
+    print(f"[bench] timed: {ms_per_step * 1e3:.1f} us/step ({wall:.3f} s wall)", file=sys.stderr, flush=True)
+
+    # per-kernel durations from events on the launch stream (separate region, same work)
+    names = srtm.kernel_names(True)
+    per_kernel = {n: 0.0 for n in names}
+    prof_ms = None
+    if not args.no_profile_events:
+        ev = EventArray(2 * len(names) * args.steps)
+        torch.cuda.synchronize()
+        for s in range(args.steps):
+            sub = ev.arr[2 * len(names) * s:2 * len(names) * (s + 1)]
+            step(events=(ctypes.c_void_p * (2 * len(names)))(*sub))
+        torch.cuda.synchronize()
+        for s in range(args.steps):
+            base = 2 * len(names) * s
+            for j, n in enumerate(names):
+                per_kernel[n] += ev.elapsed_ms(base + 2 * j, base + 2 * j + 1) / args.steps
+        prof_ms = ev.elapsed_ms(0, 2 * len(names) * args.steps - 1) / args.steps
+        ev.close()
+    if int(info.item()) != 0:
+        raise RuntimeError(f"numerical failure: info={int(info.item())}")
+
+    ab = algorithmic_bytes(nx, ny, L, N, esz)
+    dom = max(per_kernel, key=per_kernel.get) if not args.no_profile_events else "k_bwd_final"
+    dom_ms = per_kernel.get(dom, 0.0)
+    dom_bytes = ab.get(dom, None)
+    roof = None
+    if dom_ms > 0 and dom_bytes:
+        ach = dom_bytes / (dom_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5)}
+    whole_gbs = ab["total"] / (ms_per_step * 1e-3) / 1e9
+    res = {
+        "metric": "fast-rate smoothed states/sec (filter+smoother)",
+        "value": round(value, 1),
+        "unit": "fast-rate smoothed states/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "one long SRTM sequence, nx=4 ny=2 L=20 N=%d (%d fast states), A=0.99*Haar, "
+                               "Q=0.01I, C Gaussian, R=0.05I" % (N, fast_states),
+                   "nx": nx, "ny": ny, "L": L, "N": N, "fast_states": fast_states},
+        "hbm_frac_whole_path": round(whole_gbs / HBM_PEAK_GBS, 4),
+        "whole_path_algorithmic_GBps": round(whole_gbs, 1),
+        "per_kernel_ms": {k: round(v, 5) for k, v in per_kernel.items()},
+        "profiled_ms_per_step": None if prof_ms is None else round(prof_ms, 5),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(model, y, args.cpu_windows)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * srtm.h -- parallel-in-time filtering and smoothing of linear Gaussian state-space
+ * models with slow-rate integrated measurements (SRTM), on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Yaghoobi & Sarkka, "Parallel state estimation for systems with integrated
+ * measurements", arXiv 2410.00627. The problem is the one stated in Sec. III
+ * (eq. original-linear-SSM and eq. dual-rate-ssm1) without inputs (B = 0):
+ *
+ *     x_t = F x_{t-1} + w_{t-1},        w ~ N(0, Q)          (F is the paper's A)
+ *     y_k = (H / L) sum_{i=1..L} x_{k,i} + v_k,  v ~ N(0, R)  (H is the paper's C)
+ *     x_0 ~ N(m0, P0);  window k = 1..N holds fast states x_{k,1..L}, i.e. fast times
+ *     (k-1)L+1 .. kL; x_0 belongs to no window.
+ *
+ * srtm_filter returns p(x_{k,i} | y_{1:k}) (Sec. III-B, eq. update-fast) and the slow-rate
+ * filter p(x_{k,L} | y_{1:k}) (Sec. III-A); srtm_smooth returns p(x_{k,i} | y_{1:N})
+ * (Sec. III-C, eq. seq-smoothing-all) and the smoother's slow state p(x_{k,1} | y_{1:N})
+ * (eq. seq-smoothing-1). Both are computed with the associative scans of Sec. IV
+ * (eq. op-filter forward, eq. op-smoother in reverse) followed by a per-window pass that
+ * recovers the fast-rate states (Remarks fast-par-filter and parallel-fast-smoothing).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or equivalent), row-major,
+ *    contiguous, of one element type given by srtm_shape.dtype, aligned to 16 bytes.
+ *  - Index [k-1][i-1] addresses window k, fast step i. Covariances are full nx x nx,
+ *    exactly symmetric, and only marginal (diagonal-block) covariances are returned.
+ *  - The caller owns every buffer. The library allocates nothing, keeps no pointer
+ *    after a call returns and holds no global mutable state; calls are reentrant.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and the
+ *    call returns without synchronising. Buffers must stay alive until the stream
+ *    reaches the end of the call. Results are bitwise deterministic for a given shape.
+ *  - Argument errors are returned synchronously before anything is enqueued.
+ *    Numerical failures are OR-ed into the device int32 *info (which the caller zeroes
+ *    beforehand; may be NULL): SRTM_INFO_* bits below. Outputs are unspecified when
+ *    *info != 0.
+ */
+#ifndef SRTM_H
+#define SRTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SRTM_F32 = 0, SRTM_F64 = 1 } srtm_dtype;
+
+typedef enum {
+  SRTM_OK = 0,
+  SRTM_E_NULL = 1,        /* a required pointer is NULL                                */
+  SRTM_E_SHAPE = 2,       /* N < 1, L < 1, nx < 1 or ny < 1, or sizes overflow          */
+  SRTM_E_DTYPE = 3,       /* dtype is neither SRTM_F32 nor SRTM_F64                     */
+  SRTM_E_UNSUPPORTED = 4, /* (nx, ny) pair not compiled, or L / N above the limits      */
+  SRTM_E_ALIGN = 5,       /* an array is not 16-byte aligned (workspace: 256 bytes)     */
+  SRTM_E_WORKSPACE = 6,   /* workspace_bytes smaller than srtm_workspace_size()         */
+  SRTM_E_HIP = 7          /* a HIP runtime call (kernel launch, event record) failed    */
+} srtm_status;
+
+/* Device-side numerical status bits (OR-ed into *info). */
+#define SRTM_INFO_INNOVATION_NOT_PD 1 /* C_bar P C_bar^T + R_x (eq. m-h-k-l) not positive definite */
+#define SRTM_INFO_COMBINE_SINGULAR 2  /* I + D_i J_j of eq. op-filter numerically singular          */
+#define SRTM_INFO_PRED_SINGULAR 4     /* A P^f_{k,l} A^T + Q of eq. parallel-ak-smoothing singular  */
+#define SRTM_INFO_NONFINITE 8         /* a non-finite value reached an output                       */
+
+/* Problem shape. nx = state size, ny = measurement size, L = window length (the
+ * paper's l), N = number of windows (slow steps), dtype = element type of every array. */
+typedef struct {
+  int32_t nx;
+  int32_t ny;
+  int32_t L;
+  int32_t dtype;
+  int64_t N;
+} srtm_shape;
+
+/* Limits of this build (L bounds the per-step constant tables held in LDS). */
+#define SRTM_MAX_L 128
+#define SRTM_MAX_N (1LL << 26)
+
+/* Bytes of device workspace srtm_filter (smoother = 0) or srtm_smooth (smoother = 1)
+ * needs for `shape`. Returns SRTM_OK and writes *bytes, or an argument error. */
+srtm_status srtm_workspace_size(const srtm_shape* shape, int32_t smoother, size_t* bytes);
+
+/* Nonzero when the (nx, ny) pair is compiled into this library. */
+int32_t srtm_supported(int32_t nx, int32_t ny);
+
+/* Filtering (Sec. III-A/B, parallel IMKF of Sec. IV).
+ *  Inputs (required):  F [nx][nx], Q [nx][nx], H [ny][nx], R [ny][ny], m0 [nx],
+ *                      P0 [nx][nx], y [N][ny]   (Q, R, P0 symmetric PSD; R + H-part PD)
+ *  Outputs (each may be NULL to skip it):
+ *      m_fast [N][L][nx], P_fast [N][L][nx][nx]  : p(x_{k,i} | y_{1:k})
+ *      m_slow [N][nx],    P_slow [N][nx][nx]     : p(x_{k,L} | y_{1:k})
+ *  workspace: device buffer of at least srtm_workspace_size(shape, 0) bytes. */
+srtm_status srtm_filter(const srtm_shape* shape,
+                        const void* F, const void* Q, const void* H, const void* R,
+                        const void* m0, const void* P0, const void* y,
+                        void* m_fast, void* P_fast, void* m_slow, void* P_slow,
+                        void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
+/* Smoothing (Sec. III-C, parallel IMS of Sec. IV), same inputs as srtm_filter.
+ *  Outputs (each may be NULL to skip it):
+ *      ms_fast [N][L][nx], Ps_fast [N][L][nx][nx] : p(x_{k,i} | y_{1:N})
+ *      ms_slow [N][nx],    Ps_slow [N][nx][nx]    : p(x_{k,1} | y_{1:N})
+ *      mf_fast, Pf_fast, mf_slow, Pf_slow          : the filter outputs of srtm_filter
+ *  workspace: device buffer of at least srtm_workspace_size(shape, 1) bytes. */
+srtm_status srtm_smooth(const srtm_shape* shape,
+                        const void* F, const void* Q, const void* H, const void* R,
+                        const void* m0, const void* P0, const void* y,
+                        void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                        void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
+                        void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
+/* Profiling variant of srtm_smooth: identical work, and additionally records
+ * events[2j] before and events[2j+1] after the j-th kernel it enqueues, j = 0 ..
+ * srtm_kernel_count(1) - 1. `events` holds caller-created hipEvent_t handles and
+ * n_events must be at least 2 * srtm_kernel_count(1). For measurement only. */
+srtm_status srtm_smooth_profiled(const srtm_shape* shape,
+                                 const void* F, const void* Q, const void* H, const void* R,
+                                 const void* m0, const void* P0, const void* y,
+                                 void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                                 void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
+                                 void* workspace, size_t workspace_bytes, int32_t* info,
+                                 void* stream, void* const* events, int32_t n_events);
+
+/* Number of kernels one srtm_filter (smoother = 0) or srtm_smooth (smoother = 1) call
+ * enqueues, and the name of kernel j of that sequence (static string, or NULL). */
+int32_t srtm_kernel_count(int32_t smoother);
+const char* srtm_kernel_name(int32_t smoother, int32_t j);
+
+/* Static text for a status code. */
+const char* srtm_status_string(int32_t status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t srtm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRTM_H */

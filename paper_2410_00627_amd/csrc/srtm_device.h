@@ -1,0 +1,242 @@
+// Small fixed-size matrix helpers for the SRTM kernels (gfx950).
+//
+// Every matrix lives in registers as a T[R][C] array with compile-time shape; loops
+// are fully unrolled so no array is ever indexed dynamically (which would force it
+// into scratch memory).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define SRTM_DEV __device__ __forceinline__
+
+namespace srtm {
+
+template <typename T> SRTM_DEV T my_fma(T a, T b, T c) { return fma(a, b, c); }
+
+template <typename T, int R, int C>
+SRTM_DEV void load(T (&a)[R][C], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[r][c] = p[r * C + c];
+}
+
+template <typename T, int R>
+SRTM_DEV void loadv(T (&a)[R], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = p[r];
+}
+
+// C = A B
+template <typename T, int M, int K, int N>
+SRTM_DEV void mm(const T (&A)[M][K], const T (&B)[K][N], T (&C)[M][N]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = A[i][0] * B[0][j];
+#pragma unroll
+      for (int k = 1; k < K; ++k) s = my_fma(A[i][k], B[k][j], s);
+      C[i][j] = s;
+    }
+}
+
+// C = A B^T   (A: M x K, B: N x K)
+template <typename T, int M, int K, int N>
+SRTM_DEV void mm_nt(const T (&A)[M][K], const T (&B)[N][K], T (&C)[M][N]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = A[i][0] * B[j][0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) s = my_fma(A[i][k], B[j][k], s);
+      C[i][j] = s;
+    }
+}
+
+// C = A^T B   (A: K x M, B: K x N)
+template <typename T, int M, int K, int N>
+SRTM_DEV void mm_tn(const T (&A)[K][M], const T (&B)[K][N], T (&C)[M][N]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = A[0][i] * B[0][j];
+#pragma unroll
+      for (int k = 1; k < K; ++k) s = my_fma(A[k][i], B[k][j], s);
+      C[i][j] = s;
+    }
+}
+
+// S = A B A^T + D for symmetric B and D (upper triangle computed, then mirrored).
+template <typename T, int M, int K>
+SRTM_DEV void sandwich(const T (&A)[M][K], const T (&B)[K][K], const T (&D)[M][M], T (&S)[M][M]) {
+  T AB[M][K];
+  mm(A, B, AB);
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = i; j < M; ++j) {
+      T s = D[i][j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) s = my_fma(AB[i][k], A[j][k], s);
+      S[i][j] = s;
+      S[j][i] = s;
+    }
+}
+
+// y = A x (+ b)
+template <typename T, int M, int K>
+SRTM_DEV void mv(const T (&A)[M][K], const T (&x)[K], T (&y)[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = A[i][0] * x[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) s = my_fma(A[i][k], x[k], s);
+    y[i] = s;
+  }
+}
+
+template <typename T, int M, int K>
+SRTM_DEV void mv_acc(const T (&A)[M][K], const T (&x)[K], T (&y)[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int k = 0; k < K; ++k) y[i] = my_fma(A[i][k], x[k], y[i]);
+}
+
+// y = A^T x
+template <typename T, int K, int M>
+SRTM_DEV void mtv(const T (&A)[K][M], const T (&x)[K], T (&y)[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    T s = A[0][i] * x[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) s = my_fma(A[k][i], x[k], s);
+    y[i] = s;
+  }
+}
+
+template <typename T, int R, int C>
+SRTM_DEV void symmetrize(T (&A)[R][C]) {
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = i + 1; j < C; ++j) {
+      T s = T(0.5) * (A[i][j] + A[j][i]);
+      A[i][j] = s;
+      A[j][i] = s;
+    }
+}
+
+// Solves A X = B for X (returned in B) by Gaussian elimination with partial pivoting.
+// A is destroyed. For each column the row with the strictly largest magnitude is
+// brought up by conditional swaps (ties keep the upper row). Returns false when a
+// pivot is zero or not finite.
+template <typename T, int N, int M>
+SRTM_DEV bool solve_pp(T (&A)[N][N], T (&B)[N][M]) {
+  bool ok = true;
+  T ipiv[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      const bool sw = fabs(A[r][c]) > fabs(A[c][c]);
+#pragma unroll
+      for (int j = c; j < N; ++j) {
+        const T a = A[c][j], b = A[r][j];
+        A[c][j] = sw ? b : a;
+        A[r][j] = sw ? a : b;
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const T a = B[c][j], b = B[r][j];
+        B[c][j] = sw ? b : a;
+        B[r][j] = sw ? a : b;
+      }
+    }
+    const T piv = A[c][c];
+    ok = ok && (piv != T(0)) && isfinite(piv);
+    ipiv[c] = T(1) / piv;
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      const T f = A[r][c] * ipiv[c];
+#pragma unroll
+      for (int j = c + 1; j < N; ++j) A[r][j] = my_fma(-f, A[c][j], A[r][j]);
+#pragma unroll
+      for (int j = 0; j < M; ++j) B[r][j] = my_fma(-f, B[c][j], B[r][j]);
+    }
+  }
+#pragma unroll
+  for (int c = N - 1; c >= 0; --c)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      T s = B[c][j];
+#pragma unroll
+      for (int k = c + 1; k < N; ++k) s = my_fma(-A[c][k], B[k][j], s);
+      B[c][j] = s * ipiv[c];
+    }
+  return ok;
+}
+
+// Inverse of a symmetric positive-definite matrix through its Cholesky factor.
+// Returns false when a diagonal pivot is not positive (the result is then garbage).
+template <typename T, int N>
+SRTM_DEV bool chol_inv(const T (&A)[N][N], T (&Ai)[N][N]) {
+  T Lf[N][N];
+  T id[N];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T s = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = my_fma(-Lf[j][k], Lf[j][k], s);
+    ok = ok && (s > T(0));
+    const T d = sqrt(s);
+    id[j] = T(1) / d;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      T t = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = my_fma(-Lf[i][k], Lf[j][k], t);
+      Lf[i][j] = t * id[j];
+    }
+  }
+  // Li = L^{-1} (lower triangular)
+  T Li[N][N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    Li[j][j] = id[j];
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      T s = T(0);
+#pragma unroll
+      for (int k = j; k < i; ++k) s = my_fma(Lf[i][k], Li[k][j], s);
+      Li[i][j] = -s * id[i];
+    }
+  }
+  // A^{-1} = Li^T Li
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int k = j; k < N; ++k) s = my_fma(Li[k][i], Li[k][j], s);
+      Ai[i][j] = s;
+      Ai[j][i] = s;
+    }
+  return ok;
+}
+
+template <typename T> SRTM_DEV bool all_finite(T x) { return isfinite(x); }
+
+// Wave-level barrier with LDS visibility between the lanes of one wavefront.
+SRTM_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace srtm

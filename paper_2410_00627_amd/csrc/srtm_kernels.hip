@@ -1,0 +1,1586 @@
+// HIP kernels for parallel-in-time SRTM filtering and smoothing on gfx950.
+//
+// Method: Yaghoobi & Sarkka, arXiv 2410.00627, Sec. IV. The forward pass is the
+// parallel IMKF: an inclusive scan of the filter elements (eq. a-k-f) under the
+// operator of eq. op-filter, which yields the slow-rate carry (m^f_{k,l}, P^f_{k,l}).
+// The reverse pass is the parallel IMS: a suffix scan of the smoother elements
+// (eq. parallel-ak-smoothing) under eq. op-smoother, which yields (m^s_{k,1}, P^s_{k,1}),
+// followed by the per-window fast-rate recovery of eq. seq-smoothing-all
+// (Remarks fast-par-filter and parallel-fast-smoothing).
+//
+// Design points specific to this implementation (the paper's equations are unchanged):
+//  * The model is time invariant, so every filter element with k > 1 shares its matrix
+//    part (F, D, J); a run of 2^p consecutive elements therefore has matrices that depend
+//    on p only. The constants kernel computes them once per call (repeated squaring under
+//    eq. op-filter), and the per-tile up-sweeps combine only the vector parts (d, eta)
+//    with per-level coefficient matrices shared by every lane.
+//  * The first element is written as a prior state (0, m0, P0, 0, 0) combined with the
+//    generic element of window 1; this equals the paper's a_1 = (0, m^f_{1,l}, P^f_{1,l}).
+//  * A prefix that contains the prior has F = 0, so every exclusive prefix is a "state"
+//    (m, P) and the down-sweeps combine states with aligned segments.
+//  * The suffix scan runs as a prefix scan over reversed window order with the operands
+//    of eq. op-smoother swapped.
+//  * Within a window only the blocks the outputs need are formed (Remark
+//    cross-covariances): P^f_{k,i,i}, P^f_{k,i,l} and means, from per-step constants
+//    A^i, Q_ii, Q_il, c_i, instead of the dense (l nx)^2 window covariance.
+
+#include "srtm_device.h"
+#include "srtm_layout.h"
+#include "../../include/srtm.h"
+
+namespace srtm {
+
+// ============================================================================ constants
+// One workgroup, float64 throughout. Per-step tables are built in LDS by parallel
+// loops; the slow-rate constants and the level tables by one lane in registers.
+//
+// With Q_ij = Cov(x_{k,i}, x_{k,j} | x_{k-1,l}) = sum_{t=1..min(i,j)} A^{i-t} Q A^{(j-t)T}:
+//   Q_ii = sum_{t=0}^{i-1} A^t Q A^{tT},   Q_il = Q_ii (A^{l-i})^T,
+//   c_i  = (1/l) sum_j Q_ij C^T = Cov(x_{k,i}, y_k | x_{k-1,l})  (noise part),
+//   C_bar = (C/l) sum_{i=1..l} A^i,  R_x = (1/l) sum_i C c_i + R,  G_bar Q~ M_bar^T = c_l,
+//   Q_bar = Q_ll, A_bar = A^l   (eq. h-k-l-2, eq. y-k-l-2 and eq. a-k-f).
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(256)
+k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
+            const T* __restrict__ Rm, int L, T* __restrict__ cst, int32_t* info) {
+  constexpr int NN = NX * NX, NXY = NX * NY;
+  constexpr int W2S = (NN > 2 * NXY ? NN : 2 * NXY);
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const ConstLayout lay = make_const_layout(NX, NY, L);
+  double* sA = sm;
+  double* sQ = sA + NN;
+  double* sC = sQ + NN;
+  double* sR = sC + NXY;
+  double* Apow = sR + NY * NY;          // (L+1) NN, Apow[i] = A^i
+  double* Qii = Apow + (L + 1) * NN;    // (L+1) NN, Qii[i] = Q_ii (Qii[0] = 0)
+  double* W1 = Qii + (L + 1) * NN;      // (L+1) NN scratch
+  double* W2 = W1 + (L + 1) * NN;       // (L+1) W2S scratch
+  double* ci = W2 + (L + 1) * W2S;      // (L+1) NXY, ci[i] = c_i
+
+  for (int e = tid; e < NN; e += nthr) {
+    sA[e] = (double)Fm[e];
+    sQ[e] = (double)Qm[e];
+    Apow[e] = (e / NX == e % NX) ? 1.0 : 0.0;
+    Apow[NN + e] = (double)Fm[e];
+  }
+  for (int e = tid; e < NXY; e += nthr) sC[e] = (double)Hm[e];
+  for (int e = tid; e < NY * NY; e += nthr) sR[e] = (double)Rm[e];
+  __syncthreads();
+
+  // A^i by doubling: A^i = A^s A^{i-s} for i in (s, 2s].
+  for (int s = 1; s < L; s *= 2) {
+    const int hi = (2 * s < L) ? 2 * s : L;
+    for (int e = tid; e < (hi - s) * NN; e += nthr) {
+      const int i = s + 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+      double acc = 0.0;
+      for (int k = 0; k < NX; ++k) acc += Apow[s * NN + r * NX + k] * Apow[(i - s) * NN + k * NX + c];
+      Apow[i * NN + rc] = acc;
+    }
+    __syncthreads();
+  }
+  // W1[t] = A^t Q, W2[t] = A^t Q A^tT, t = 0..L-1
+  for (int e = tid; e < L * NN; e += nthr) {
+    const int t = e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+    double acc = 0.0;
+    for (int k = 0; k < NX; ++k) acc += Apow[t * NN + r * NX + k] * sQ[k * NX + c];
+    W1[t * NN + rc] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < L * NN; e += nthr) {
+    const int t = e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+    double acc = 0.0;
+    for (int k = 0; k < NX; ++k) acc += W1[t * NN + r * NX + k] * Apow[t * NN + c * NX + k];
+    W2[t * NN + rc] = acc;
+  }
+  __syncthreads();
+  // Q_ii = sum_{t<i} W2[t]  (running sum, symmetrised afterwards)
+  for (int e = tid; e < NN; e += nthr) {
+    double acc = 0.0;
+    Qii[e] = 0.0;
+    for (int t = 0; t < L; ++t) {
+      acc += W2[t * NN + e];
+      Qii[(t + 1) * NN + e] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < L * NN; e += nthr) {
+    const int i = 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+    if (c > r) {
+      const double s = 0.5 * (Qii[i * NN + r * NX + c] + Qii[i * NN + c * NX + r]);
+      Qii[i * NN + r * NX + c] = s;
+      Qii[i * NN + c * NX + r] = s;
+    }
+  }
+  __syncthreads();
+  // W1[s] = Sig_s = sum_{u=0}^{s} A^u, s = 0..L
+  for (int e = tid; e < NN; e += nthr) {
+    double acc = 0.0;
+    for (int s = 0; s <= L; ++s) {
+      acc += Apow[s * NN + e];
+      W1[s * NN + e] = acc;
+    }
+  }
+  __syncthreads();
+  // CS[s] = C Sig_s (NY x NX) in W2[0 ..], QC[j] = Q_jj C^T (NX x NY) in W2[(L+1) NXY ..]
+  double* CS = W2;
+  double* QC = W2 + (L + 1) * NXY;
+  for (int e = tid; e < (L + 1) * NXY; e += nthr) {
+    const int s = e / NXY, rc = e % NXY;
+    {
+      const int r = rc / NX, c = rc % NX;   // CS: NY x NX
+      double acc = 0.0;
+      for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * W1[s * NN + k * NX + c];
+      CS[s * NXY + rc] = acc;
+    }
+    {
+      const int r = rc / NY, c = rc % NY;   // QC: NX x NY
+      double acc = 0.0;
+      for (int k = 0; k < NX; ++k) acc += Qii[s * NN + r * NX + k] * sC[c * NX + k];
+      QC[s * NXY + rc] = acc;
+    }
+  }
+  __syncthreads();
+  // c_i = (1/l) [ sum_{j<i} A^{i-j} Q_jj C^T + Q_ii (C Sig_{l-i})^T ]
+  for (int e = tid; e < L * NXY; e += nthr) {
+    const int i = 1 + e / NXY, rc = e % NXY, r = rc / NY, c = rc % NY;
+    double acc = 0.0;
+    for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * CS[(L - i) * NXY + c * NX + k];
+    for (int j = 1; j < i; ++j)
+      for (int k = 0; k < NX; ++k) acc += Apow[(i - j) * NN + r * NX + k] * QC[j * NXY + k * NY + c];
+    ci[i * NXY + rc] = acc / (double)L;
+  }
+  __syncthreads();
+
+  // Per-step tables to the constants block: A^i, Q_ii, Q_il = Q_ii (A^{l-i})^T, c_i.
+  for (int e = tid; e < L * NN; e += nthr) {
+    const int i = 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+    T* dst = cst + lay.per_i + (i - 1) * lay.per_i_stride;
+    dst[lay.o_Ai + rc] = (T)Apow[i * NN + rc];
+    dst[lay.o_Qii + rc] = (T)Qii[i * NN + rc];
+    double acc = 0.0;
+    for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * Apow[(L - i) * NN + c * NX + k];
+    dst[lay.o_QiL + rc] = (T)acc;
+  }
+  for (int e = tid; e < L * NXY; e += nthr) {
+    const int i = 1 + e / NXY, rc = e % NXY;
+    cst[lay.per_i + (i - 1) * lay.per_i_stride + lay.o_ci + rc] = (T)ci[i * NXY + rc];
+  }
+  for (int e = tid; e < NN; e += nthr) {
+    cst[lay.A + e] = (T)sA[e];
+    cst[lay.Q + e] = (T)sQ[e];
+  }
+
+  if (tid != 0) return;
+  // ---------------------------------------------------------------- one lane
+  double Cd[NY][NX], Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NX; ++c) Cd[r][c] = sC[r * NX + c];
+  // C_bar = (C/l)(Sig_l - I)
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NX; ++c) {
+      double acc = 0.0;
+      for (int k = 0; k < NX; ++k) acc += Cd[r][k] * (W1[L * NN + k * NX + c] - (k == c ? 1.0 : 0.0));
+      Cbar[r][c] = acc / (double)L;
+    }
+  // R_x = (1/l) sum_i C c_i + R
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NY; ++c) {
+      double acc = 0.0;
+      for (int i = 1; i <= L; ++i)
+        for (int k = 0; k < NX; ++k) acc += Cd[r][k] * ci[i * NXY + k * NY + c];
+      Rx[r][c] = acc / (double)L + sR[r * NY + c];
+    }
+  symmetrize(Rx);
+  for (int r = 0; r < NX; ++r)
+    for (int c = 0; c < NY; ++c) Sxy[r][c] = ci[L * NXY + r * NY + c];
+  double Rxi[NY][NY];
+  if (!chol_inv(Rx, Rxi) && info) atomicOr(info, SRTM_INFO_INNOVATION_NOT_PD);
+  double K[NX][NY], Heta[NX][NY];
+  mm(Sxy, Rxi, K);
+  mm_tn(Cbar, Rxi, Heta);
+  double F[NX][NX], D[NX][NX], J[NX][NX];
+  for (int r = 0; r < NX; ++r)
+    for (int c = 0; c < NX; ++c) {
+      double f = Apow[L * NN + r * NX + c], d = Qii[L * NN + r * NX + c];
+      for (int k = 0; k < NY; ++k) {
+        f -= K[r][k] * Cbar[k][c];
+        d -= K[r][k] * Sxy[c][k];
+      }
+      F[r][c] = f;
+      D[r][c] = d;
+    }
+  mm(Heta, Cbar, J);
+  symmetrize(D);
+  symmetrize(J);
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NX; ++c) cst[lay.Cbar + r * NX + c] = (T)Cbar[r][c];
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NY; ++c) cst[lay.Rx + r * NY + c] = (T)Rx[r][c];
+  for (int r = 0; r < NX; ++r)
+    for (int c = 0; c < NY; ++c) {
+      cst[lay.K + r * NY + c] = (T)K[r][c];
+      cst[lay.Heta + r * NY + c] = (T)Heta[r][c];
+    }
+  // Levels: Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, and the
+  // coefficients that combine the vector parts of two runs of 2^p elements:
+  //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
+  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J,  W = (I + D J)^{-1}.
+  for (int p = 0; p < NLEV; ++p) {
+    T* dst = cst + lay.lev + p * lay.lev_stride;
+    double M[NX][NX], X[NX][2 * NX];
+    mm(D, J, M);
+    for (int r = 0; r < NX; ++r) {
+      M[r][r] += 1.0;
+      for (int c = 0; c < NX; ++c) {
+        X[r][c] = F[r][c];
+        X[r][NX + c] = (r == c) ? 1.0 : 0.0;
+      }
+    }
+    if (!solve_pp(M, X) && info) atomicOr(info, SRTM_INFO_COMBINE_SINGULAR);
+    double WF[NX][NX], Wm[NX][NX], G1[NX][NX], G2[NX][NX], G4[NX][NX];
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        WF[r][c] = X[r][c];
+        Wm[r][c] = X[r][NX + c];
+      }
+    mm(F, Wm, G1);
+    mm(G1, D, G2);
+    mm_tn(WF, J, G4);  // G4 = (W F)^T J ; G3 = (W F)^T
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        dst[lay.o_F + r * NX + c] = (T)F[r][c];
+        dst[lay.o_D + r * NX + c] = (T)D[r][c];
+        dst[lay.o_J + r * NX + c] = (T)J[r][c];
+        dst[lay.o_G1 + r * NX + c] = (T)G1[r][c];
+        dst[lay.o_G2 + r * NX + c] = (T)G2[r][c];
+        dst[lay.o_G3 + r * NX + c] = (T)WF[c][r];
+        dst[lay.o_G4 + r * NX + c] = (T)G4[r][c];
+      }
+    double Fn[NX][NX], Dn[NX][NX], Jn[NX][NX];
+    mm(F, WF, Fn);           // F W F
+    mm_nt(G2, F, Dn);        // F W D F^T
+    mm(G4, F, Jn);           // F^T W^T J F
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        F[r][c] = Fn[r][c];
+        D[r][c] = Dn[r][c] + D[r][c];
+        J[r][c] = Jn[r][c] + J[r][c];
+      }
+    symmetrize(D);
+    symmetrize(J);
+  }
+}
+
+// ============================================================================ helpers
+template <typename T, int NX, int NY>
+struct Model {
+  const T* __restrict__ cst;
+  ConstLayout lay;
+  SRTM_DEV const T* per_i(int i) const { return cst + lay.per_i + (i - 1) * lay.per_i_stride; }
+  SRTM_DEV const T* level(int p) const { return cst + lay.lev + p * lay.lev_stride; }
+};
+
+template <typename T, int N>
+SRTM_DEV T symget(const T (&P)[N][N], int r, int c) { return r <= c ? P[r][c] : P[c][r]; }
+
+// state (m, P) (x) segment (F, d, D, eta, J): the eq. op-filter combination whose left
+// operand holds the prior (F = 0):  W = (I + P J)^{-1},
+//   m' = F W (m + P eta) + d,   P' = F W P F^T + D.
+template <typename T, int NX>
+SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
+                            const T (&D)[NX][NX], const T (&eta)[NX], const T (&J)[NX][NX]) {
+  T M[NX][NX], X[NX][NX + 1];
+  mm(P, J, M);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    M[r][r] += T(1);
+    T u = m[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) u = my_fma(P[r][k], eta[k], u);
+    X[r][NX] = u;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) X[r][c] = P[r][c];
+  }
+  const bool ok = solve_pp(M, X);
+  T FX[NX][NX + 1];
+  mm(F, X, FX);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    m[r] = FX[r][NX] + d[r];
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T s = D[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = my_fma(FX[r][k], F[c][k], s);
+      P[r][c] = s;
+      P[c][r] = s;
+    }
+  }
+  return ok;
+}
+
+// Full filter element and a_i (x) a_j of eq. op-filter, with one elimination:
+//   X = (I + D_i J_j)^{-1} [F_i | d_i + D_i eta_j | D_i],  (I + J_j D_i)^{-1} = W^T,
+//   F = F_j X_F, d = F_j X_u + d_j, D = F_j X_D F_j^T + D_j,
+//   eta = X_F^T (eta_j - J_j d_i) + eta_i, J = X_F^T J_j F_i + J_i.
+template <typename T, int NX>
+struct FElem {
+  T F[NX][NX], d[NX], D[NX][NX], e[NX], J[NX][NX];
+};
+
+template <typename T, int NX>
+SRTM_DEV bool elem_combine(const FElem<T, NX>& a, const FElem<T, NX>& b, FElem<T, NX>& o) {
+  T M[NX][NX], X[NX][2 * NX + 1];
+  mm(a.D, b.J, M);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    M[r][r] += T(1);
+    T u = a.d[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) u = my_fma(a.D[r][k], b.e[k], u);
+    X[r][NX] = u;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      X[r][c] = a.F[r][c];
+      X[r][NX + 1 + c] = a.D[r][c];
+    }
+  }
+  const bool ok = solve_pp(M, X);
+  T FX[NX][2 * NX + 1];
+  mm(b.F, X, FX);
+  T v[NX], JF[NX][NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = b.e[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(-b.J[r][k], a.d[k], s);
+    v[r] = s;
+  }
+  mm(b.J, a.F, JF);
+  FElem<T, NX> t;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    t.d[r] = FX[r][NX] + b.d[r];
+    T s = a.e[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(X[k][r], v[k], s);
+    t.e[r] = s;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) t.F[r][c] = FX[r][c];
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T sd = b.D[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) sd = my_fma(FX[r][NX + 1 + k], b.F[c][k], sd);
+      t.D[r][c] = sd;
+      t.D[c][r] = sd;
+      T sj = a.J[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) sj = my_fma(X[k][r], JF[k][c], sj);
+      t.J[r][c] = sj;
+      t.J[c][r] = sj;
+    }
+  }
+  o = t;
+  return ok;
+}
+
+template <typename T, int NX>
+SRTM_DEV void elem_identity(FElem<T, NX>& a) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    a.d[r] = T(0);
+    a.e[r] = T(0);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      a.F[r][c] = (r == c) ? T(1) : T(0);
+      a.D[r][c] = T(0);
+      a.J[r][c] = T(0);
+    }
+  }
+}
+
+// Smoother element (E, g, S) and eq. op-smoother: for a (earlier) and b (later),
+//   E = E_a E_b, g = E_a g_b + g_a, S = E_a S_b E_a^T + S_a.
+template <typename T, int NX>
+struct SElem {
+  T E[NX][NX], g[NX], S[NX][NX];
+};
+
+template <typename T, int NX>
+SRTM_DEV void selem_combine(const SElem<T, NX>& a, const SElem<T, NX>& b, SElem<T, NX>& o) {
+  SElem<T, NX> t;
+  mm(a.E, b.E, t.E);
+  T ES[NX][NX];
+  mm(a.E, b.S, ES);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = a.g[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(a.E[r][k], b.g[k], s);
+    t.g[r] = s;
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T q = a.S[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) q = my_fma(ES[r][k], a.E[c][k], q);
+      t.S[r][c] = q;
+      t.S[c][r] = q;
+    }
+  }
+  o = t;
+}
+
+// segment (E, g, S) applied to the smoothed state after it: m' = E m + g, P' = E P E^T + S.
+template <typename T, int NX>
+SRTM_DEV void sstate_combine(const SElem<T, NX>& a, T (&m)[NX], T (&P)[NX][NX]) {
+  T EP[NX][NX], mn[NX];
+  mm(a.E, P, EP);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = a.g[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(a.E[r][k], m[k], s);
+    mn[r] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    m[r] = mn[r];
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T q = a.S[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) q = my_fma(EP[r][k], a.E[c][k], q);
+      P[r][c] = q;
+      P[c][r] = q;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- LDS slot storage (SoA)
+template <typename T>
+struct Slots {
+  T* base;
+  int n;  // slots per field row
+  SRTM_DEV T& at(int f, int s) const { return base[f * n + s]; }
+};
+
+template <typename T, int NX>
+SRTM_DEV void st_state(const Slots<T>& S, int s, const T (&m)[NX], const T (&P)[NX][NX]) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) S.at(r, s) = m[r];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = r; c < NX; ++c) S.at(NX + r * NX + c, s) = P[r][c];
+}
+template <typename T, int NX>
+SRTM_DEV void ld_state(const Slots<T>& S, int s, T (&m)[NX], T (&P)[NX][NX]) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) m[r] = S.at(r, s);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      P[r][c] = S.at(NX + r * NX + c, s);
+      P[c][r] = P[r][c];
+    }
+}
+template <typename T, int NX>
+SRTM_DEV void st_felem(const Slots<T>& S, int s, const FElem<T, NX>& a) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    S.at(NN + r, s) = a.d[r];
+    S.at(2 * NN + NX + r, s) = a.e[r];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      S.at(r * NX + c, s) = a.F[r][c];
+      S.at(NN + NX + r * NX + c, s) = a.D[r][c];
+      S.at(2 * NN + 2 * NX + r * NX + c, s) = a.J[r][c];
+    }
+  }
+}
+template <typename T, int NX>
+SRTM_DEV void ld_felem(const Slots<T>& S, int s, FElem<T, NX>& a) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    a.d[r] = S.at(NN + r, s);
+    a.e[r] = S.at(2 * NN + NX + r, s);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      a.F[r][c] = S.at(r * NX + c, s);
+      a.D[r][c] = S.at(NN + NX + r * NX + c, s);
+      a.J[r][c] = S.at(2 * NN + 2 * NX + r * NX + c, s);
+    }
+  }
+}
+template <typename T, int NX>
+SRTM_DEV void st_selem(const Slots<T>& S, int s, const SElem<T, NX>& a) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    S.at(NN + r, s) = a.g[r];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      S.at(r * NX + c, s) = a.E[r][c];
+      S.at(NN + NX + r * NX + c, s) = a.S[r][c];
+    }
+  }
+}
+template <typename T, int NX>
+SRTM_DEV void ld_selem(const Slots<T>& S, int s, SElem<T, NX>& a) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    a.g[r] = S.at(NN + r, s);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      a.E[r][c] = S.at(r * NX + c, s);
+      a.S[r][c] = S.at(NN + NX + r * NX + c, s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- per-window quantities
+// Window k with prior (m, P) = (m^f_{k-1,l}, P^f_{k-1,l}) and measurement y_k. With
+// V = P C_bar^T, S = C_bar V + R_x, U_i = A^i V + c_i = Cov(x_{k,i}, y_k | y_{1:k-1}):
+//   m^f_{k,i} = A^i m + U_i S^{-1} e,   e = y_k - C_bar m,
+//   P^f_{k,i,i} = A^i P A^{iT} + Q_ii - U_i S^{-1} U_i^T,
+//   P^f_{k,i,l} = A^i P A^{lT} + Q_il - U_i S^{-1} U_l^T          (eq. update-fast, blockwise).
+template <typename T, int NX, int NY>
+struct Window {
+  T mp[NX];        // m' = m + V S^{-1} e      ->  m^f_i = A^i m' + c_i Se
+  T Se[NY];        // S^{-1} e
+  T P[NX][NX];     // prior covariance (symmetric)
+  T V[NX][NY];     // P C_bar^T
+  T Si[NY][NY];    // S^{-1} (symmetric)
+  T Y1[NX][NX];    // P A^{lT} - V Y2      ->  P^f_{i,l} = A^i Y1 + Q_il - c_i Y2
+  T Y2[NY][NX];    // S^{-1} U_l^T
+};
+
+template <typename T, int NX, int NY>
+SRTM_DEV bool window_setup(const Model<T, NX, NY>& M, int L, const T (&m)[NX], const T (&P)[NX][NX],
+                           const T (&yk)[NY], Window<T, NX, NY>& w) {
+  T Cb[NY][NX], Rx[NY][NY];
+  load(Cb, M.cst + M.lay.Cbar);
+  load(Rx, M.cst + M.lay.Rx);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) w.P[r][c] = P[r][c];
+  mm_nt(P, Cb, w.V);
+  T S[NY][NY];
+  mm(Cb, w.V, S);
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) S[r][c] += Rx[r][c];
+  symmetrize(S);
+  const bool ok = chol_inv(S, w.Si);
+  T e[NY];
+#pragma unroll
+  for (int r = 0; r < NY; ++r) {
+    T s = yk[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(-Cb[r][k], m[k], s);
+    e[r] = s;
+  }
+  mv(w.Si, e, w.Se);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = m[r];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) s = my_fma(w.V[r][k], w.Se[k], s);
+    w.mp[r] = s;
+  }
+  // U_l = A^l V + c_l, Y2 = S^{-1} U_l^T, Y1 = P A^{lT} - V Y2
+  T AL[NX][NX], cL[NX][NY];
+  load(AL, M.per_i(L) + M.lay.o_Ai);
+  load(cL, M.per_i(L) + M.lay.o_ci);
+  T UL[NX][NY];
+  mm(AL, w.V, UL);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) UL[r][c] += cL[r][c];
+  mm_nt(w.Si, UL, w.Y2);
+  T PAL[NX][NX];
+  mm_nt(P, AL, PAL);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      T s = PAL[r][c];
+#pragma unroll
+      for (int k = 0; k < NY; ++k) s = my_fma(-w.V[r][k], w.Y2[k][c], s);
+      w.Y1[r][c] = s;
+    }
+  return ok;
+}
+
+// Filter blocks of fast step i: mean, P^f_{i,i} and (optionally) P^f_{i,l}.
+template <typename T, int NX, int NY, bool CROSS>
+SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w, int i, T (&mf)[NX],
+                          T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
+  const T* pi = M.per_i(i);
+  T Ai[NX][NX], ci[NX][NY];
+  load(Ai, pi + M.lay.o_Ai);
+  load(ci, pi + M.lay.o_ci);
+  // mean
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) s = my_fma(Ai[r][k], w.mp[k], s);
+#pragma unroll
+    for (int k = 0; k < NY; ++k) s = my_fma(ci[r][k], w.Se[k], s);
+    mf[r] = s;
+  }
+  // U_i = A^i V + c_i ; US = U_i S^{-1}
+  T U[NX][NY], US[NX][NY];
+  mm(Ai, w.V, U);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) U[r][c] += ci[r][c];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < NY; ++k) s = my_fma(U[r][k], symget(w.Si, k, c), s);
+      US[r][c] = s;
+    }
+  // P^f_{i,i} = (A^i P) A^{iT} + Q_ii - US U^T  (upper triangle, mirrored)
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T AP[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = my_fma(Ai[r][k], symget(w.P, k, c), s);
+      AP[c] = s;
+    }
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T s = pi[M.lay.o_Qii + r * NX + c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = my_fma(AP[k], Ai[c][k], s);
+#pragma unroll
+      for (int k = 0; k < NY; ++k) s = my_fma(-US[r][k], U[c][k], s);
+      Pii[r][c] = s;
+      Pii[c][r] = s;
+    }
+  }
+  if (CROSS) {
+    // P^f_{i,l} = A^i Y1 + Q_il - c_i Y2
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        T s = pi[M.lay.o_QiL + r * NX + c];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) s = my_fma(Ai[r][k], w.Y1[k][c], s);
+#pragma unroll
+        for (int k = 0; k < NY; ++k) s = my_fma(-ci[r][k], w.Y2[k][c], s);
+        PiL[r][c] = s;
+      }
+  }
+}
+
+template <typename T, int NX, int NY>
+SRTM_DEV void load_prior(const T* __restrict__ carry, const T* __restrict__ m0, const T* __restrict__ P0,
+                         int64_t k, T (&m)[NX], T (&P)[NX][NX]) {
+  constexpr int ST = NX + NX * NX;
+  if (k == 0) {
+    loadv(m, m0);
+    load(P, P0);
+  } else {
+    loadv(m, carry + (k - 1) * ST);
+    load(P, carry + (k - 1) * ST + NX);
+  }
+}
+
+// Smoother element of window k (eq. parallel-ak-smoothing, transposed S_k):
+//   P^- = A P^f_{k,l} A^T + Q,  E = P^f_{k,1,l} A^T (P^-)^{-1},  g = m^f_{k,1} - E A m^f_{k,l},
+//   S = P^f_{k,1} - E A (P^f_{k,1,l})^T = P^f_{k,1} - E P^- E^T;   last window: (0, m^f_{N,1}, P^f_{N,1}).
+// Also returns (P^-)^{-1} and A m^f_{k,l}, which the fast-rate recovery reuses.
+template <typename T, int NX, int NY>
+SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, bool last,
+                              const T (&mL)[NX], const T (&PL)[NX][NX], SElem<T, NX>& el,
+                              T (&Pmi)[NX][NX], T (&mpred)[NX]) {
+  T mf1[NX], Pf11[NX][NX], Pf1L[NX][NX];
+  window_step<T, NX, NY, true>(M, w, 1, mf1, Pf11, Pf1L);
+  int flag = 0;
+  if (last) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      el.g[r] = mf1[r];
+      mpred[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        el.E[r][c] = T(0);
+        el.S[r][c] = Pf11[r][c];
+        Pmi[r][c] = T(0);
+      }
+    }
+    return 0;
+  }
+  T A[NX][NX], Qm[NX][NX];
+  load(A, M.cst + M.lay.A);
+  load(Qm, M.cst + M.lay.Q);
+  T Pm[NX][NX];
+  sandwich(A, PL, Qm, Pm);
+  if (!chol_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
+  mv(A, mL, mpred);
+  T PA[NX][NX];
+  mm_nt(Pf1L, A, PA);
+  mm(PA, Pmi, el.E);
+  T Em[NX];
+  mv(el.E, mpred, Em);
+  T EPm[NX][NX];
+  mm(el.E, Pm, EPm);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    el.g[r] = mf1[r] - Em[r];
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T s = Pf11[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) s = my_fma(-EPm[r][k], el.E[c][k], s);
+      el.S[r][c] = s;
+      el.S[c][r] = s;
+    }
+  }
+  return flag;
+}
+
+// ============================================================================ forward
+// Vector part of eq. op-filter for two runs of 2^p elements (level-p coefficients).
+template <typename T, int NX>
+SRTM_DEV void level_vec_combine(const T* __restrict__ lev, const ConstLayout& lay, const T (&di)[NX],
+                                const T (&ei)[NX], T (&dj)[NX], T (&ej)[NX]) {
+  T G1[NX][NX], G2[NX][NX], G3[NX][NX], G4[NX][NX];
+  load(G1, lev + lay.o_G1);
+  load(G2, lev + lay.o_G2);
+  load(G3, lev + lay.o_G3);
+  load(G4, lev + lay.o_G4);
+  T nd[NX], ne[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T s = dj[r], t = ei[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      s = my_fma(G1[r][k], di[k], s);
+      s = my_fma(G2[r][k], ej[k], s);
+      t = my_fma(G3[r][k], ej[k], t);
+      t = my_fma(-G4[r][k], di[k], t);
+    }
+    nd[r] = s;
+    ne[r] = t;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    dj[r] = nd[r];
+    ej[r] = ne[r];
+  }
+}
+
+// In-place up-sweep over the vector parts of the tile's elements (slots 0..TILE-1).
+template <typename T, int NX, int NY>
+SRTM_DEV void fwd_upsweep(const Model<T, NX, NY>& M, const Slots<T>& S, int tid) {
+#pragma unroll 1
+  for (int p = 0; p < LOG_TILE; ++p) {
+    const int s = 1 << p;
+    if (((tid + 1) & (2 * s - 1)) == 0) {
+      T di[NX], ei[NX], dj[NX], ej[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        di[r] = S.at(r, tid - s);
+        ei[r] = S.at(NX + r, tid - s);
+        dj[r] = S.at(r, tid);
+        ej[r] = S.at(NX + r, tid);
+      }
+      level_vec_combine(M.level(p), M.lay, di, ei, dj, ej);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        S.at(r, tid) = dj[r];
+        S.at(NX + r, tid) = ej[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NX, int NY>
+SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N,
+                          T (&d)[NX], T (&e)[NX]) {
+  T yk[NY];
+#pragma unroll
+  for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? y[k * NY + r] : T(0);
+  T K[NX][NY], He[NX][NY];
+  load(K, M.cst + M.lay.K);
+  load(He, M.cst + M.lay.Heta);
+  mv(K, yk, d);
+  mv(He, yk, e);
+}
+
+// K1: per-tile aggregate of the vector parts (d, eta) of the filter elements.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE)
+k_fwd_reduce(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L, T* __restrict__ tagg) {
+  __shared__ T smem[2 * NX * TILE];
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Slots<T> S{smem, TILE};
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  T d[NX], e[NX];
+  fwd_element(M, y, k, N, d, e);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    S.at(r, tid) = d[r];
+    S.at(NX + r, tid) = e[r];
+  }
+  __syncthreads();
+  fwd_upsweep(M, S, tid);
+  if (tid == TILE - 1) {
+#pragma unroll
+    for (int r = 0; r < 2 * NX; ++r) tagg[blockIdx.x * 2 * NX + r] = S.at(r, TILE - 1);
+  }
+}
+
+// K2: one workgroup scans the tile aggregates (matrices Theta(TILE), vectors from K1) and
+// writes each tile's exclusive prefix as a state (m, P), starting from (m0, P0).
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TREE)
+k_fwd_tiles(const T* __restrict__ tagg, int64_t nt, const T* __restrict__ cst, int L,
+            const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TREE};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int tid = threadIdx.x;
+  const int64_t per = (nt + TREE - 1) / TREE;
+  const int64_t t0 = tid * per;
+  int flag = 0;
+  const T* lv = M.level(LOG_TILE);
+  FElem<T, NX> base;  // matrices of one full tile
+  load(base.F, lv + M.lay.o_F);
+  load(base.D, lv + M.lay.o_D);
+  load(base.J, lv + M.lay.o_J);
+  FElem<T, NX> acc;
+  elem_identity(acc);
+#pragma unroll 1
+  for (int64_t t = t0; t < t0 + per && t < nt; ++t) {
+    FElem<T, NX> b = base;
+    loadv(b.d, tagg + t * 2 * NX);
+    loadv(b.e, tagg + t * 2 * NX + NX);
+    if (!elem_combine(acc, b, acc)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  }
+  st_felem(S, tid, acc);
+  __syncthreads();
+#pragma unroll 1
+  for (int s = 1; s < TREE; s *= 2) {
+    if (((tid + 1) & (2 * s - 1)) == 0) {
+      FElem<T, NX> a, b;
+      ld_felem(S, tid - s, a);
+      ld_felem(S, tid, b);
+      if (!elem_combine(a, b, b)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      st_felem(S, tid, b);
+    }
+    __syncthreads();
+  }
+  // down-sweep with states; slot TREE-1 starts with the prior (m0, P0)
+  if (tid == TREE - 1) {  // the up-sweep ended with a barrier; the total is not needed
+    T m[NX], P[NX][NX];
+    loadv(m, m0);
+    load(P, P0);
+    symmetrize(P);
+    st_state<T, NX>(S, tid, m, P);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int s = TREE / 2; s >= 1; s /= 2) {
+    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
+    FElem<T, NX> a;
+    T m[NX], P[NX][NX];
+    if (act) {
+      ld_felem(S, tid - s, a);
+      ld_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+    if (act) {
+      st_state<T, NX>(S, tid - s, m, P);
+      if (!state_combine(m, P, a.F, a.d, a.D, a.e, a.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      st_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+  }
+  T m[NX], P[NX][NX];
+  ld_state<T, NX>(S, tid, m, P);
+#pragma unroll 1
+  for (int64_t t = t0; t < t0 + per && t < nt; ++t) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) tstate[t * ST + r] = m[r];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + r * NX + c] = P[r][c];
+    if (t + 1 < nt) {
+      T d[NX], e[NX];
+      loadv(d, tagg + t * 2 * NX);
+      loadv(e, tagg + t * 2 * NX + NX);
+      if (!state_combine(m, P, base.F, d, base.D, e, base.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    }
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+// Output staging: per wave, one record of (mean, covariance) per lane, then stores in
+// which consecutive lanes write consecutive addresses.
+template <typename T, int NX>
+struct Stage {
+  static constexpr int NN = NX * NX;
+  static constexpr int STR = NX + NN + 1;  // odd stride against LDS bank conflicts
+  T* buf;                                  // 64 * STR per wave
+  SRTM_DEV void put(int lane, const T (&m)[NX], const T (&P)[NX][NX]) const {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) buf[lane * STR + r] = m[r];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) buf[lane * STR + NX + r * NX + c] = P[r][c];
+  }
+  // Writes records of lanes 0..nvalid-1: mean of window (w0 + w) at m_out + (w0 + w) * mstride,
+  // covariance at P_out + (w0 + w) * Pstride (element strides).
+  SRTM_DEV void flush(int lane, int nvalid, T* __restrict__ m_out, T* __restrict__ P_out, int64_t w0,
+                      int64_t mstride, int64_t Pstride) const {
+    if (m_out) {
+      for (int j = lane; j < nvalid * NX; j += 64) {
+        const int w = j / NX, c = j - w * NX;
+        m_out[(w0 + w) * mstride + c] = buf[w * STR + c];
+      }
+    }
+    if (P_out) {
+      for (int j = lane; j < nvalid * NN; j += 64) {
+        const int w = j / NN, c = j - w * NN;
+        P_out[(w0 + w) * Pstride + c] = buf[w * STR + NX + c];
+      }
+    }
+  }
+};
+
+template <typename T, int NX>
+SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    ok = ok && isfinite(m[r]);
+#pragma unroll
+    for (int c = r; c < NX; ++c) ok = ok && isfinite(P[r][c]);
+  }
+  return ok;
+}
+
+// K3: per tile, down-sweep from the tile's exclusive state to every window, giving the
+// slow-rate carry (m^f_{k,l}, P^f_{k,l}); optionally the fast-rate filter outputs.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE)
+k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
+            T* __restrict__ carry, T* __restrict__ m_fast, T* __restrict__ P_fast,
+            T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  T* smem = reinterpret_cast<T*>(smraw);
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Slots<T> S{smem, TILE};
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  int flag = 0;
+  T d[NX], e[NX];
+  fwd_element(M, y, k, N, d, e);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    S.at(r, tid) = d[r];
+    S.at(NX + r, tid) = e[r];
+  }
+  __syncthreads();
+  fwd_upsweep(M, S, tid);
+  // down-sweep with states; slot TILE-1 <- the tile's exclusive state
+  if (tid == TILE - 1) {
+    T m[NX], P[NX][NX];
+    loadv(m, tstate + blockIdx.x * ST);
+    load(P, tstate + blockIdx.x * ST + NX);
+    st_state<T, NX>(S, tid, m, P);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int p = LOG_TILE - 1; p >= 0; --p) {
+    const int s = 1 << p;
+    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
+    T dl[NX], el[NX], m[NX], P[NX][NX];
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        dl[r] = S.at(r, tid - s);
+        el[r] = S.at(NX + r, tid - s);
+      }
+      ld_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+    if (act) {
+      st_state<T, NX>(S, tid - s, m, P);
+      const T* lv = M.level(p);
+      T F[NX][NX], D[NX][NX], J[NX][NX];
+      load(F, lv + M.lay.o_F);
+      load(D, lv + M.lay.o_D);
+      load(J, lv + M.lay.o_J);
+      if (!state_combine(m, P, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      st_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+  }
+  // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
+  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
+  ld_state<T, NX>(S, tid, mprev, Pprev);
+  if (k == 0) {  // the prior itself, not a rounded copy through the tree
+    loadv(mprev, m0);
+    load(Pprev, P0);
+    symmetrize(Pprev);
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    m[r] = mprev[r];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) P[r][c] = Pprev[r][c];
+  }
+  {
+    const T* lv = M.level(0);
+    T F[NX][NX], D[NX][NX], J[NX][NX];
+    load(F, lv + M.lay.o_F);
+    load(D, lv + M.lay.o_D);
+    load(J, lv + M.lay.o_J);
+    if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  }
+  if (k < N) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) carry[k * ST + r] = m[r];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) carry[k * ST + NX + r * NX + c] = P[r][c];
+    if (m_slow) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) m_slow[k * NX + r] = m[r];
+    }
+    if (P_slow) {
+#pragma unroll
+      for (int r = 0; r < NN; ++r) P_slow[k * NN + r] = P[r / NX][r % NX];
+    }
+    if (!finite_state(m, P)) flag |= SRTM_INFO_NONFINITE;
+  }
+  if (m_fast || P_fast) {
+    __syncthreads();  // LDS becomes the output stage
+    const int lane = tid & 63, wv = tid >> 6;
+    const Stage<T, NX> stg{smem + wv * 64 * Stage<T, NX>::STR};
+    const int64_t w0 = (int64_t)blockIdx.x * TILE + wv * 64;
+    const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
+    Window<T, NX, NY> w;
+    T yk[NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? y[k * NY + r] : T(0);
+    if (!window_setup(M, L, mprev, Pprev, yk, w) && k < N) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    bool fin = true;
+#pragma unroll 1
+    for (int i = 1; i <= L; ++i) {
+      T mf[NX], Pii[NX][NX], PiL[NX][NX];
+      window_step<T, NX, NY, false>(M, w, i, mf, Pii, PiL);
+      fin = fin && finite_state(mf, Pii);
+      stg.put(lane, mf, Pii);
+      wave_sync();
+      stg.flush(lane, nvalid, m_fast ? m_fast + (int64_t)(i - 1) * NX : nullptr,
+                P_fast ? P_fast + (int64_t)(i - 1) * NN : nullptr, w0, (int64_t)L * NX, (int64_t)L * NN);
+      wave_sync();
+    }
+    if (!fin && k < N) flag |= SRTM_INFO_NONFINITE;
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+// ============================================================================ backward
+// Builds the smoother element of window k (zero element past the end).
+template <typename T, int NX, int NY>
+SRTM_DEV int bwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N, int L,
+                         const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+                         SElem<T, NX>& el, Window<T, NX, NY>& w, T (&Pmi)[NX][NX], T (&mpred)[NX]) {
+  constexpr int ST = NX + NX * NX;
+  int flag = 0;
+  if (k < N) {
+    T m[NX], P[NX][NX], mL[NX], PL[NX][NX], yk[NY];
+    load_prior<T, NX, NY>(carry, m0, P0, k, m, P);
+    loadv(mL, carry + k * ST);
+    load(PL, carry + k * ST + NX);
+    loadv(yk, y + k * NY);
+    if (!window_setup(M, L, m, P, yk, w)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    flag |= smoother_element(M, L, w, k == N - 1, mL, PL, el, Pmi, mpred);
+  } else {  // past the last window: a zero element and a zero window (never stored)
+    T z[NX], Z[NX][NX], zy[NY];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      z[r] = T(0);
+      mpred[r] = T(0);
+      el.g[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        Z[r][c] = (r == c) ? T(1) : T(0);
+        el.E[r][c] = T(0);
+        el.S[r][c] = T(0);
+        Pmi[r][c] = T(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NY; ++r) zy[r] = T(0);
+    window_setup(M, L, z, Z, zy, w);
+  }
+  return flag;
+}
+
+// Reversed in-place up-sweep: slot r holds window (tile end - r); combining slot j - s
+// (later windows) with slot j (earlier windows) gives  a_j (x) a_{j-s}.
+template <typename T, int NX>
+SRTM_DEV void bwd_upsweep(const Slots<T>& S, int tid, int n) {
+#pragma unroll 1
+  for (int s = 1; s < n; s *= 2) {
+    if (((tid + 1) & (2 * s - 1)) == 0) {
+      SElem<T, NX> later, earlier;
+      ld_selem(S, tid - s, later);
+      ld_selem(S, tid, earlier);
+      selem_combine(earlier, later, earlier);
+      st_selem(S, tid, earlier);
+    }
+    __syncthreads();
+  }
+}
+
+// K4: per-tile smoother aggregate a_first (x) ... (x) a_last.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE)
+k_bwd_reduce(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
+             const T* __restrict__ P0, const T* __restrict__ carry, T* __restrict__ tagg, int32_t* info) {
+  constexpr int NN = NX * NX, SE = 2 * NN + NX;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  SElem<T, NX> el;
+  Window<T, NX, NY> w;
+  T Pmi[NX][NX], mpred[NX];
+  const int flag = bwd_element(M, y, k, N, L, m0, P0, carry, el, w, Pmi, mpred);
+  st_selem(S, TILE - 1 - tid, el);
+  __syncthreads();
+  bwd_upsweep<T, NX>(S, tid, TILE);
+  if (tid == 0) {
+    for (int f = 0; f < SE; ++f) tagg[blockIdx.x * SE + f] = S.at(f, TILE - 1);
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+// K5: one workgroup scans the tile aggregates in reverse and writes, per tile, the
+// smoothed state of the first window after it (m^s_{k+1,1}, P^s_{k+1,1}).
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TREE)
+k_bwd_tiles(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
+  constexpr int NN = NX * NX, SE = 2 * NN + NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TREE};
+  const int tid = threadIdx.x;
+  const int64_t per = (nt + TREE - 1) / TREE;
+  const int64_t r0 = tid * per;  // reversed tile indices r0 .. r0+per-1 (tile = nt-1-r)
+  SElem<T, NX> acc;
+  bool have = false;
+#pragma unroll 1
+  for (int64_t r = r0; r < r0 + per && r < nt; ++r) {
+    const T* src = tagg + (nt - 1 - r) * SE;
+    SElem<T, NX> b;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      b.g[i] = src[NN + i];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        b.E[i][c] = src[i * NX + c];
+        b.S[i][c] = src[NN + NX + i * NX + c];
+      }
+    }
+    if (have) {
+      selem_combine(b, acc, acc);  // earlier tile (x) later aggregate
+    } else {
+      acc = b;
+      have = true;
+    }
+  }
+  if (!have) {  // identity (I, 0, 0)
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      acc.g[i] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        acc.E[i][c] = (i == c) ? T(1) : T(0);
+        acc.S[i][c] = T(0);
+      }
+    }
+  }
+  st_selem(S, tid, acc);
+  __syncthreads();
+  bwd_upsweep<T, NX>(S, tid, TREE);
+  // down-sweep with states; the state after the last window is irrelevant (E_N = 0)
+  if (tid == TREE - 1) {
+    T m[NX], P[NX][NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      m[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) P[r][c] = T(0);
+    }
+    st_state<T, NX>(S, tid, m, P);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int s = TREE / 2; s >= 1; s /= 2) {
+    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
+    SElem<T, NX> later;
+    T m[NX], P[NX][NX];
+    if (act) {
+      ld_selem(S, tid - s, later);
+      ld_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+    if (act) {
+      st_state<T, NX>(S, tid - s, m, P);
+      sstate_combine(later, m, P);
+      st_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+  }
+  T m[NX], P[NX][NX];
+  ld_state<T, NX>(S, tid, m, P);
+#pragma unroll 1
+  for (int64_t r = r0; r < r0 + per && r < nt; ++r) {
+    const int64_t t = nt - 1 - r;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) tstate[t * ST + i] = m[i];
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + i * NX + c] = P[i][c];
+    const T* src = tagg + t * SE;
+    SElem<T, NX> b;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      b.g[i] = src[NN + i];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        b.E[i][c] = src[i * NX + c];
+        b.S[i][c] = src[NN + NX + i * NX + c];
+      }
+    }
+    sstate_combine(b, m, P);
+  }
+}
+
+// K6: per tile, down-sweep of smoothed states, then the fast-rate smoothed recovery of
+// eq. seq-smoothing-all, blockwise: with v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}) and
+// W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A,
+//   m^s_{k,i} = m^f_{k,i} + P^f_{k,i,l} v,   P^s_{k,i} = P^f_{k,i,i} + P^f_{k,i,l} W P^f_{k,i,l}^T.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE)
+k_bwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
+            const T* __restrict__ P0, const T* __restrict__ carry, const T* __restrict__ tstate,
+            T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow, T* __restrict__ Ps_slow,
+            int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  T* smem = reinterpret_cast<T*>(smraw);
+  const Slots<T> S{smem, TILE};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int tid = threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  SElem<T, NX> el;
+  Window<T, NX, NY> w;
+  T Pmi[NX][NX], mpred[NX];
+  int flag = bwd_element(M, y, k, N, L, m0, P0, carry, el, w, Pmi, mpred);
+  st_selem(S, TILE - 1 - tid, el);
+  __syncthreads();
+  bwd_upsweep<T, NX>(S, tid, TILE);
+  if (tid == TILE - 1) {
+    T m[NX], P[NX][NX];
+    loadv(m, tstate + blockIdx.x * ST);
+    load(P, tstate + blockIdx.x * ST + NX);
+    st_state<T, NX>(S, tid, m, P);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int s = TILE / 2; s >= 1; s /= 2) {
+    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
+    SElem<T, NX> later;
+    T m[NX], P[NX][NX];
+    if (act) {
+      ld_selem(S, tid - s, later);
+      ld_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+    if (act) {
+      st_state<T, NX>(S, tid - s, m, P);
+      sstate_combine(later, m, P);
+      st_state<T, NX>(S, tid, m, P);
+    }
+    __syncthreads();
+  }
+  // exclusive suffix state of window k = smoothed state of window k+1, block 1
+  T msn[NX], Psn[NX][NX];
+  ld_state<T, NX>(S, TILE - 1 - tid, msn, Psn);
+  __syncthreads();  // LDS becomes the output stage
+  // v and W (zero for the last window, whose smoothed blocks equal the filtered ones)
+  T v[NX], W[NX][NX];
+  if (k < N - 1) {
+    T A[NX][NX], PL[NX][NX], Qm[NX][NX];
+    load(A, cst + M.lay.A);
+    load(Qm, cst + M.lay.Q);
+    load(PL, carry + k * ST + NX);
+    T Pm[NX][NX];
+    sandwich(A, PL, Qm, Pm);
+    T B[NX][NX];  // B = (P^-)^{-1} A
+    mm(Pmi, A, B);
+    T dm[NX], Dm[NX][NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      dm[r] = msn[r] - mpred[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) Dm[r][c] = Psn[r][c] - Pm[r][c];
+    }
+    mtv(B, dm, v);
+    T DB[NX][NX];
+    mm(Dm, B, DB);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) s = my_fma(B[q][r], DB[q][c], s);
+        W[r][c] = s;
+        W[c][r] = s;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      v[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) W[r][c] = T(0);
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  const Stage<T, NX> stg{smem + wv * 64 * Stage<T, NX>::STR};
+  const int64_t w0 = (int64_t)blockIdx.x * TILE + wv * 64;
+  const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
+  bool fin = true;
+#pragma unroll 1
+  for (int i = 1; i <= L; ++i) {
+    T mf[NX], Pii[NX][NX], PiL[NX][NX];
+    window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
+    T ms[NX], Ps[NX][NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      T s = mf[r];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
+      ms[r] = s;
+      T TW[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        T t = T(0);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(PiL[r][q], symget(W, q, c), t);
+        TW[c] = t;
+      }
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T t = Pii[r][c];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(TW[q], PiL[c][q], t);
+        Ps[r][c] = t;
+        Ps[c][r] = t;
+      }
+    }
+    fin = fin && finite_state(ms, Ps);
+    stg.put(lane, ms, Ps);
+    wave_sync();
+    stg.flush(lane, nvalid, ms_fast ? ms_fast + (int64_t)(i - 1) * NX : nullptr,
+              Ps_fast ? Ps_fast + (int64_t)(i - 1) * NN : nullptr, w0, (int64_t)L * NX, (int64_t)L * NN);
+    if (i == 1) stg.flush(lane, nvalid, ms_slow, Ps_slow, w0, NX, NN);
+    wave_sync();
+  }
+  if (!fin && k < N) flag |= SRTM_INFO_NONFINITE;
+  if (flag && info) atomicOr(info, flag);
+}
+
+// ============================================================================ launchers
+struct Ptrs {
+  const void *F, *Q, *H, *R, *m0, *P0, *y;
+  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow;
+  void *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
+  void* ws;
+  int32_t* info;
+};
+
+struct Events {
+  hipEvent_t const* ev;
+  int n;
+  int j;
+  hipError_t pre(hipStream_t s) {
+    if (!ev || 2 * j + 1 >= n) return hipSuccess;
+    return hipEventRecord(ev[2 * j], s);
+  }
+  hipError_t post(hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (ev && 2 * j + 1 < n) e = hipEventRecord(ev[2 * j + 1], s);
+    ++j;
+    return e;
+  }
+};
+
+size_t constants_lds_bytes(int nx, int ny, int L) {
+  const int nn = nx * nx, nxy = nx * ny;
+  const int w2s = nn > 2 * nxy ? nn : 2 * nxy;
+  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy));
+}
+
+#define SRTM_CHECK_LAUNCH()                    \
+  do {                                         \
+    hipError_t _e = hipGetLastError();         \
+    if (_e != hipSuccess) return SRTM_E_HIP;   \
+  } while (0)
+
+#define SRTM_EV(call)                          \
+  do {                                         \
+    if ((call) != hipSuccess) return SRTM_E_HIP; \
+  } while (0)
+
+template <typename T, int NX, int NY>
+srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, Events ev) {
+  constexpr int NN = NX * NX;
+  const int L = sh.L;
+  const int64_t N = sh.N;
+  const int64_t nt = (N + TILE - 1) / TILE;
+  const WorkLayout wl = make_work_layout(NX, NY, L, N, sizeof(T), smoother);
+  char* ws = static_cast<char*>(p.ws);
+  T* cst = reinterpret_cast<T*>(ws + wl.consts);
+  T* ftagg = reinterpret_cast<T*>(ws + wl.ftile_agg);
+  T* ftst = reinterpret_cast<T*>(ws + wl.ftile_state);
+  T* carry = reinterpret_cast<T*>(ws + wl.carry);
+  const T* y = static_cast<const T*>(p.y);
+  const T* m0 = static_cast<const T*>(p.m0);
+  const T* P0 = static_cast<const T*>(p.P0);
+
+  const size_t lds0 = constants_lds_bytes(NX, NY, L);
+  // Dynamic LDS above 64 KiB must be allowed per kernel before launching.
+  auto allow = [](const void* f, size_t bytes) {
+    if (bytes > 65536) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  };
+  allow((const void*)k_constants<T, NX, NY>, lds0);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(1), dim3(256), lds0, st, static_cast<const T*>(p.F),
+                     static_cast<const T*>(p.Q), static_cast<const T*>(p.H), static_cast<const T*>(p.R), L, cst,
+                     p.info);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), 0, st, y, N, cst, L, ftagg);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  const size_t lds_ft = sizeof(T) * (size_t)TREE * (3 * NN + 2 * NX);
+  allow((const void*)k_fwd_tiles<T, NX, NY>, lds_ft);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_fwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_ft, st, ftagg, nt, cst, L, m0, P0, ftst,
+                     p.info);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  T* mf_fast = static_cast<T*>(p.mf_fast);
+  T* Pf_fast = static_cast<T*>(p.Pf_fast);
+  T* mf_slow = static_cast<T*>(p.mf_slow);
+  T* Pf_slow = static_cast<T*>(p.Pf_slow);
+  const size_t fslot = (2 * NX > NX + NN) ? 2 * NX : NX + NN;
+  const size_t fstage = (size_t)4 * 64 * Stage<T, NX>::STR;
+  const size_t lds_ff = sizeof(T) * (fslot * TILE > fstage ? fslot * TILE : fstage);
+  allow((const void*)k_fwd_final<T, NX, NY>, lds_ff);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0, ftst,
+                     carry, mf_fast, Pf_fast, mf_slow, Pf_slow, p.info);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+  if (!smoother) return SRTM_OK;
+
+  T* btagg = reinterpret_cast<T*>(ws + wl.btile_agg);
+  T* btst = reinterpret_cast<T*>(ws + wl.btile_state);
+  const size_t lds_br = sizeof(T) * (size_t)TILE * (2 * NN + NX);
+  allow((const void*)k_bwd_reduce<T, NX, NY>, lds_br);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_bwd_reduce<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_br, st, y, N, L, cst, m0, P0,
+                     carry, btagg, p.info);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  const size_t lds_bt = sizeof(T) * (size_t)TREE * (2 * NN + NX);
+  allow((const void*)k_bwd_tiles<T, NX, NY>, lds_bt);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_bt, st, btagg, nt, btst);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  const size_t stage = sizeof(T) * (size_t)4 * 64 * Stage<T, NX>::STR;
+  const size_t lds_bf = lds_br > stage ? lds_br : stage;
+  allow((const void*)k_bwd_final<T, NX, NY>, lds_bf);
+  SRTM_EV(ev.pre(st));
+  hipLaunchKernelGGL((k_bwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_bf, st, y, N, L, cst, m0, P0,
+                     carry, btst, static_cast<T*>(p.ms_fast), static_cast<T*>(p.Ps_fast),
+                     static_cast<T*>(p.ms_slow), static_cast<T*>(p.Ps_slow), p.info);
+  SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+  return SRTM_OK;
+}
+
+}  // namespace srtm
+
+// ---------------------------------------------------------------- dispatch (C++ linkage)
+#define SRTM_PAIRS(X) X(1, 1) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2)
+
+namespace srtm {
+bool pair_supported(int nx, int ny) {
+#define SRTM_SUP(a, b) if (nx == a && ny == b) return true;
+  SRTM_PAIRS(SRTM_SUP)
+#undef SRTM_SUP
+  return false;
+}
+
+srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, hipEvent_t const* ev,
+                     int nev) {
+  Events E{ev, nev, 0};
+#define SRTM_DISP(a, b)                                                            \
+  if (sh.nx == a && sh.ny == b) {                                                  \
+    if (sh.dtype == SRTM_F64) return run<double, a, b>(sh, p, smoother, st, E);   \
+    return run<float, a, b>(sh, p, smoother, st, E);                               \
+  }
+  SRTM_PAIRS(SRTM_DISP)
+#undef SRTM_DISP
+  return SRTM_E_UNSUPPORTED;
+}
+}  // namespace srtm

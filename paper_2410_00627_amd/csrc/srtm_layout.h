@@ -1,0 +1,74 @@
+// Layout of the per-call constants block and of the workspace (host and device).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace srtm {
+
+constexpr int TILE = 256;       // windows per workgroup in the per-tile kernels
+constexpr int LOG_TILE = 8;
+constexpr int NLEV = LOG_TILE + 1;  // scan-table levels p = 0..LOG_TILE (segments of 2^p windows)
+constexpr int TREE = 256;       // threads of the single-workgroup tile-level scans
+
+// Offsets (in scalars) into the constants block written by the constants kernel.
+struct ConstLayout {
+  int nx, ny, L;
+  int A, Q, Cbar, Rx, K, Heta;   // model and slow-rate constants
+  int per_i, per_i_stride;       // per fast step i = 1..L: A^i, Q_ii, Q_iL, c_i
+  int o_Ai, o_Qii, o_QiL, o_ci;
+  int lev, lev_stride;           // per level p: F, D, J of 2^p merged windows and
+  int o_F, o_D, o_J, o_G1, o_G2, o_G3, o_G4;  // the vector-combine coefficients
+  int total;
+};
+
+inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L) {
+  ConstLayout c;
+  const int nn = nx * nx, nxy = nx * ny;
+  c.nx = nx; c.ny = ny; c.L = L;
+  int o = 0;
+  c.A = o; o += nn;
+  c.Q = o; o += nn;
+  c.Cbar = o; o += nxy;
+  c.Rx = o; o += ny * ny;
+  c.K = o; o += nxy;
+  c.Heta = o; o += nxy;
+  o = (o + 7) & ~7;
+  c.o_Ai = 0; c.o_Qii = nn; c.o_QiL = 2 * nn; c.o_ci = 3 * nn;
+  c.per_i_stride = (3 * nn + nxy + 7) & ~7;
+  c.per_i = o; o += L * c.per_i_stride;
+  c.o_F = 0; c.o_D = nn; c.o_J = 2 * nn; c.o_G1 = 3 * nn; c.o_G2 = 4 * nn; c.o_G3 = 5 * nn; c.o_G4 = 6 * nn;
+  c.lev_stride = (7 * nn + 7) & ~7;
+  c.lev = o; o += NLEV * c.lev_stride;
+  c.total = o;
+  return c;
+}
+
+// Workspace regions, byte offsets (256-byte aligned).
+struct WorkLayout {
+  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother) {
+  WorkLayout w;
+  const ConstLayout c = make_const_layout(nx, ny, L);
+  const int64_t nt = (N + TILE - 1) / TILE;
+  const size_t nn = (size_t)nx * nx;
+  size_t o = 0;
+  w.consts = o; o = align256(o + (size_t)c.total * esz);
+  w.ftile_agg = o; o = align256(o + (size_t)nt * 2 * nx * esz);
+  w.ftile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
+  w.carry = o; o = align256(o + (size_t)N * (nx + nn) * esz);
+  if (smoother) {
+    w.btile_agg = o; o = align256(o + (size_t)nt * (2 * nn + nx) * esz);
+    w.btile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
+  } else {
+    w.btile_agg = w.btile_state = 0;
+  }
+  w.total = o;
+  return w;
+}
+
+}  // namespace srtm

@@ -1,0 +1,218 @@
+"""Python binding of libsrtm (argument marshalling only).
+
+Every function here validates tensor placement, allocates outputs and workspace with
+torch on the current device and stream, and calls the C-ABI entry point of the same
+name in libsrtm.so. All arithmetic runs in the HIP kernels; there is no fallback. A
+missing library or a non-GPU tensor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsrtm.so")
+
+SRTM_F32, SRTM_F64 = 0, 1
+INFO_BITS = {1: "innovation covariance not positive definite", 2: "I + D_i J_j singular in the filter combine",
+             4: "smoother prediction covariance singular", 8: "non-finite output"}
+
+
+class SrtmError(RuntimeError):
+    pass
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("N", ctypes.c_int64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded libsrtm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SrtmError(f"{LIB_PATH} not found: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    L.srtm_workspace_size.argtypes = [ctypes.POINTER(Shape), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.srtm_workspace_size.restype = ctypes.c_int
+    L.srtm_supported.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.srtm_supported.restype = ctypes.c_int32
+    L.srtm_filter.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_filter.restype = ctypes.c_int
+    L.srtm_smooth.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 16 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth.restype = ctypes.c_int
+    L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
+                                       [ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_int32])
+    L.srtm_smooth_profiled.restype = ctypes.c_int
+    L.srtm_kernel_count.argtypes = [ctypes.c_int32]
+    L.srtm_kernel_count.restype = ctypes.c_int32
+    L.srtm_kernel_name.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.srtm_kernel_name.restype = ctypes.c_char_p
+    L.srtm_status_string.argtypes = [ctypes.c_int32]
+    L.srtm_status_string.restype = ctypes.c_char_p
+    L.srtm_version.argtypes = []
+    L.srtm_version.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return lib().srtm_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise SrtmError(f"{what}: status {code} ({status_string(code)})")
+
+
+def _dtype_code(dtype: torch.dtype) -> int:
+    if dtype == torch.float64:
+        return SRTM_F64
+    if dtype == torch.float32:
+        return SRTM_F32
+    raise SrtmError(f"unsupported dtype {dtype}; use torch.float32 or torch.float64")
+
+
+def shape_of(nx: int, ny: int, L: int, N: int, dtype: torch.dtype) -> Shape:
+    return Shape(nx, ny, L, _dtype_code(dtype), N)
+
+
+def workspace_size(nx: int, ny: int, L: int, N: int, dtype: torch.dtype, smoother: bool) -> int:
+    out = ctypes.c_size_t(0)
+    sh = shape_of(nx, ny, L, N, dtype)
+    _check(lib().srtm_workspace_size(ctypes.byref(sh), int(smoother), ctypes.byref(out)), "srtm_workspace_size")
+    return int(out.value)
+
+
+def kernel_names(smoother: bool):
+    L = lib()
+    return [L.srtm_kernel_name(int(smoother), j).decode() for j in range(L.srtm_kernel_count(int(smoother)))]
+
+
+def _prep(F, Q, H, R, L, m0, P0, y):
+    ts = dict(F=F, Q=Q, H=H, R=R, m0=m0, P0=P0, y=y)
+    dev, dt = y.device, y.dtype
+    for k, t in ts.items():
+        if not isinstance(t, torch.Tensor):
+            raise SrtmError(f"{k} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise SrtmError(f"{k} must be on a GPU (got {t.device}); there is no CPU path")
+        if t.device != dev or t.dtype != dt:
+            raise SrtmError(f"{k} must share device {dev} and dtype {dt}")
+    nx, ny = F.shape[0], H.shape[0]
+    N = y.shape[0]
+    exp = dict(F=(nx, nx), Q=(nx, nx), H=(ny, nx), R=(ny, ny), m0=(nx,), P0=(nx, nx), y=(N, ny))
+    for k, s in exp.items():
+        if tuple(ts[k].shape) != s:
+            raise SrtmError(f"{k} has shape {tuple(ts[k].shape)}, expected {s}")
+    ts = {k: v.contiguous() for k, v in ts.items()}
+    return ts, nx, ny, N
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _raise_info(info: torch.Tensor, what: str):
+    v = int(info.item())
+    if v:
+        msgs = [m for b, m in INFO_BITS.items() if v & b]
+        raise SrtmError(f"{what}: numerical failure, info={v} ({'; '.join(msgs)})")
+
+
+def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = True,
+           workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
+           check: bool = True) -> Dict[str, torch.Tensor]:
+    """p(x_{k,i} | y_{1:k}) as m_fast [N,L,nx], P_fast [N,L,nx,nx]; p(x_{k,L} | y_{1:k}) as m_slow, P_slow."""
+    ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    dev, dt = y.device, y.dtype
+    out = {}
+    if fast:
+        out["m_fast"] = torch.empty((N, L, nx), device=dev, dtype=dt)
+        out["P_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
+    if slow:
+        out["m_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
+        out["P_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+    nbytes = workspace_size(nx, ny, L, N, dt, False)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
+    if info is None:
+        info = torch.zeros(1, device=dev, dtype=torch.int32)
+    sh = shape_of(nx, ny, L, N, dt)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    code = lib().srtm_filter(ctypes.byref(sh), *(_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")),
+                             _ptr(out.get("m_fast")), _ptr(out.get("P_fast")), _ptr(out.get("m_slow")),
+                             _ptr(out.get("P_slow")), _ptr(workspace), workspace.numel(), _ptr(info),
+                             ctypes.c_void_p(stream))
+    _check(code, "srtm_filter")
+    if check:
+        _raise_info(info, "srtm_filter")
+    out["info"] = info
+    return out
+
+
+def _smooth_args(ts, out, workspace, info):
+    return ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
+            [_ptr(out.get(k)) for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow",
+                                        "mf_fast", "Pf_fast", "mf_slow", "Pf_slow")] +
+            [_ptr(workspace), workspace.numel(), _ptr(info)])
+
+
+def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = True, with_filter: bool = False,
+           workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
+           out: Optional[Dict[str, torch.Tensor]] = None, check: bool = True,
+           events=None) -> Dict[str, torch.Tensor]:
+    """p(x_{k,i} | y_{1:N}) as ms_fast [N,L,nx], Ps_fast [N,L,nx,nx]; p(x_{k,1} | y_{1:N}) as ms_slow, Ps_slow.
+
+    with_filter also returns the filter outputs (mf_fast, Pf_fast, mf_slow, Pf_slow). `out` may
+    supply preallocated output tensors; `events` (a ctypes array of hipEvent_t) selects the
+    profiling entry point.
+    """
+    ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    dev, dt = y.device, y.dtype
+    if out is None:
+        out = {}
+        if fast:
+            out["ms_fast"] = torch.empty((N, L, nx), device=dev, dtype=dt)
+            out["Ps_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
+        if slow:
+            out["ms_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
+            out["Ps_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+        if with_filter:
+            out["mf_fast"] = torch.empty((N, L, nx), device=dev, dtype=dt)
+            out["Pf_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
+            out["mf_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
+            out["Pf_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+    nbytes = workspace_size(nx, ny, L, N, dt, True)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
+    if info is None:
+        info = torch.zeros(1, device=dev, dtype=torch.int32)
+    sh = shape_of(nx, ny, L, N, dt)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    args = _smooth_args(ts, out, workspace, info)
+    if events is None:
+        code = lib().srtm_smooth(ctypes.byref(sh), *args, stream)
+        _check(code, "srtm_smooth")
+    else:
+        code = lib().srtm_smooth_profiled(ctypes.byref(sh), *args, stream, events, len(events))
+        _check(code, "srtm_smooth_profiled")
+    if check:
+        _raise_info(info, "srtm_smooth")
+    out["info"] = info
+    return out
+
+
+def model_tensors(model, device="cuda", dtype=torch.float64):
+    """(F, Q, H, R, m0, P0) of a workloads.Model as device tensors."""
+    conv = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()  # noqa: E731
+    return conv(model.A), conv(model.Q), conv(model.C), conv(model.R), conv(model.m0), conv(model.P0)

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 CPU reference.
+
+Tolerances (relative, per fast state, metric of conftest.rel_errors): 1e-8 for the
+float64 path, 1e-3 for the float32 path. The float32 path is compared with the
+reference evaluated on the float32-rounded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_00627_amd import workloads as wl
+from conftest import assert_close_states, rel_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-8, torch.float32: 1e-3}
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_00627_amd import srtm
+    srtm.lib()
+    return srtm
+
+
+def _rounded(model, y, dtype):
+    if dtype == torch.float64:
+        return model, y
+    r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+    m = wl.Model(r(model.A), r(model.Q), r(model.C), r(model.R), model.L, r(model.m0), r(model.P0), model.name)
+    return m, r(y)
+
+
+def _args(m):
+    return (m.A, m.Q, m.C, m.R, m.L, m.m0, m.P0)
+
+
+def run_gpu(model, y, dtype, *, filter_only=False, with_filter=True):
+    srtm = _need_gpu()
+    F, Q, H, R, m0, P0 = srtm.model_tensors(model, "cuda", dtype)
+    yt = torch.as_tensor(y, dtype=torch.float64).to("cuda", dtype)
+    print(f"[gpu] {'filter' if filter_only else 'smooth'} nx={model.nx} ny={model.ny} L={model.L} "
+          f"N={y.shape[0]} dtype={dtype}", flush=True)
+    if filter_only:
+        out = srtm.filter(F, Q, H, R, model.L, m0, P0, yt)
+    else:
+        out = srtm.smooth(F, Q, H, R, model.L, m0, P0, yt, with_filter=with_filter)
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in out.items()}
+
+
+def check_smoother(model, y, dtype, what=""):
+    out = run_gpu(model, y, dtype)
+    mr, yr = _rounded(model, y, dtype)
+    ref = oracle.srtm_smoother(*_args(mr), yr, with_filter=True)
+    tol = TOL[dtype]
+    assert int(out["info"][0]) == 0
+    assert_close_states(out["ms_fast"], out["Ps_fast"], ref["ms_fast"], ref["Ps_fast"], tol, what + " smoothed fast")
+    assert_close_states(out["ms_slow"], out["Ps_slow"], ref["ms_slow"], ref["Ps_slow"], tol, what + " smoothed slow")
+    assert_close_states(out["mf_fast"], out["Pf_fast"], ref["m_fast"], ref["P_fast"], tol, what + " filtered fast")
+    assert_close_states(out["mf_slow"], out["Pf_slow"], ref["m_slow"], ref["P_slow"], tol, what + " filtered slow")
+    for k in ("Ps_fast", "Pf_fast", "Ps_slow", "Pf_slow"):
+        assert np.array_equal(out[k], np.swapaxes(out[k], -1, -2)), f"{k} not exactly symmetric"
+    return out, ref
+
+
+# ----------------------------------------------------------------------------- tiny case
+@pytest.mark.parametrize("dtype", [torch.float64])
+def test_wna_tiny(dtype):
+    """Position/velocity model, l = 10, N = 100 (the tiny float64 case)."""
+    m = wl.wna_model()
+    y = wl.simulate(m, wl.WNA_N, seed=1)
+    check_smoother(m, y, dtype, "wna")
+
+
+# ----------------------------------------------------------------------------- shapes
+CASES = [
+    # nx, ny, L, N, seed  -- N spans several 256-window tiles with a ragged tail
+    (4, 2, 20, 845, 1),
+    (2, 1, 10, 600, 2),
+    (3, 2, 7, 300, 3),
+    (4, 1, 5, 1100, 4),
+    (1, 1, 3, 513, 5),
+    (2, 2, 1, 700, 6),      # l = 1: Kalman filter + RTS smoother
+    (3, 1, 16, 257, 7),
+]
+
+
+@pytest.mark.parametrize("nx,ny,L,N,seed", CASES, ids=[f"nx{c[0]}ny{c[1]}L{c[2]}N{c[3]}" for c in CASES])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_parity_shapes(nx, ny, L, N, seed, dtype):
+    m = wl.random_stable_model(nx, ny, L, seed)
+    y = wl.simulate(m, N, seed + 50)
+    check_smoother(m, y, dtype, f"nx{nx} ny{ny} L{L} N{N}")
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 255, 256, 257, 512, 513])
+def test_edge_lengths(N):
+    m = wl.random_general_model(3, 2, 4, 11)
+    y = wl.simulate(m, N, 12)
+    check_smoother(m, y, torch.float64, f"N={N}")
+
+
+def test_general_model_nonzero_prior():
+    """Non-orthogonal A, full Q, R, P0 and nonzero m0."""
+    m = wl.random_general_model(4, 2, 6, 21)
+    y = wl.simulate(m, 400, 22)
+    check_smoother(m, y, torch.float64, "general")
+
+
+def test_filter_entry_point_matches_smoother_filter_outputs():
+    m = wl.random_stable_model(4, 2, 20, 31)
+    y = wl.simulate(m, 300, 32)
+    f = run_gpu(m, y, torch.float64, filter_only=True)
+    ref = oracle.srtm_filter(*_args(m), y)
+    assert_close_states(f["m_fast"], f["P_fast"], ref["m_fast"], ref["P_fast"], 1e-8, "srtm_filter fast")
+    assert_close_states(f["m_slow"], f["P_slow"], ref["m_slow"], ref["P_slow"], 1e-8, "srtm_filter slow")
+
+
+def test_bitwise_deterministic():
+    m = wl.random_stable_model(4, 2, 20, 41)
+    y = wl.simulate(m, 1000, 42)
+    a = run_gpu(m, y, torch.float64)
+    b = run_gpu(m, y, torch.float64)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_info_flags_forced_from_host():
+    """Conditions forced through the inputs (kernels still exit normally)."""
+    srtm = _need_gpu()
+    m = wl.random_stable_model(2, 1, 4, 51)
+    y = wl.simulate(m, 300, 52)
+    y[100, 0] = np.nan
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", torch.float64)
+    yt = torch.as_tensor(y, device="cuda")
+    out = srtm.smooth(F, Q, H, R, m.L, m0, P0, yt, check=False)
+    torch.cuda.synchronize()
+    assert int(out["info"].item()) & 8
+    with pytest.raises(srtm.SrtmError):
+        srtm.smooth(F, Q, H, R, m.L, m0, P0, yt)
+    # zero measurement noise and a zero measurement matrix: innovation covariance is 0
+    Z = torch.zeros_like(R)
+    out = srtm.smooth(F, Q, torch.zeros_like(H), Z, m.L, m0, P0, torch.zeros_like(yt), check=False)
+    torch.cuda.synchronize()
+    assert int(out["info"].item()) & 1
+
+
+# ----------------------------------------------------------------------------- full size
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_headline_full_size(dtype):
+    """One long sequence: nx=4, ny=2, L=20, N=2^17, in the benchmark's launch configuration.
+
+    Exact checks: slow filter at every window (sequential IMKF over the whole sequence),
+    fast filter at sampled windows, smoother over the last 24 windows (dense smoother
+    started from the IMKF carry). Property check at sampled windows elsewhere: one step
+    of the sequential smoother (eq. seq-smoothing-all) from the GPU's smoothed state of
+    window k+1 reproduces the GPU's window k.
+    """
+    m = wl.headline_model()
+    N = wl.HEADLINE_N
+    y = wl.simulate(m, N, seed=2024)
+    out = run_gpu(m, y, dtype)
+    assert int(out["info"][0]) == 0
+    mr, yr = _rounded(m, y, dtype)
+    tol = TOL[dtype]
+    ms, Ps, _ = oracle.imkf(*_args(mr), yr)
+    assert_close_states(out["mf_slow"], out["Pf_slow"], ms, Ps, tol, "IMKF slow filter, all windows")
+    bm = oracle.batch_model(mr.A, mr.Q, mr.C, mr.L)
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([[0, 1, 255, 256, N // 2, N - 26], rng.integers(1, N - 25, 24)]))
+    nx, L = m.nx, m.L
+    Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), mr.A])
+    for k in sample:
+        mp, Pp = (mr.m0, mr.P0) if k == 0 else (ms[k - 1], Ps[k - 1])
+        M_f, P_f = oracle.fast_filter_window(bm, mr.R, mp, Pp, yr[k])
+        mf = M_f.reshape(L, nx)
+        Pf = np.stack([P_f[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] for i in range(L)])
+        assert_close_states(out["mf_fast"][k], out["Pf_fast"][k], mf, Pf, tol, f"fast filter window {k}")
+        # one smoother step from the GPU's smoothed block 1 of window k+1
+        m1 = out["ms_slow"][k + 1]
+        P1 = out["Ps_slow"][k + 1]
+        mpr = Ahat @ M_f
+        Ppr = Ahat @ P_f @ Ahat.T + mr.Q
+        G = np.linalg.solve(Ppr.T, (P_f @ Ahat.T).T).T
+        M_s = M_f + G @ (m1 - mpr)
+        P_s = P_f + G @ (P1 - Ppr) @ G.T
+        msk = M_s.reshape(L, nx)
+        Psk = np.stack([P_s[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] for i in range(L)])
+        assert_close_states(out["ms_fast"][k], out["Ps_fast"][k], msk, Psk, 10 * tol, f"smoother step window {k}")
+    n = 24
+    tail = oracle.srtm_smoother(mr.A, mr.Q, mr.C, mr.R, L, ms[N - n - 1], Ps[N - n - 1], yr[N - n:])
+    assert_close_states(out["ms_fast"][N - n:], out["Ps_fast"][N - n:], tail["ms_fast"], tail["Ps_fast"], tol,
+                        "smoother tail")
+    em, eP = rel_errors(out["ms_fast"][N - n:], out["Ps_fast"][N - n:], tail["ms_fast"], tail["Ps_fast"])
+    print(f"[gpu] headline {dtype}: tail max err mean {em.max():.2e} cov {eP.max():.2e}", flush=True)
