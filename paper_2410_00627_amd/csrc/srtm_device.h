@@ -180,6 +180,77 @@ SRTM_DEV bool solve_pp(T (&A)[N][N], T (&B)[N][M]) {
   return ok;
 }
 
+// 1/sqrt(s) for s > 0: hardware estimate refined by Newton steps y <- y (3 - s y^2) / 2
+// (two steps for double, one for float).
+SRTM_DEV double rsqrt_nr(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  const double h = 0.5 * s;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+SRTM_DEV float rsqrt_nr(float s) {
+  float y = __builtin_amdgcn_rsqf(s);
+  const float h = 0.5f * s;
+  y = y * fmaf(-h * y, y, 1.5f);
+  return y;
+}
+
+// Lower-triangular L with L L^T = A for a symmetric positive semi-definite A, and the
+// reciprocal diagonal idg. A pivot that is not positive gives a zero column (idg = 0).
+// Returns false if a pivot was dropped.
+template <typename T, int N>
+SRTM_DEV bool chol_lower(const T (&A)[N][N], T (&Lf)[N][N], T (&idg)[N]) {
+  bool pd = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T s = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = my_fma(-Lf[j][k], Lf[j][k], s);
+    const bool pos = s > T(0);
+    pd = pd && pos;
+    const T d = pos ? rsqrt_nr(s) : T(0);
+    idg[j] = d;
+    Lf[j][j] = s * d;
+#pragma unroll
+    for (int i = 0; i < j; ++i) Lf[i][j] = T(0);
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      T t = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = my_fma(-Lf[i][k], Lf[j][k], t);
+      Lf[i][j] = t * d;
+    }
+  }
+  return pd;
+}
+
+// X = B N^{-T} for lower-triangular N with reciprocal diagonal idg (row-wise forward substitution).
+template <typename T, int M, int N>
+SRTM_DEV void right_solve_lt(const T (&B)[M][N], const T (&Nf)[N][N], const T (&idg)[N], T (&X)[M][N]) {
+#pragma unroll
+  for (int r = 0; r < M; ++r)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T t = B[r][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = my_fma(-X[r][k], Nf[j][k], t);
+      X[r][j] = t * idg[j];
+    }
+}
+
+// x = N^{-1} b for lower-triangular N (forward substitution).
+template <typename T, int N>
+SRTM_DEV void left_solve_l(const T (&Nf)[N][N], const T (&idg)[N], const T (&b)[N], T (&x)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T t = b[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) t = my_fma(-Nf[j][k], x[k], t);
+    x[j] = t * idg[j];
+  }
+}
+
 // Inverse of a symmetric positive-definite matrix through its Cholesky factor.
 // Returns false when a diagonal pivot is not positive (the result is then garbage).
 template <typename T, int N>
@@ -193,8 +264,7 @@ SRTM_DEV bool chol_inv(const T (&A)[N][N], T (&Ai)[N][N]) {
 #pragma unroll
     for (int k = 0; k < j; ++k) s = my_fma(-Lf[j][k], Lf[j][k], s);
     ok = ok && (s > T(0));
-    const T d = sqrt(s);
-    id[j] = T(1) / d;
+    id[j] = rsqrt_nr(s);
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       T t = A[i][j];

@@ -171,26 +171,32 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
     cst[lay.Q + e] = (T)sQ[e];
   }
 
-  if (tid != 0) return;
-  // ---------------------------------------------------------------- one lane
-  double Cd[NY][NX], Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NX; ++c) Cd[r][c] = sC[r * NX + c];
-  // C_bar = (C/l)(Sig_l - I)
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NX; ++c) {
+  // C_bar = (C/l)(Sig_l - I) and R_x = (1/l) sum_i C c_i + R, into LDS (W2 is free again)
+  __syncthreads();
+  double* sCbar = W2;
+  double* sRx = W2 + NXY;
+  for (int e = tid; e < NXY + NY * NY; e += nthr) {
+    if (e < NXY) {
+      const int r = e / NX, c = e % NX;
       double acc = 0.0;
-      for (int k = 0; k < NX; ++k) acc += Cd[r][k] * (W1[L * NN + k * NX + c] - (k == c ? 1.0 : 0.0));
-      Cbar[r][c] = acc / (double)L;
-    }
-  // R_x = (1/l) sum_i C c_i + R
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NY; ++c) {
+      for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * (W1[L * NN + k * NX + c] - (k == c ? 1.0 : 0.0));
+      sCbar[e] = acc / (double)L;
+    } else {
+      const int q = e - NXY, r = q / NY, c = q % NY;
       double acc = 0.0;
       for (int i = 1; i <= L; ++i)
-        for (int k = 0; k < NX; ++k) acc += Cd[r][k] * ci[i * NXY + k * NY + c];
-      Rx[r][c] = acc / (double)L + sR[r * NY + c];
+        for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * ci[i * NXY + k * NY + c];
+      sRx[q] = acc / (double)L + sR[r * NY + c];
     }
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  // ---------------------------------------------------------------- one lane
+  double Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NX; ++c) Cbar[r][c] = sCbar[r * NX + c];
+  for (int r = 0; r < NY; ++r)
+    for (int c = 0; c < NY; ++c) Rx[r][c] = sRx[r * NY + c];
   symmetrize(Rx);
   for (int r = 0; r < NX; ++r)
     for (int c = 0; c < NY; ++c) Sxy[r][c] = ci[L * NXY + r * NY + c];
@@ -222,36 +228,54 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
       cst[lay.K + r * NY + c] = (T)K[r][c];
       cst[lay.Heta + r * NY + c] = (T)Heta[r][c];
     }
-  // Levels: Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, and the
-  // coefficients that combine the vector parts of two runs of 2^p elements:
+  // Levels: Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, with
+  // W = (I + D J)^{-1} evaluated through J = Z Z^T and M = I + Z^T D Z = N N^T:
+  //   W = I - B C^T,  B = D Z N^{-T},  C = Z N^{-T},  W D = D - B B^T.
+  // Coefficients that combine the vector parts of two runs of 2^p elements:
   //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
-  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J,  W = (I + D J)^{-1}.
+  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J.
+  int lflag = 0;
   for (int p = 0; p < NLEV; ++p) {
     T* dst = cst + lay.lev + p * lay.lev_stride;
-    double M[NX][NX], X[NX][2 * NX];
-    mm(D, J, M);
-    for (int r = 0; r < NX; ++r) {
-      M[r][r] += 1.0;
-      for (int c = 0; c < NX; ++c) {
-        X[r][c] = F[r][c];
-        X[r][NX + c] = (r == c) ? 1.0 : 0.0;
-      }
-    }
-    if (!solve_pp(M, X) && info) atomicOr(info, SRTM_INFO_COMBINE_SINGULAR);
-    double WF[NX][NX], Wm[NX][NX], G1[NX][NX], G2[NX][NX], G4[NX][NX];
+    double Z[NX][NX], zi[NX];
+    chol_lower(J, Z, zi);
+    double DZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX];
+    mm(D, Z, DZ);
     for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) {
-        WF[r][c] = X[r][c];
-        Wm[r][c] = X[r][NX + c];
+      for (int c = r; c < NX; ++c) {
+        double acc = (r == c) ? 1.0 : 0.0;
+        for (int k = 0; k < NX; ++k) acc += Z[k][r] * DZ[k][c];
+        M[r][c] = acc;
+        M[c][r] = acc;
       }
-    mm(F, Wm, G1);
-    mm(G1, D, G2);
-    mm_tn(WF, J, G4);  // G4 = (W F)^T J ; G3 = (W F)^T
+    if (!chol_lower(M, Nf, ni)) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+    double B[NX][NX], Cm[NX][NX];
+    right_solve_lt(DZ, Nf, ni, B);
+    right_solve_lt(Z, Nf, ni, Cm);
+    double CtF[NX][NX], WF[NX][NX], FB[NX][NX], G1[NX][NX], XD[NX][NX], G2[NX][NX], G4[NX][NX];
+    mm_tn(Cm, F, CtF);
+    mm(B, CtF, WF);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) WF[r][c] = F[r][c] - WF[r][c];   // W F
+    mm(F, B, FB);
+    mm_nt(FB, Cm, G1);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) G1[r][c] = F[r][c] - G1[r][c];   // F W
+    for (int r = 0; r < NX; ++r)
+      for (int c = r; c < NX; ++c) {
+        double acc = D[r][c];
+        for (int k = 0; k < NX; ++k) acc -= B[r][k] * B[c][k];
+        XD[r][c] = acc;
+        XD[c][r] = acc;                                              // W D
+      }
+    mm(F, XD, G2);
+    mm_tn(WF, J, G4);
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) {
         dst[lay.o_F + r * NX + c] = (T)F[r][c];
         dst[lay.o_D + r * NX + c] = (T)D[r][c];
         dst[lay.o_J + r * NX + c] = (T)J[r][c];
+        dst[lay.o_Z + r * NX + c] = (T)Z[r][c];
         dst[lay.o_G1 + r * NX + c] = (T)G1[r][c];
         dst[lay.o_G2 + r * NX + c] = (T)G2[r][c];
         dst[lay.o_G3 + r * NX + c] = (T)WF[c][r];
@@ -270,6 +294,7 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
     symmetrize(D);
     symmetrize(J);
   }
+  if (lflag && info) atomicOr(info, lflag);
 }
 
 // ============================================================================ helpers
@@ -285,45 +310,79 @@ template <typename T, int N>
 SRTM_DEV T symget(const T (&P)[N][N], int r, int c) { return r <= c ? P[r][c] : P[c][r]; }
 
 // state (m, P) (x) segment (F, d, D, eta, J): the eq. op-filter combination whose left
-// operand holds the prior (F = 0):  W = (I + P J)^{-1},
-//   m' = F W (m + P eta) + d,   P' = F W P F^T + D.
+// operand holds the prior (F = 0). With J = Z Z^T, M = I + Z^T P Z = N N^T (positive
+// definite, pivots >= 1) and B = P Z N^{-T}, Woodbury gives
+//   (I + P J)^{-1} = I - P Z M^{-1} Z^T,  (I + P J)^{-1} P = P - B B^T,
+//   m' = F [u - B N^{-1} Z^T u] + d  (u = m + P eta),   P' = F (P - B B^T) F^T + D.
 template <typename T, int NX>
-SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
-                            const T (&D)[NX][NX], const T (&eta)[NX], const T (&J)[NX][NX]) {
-  T M[NX][NX], X[NX][NX + 1];
-  mm(P, J, M);
+SRTM_DEV bool state_combine_z(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
+                              const T (&D)[NX][NX], const T (&eta)[NX], const T (&Z)[NX][NX]) {
+  T PZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX], B[NX][NX];
+  mm(P, Z, PZ);
 #pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    M[r][r] += T(1);
-    T u = m[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) u = my_fma(P[r][k], eta[k], u);
-    X[r][NX] = u;
-#pragma unroll
-    for (int c = 0; c < NX; ++c) X[r][c] = P[r][c];
-  }
-  const bool ok = solve_pp(M, X);
-  T FX[NX][NX + 1];
-  mm(F, X, FX);
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    m[r] = FX[r][NX] + d[r];
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T s = D[r][c];
+      T acc = (r == c) ? T(1) : T(0);
 #pragma unroll
-      for (int k = 0; k < NX; ++k) s = my_fma(FX[r][k], F[c][k], s);
-      P[r][c] = s;
-      P[c][r] = s;
+      for (int k = 0; k < NX; ++k) acc = my_fma(Z[k][r], PZ[k][c], acc);
+      M[r][c] = acc;
+      M[c][r] = acc;
     }
+  const bool ok = chol_lower(M, Nf, ni);
+  right_solve_lt(PZ, Nf, ni, B);
+  T u[NX], zu[NX], z[NX], v[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = m[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(P[r][k], eta[k], t);
+    u[r] = t;
   }
+  mtv(Z, u, zu);
+  left_solve_l(Nf, ni, zu, z);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = u[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], z[k], t);
+    v[r] = t;
+  }
+  T WP[NX][NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T t = P[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], B[c][k], t);
+      WP[r][c] = t;
+      WP[c][r] = t;
+    }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = d[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(F[r][k], v[k], t);
+    m[r] = t;
+  }
+  sandwich(F, WP, D, P);
   return ok;
 }
 
-// Full filter element and a_i (x) a_j of eq. op-filter, with one elimination:
-//   X = (I + D_i J_j)^{-1} [F_i | d_i + D_i eta_j | D_i],  (I + J_j D_i)^{-1} = W^T,
-//   F = F_j X_F, d = F_j X_u + d_j, D = F_j X_D F_j^T + D_j,
-//   eta = X_F^T (eta_j - J_j d_i) + eta_i, J = X_F^T J_j F_i + J_i.
+template <typename T, int NX>
+SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
+                            const T (&D)[NX][NX], const T (&eta)[NX], const T (&J)[NX][NX]) {
+  T Z[NX][NX], zi[NX];
+  chol_lower(J, Z, zi);
+  return state_combine_z(m, P, F, d, D, eta, Z);
+}
+
+// Full filter element and a_i (x) a_j of eq. op-filter. With J_j = Z Z^T,
+// M = I + Z^T D_i Z = N N^T, B = D_i Z N^{-T} and C = Z N^{-T}:
+//   W = (I + D_i J_j)^{-1} = I - B C^T,  W D_i = D_i - B B^T,  (I + J_j D_i)^{-1} = W^T,
+//   F = F_j W F_i, d = F_j W (d_i + D_i eta_j) + d_j, D = F_j W D_i F_j^T + D_j,
+//   eta = (W F_i)^T (eta_j - J_j d_i) + eta_i,  J = (W F_i)^T J_j F_i + J_i.
 template <typename T, int NX>
 struct FElem {
   T F[NX][NX], d[NX], D[NX][NX], e[NX], J[NX][NX];
@@ -331,53 +390,85 @@ struct FElem {
 
 template <typename T, int NX>
 SRTM_DEV bool elem_combine(const FElem<T, NX>& a, const FElem<T, NX>& b, FElem<T, NX>& o) {
-  T M[NX][NX], X[NX][2 * NX + 1];
-  mm(a.D, b.J, M);
+  T Z[NX][NX], zi[NX], DZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX], B[NX][NX], C[NX][NX];
+  chol_lower(b.J, Z, zi);
+  mm(a.D, Z, DZ);
 #pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    M[r][r] += T(1);
-    T u = a.d[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) u = my_fma(a.D[r][k], b.e[k], u);
-    X[r][NX] = u;
-#pragma unroll
-    for (int c = 0; c < NX; ++c) {
-      X[r][c] = a.F[r][c];
-      X[r][NX + 1 + c] = a.D[r][c];
-    }
-  }
-  const bool ok = solve_pp(M, X);
-  T FX[NX][2 * NX + 1];
-  mm(b.F, X, FX);
-  T v[NX], JF[NX][NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    T s = b.e[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) s = my_fma(-b.J[r][k], a.d[k], s);
-    v[r] = s;
-  }
-  mm(b.J, a.F, JF);
-  FElem<T, NX> t;
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    t.d[r] = FX[r][NX] + b.d[r];
-    T s = a.e[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) s = my_fma(X[k][r], v[k], s);
-    t.e[r] = s;
-#pragma unroll
-    for (int c = 0; c < NX; ++c) t.F[r][c] = FX[r][c];
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T sd = b.D[r][c];
+      T acc = (r == c) ? T(1) : T(0);
 #pragma unroll
-      for (int k = 0; k < NX; ++k) sd = my_fma(FX[r][NX + 1 + k], b.F[c][k], sd);
-      t.D[r][c] = sd;
-      t.D[c][r] = sd;
+      for (int k = 0; k < NX; ++k) acc = my_fma(Z[k][r], DZ[k][c], acc);
+      M[r][c] = acc;
+      M[c][r] = acc;
+    }
+  const bool ok = chol_lower(M, Nf, ni);
+  right_solve_lt(DZ, Nf, ni, B);
+  right_solve_lt(Z, Nf, ni, C);
+  // X_F = W F_i, X_u = W (d_i + D_i eta_j), X_D = W D_i
+  T CtF[NX][NX], XF[NX][NX], u[NX], Ctu[NX], Xu[NX], XD[NX][NX];
+  mm_tn(C, a.F, CtF);
+  mm(B, CtF, XF);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) XF[r][c] = a.F[r][c] - XF[r][c];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = a.d[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(a.D[r][k], b.e[k], t);
+    u[r] = t;
+  }
+  mtv(C, u, Ctu);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = u[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], Ctu[k], t);
+    Xu[r] = t;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T t = a.D[r][c];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], B[c][k], t);
+      XD[r][c] = t;
+      XD[c][r] = t;
+    }
+  FElem<T, NX> t;
+  mm(b.F, XF, t.F);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T q = b.d[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) q = my_fma(b.F[r][k], Xu[k], q);
+    t.d[r] = q;
+  }
+  sandwich(b.F, XD, b.D, t.D);
+  T vv[NX], JF[NX][NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T q = b.e[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) q = my_fma(-b.J[r][k], a.d[k], q);
+    vv[r] = q;
+  }
+  mm(b.J, a.F, JF);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T q = a.e[r];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) q = my_fma(XF[k][r], vv[k], q);
+    t.e[r] = q;
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
       T sj = a.J[r][c];
 #pragma unroll
-      for (int k = 0; k < NX; ++k) sj = my_fma(X[k][r], JF[k][c], sj);
+      for (int k = 0; k < NX; ++k) sj = my_fma(XF[k][r], JF[k][c], sj);
       t.J[r][c] = sj;
       t.J[c][r] = sj;
     }
@@ -873,6 +964,8 @@ k_fwd_tiles(const T* __restrict__ tagg, int64_t nt, const T* __restrict__ cst, i
   load(base.F, lv + M.lay.o_F);
   load(base.D, lv + M.lay.o_D);
   load(base.J, lv + M.lay.o_J);
+  T baseZ[NX][NX];
+  load(baseZ, lv + M.lay.o_Z);
   FElem<T, NX> acc;
   elem_identity(acc);
 #pragma unroll 1
@@ -935,43 +1028,121 @@ k_fwd_tiles(const T* __restrict__ tagg, int64_t nt, const T* __restrict__ cst, i
       T d[NX], e[NX];
       loadv(d, tagg + t * 2 * NX);
       loadv(e, tagg + t * 2 * NX + NX);
-      if (!state_combine(m, P, base.F, d, base.D, e, base.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      if (!state_combine_z(m, P, base.F, d, base.D, e, baseZ)) flag |= SRTM_INFO_COMBINE_SINGULAR;
     }
   }
   if (flag && info) atomicOr(info, flag);
 }
 
-// Output staging: per wave, one record of (mean, covariance) per lane, then stores in
-// which consecutive lanes write consecutive addresses.
-template <typename T, int NX>
-struct Stage {
-  static constexpr int NN = NX * NX;
-  static constexpr int STR = NX + NN + 1;  // odd stride against LDS bank conflicts
-  T* buf;                                  // 64 * STR per wave
-  SRTM_DEV void put(int lane, const T (&m)[NX], const T (&P)[NX][NX]) const {
+// Output staging. Each lane computes one window's blocks; records are written to LDS
+// and copied out by the whole wave so that consecutive lanes store consecutive 16-byte
+// chunks. Covariance records (nx^2 scalars) are flushed every fast step; means are
+// gathered over G consecutive fast steps so that a record fills whole cache lines.
+template <int CH> struct Chunk;
+template <> struct Chunk<16> { using type = uint4; };
+template <> struct Chunk<8> { using type = uint2; };
+template <> struct Chunk<4> { using type = unsigned int; };
+
+// Copies records w = 0..nvalid-1 of RB bytes (stride SB bytes in LDS) to dst + w * gstride
+// bytes in chunks of CH bytes. When a record holds a power-of-two number of chunks, lane l
+// always moves chunk (l mod PER) of windows l / PER + r * 64 / PER: every store address is
+// a wave-uniform base plus one loop-invariant 32-bit lane offset.
+template <int RB, int SB>
+SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, char* __restrict__ dst,
+                            int64_t gstride) {
+  constexpr int CH = (RB % 16 == 0 && SB % 16 == 0) ? 16 : ((RB % 8 == 0 && SB % 8 == 0) ? 8 : 4);
+  constexpr int PER = RB / CH;
+  using V = typename Chunk<CH>::type;
+  if (((reinterpret_cast<uintptr_t>(dst) | (uintptr_t)gstride) % CH) != 0 || (64 % PER) != 0) {
+    for (int c = lane; c < nvalid * (RB / 4); c += 64) {  // generic: 4-byte words
+      const int w = c / (RB / 4), e = c - w * (RB / 4);
+      reinterpret_cast<unsigned int*>(dst + w * gstride)[e] = reinterpret_cast<const unsigned int*>(lds + w * SB)[e];
+    }
+    return;
+  }
+  constexpr int WPI = (64 % PER == 0) ? 64 / PER : 1;  // windows per store instruction
+  const int wl = lane / PER, pl = lane - wl * PER;
+  const unsigned int lo = (unsigned int)(wl * gstride) + (unsigned int)(pl * CH);
+  const char* lsrc = lds + wl * SB + pl * CH;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) buf[lane * STR + r] = m[r];
+  for (int r = 0; r < PER; ++r) {
+    const V v = *reinterpret_cast<const V*>(lsrc + r * WPI * SB);
+    char* ub = dst + (int64_t)r * WPI * gstride;
+    if (wl + r * WPI < nvalid) *reinterpret_cast<V*>(ub + lo) = v;
+  }
+}
+
+// Element-wise variant for a run-time record length (the last, partial group of means).
+template <typename T>
+SRTM_DEV void flush_records_rt(int lane, int nvalid, const char* __restrict__ lds, int SB, T* __restrict__ dst,
+                               int64_t gstride_elems, int nel) {
+  for (int c = lane; c < nvalid * nel; c += 64) {
+    const int w = c / nel, e = c - w * nel;
+    dst[w * gstride_elems + e] = reinterpret_cast<const T*>(lds + w * SB)[e];
+  }
+}
+
+// Stores one lane's record of N scalars at dst (16-byte chunks when N * sizeof(T) allows).
+template <typename T, int N>
+SRTM_DEV void store_record(T* __restrict__ dst, const T* vals) {
+  if constexpr ((N * sizeof(T)) % 16 == 0) {
+    constexpr int PER = N * sizeof(T) / 16, E = 16 / sizeof(T);
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      uint4 u;
+      __builtin_memcpy(&u, vals + r * E, 16);
+      reinterpret_cast<uint4*>(dst)[r] = u;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < N; ++r) dst[r] = vals[r];
+  }
+}
+
+template <typename T, int NX, int G>
+struct OutStage {
+  static constexpr int NN = NX * NX;
+  static constexpr int SBP = ((NN * (int)sizeof(T) + 15) / 16) * 16 + 16;      // bytes per P record
+  static constexpr int SBM = ((G * NX * (int)sizeof(T) + 15) / 16) * 16 + 16;  // bytes per m record
+  static constexpr int BYTES = 64 * (SBP + SBM);                                // per wave
+  char* pbuf;
+  char* mbuf;
+  SRTM_DEV OutStage(char* base) : pbuf(base), mbuf(base + 64 * SBP) {}
+  SRTM_DEV void put(int lane, int slot, const T (&m)[NX], const T (&P)[NX][NX]) const {
+    T* pp = reinterpret_cast<T*>(pbuf + lane * SBP);
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) buf[lane * STR + NX + r * NX + c] = P[r][c];
+      for (int c = 0; c < NX; ++c) pp[r * NX + c] = P[r][c];
+    T* mp = reinterpret_cast<T*>(mbuf + lane * SBM) + slot * NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) mp[r] = m[r];
   }
-  // Writes records of lanes 0..nvalid-1: mean of window (w0 + w) at m_out + (w0 + w) * mstride,
-  // covariance at P_out + (w0 + w) * Pstride (element strides).
-  SRTM_DEV void flush(int lane, int nvalid, T* __restrict__ m_out, T* __restrict__ P_out, int64_t w0,
-                      int64_t mstride, int64_t Pstride) const {
-    if (m_out) {
-      for (int j = lane; j < nvalid * NX; j += 64) {
-        const int w = j / NX, c = j - w * NX;
-        m_out[(w0 + w) * mstride + c] = buf[w * STR + c];
-      }
-    }
-    if (P_out) {
-      for (int j = lane; j < nvalid * NN; j += 64) {
-        const int w = j / NN, c = j - w * NN;
-        P_out[(w0 + w) * Pstride + c] = buf[w * STR + NX + c];
-      }
-    }
+  // covariance of fast step i (1-based) for windows w0 + w: P_out[((w0 + w) L + i - 1) nx^2]
+  SRTM_DEV void flush_P(int lane, int nvalid, T* P_out, int64_t w0, int L, int i) const {
+    if (!P_out) return;
+    T* dst = P_out + (w0 * L + (i - 1)) * NN;
+    flush_records<NN * (int)sizeof(T), SBP>(lane, nvalid, pbuf, reinterpret_cast<char*>(dst),
+                                            (int64_t)L * NN * sizeof(T));
+  }
+  // means of fast steps i0 .. i0+g-1 (1-based) held in slots 0 .. g-1
+  SRTM_DEV void flush_m(int lane, int nvalid, T* m_out, int64_t w0, int L, int i0, int g) const {
+    if (!m_out) return;
+    T* dst = m_out + (w0 * L + (i0 - 1)) * NX;
+    if (g == G)
+      flush_records<G * NX * (int)sizeof(T), SBM>(lane, nvalid, mbuf, reinterpret_cast<char*>(dst),
+                                                  (int64_t)L * NX * sizeof(T));
+    else
+      flush_records_rt<T>(lane, nvalid, mbuf, SBM, dst, (int64_t)L * NX, g * NX);
+  }
+  // slow-rate output from slot 0 and the current covariance record (contiguous windows)
+  SRTM_DEV void flush_slow(int lane, int nvalid, T* m_out, T* P_out, int64_t w0) const {
+    if (m_out)
+      flush_records<NX * (int)sizeof(T), SBM>(lane, nvalid, mbuf, reinterpret_cast<char*>(m_out + w0 * NX),
+                                              (int64_t)NX * sizeof(T));
+    if (P_out)
+      flush_records<NN * (int)sizeof(T), SBP>(lane, nvalid, pbuf, reinterpret_cast<char*>(P_out + w0 * NN),
+                                              (int64_t)NN * sizeof(T));
   }
 };
 
@@ -988,13 +1159,12 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
 }
 
 // K3: per tile, down-sweep from the tile's exclusive state to every window, giving the
-// slow-rate carry (m^f_{k,l}, P^f_{k,l}); optionally the fast-rate filter outputs.
+// slow-rate carry (m^f_{k,l}, P^f_{k,l}) and, when requested, the slow-rate filter outputs.
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(TILE)
 k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
             const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
-            T* __restrict__ carry, T* __restrict__ m_fast, T* __restrict__ P_fast,
-            T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
+            T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
   constexpr int NN = NX * NX, ST = NX + NN;
   extern __shared__ char smraw[];
   T* smem = reinterpret_cast<T*>(smraw);
@@ -1037,11 +1207,11 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
     if (act) {
       st_state<T, NX>(S, tid - s, m, P);
       const T* lv = M.level(p);
-      T F[NX][NX], D[NX][NX], J[NX][NX];
+      T F[NX][NX], D[NX][NX], Z[NX][NX];
       load(F, lv + M.lay.o_F);
       load(D, lv + M.lay.o_D);
-      load(J, lv + M.lay.o_J);
-      if (!state_combine(m, P, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      load(Z, lv + M.lay.o_Z);
+      if (!state_combine_z(m, P, F, dl, D, el, Z)) flag |= SRTM_INFO_COMBINE_SINGULAR;
       st_state<T, NX>(S, tid, m, P);
     }
     __syncthreads();
@@ -1062,11 +1232,11 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
   }
   {
     const T* lv = M.level(0);
-    T F[NX][NX], D[NX][NX], J[NX][NX];
+    T F[NX][NX], D[NX][NX], Z[NX][NX];
     load(F, lv + M.lay.o_F);
     load(D, lv + M.lay.o_D);
-    load(J, lv + M.lay.o_J);
-    if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    load(Z, lv + M.lay.o_Z);
+    if (!state_combine_z(m, P, F, d, D, e, Z)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
   if (k < N) {
 #pragma unroll
@@ -1084,31 +1254,6 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
       for (int r = 0; r < NN; ++r) P_slow[k * NN + r] = P[r / NX][r % NX];
     }
     if (!finite_state(m, P)) flag |= SRTM_INFO_NONFINITE;
-  }
-  if (m_fast || P_fast) {
-    __syncthreads();  // LDS becomes the output stage
-    const int lane = tid & 63, wv = tid >> 6;
-    const Stage<T, NX> stg{smem + wv * 64 * Stage<T, NX>::STR};
-    const int64_t w0 = (int64_t)blockIdx.x * TILE + wv * 64;
-    const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
-    Window<T, NX, NY> w;
-    T yk[NY];
-#pragma unroll
-    for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? y[k * NY + r] : T(0);
-    if (!window_setup(M, L, mprev, Pprev, yk, w) && k < N) flag |= SRTM_INFO_INNOVATION_NOT_PD;
-    bool fin = true;
-#pragma unroll 1
-    for (int i = 1; i <= L; ++i) {
-      T mf[NX], Pii[NX][NX], PiL[NX][NX];
-      window_step<T, NX, NY, false>(M, w, i, mf, Pii, PiL);
-      fin = fin && finite_state(mf, Pii);
-      stg.put(lane, mf, Pii);
-      wave_sync();
-      stg.flush(lane, nvalid, m_fast ? m_fast + (int64_t)(i - 1) * NX : nullptr,
-                P_fast ? P_fast + (int64_t)(i - 1) * NN : nullptr, w0, (int64_t)L * NX, (int64_t)L * NN);
-      wave_sync();
-    }
-    if (!fin && k < N) flag |= SRTM_INFO_NONFINITE;
   }
   if (flag && info) atomicOr(info, flag);
 }
@@ -1294,17 +1439,17 @@ k_bwd_tiles(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
   }
 }
 
-// K6: per tile, down-sweep of smoothed states, then the fast-rate smoothed recovery of
-// eq. seq-smoothing-all, blockwise: with v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}) and
-// W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A,
-//   m^s_{k,i} = m^f_{k,i} + P^f_{k,i,l} v,   P^s_{k,i} = P^f_{k,i,i} + P^f_{k,i,l} W P^f_{k,i,l}^T.
+// K6: per tile, down-sweep of smoothed states. For every window k < N it writes the
+// correction that turns its filter blocks into smoothed ones (eq. seq-smoothing-all):
+//   v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}),  W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A,
+// so that m^s_{k,i} = m^f_{k,i} + P^f_{k,i,l} v and P^s_{k,i} = P^f_{k,i,i} + P^f_{k,i,l} W P^f_{k,i,l}^T;
+// (v, W) = 0 for the last window, whose smoothed blocks equal the filtered ones.
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(TILE)
-k_bwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
-            const T* __restrict__ P0, const T* __restrict__ carry, const T* __restrict__ tstate,
-            T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow, T* __restrict__ Ps_slow,
-            int32_t* info) {
-  constexpr int NN = NX * NX, ST = NX + NN;
+k_bwd_scan(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
+           const T* __restrict__ P0, const T* __restrict__ carry, const T* __restrict__ tstate,
+           T* __restrict__ vw, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN, VWS = vw_stride(NX);
   extern __shared__ char smraw[];
   T* smem = reinterpret_cast<T*>(smraw);
   const Slots<T> S{smem, TILE};
@@ -1345,8 +1490,6 @@ k_bwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
   // exclusive suffix state of window k = smoothed state of window k+1, block 1
   T msn[NX], Psn[NX][NX];
   ld_state<T, NX>(S, TILE - 1 - tid, msn, Psn);
-  __syncthreads();  // LDS becomes the output stage
-  // v and W (zero for the last window, whose smoothed blocks equal the filtered ones)
   T v[NX], W[NX][NX];
   if (k < N - 1) {
     T A[NX][NX], PL[NX][NX], Qm[NX][NX];
@@ -1385,48 +1528,136 @@ k_bwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
       for (int c = 0; c < NX; ++c) W[r][c] = T(0);
     }
   }
-  const int lane = tid & 63, wv = tid >> 6;
-  const Stage<T, NX> stg{smem + wv * 64 * Stage<T, NX>::STR};
-  const int64_t w0 = (int64_t)blockIdx.x * TILE + wv * 64;
+  if (k < N) {
+    T* dst = vw + k * VWS;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) dst[r] = v[r];
+    int o = NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) dst[o++] = W[r][c];
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+// K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
+// MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
+// from the (v, W) of K6 (and the smoother's slow state, block i = 1). `ilim` is L when
+// fast-rate outputs are requested and 1 when only the slow smoothed state is.
+constexpr int REC_G = 4;  // fast steps whose means are gathered into one record
+#ifndef SRTM_REC_DIRECT
+#define SRTM_REC_DIRECT 0
+#endif
+constexpr bool REC_DIRECT = SRTM_REC_DIRECT != 0;  // smoothed records stored by their own lane
+
+template <typename T, int NX, int NY, int MODE>
+__global__ void __launch_bounds__(256)
+k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
+          const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+          const T* __restrict__ vw, T* __restrict__ mf_fast, T* __restrict__ Pf_fast,
+          T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow,
+          T* __restrict__ Ps_slow, int32_t* info) {
+  constexpr int NN = NX * NX, VWS = vw_stride(NX);
+  constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
+  using Stg = OutStage<T, NX, REC_G>;
+  extern __shared__ char smraw[];
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t w0 = (int64_t)blockIdx.x * 256 + wv * 64;
   const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
-  bool fin = true;
-#pragma unroll 1
-  for (int i = 1; i <= L; ++i) {
-    T mf[NX], Pii[NX][NX], PiL[NX][NX];
-    window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
-    T ms[NX], Ps[NX][NX];
+  const Stg fst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
+  const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
+  const bool valid = k < N;
+  const int64_t kc = valid ? k : 0;   // clamped index for loads of padding lanes
+  T m[NX], P[NX][NX], yk[NY];
+  load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
+  loadv(yk, y + kc * NY);
+  Window<T, NX, NY> w;
+  int flag = 0;
+  if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  T v[NX], W[NX][NX];
+  if (SMOOTH) {
+    const T* src = vw + kc * VWS;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      T s = mf[r];
+    for (int r = 0; r < NX; ++r) v[r] = src[r];
+    int o = NX;
 #pragma unroll
-      for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
-      ms[r] = s;
-      T TW[NX];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        T t = T(0);
-#pragma unroll
-        for (int q = 0; q < NX; ++q) t = my_fma(PiL[r][q], symget(W, q, c), t);
-        TW[c] = t;
-      }
+    for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = r; c < NX; ++c) {
-        T t = Pii[r][c];
+        W[r][c] = src[o++];
+        W[c][r] = W[r][c];
+      }
+  }
+  bool fin = true;
+#pragma unroll 1
+  for (int i = 1; i <= ilim; ++i) {
+    const int slot = (i - 1) % REC_G;
+    T mf[NX], Pii[NX][NX], PiL[NX][NX];
+    window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
+    if (FILT) {
+      fin = fin && finite_state(mf, Pii);
+      fst.put(lane, slot, mf, Pii);
+    }
+    if (SMOOTH) {
+      T ms[NX], Ps[NX][NX];
 #pragma unroll
-        for (int q = 0; q < NX; ++q) t = my_fma(TW[q], PiL[c][q], t);
-        Ps[r][c] = t;
-        Ps[c][r] = t;
+      for (int r = 0; r < NX; ++r) {
+        T s = mf[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
+        ms[r] = s;
+        T TW[NX];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T t = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(PiL[r][q], symget(W, q, c), t);
+          TW[c] = t;
+        }
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = Pii[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(TW[q], PiL[c][q], t);
+          Ps[r][c] = t;
+          Ps[c][r] = t;
+        }
+      }
+      fin = fin && finite_state(ms, Ps);
+      if (REC_DIRECT) {
+        if (valid) {
+          T pv[NN];
+#pragma unroll
+          for (int r = 0; r < NX; ++r)
+#pragma unroll
+            for (int c = 0; c < NX; ++c) pv[r * NX + c] = Ps[r][c];
+          if (Ps_fast) store_record<T, NN>(Ps_fast + (k * L + i - 1) * NN, pv);
+          if (ms_fast) store_record<T, NX>(ms_fast + (k * L + i - 1) * NX, ms);
+          if (i == 1 && Ps_slow) store_record<T, NN>(Ps_slow + k * NN, pv);
+          if (i == 1 && ms_slow) store_record<T, NX>(ms_slow + k * NX, ms);
+        }
+      } else {
+        sst.put(lane, slot, ms, Ps);
       }
     }
-    fin = fin && finite_state(ms, Ps);
-    stg.put(lane, ms, Ps);
+    if (REC_DIRECT && !FILT) continue;
     wave_sync();
-    stg.flush(lane, nvalid, ms_fast ? ms_fast + (int64_t)(i - 1) * NX : nullptr,
-              Ps_fast ? Ps_fast + (int64_t)(i - 1) * NN : nullptr, w0, (int64_t)L * NX, (int64_t)L * NN);
-    if (i == 1) stg.flush(lane, nvalid, ms_slow, Ps_slow, w0, NX, NN);
+    const bool group_end = (slot == REC_G - 1) || (i == ilim);
+    if (FILT) {
+      fst.flush_P(lane, nvalid, Pf_fast, w0, L, i);
+      if (group_end) fst.flush_m(lane, nvalid, mf_fast, w0, L, i - slot, slot + 1);
+    }
+    if (SMOOTH && !REC_DIRECT) {
+      sst.flush_P(lane, nvalid, Ps_fast, w0, L, i);
+      if (i == 1) sst.flush_slow(lane, nvalid, ms_slow, Ps_slow, w0);
+      if (group_end) sst.flush_m(lane, nvalid, ms_fast, w0, L, i - slot, slot + 1);
+    }
     wave_sync();
   }
-  if (!fin && k < N) flag |= SRTM_INFO_NONFINITE;
+  if (!fin && valid) flag |= SRTM_INFO_NONFINITE;
   if (flag && info) atomicOr(info, flag);
 }
 
@@ -1472,6 +1703,21 @@ size_t constants_lds_bytes(int nx, int ny, int L) {
     if ((call) != hipSuccess) return SRTM_E_HIP; \
   } while (0)
 
+template <typename T, int NX, int NY, int MODE>
+srtm_status launch_recover(const Ptrs& p, const T* y, int64_t N, int L, int ilim, const T* cst, const T* m0,
+                           const T* P0, const T* carry, const T* vw, hipStream_t st) {
+  const size_t lds = (size_t)4 * OutStage<T, NX, REC_G>::BYTES * ((MODE == 3) ? 2 : 1);
+  if (lds > 65536)
+    hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const unsigned grid = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL((k_recover<T, NX, NY, MODE>), dim3(grid), dim3(256), lds, st, y, N, L, ilim, cst, m0, P0,
+                     carry, vw, static_cast<T*>(p.mf_fast), static_cast<T*>(p.Pf_fast),
+                     static_cast<T*>(p.ms_fast), static_cast<T*>(p.Ps_fast), static_cast<T*>(p.ms_slow),
+                     static_cast<T*>(p.Ps_slow), p.info);
+  SRTM_CHECK_LAUNCH();
+  return SRTM_OK;
+}
+
 template <typename T, int NX, int NY>
 srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, Events ev) {
   constexpr int NN = NX * NX;
@@ -1487,12 +1733,12 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   const T* y = static_cast<const T*>(p.y);
   const T* m0 = static_cast<const T*>(p.m0);
   const T* P0 = static_cast<const T*>(p.P0);
-
-  const size_t lds0 = constants_lds_bytes(NX, NY, L);
   // Dynamic LDS above 64 KiB must be allowed per kernel before launching.
   auto allow = [](const void* f, size_t bytes) {
     if (bytes > 65536) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   };
+
+  const size_t lds0 = constants_lds_bytes(NX, NY, L);
   allow((const void*)k_constants<T, NX, NY>, lds0);
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(1), dim3(256), lds0, st, static_cast<const T*>(p.F),
@@ -1514,23 +1760,32 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  T* mf_fast = static_cast<T*>(p.mf_fast);
-  T* Pf_fast = static_cast<T*>(p.Pf_fast);
   T* mf_slow = static_cast<T*>(p.mf_slow);
   T* Pf_slow = static_cast<T*>(p.Pf_slow);
-  const size_t fslot = (2 * NX > NX + NN) ? 2 * NX : NX + NN;
-  const size_t fstage = (size_t)4 * 64 * Stage<T, NX>::STR;
-  const size_t lds_ff = sizeof(T) * (fslot * TILE > fstage ? fslot * TILE : fstage);
+  const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
   allow((const void*)k_fwd_final<T, NX, NY>, lds_ff);
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0, ftst,
-                     carry, mf_fast, Pf_fast, mf_slow, Pf_slow, p.info);
+                     carry, mf_slow, Pf_slow, p.info);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
-  if (!smoother) return SRTM_OK;
+
+  const bool want_f = p.mf_fast || p.Pf_fast;
+  const bool want_sfast = p.ms_fast || p.Ps_fast;
+  const bool want_sslow = p.ms_slow || p.Ps_slow;
+  if (!smoother) {
+    SRTM_EV(ev.pre(st));
+    if (want_f) {
+      srtm_status s = launch_recover<T, NX, NY, 1>(p, y, N, L, L, cst, m0, P0, carry, nullptr, st);
+      if (s != SRTM_OK) return s;
+    }
+    SRTM_EV(ev.post(st));
+    return SRTM_OK;
+  }
 
   T* btagg = reinterpret_cast<T*>(ws + wl.btile_agg);
   T* btst = reinterpret_cast<T*>(ws + wl.btile_state);
+  T* vw = reinterpret_cast<T*>(ws + wl.vw);
   const size_t lds_br = sizeof(T) * (size_t)TILE * (2 * NN + NX);
   allow((const void*)k_bwd_reduce<T, NX, NY>, lds_br);
   SRTM_EV(ev.pre(st));
@@ -1546,14 +1801,20 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  const size_t stage = sizeof(T) * (size_t)4 * 64 * Stage<T, NX>::STR;
-  const size_t lds_bf = lds_br > stage ? lds_br : stage;
-  allow((const void*)k_bwd_final<T, NX, NY>, lds_bf);
+  allow((const void*)k_bwd_scan<T, NX, NY>, lds_br);
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_bf, st, y, N, L, cst, m0, P0,
-                     carry, btst, static_cast<T*>(p.ms_fast), static_cast<T*>(p.Ps_fast),
-                     static_cast<T*>(p.ms_slow), static_cast<T*>(p.Ps_slow), p.info);
+  hipLaunchKernelGGL((k_bwd_scan<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_br, st, y, N, L, cst, m0, P0,
+                     carry, btst, vw, p.info);
   SRTM_CHECK_LAUNCH();
+  SRTM_EV(ev.post(st));
+
+  SRTM_EV(ev.pre(st));
+  const int ilim = (want_f || want_sfast) ? L : (want_sslow ? 1 : 0);
+  if (ilim > 0) {
+    srtm_status s = want_f ? launch_recover<T, NX, NY, 3>(p, y, N, L, ilim, cst, m0, P0, carry, vw, st)
+                           : launch_recover<T, NX, NY, 2>(p, y, N, L, ilim, cst, m0, P0, carry, vw, st);
+    if (s != SRTM_OK) return s;
+  }
   SRTM_EV(ev.post(st));
   return SRTM_OK;
 }

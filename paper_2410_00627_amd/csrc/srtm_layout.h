@@ -17,8 +17,8 @@ struct ConstLayout {
   int A, Q, Cbar, Rx, K, Heta;   // model and slow-rate constants
   int per_i, per_i_stride;       // per fast step i = 1..L: A^i, Q_ii, Q_iL, c_i
   int o_Ai, o_Qii, o_QiL, o_ci;
-  int lev, lev_stride;           // per level p: F, D, J of 2^p merged windows and
-  int o_F, o_D, o_J, o_G1, o_G2, o_G3, o_G4;  // the vector-combine coefficients
+  int lev, lev_stride;           // per level p: F, D, J of 2^p merged windows, a factor
+  int o_F, o_D, o_J, o_Z, o_G1, o_G2, o_G3, o_G4;  // Z Z^T = J, and the vector-combine coefficients
   int total;
 };
 
@@ -37,8 +37,9 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L) 
   c.o_Ai = 0; c.o_Qii = nn; c.o_QiL = 2 * nn; c.o_ci = 3 * nn;
   c.per_i_stride = (3 * nn + nxy + 7) & ~7;
   c.per_i = o; o += L * c.per_i_stride;
-  c.o_F = 0; c.o_D = nn; c.o_J = 2 * nn; c.o_G1 = 3 * nn; c.o_G2 = 4 * nn; c.o_G3 = 5 * nn; c.o_G4 = 6 * nn;
-  c.lev_stride = (7 * nn + 7) & ~7;
+  c.o_F = 0; c.o_D = nn; c.o_J = 2 * nn; c.o_Z = 3 * nn;
+  c.o_G1 = 4 * nn; c.o_G2 = 5 * nn; c.o_G3 = 6 * nn; c.o_G4 = 7 * nn;
+  c.lev_stride = (8 * nn + 7) & ~7;
   c.lev = o; o += NLEV * c.lev_stride;
   c.total = o;
   return c;
@@ -46,8 +47,11 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L) 
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, total;
+  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, vw, total;
 };
+
+// Per-window smoother correction (v, W) with W stored as its upper triangle.
+inline __host__ __device__ constexpr int vw_stride(int nx) { return nx + nx * (nx + 1) / 2; }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -64,8 +68,9 @@ inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz,
   if (smoother) {
     w.btile_agg = o; o = align256(o + (size_t)nt * (2 * nn + nx) * esz);
     w.btile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
+    w.vw = o; o = align256(o + (size_t)N * vw_stride(nx) * esz);
   } else {
-    w.btile_agg = w.btile_state = 0;
+    w.btile_agg = w.btile_state = w.vw = 0;
   }
   w.total = o;
   return w;
