@@ -196,6 +196,88 @@ SRTM_DEV float rsqrt_nr(float s) {
   return y;
 }
 
+// 1/x: hardware estimate refined by Newton steps y <- y (2 - x y).
+SRTM_DEV double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+SRTM_DEV float rcp_nr(float x) {
+  float y = __builtin_amdgcn_rcpf(x);
+  y = y * fmaf(-x, y, 2.0f);
+  return y;
+}
+
+// Explicit inverse through the adjugate (cofactors over the determinant) for N <= 4: a short
+// dependency chain with wide instruction-level parallelism, for the small, well-conditioned
+// matrices of the scan combines. Returns false when the determinant is zero or not finite.
+template <typename T, int N>
+SRTM_DEV bool inv_adj(const T (&a)[N][N], T (&b)[N][N]) {
+  static_assert(N >= 1 && N <= 4, "inv_adj: N <= 4");
+  T det;
+  if constexpr (N == 1) {
+    det = a[0][0];
+    b[0][0] = T(1);
+  } else if constexpr (N == 2) {
+    det = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+    b[0][0] = a[1][1];
+    b[0][1] = -a[0][1];
+    b[1][0] = -a[1][0];
+    b[1][1] = a[0][0];
+  } else if constexpr (N == 3) {
+    const T c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+    const T c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+    const T c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+    det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+    b[0][0] = c00;
+    b[0][1] = a[0][2] * a[2][1] - a[0][1] * a[2][2];
+    b[0][2] = a[0][1] * a[1][2] - a[0][2] * a[1][1];
+    b[1][0] = c01;
+    b[1][1] = a[0][0] * a[2][2] - a[0][2] * a[2][0];
+    b[1][2] = a[0][2] * a[1][0] - a[0][0] * a[1][2];
+    b[2][0] = c02;
+    b[2][1] = a[0][1] * a[2][0] - a[0][0] * a[2][1];
+    b[2][2] = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+  } else {
+    // 2x2 minors of rows {0,1} (s) and rows {2,3} (c)
+    const T s0 = a[0][0] * a[1][1] - a[1][0] * a[0][1], s1 = a[0][0] * a[1][2] - a[1][0] * a[0][2];
+    const T s2 = a[0][0] * a[1][3] - a[1][0] * a[0][3], s3 = a[0][1] * a[1][2] - a[1][1] * a[0][2];
+    const T s4 = a[0][1] * a[1][3] - a[1][1] * a[0][3], s5 = a[0][2] * a[1][3] - a[1][2] * a[0][3];
+    const T c5 = a[2][2] * a[3][3] - a[3][2] * a[2][3], c4 = a[2][1] * a[3][3] - a[3][1] * a[2][3];
+    const T c3 = a[2][1] * a[3][2] - a[3][1] * a[2][2], c2 = a[2][0] * a[3][3] - a[3][0] * a[2][3];
+    const T c1 = a[2][0] * a[3][2] - a[3][0] * a[2][2], c0 = a[2][0] * a[3][1] - a[3][0] * a[2][1];
+    det = s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
+    b[0][0] = a[1][1] * c5 - a[1][2] * c4 + a[1][3] * c3;
+    b[0][1] = -a[0][1] * c5 + a[0][2] * c4 - a[0][3] * c3;
+    b[0][2] = a[3][1] * s5 - a[3][2] * s4 + a[3][3] * s3;
+    b[0][3] = -a[2][1] * s5 + a[2][2] * s4 - a[2][3] * s3;
+    b[1][0] = -a[1][0] * c5 + a[1][2] * c2 - a[1][3] * c1;
+    b[1][1] = a[0][0] * c5 - a[0][2] * c2 + a[0][3] * c1;
+    b[1][2] = -a[3][0] * s5 + a[3][2] * s2 - a[3][3] * s1;
+    b[1][3] = a[2][0] * s5 - a[2][2] * s2 + a[2][3] * s1;
+    b[2][0] = a[1][0] * c4 - a[1][1] * c2 + a[1][3] * c0;
+    b[2][1] = -a[0][0] * c4 + a[0][1] * c2 - a[0][3] * c0;
+    b[2][2] = a[3][0] * s4 - a[3][1] * s2 + a[3][3] * s0;
+    b[2][3] = -a[2][0] * s4 + a[2][1] * s2 - a[2][3] * s0;
+    b[3][0] = -a[1][0] * c3 + a[1][1] * c1 - a[1][2] * c0;
+    b[3][1] = a[0][0] * c3 - a[0][1] * c1 + a[0][2] * c0;
+    b[3][2] = -a[3][0] * s3 + a[3][1] * s1 - a[3][2] * s0;
+    b[3][3] = a[2][0] * s3 - a[2][1] * s1 + a[2][2] * s0;
+  }
+  const T id = rcp_nr(det);
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c < N; ++c) b[r][c] *= id;
+  return det != T(0) && isfinite(id);
+}
+
+// Inverse of a symmetric positive-definite matrix (N <= 4: adjugate, exactly symmetrised;
+// larger N: Cholesky). Returns false when the matrix is not numerically positive definite.
+template <typename T, int N>
+SRTM_DEV bool spd_inv(const T (&A)[N][N], T (&Ai)[N][N]);
+
 // Lower-triangular L with L L^T = A for a symmetric positive semi-definite A, and the
 // reciprocal diagonal idg. A pivot that is not positive gives a zero column (idg = 0).
 // Returns false if a pivot was dropped.
@@ -309,4 +391,19 @@ SRTM_DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+}  // namespace srtm
+
+namespace srtm {
+template <typename T, int N>
+SRTM_DEV bool spd_inv(const T (&A)[N][N], T (&Ai)[N][N]) {
+  if constexpr (N <= 4) {
+    bool ok = inv_adj(A, Ai);
+    symmetrize(Ai);
+#pragma unroll
+    for (int j = 0; j < N; ++j) ok = ok && (A[j][j] > T(0)) && (Ai[j][j] > T(0));
+    return ok;
+  } else {
+    return chol_inv(A, Ai);
+  }
+}
 }  // namespace srtm

@@ -42,12 +42,12 @@ namespace srtm {
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(256)
 k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
-            const T* __restrict__ Rm, int L, T* __restrict__ cst, int32_t* info) {
+            const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst, int32_t* info) {
   constexpr int NN = NX * NX, NXY = NX * NY;
   constexpr int W2S = (NN > 2 * NXY ? NN : 2 * NXY);
   extern __shared__ double sm[];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const ConstLayout lay = make_const_layout(NX, NY, L);
+  const ConstLayout lay = make_const_layout(NX, NY, L, nlev);
   double* sA = sm;
   double* sQ = sA + NN;
   double* sC = sQ + NN;
@@ -57,6 +57,7 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
   double* W1 = Qii + (L + 1) * NN;      // (L+1) NN scratch
   double* W2 = W1 + (L + 1) * NN;       // (L+1) W2S scratch
   double* ci = W2 + (L + 1) * W2S;      // (L+1) NXY, ci[i] = c_i
+  double* chain = ci + (L + 1) * NXY;   // 16 NN: level-chain matrices
 
   for (int e = tid; e < NN; e += nthr) {
     sA[e] = (double)Fm[e];
@@ -190,109 +191,159 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
     }
   }
   __syncthreads();
-  if (tid != 0) return;
-  // ---------------------------------------------------------------- one lane
-  double Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NX; ++c) Cbar[r][c] = sCbar[r * NX + c];
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NY; ++c) Rx[r][c] = sRx[r * NY + c];
-  symmetrize(Rx);
-  for (int r = 0; r < NX; ++r)
-    for (int c = 0; c < NY; ++c) Sxy[r][c] = ci[L * NXY + r * NY + c];
-  double Rxi[NY][NY];
-  if (!chol_inv(Rx, Rxi) && info) atomicOr(info, SRTM_INFO_INNOVATION_NOT_PD);
-  double K[NX][NY], Heta[NX][NY];
-  mm(Sxy, Rxi, K);
-  mm_tn(Cbar, Rxi, Heta);
-  double F[NX][NX], D[NX][NX], J[NX][NX];
-  for (int r = 0; r < NX; ++r)
-    for (int c = 0; c < NX; ++c) {
-      double f = Apow[L * NN + r * NX + c], d = Qii[L * NN + r * NX + c];
-      for (int k = 0; k < NY; ++k) {
-        f -= K[r][k] * Cbar[k][c];
-        d -= K[r][k] * Sxy[c][k];
-      }
-      F[r][c] = f;
-      D[r][c] = d;
-    }
-  mm(Heta, Cbar, J);
-  symmetrize(D);
-  symmetrize(J);
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NX; ++c) cst[lay.Cbar + r * NX + c] = (T)Cbar[r][c];
-  for (int r = 0; r < NY; ++r)
-    for (int c = 0; c < NY; ++c) cst[lay.Rx + r * NY + c] = (T)Rx[r][c];
-  for (int r = 0; r < NX; ++r)
-    for (int c = 0; c < NY; ++c) {
-      cst[lay.K + r * NY + c] = (T)K[r][c];
-      cst[lay.Heta + r * NY + c] = (T)Heta[r][c];
-    }
-  // Levels: Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, with
-  // W = (I + D J)^{-1} evaluated through J = Z Z^T and M = I + Z^T D Z = N N^T:
-  //   W = I - B C^T,  B = D Z N^{-T},  C = Z N^{-T},  W D = D - B B^T.
-  // Coefficients that combine the vector parts of two runs of 2^p elements:
-  //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
-  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J.
+  if (tid >= 64) return;  // the rest is done by wave 0
+  double* cF = chain;            // current Theta(2^p): F, D, J
+  double* cD = chain + NN;
+  double* cJ = chain + 2 * NN;
+  double* nF = chain + 3 * NN;   // next level
+  double* nD = chain + 4 * NN;
+  double* nJ = chain + 5 * NN;
+  double* cM = chain + 6 * NN;
+  double* cW = chain + 7 * NN;
+  double* cWF = chain + 8 * NN;
+  double* cG1 = chain + 9 * NN;
+  double* cXD = chain + 10 * NN;
+  double* cG2 = chain + 11 * NN;
+  double* cG4 = chain + 12 * NN;
   int lflag = 0;
-  for (int p = 0; p < NLEV; ++p) {
-    T* dst = cst + lay.lev + p * lay.lev_stride;
-    double Z[NX][NX], zi[NX];
-    chol_lower(J, Z, zi);
-    double DZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX];
-    mm(D, Z, DZ);
+  if (tid == 0) {
+    // ------------------------------------------------------------ generic element (one lane)
+    double Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NX; ++c) Cbar[r][c] = sCbar[r * NX + c];
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NY; ++c) Rx[r][c] = sRx[r * NY + c];
+    symmetrize(Rx);
     for (int r = 0; r < NX; ++r)
-      for (int c = r; c < NX; ++c) {
-        double acc = (r == c) ? 1.0 : 0.0;
-        for (int k = 0; k < NX; ++k) acc += Z[k][r] * DZ[k][c];
-        M[r][c] = acc;
-        M[c][r] = acc;
-      }
-    if (!chol_lower(M, Nf, ni)) lflag |= SRTM_INFO_COMBINE_SINGULAR;
-    double B[NX][NX], Cm[NX][NX];
-    right_solve_lt(DZ, Nf, ni, B);
-    right_solve_lt(Z, Nf, ni, Cm);
-    double CtF[NX][NX], WF[NX][NX], FB[NX][NX], G1[NX][NX], XD[NX][NX], G2[NX][NX], G4[NX][NX];
-    mm_tn(Cm, F, CtF);
-    mm(B, CtF, WF);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) WF[r][c] = F[r][c] - WF[r][c];   // W F
-    mm(F, B, FB);
-    mm_nt(FB, Cm, G1);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) G1[r][c] = F[r][c] - G1[r][c];   // F W
-    for (int r = 0; r < NX; ++r)
-      for (int c = r; c < NX; ++c) {
-        double acc = D[r][c];
-        for (int k = 0; k < NX; ++k) acc -= B[r][k] * B[c][k];
-        XD[r][c] = acc;
-        XD[c][r] = acc;                                              // W D
-      }
-    mm(F, XD, G2);
-    mm_tn(WF, J, G4);
+      for (int c = 0; c < NY; ++c) Sxy[r][c] = ci[L * NXY + r * NY + c];
+    double Rxi[NY][NY];
+    if (!spd_inv(Rx, Rxi)) lflag |= SRTM_INFO_INNOVATION_NOT_PD;
+    double K[NX][NY], Heta[NX][NY];
+    mm(Sxy, Rxi, K);
+    mm_tn(Cbar, Rxi, Heta);
+    double F[NX][NX], D[NX][NX], J[NX][NX];
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) {
-        dst[lay.o_F + r * NX + c] = (T)F[r][c];
-        dst[lay.o_D + r * NX + c] = (T)D[r][c];
-        dst[lay.o_J + r * NX + c] = (T)J[r][c];
-        dst[lay.o_Z + r * NX + c] = (T)Z[r][c];
-        dst[lay.o_G1 + r * NX + c] = (T)G1[r][c];
-        dst[lay.o_G2 + r * NX + c] = (T)G2[r][c];
-        dst[lay.o_G3 + r * NX + c] = (T)WF[c][r];
-        dst[lay.o_G4 + r * NX + c] = (T)G4[r][c];
+        double f = Apow[L * NN + r * NX + c], d = Qii[L * NN + r * NX + c];
+        for (int k = 0; k < NY; ++k) {
+          f -= K[r][k] * Cbar[k][c];
+          d -= K[r][k] * Sxy[c][k];
+        }
+        F[r][c] = f;
+        D[r][c] = d;
       }
-    double Fn[NX][NX], Dn[NX][NX], Jn[NX][NX];
-    mm(F, WF, Fn);           // F W F
-    mm_nt(G2, F, Dn);        // F W D F^T
-    mm(G4, F, Jn);           // F^T W^T J F
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) {
-        F[r][c] = Fn[r][c];
-        D[r][c] = Dn[r][c] + D[r][c];
-        J[r][c] = Jn[r][c] + J[r][c];
-      }
+    mm(Heta, Cbar, J);
     symmetrize(D);
     symmetrize(J);
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NX; ++c) cst[lay.Cbar + r * NX + c] = (T)Cbar[r][c];
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NY; ++c) cst[lay.Rx + r * NY + c] = (T)Rx[r][c];
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NY; ++c) {
+        cst[lay.K + r * NY + c] = (T)K[r][c];
+        cst[lay.Heta + r * NY + c] = (T)Heta[r][c];
+      }
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        cF[r * NX + c] = F[r][c];
+        cD[r * NX + c] = D[r][c];
+        cJ[r * NX + c] = J[r][c];
+      }
+  }
+  wave_sync();
+  // ------------------------------------------------------------ level chain (wave 0, one lane per entry)
+  // Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, W = (I + D J)^{-1},
+  // and the coefficients that combine the vector parts of two runs of 2^p elements:
+  //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
+  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J.
+  const int e = tid, er = (e % NN) / NX, ec = e % NX, part = e / NN;
+  for (int p = 0; p < nlev; ++p) {
+    if (e < NN) {  // M = I + D J
+      double acc = (er == ec) ? 1.0 : 0.0;
+      for (int k = 0; k < NX; ++k) acc += cD[er * NX + k] * cJ[k * NX + ec];
+      cM[e] = acc;
+    }
+    wave_sync();
+    if (e < NN) {  // W = M^{-1} (every lane forms the adjugate, keeps its entry)
+      double Mr[NX][NX], Wr[NX][NX];
+      for (int r = 0; r < NX; ++r)
+        for (int c = 0; c < NX; ++c) Mr[r][c] = cM[r * NX + c];
+      if (!inv_adj(Mr, Wr) && e == 0) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+      double w = 0.0;
+      for (int r = 0; r < NX; ++r)
+        for (int c = 0; c < NX; ++c)
+          if (r == er && c == ec) w = Wr[r][c];
+      cW[e] = w;
+    }
+    wave_sync();
+    if (part < 3) {  // W F, F W, sym(W D)
+      double acc = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) acc += cW[er * NX + k] * cF[k * NX + ec];
+        cWF[e % NN] = acc;
+      } else if (part == 1) {
+        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cW[k * NX + ec];
+        cG1[e % NN] = acc;
+      } else {
+        double acc2 = 0.0;
+        for (int k = 0; k < NX; ++k) {
+          acc += cW[er * NX + k] * cD[k * NX + ec];
+          acc2 += cW[ec * NX + k] * cD[k * NX + er];
+        }
+        cXD[e % NN] = 0.5 * (acc + acc2);
+      }
+    }
+    wave_sync();
+    if (part < 3) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
+      double acc = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cXD[k * NX + ec];
+        cG2[e % NN] = acc;
+      } else if (part == 1) {
+        for (int k = 0; k < NX; ++k) acc += cWF[k * NX + er] * cJ[k * NX + ec];
+        cG4[e % NN] = acc;
+      } else {
+        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cWF[k * NX + ec];
+        nF[e % NN] = acc;
+      }
+    }
+    wave_sync();
+    if (part < 2) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+      double acc = 0.0, acc2 = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) {
+          acc += cG2[er * NX + k] * cF[ec * NX + k];
+          acc2 += cG2[ec * NX + k] * cF[er * NX + k];
+        }
+        nD[e % NN] = 0.5 * (acc + acc2) + cD[e % NN];
+      } else {
+        for (int k = 0; k < NX; ++k) {
+          acc += cG4[er * NX + k] * cF[k * NX + ec];
+          acc2 += cG4[ec * NX + k] * cF[k * NX + er];
+        }
+        nJ[e % NN] = 0.5 * (acc + acc2) + cJ[e % NN];
+      }
+    }
+    T* dst = cst + lay.lev + p * lay.lev_stride;
+    for (int q = e; q < 7 * NN; q += 64) {
+      const int which = q / NN, o = q % NN, r = o / NX, c = o % NX;
+      double v;
+      switch (which) {
+        case 0: v = cF[o]; dst[lay.o_F + o] = (T)v; break;
+        case 1: v = cD[o]; dst[lay.o_D + o] = (T)v; break;
+        case 2: v = cJ[o]; dst[lay.o_J + o] = (T)v; break;
+        case 3: v = cG1[o]; dst[lay.o_G1 + o] = (T)v; break;
+        case 4: v = cG2[o]; dst[lay.o_G2 + o] = (T)v; break;
+        case 5: v = cWF[c * NX + r]; dst[lay.o_G3 + o] = (T)v; break;
+        default: v = cG4[o]; dst[lay.o_G4 + o] = (T)v; break;
+      }
+    }
+    wave_sync();
+    double* t;
+    t = cF; cF = nF; nF = t;
+    t = cD; cD = nD; nD = t;
+    t = cJ; cJ = nJ; nJ = t;
   }
   if (lflag && info) atomicOr(info, lflag);
 }
@@ -310,28 +361,17 @@ template <typename T, int N>
 SRTM_DEV T symget(const T (&P)[N][N], int r, int c) { return r <= c ? P[r][c] : P[c][r]; }
 
 // state (m, P) (x) segment (F, d, D, eta, J): the eq. op-filter combination whose left
-// operand holds the prior (F = 0). With J = Z Z^T, M = I + Z^T P Z = N N^T (positive
-// definite, pivots >= 1) and B = P Z N^{-T}, Woodbury gives
-//   (I + P J)^{-1} = I - P Z M^{-1} Z^T,  (I + P J)^{-1} P = P - B B^T,
-//   m' = F [u - B N^{-1} Z^T u] + d  (u = m + P eta),   P' = F (P - B B^T) F^T + D.
+// operand holds the prior (F = 0):  W = (I + P J)^{-1},
+//   m' = F W (m + P eta) + d,   P' = F W P F^T + D   (W P is symmetric; its upper triangle is used).
 template <typename T, int NX>
-SRTM_DEV bool state_combine_z(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
-                              const T (&D)[NX][NX], const T (&eta)[NX], const T (&Z)[NX][NX]) {
-  T PZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX], B[NX][NX];
-  mm(P, Z, PZ);
+SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
+                            const T (&D)[NX][NX], const T (&eta)[NX], const T (&J)[NX][NX]) {
+  T M[NX][NX], W[NX][NX];
+  mm(P, J, M);
 #pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = r; c < NX; ++c) {
-      T acc = (r == c) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < NX; ++k) acc = my_fma(Z[k][r], PZ[k][c], acc);
-      M[r][c] = acc;
-      M[c][r] = acc;
-    }
-  const bool ok = chol_lower(M, Nf, ni);
-  right_solve_lt(PZ, Nf, ni, B);
-  T u[NX], zu[NX], z[NX], v[NX];
+  for (int r = 0; r < NX; ++r) M[r][r] += T(1);
+  const bool ok = inv_adj(M, W);
+  T u[NX], Wu[NX], WP[NX][NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     T t = m[r];
@@ -339,23 +379,14 @@ SRTM_DEV bool state_combine_z(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], 
     for (int k = 0; k < NX; ++k) t = my_fma(P[r][k], eta[k], t);
     u[r] = t;
   }
-  mtv(Z, u, zu);
-  left_solve_l(Nf, ni, zu, z);
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    T t = u[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], z[k], t);
-    v[r] = t;
-  }
-  T WP[NX][NX];
+  mv(W, u, Wu);
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T t = P[r][c];
+      T t = T(0);
 #pragma unroll
-      for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], B[c][k], t);
+      for (int k = 0; k < NX; ++k) t = my_fma(W[r][k], P[k][c], t);
       WP[r][c] = t;
       WP[c][r] = t;
     }
@@ -363,24 +394,15 @@ SRTM_DEV bool state_combine_z(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], 
   for (int r = 0; r < NX; ++r) {
     T t = d[r];
 #pragma unroll
-    for (int k = 0; k < NX; ++k) t = my_fma(F[r][k], v[k], t);
+    for (int k = 0; k < NX; ++k) t = my_fma(F[r][k], Wu[k], t);
     m[r] = t;
   }
   sandwich(F, WP, D, P);
   return ok;
 }
 
-template <typename T, int NX>
-SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], const T (&d)[NX],
-                            const T (&D)[NX][NX], const T (&eta)[NX], const T (&J)[NX][NX]) {
-  T Z[NX][NX], zi[NX];
-  chol_lower(J, Z, zi);
-  return state_combine_z(m, P, F, d, D, eta, Z);
-}
-
-// Full filter element and a_i (x) a_j of eq. op-filter. With J_j = Z Z^T,
-// M = I + Z^T D_i Z = N N^T, B = D_i Z N^{-T} and C = Z N^{-T}:
-//   W = (I + D_i J_j)^{-1} = I - B C^T,  W D_i = D_i - B B^T,  (I + J_j D_i)^{-1} = W^T,
+// Full filter element and a_i (x) a_j of eq. op-filter, with W = (I + D_i J_j)^{-1} and
+// (I + J_j D_i)^{-1} = W^T (D, J symmetric):
 //   F = F_j W F_i, d = F_j W (d_i + D_i eta_j) + d_j, D = F_j W D_i F_j^T + D_j,
 //   eta = (W F_i)^T (eta_j - J_j d_i) + eta_i,  J = (W F_i)^T J_j F_i + J_i.
 template <typename T, int NX>
@@ -390,30 +412,13 @@ struct FElem {
 
 template <typename T, int NX>
 SRTM_DEV bool elem_combine(const FElem<T, NX>& a, const FElem<T, NX>& b, FElem<T, NX>& o) {
-  T Z[NX][NX], zi[NX], DZ[NX][NX], M[NX][NX], Nf[NX][NX], ni[NX], B[NX][NX], C[NX][NX];
-  chol_lower(b.J, Z, zi);
-  mm(a.D, Z, DZ);
+  T M[NX][NX], W[NX][NX];
+  mm(a.D, b.J, M);
 #pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = r; c < NX; ++c) {
-      T acc = (r == c) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < NX; ++k) acc = my_fma(Z[k][r], DZ[k][c], acc);
-      M[r][c] = acc;
-      M[c][r] = acc;
-    }
-  const bool ok = chol_lower(M, Nf, ni);
-  right_solve_lt(DZ, Nf, ni, B);
-  right_solve_lt(Z, Nf, ni, C);
-  // X_F = W F_i, X_u = W (d_i + D_i eta_j), X_D = W D_i
-  T CtF[NX][NX], XF[NX][NX], u[NX], Ctu[NX], Xu[NX], XD[NX][NX];
-  mm_tn(C, a.F, CtF);
-  mm(B, CtF, XF);
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = 0; c < NX; ++c) XF[r][c] = a.F[r][c] - XF[r][c];
+  for (int r = 0; r < NX; ++r) M[r][r] += T(1);
+  const bool ok = inv_adj(M, W);
+  T XF[NX][NX], u[NX], Xu[NX], XD[NX][NX];
+  mm(W, a.F, XF);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     T t = a.d[r];
@@ -421,21 +426,14 @@ SRTM_DEV bool elem_combine(const FElem<T, NX>& a, const FElem<T, NX>& b, FElem<T
     for (int k = 0; k < NX; ++k) t = my_fma(a.D[r][k], b.e[k], t);
     u[r] = t;
   }
-  mtv(C, u, Ctu);
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    T t = u[r];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], Ctu[k], t);
-    Xu[r] = t;
-  }
+  mv(W, u, Xu);
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T t = a.D[r][c];
+      T t = T(0);
 #pragma unroll
-      for (int k = 0; k < NX; ++k) t = my_fma(-B[r][k], B[c][k], t);
+      for (int k = 0; k < NX; ++k) t = my_fma(W[r][k], a.D[k][c], t);
       XD[r][c] = t;
       XD[c][r] = t;
     }
@@ -670,7 +668,7 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY>& M, int L, const T (&m)[NX], c
 #pragma unroll
     for (int c = 0; c < NY; ++c) S[r][c] += Rx[r][c];
   symmetrize(S);
-  const bool ok = chol_inv(S, w.Si);
+  const bool ok = spd_inv(S, w.Si);
   T e[NY];
 #pragma unroll
   for (int r = 0; r < NY; ++r) {
@@ -827,7 +825,7 @@ SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, 
   load(Qm, M.cst + M.lay.Q);
   T Pm[NX][NX];
   sandwich(A, PL, Qm, Pm);
-  if (!chol_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
+  if (!spd_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
   mv(A, mL, mpred);
   T PA[NX][NX];
   mm_nt(Pf1L, A, PA);
@@ -945,93 +943,205 @@ k_fwd_reduce(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int 
   }
 }
 
-// K2: one workgroup scans the tile aggregates (matrices Theta(TILE), vectors from K1) and
-// writes each tile's exclusive prefix as a state (m, P), starting from (m0, P0).
+// K2 (Kogge-Stone form): tile-level forward scan in one workgroup of KS threads. Thread tau
+// holds the vector parts of its chunk of 2^lchunk tiles (matrices Theta(2^lchunk TILE)); the
+// prior (m0, P0) is folded into thread 0, which makes it a state. At step q, threads in
+// [2^q, 2^{q+1}) combine the state of thread tau - 2^q with their run (one state combine,
+// eq. op-filter with F_i = 0) and become states; the others merge two runs of equal length
+// with the shared level coefficients. Thread tau then walks its chunk from its exclusive
+// state, writing each tile's incoming state.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TREE)
-k_fwd_tiles(const T* __restrict__ tagg, int64_t nt, const T* __restrict__ cst, int L,
-            const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate, int32_t* info) {
+__global__ void __launch_bounds__(KS)
+k_fwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, const T* __restrict__ cst, int L,
+               const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate, int32_t* info) {
   constexpr int NN = NX * NX, ST = NX + NN;
   extern __shared__ char smraw[];
-  const Slots<T> S{reinterpret_cast<T*>(smraw), TREE};
+  const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const int tid = threadIdx.x;
-  const int64_t per = (nt + TREE - 1) / TREE;
-  const int64_t t0 = tid * per;
+  const int64_t c = int64_t(1) << lchunk;
+  const int64_t t0 = tid * c;
   int flag = 0;
-  const T* lv = M.level(LOG_TILE);
-  FElem<T, NX> base;  // matrices of one full tile
-  load(base.F, lv + M.lay.o_F);
-  load(base.D, lv + M.lay.o_D);
-  load(base.J, lv + M.lay.o_J);
-  T baseZ[NX][NX];
-  load(baseZ, lv + M.lay.o_Z);
-  FElem<T, NX> acc;
-  elem_identity(acc);
-#pragma unroll 1
-  for (int64_t t = t0; t < t0 + per && t < nt; ++t) {
-    FElem<T, NX> b = base;
-    loadv(b.d, tagg + t * 2 * NX);
-    loadv(b.e, tagg + t * 2 * NX + NX);
-    if (!elem_combine(acc, b, acc)) flag |= SRTM_INFO_COMBINE_SINGULAR;
-  }
-  st_felem(S, tid, acc);
-  __syncthreads();
-#pragma unroll 1
-  for (int s = 1; s < TREE; s *= 2) {
-    if (((tid + 1) & (2 * s - 1)) == 0) {
-      FElem<T, NX> a, b;
-      ld_felem(S, tid - s, a);
-      ld_felem(S, tid, b);
-      if (!elem_combine(a, b, b)) flag |= SRTM_INFO_COMBINE_SINGULAR;
-      st_felem(S, tid, b);
+  const int l0 = LOG_TILE + lchunk;
+  T d[NX], e[NX];
+  if (c == 1) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      d[r] = (t0 < nt) ? tagg[t0 * 2 * NX + r] : T(0);
+      e[r] = (t0 < nt) ? tagg[t0 * 2 * NX + NX + r] : T(0);
     }
-    __syncthreads();
+  } else {  // fold the chunk with full combines (tiles past the end carry zero vectors)
+    const T* lv = M.level(LOG_TILE);
+    FElem<T, NX> acc, b;
+    load(b.F, lv + M.lay.o_F);
+    load(b.D, lv + M.lay.o_D);
+    load(b.J, lv + M.lay.o_J);
+#pragma unroll 1
+    for (int64_t j = 0; j < c; ++j) {
+      const int64_t t = t0 + j;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        b.d[r] = (t < nt) ? tagg[t * 2 * NX + r] : T(0);
+        b.e[r] = (t < nt) ? tagg[t * 2 * NX + NX + r] : T(0);
+      }
+      if (j == 0) {
+        acc = b;
+      } else if (!elem_combine(acc, b, acc)) {
+        flag |= SRTM_INFO_COMBINE_SINGULAR;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      d[r] = acc.d[r];
+      e[r] = acc.e[r];
+    }
   }
-  // down-sweep with states; slot TREE-1 starts with the prior (m0, P0)
-  if (tid == TREE - 1) {  // the up-sweep ended with a barrier; the total is not needed
-    T m[NX], P[NX][NX];
+  T m[NX], P[NX][NX];
+  if (tid == 0) {
     loadv(m, m0);
     load(P, P0);
     symmetrize(P);
-    st_state<T, NX>(S, tid, m, P);
+    const T* lv = M.level(l0);
+    T F[NX][NX], D[NX][NX], J[NX][NX];
+    load(F, lv + M.lay.o_F);
+    load(D, lv + M.lay.o_D);
+    load(J, lv + M.lay.o_J);
+    if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
-  __syncthreads();
 #pragma unroll 1
-  for (int s = TREE / 2; s >= 1; s /= 2) {
-    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
-    FElem<T, NX> a;
-    T m[NX], P[NX][NX];
-    if (act) {
-      ld_felem(S, tid - s, a);
-      ld_state<T, NX>(S, tid, m, P);
-    }
-    __syncthreads();
-    if (act) {
-      st_state<T, NX>(S, tid - s, m, P);
-      if (!state_combine(m, P, a.F, a.d, a.D, a.e, a.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  for (int q = 0; q < steps; ++q) {
+    const int s = 1 << q;
+    if (tid < s) {
       st_state<T, NX>(S, tid, m, P);
+    } else {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        S.at(r, tid) = d[r];
+        S.at(NX + r, tid) = e[r];
+      }
     }
     __syncthreads();
+    const bool gets_state = tid >= s && tid < 2 * s;
+    T mo[NX], Po[NX][NX], dl[NX], el[NX];
+    if (gets_state) {
+      ld_state<T, NX>(S, tid - s, mo, Po);
+    } else if (tid >= 2 * s) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        dl[r] = S.at(r, tid - s);
+        el[r] = S.at(NX + r, tid - s);
+      }
+    }
+    __syncthreads();
+    const T* lv = M.level(l0 + q);
+    if (gets_state) {
+      T F[NX][NX], D[NX][NX], J[NX][NX];
+      load(F, lv + M.lay.o_F);
+      load(D, lv + M.lay.o_D);
+      load(J, lv + M.lay.o_J);
+      if (!state_combine(mo, Po, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        m[r] = mo[r];
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) P[r][cc] = Po[r][cc];
+      }
+    } else if (tid >= 2 * s) {
+      level_vec_combine(lv, M.lay, dl, el, d, e);
+    }
   }
-  T m[NX], P[NX][NX];
-  ld_state<T, NX>(S, tid, m, P);
+  // every active thread now holds the inclusive state through its chunk
+  st_state<T, NX>(S, tid, m, P);
+  __syncthreads();
+  if (t0 < nt) {
+    T X[NX], XP[NX][NX];
+    if (tid == 0) {
+      loadv(X, m0);
+      load(XP, P0);
+      symmetrize(XP);
+    } else {
+      ld_state<T, NX>(S, tid - 1, X, XP);
+    }
+    const T* lv = M.level(LOG_TILE);
+    T F[NX][NX], D[NX][NX], J[NX][NX];
+    load(F, lv + M.lay.o_F);
+    load(D, lv + M.lay.o_D);
+    load(J, lv + M.lay.o_J);
 #pragma unroll 1
-  for (int64_t t = t0; t < t0 + per && t < nt; ++t) {
+    for (int64_t t = t0; t < t0 + c && t < nt; ++t) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) tstate[t * ST + r] = m[r];
+      for (int r = 0; r < NX; ++r) tstate[t * ST + r] = X[r];
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
+      for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + r * NX + c] = P[r][c];
-    if (t + 1 < nt) {
-      T d[NX], e[NX];
-      loadv(d, tagg + t * 2 * NX);
-      loadv(e, tagg + t * 2 * NX + NX);
-      if (!state_combine_z(m, P, base.F, d, base.D, e, baseZ)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+        for (int cc = 0; cc < NX; ++cc) tstate[t * ST + NX + r * NX + cc] = XP[r][cc];
+      if (t + 1 < t0 + c && t + 1 < nt) {
+        T dt[NX], et[NX];
+        loadv(dt, tagg + t * 2 * NX);
+        loadv(et, tagg + t * 2 * NX + NX);
+        if (!state_combine(X, XP, F, dt, D, et, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      }
     }
   }
   if (flag && info) atomicOr(info, flag);
+}
+
+// K5 (Kogge-Stone form, nt <= KS): reverse tile-level scan, one tile per thread in reversed
+// order (thread r holds tile nt-1-r). Step s: thread r merges its run with the later run
+// held by thread r - s (eq. op-smoother: earlier (x) later). Every run reaching the last
+// window has E = 0, i.e. is the smoothed state at its first window.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(KS)
+k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
+  constexpr int NN = NX * NX, SE = 2 * NN + NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
+  const int tid = threadIdx.x;
+  SElem<T, NX> x;
+  if (tid < nt) {
+    const T* src = tagg + (nt - 1 - tid) * SE;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      x.g[i] = src[NN + i];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        x.E[i][c] = src[i * NX + c];
+        x.S[i][c] = src[NN + NX + i * NX + c];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      x.g[i] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        x.E[i][c] = (i == c) ? T(1) : T(0);
+        x.S[i][c] = T(0);
+      }
+    }
+  }
+#pragma unroll 1
+  for (int s = 1; s < nt; s *= 2) {
+    st_selem(S, tid, x);
+    __syncthreads();
+    SElem<T, NX> later;
+    if (tid >= s) ld_selem(S, tid - s, later);
+    __syncthreads();
+    if (tid >= s) selem_combine(x, later, x);
+  }
+  st_selem(S, tid, x);
+  __syncthreads();
+  if (tid < nt) {
+    const int64_t t = nt - 1 - tid;
+    SElem<T, NX> nxt;
+    if (tid > 0) ld_selem(S, tid - 1, nxt);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) tstate[t * ST + i] = (tid > 0) ? nxt.g[i] : T(0);
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + i * NX + c] = (tid > 0) ? nxt.S[i][c] : T(0);
+  }
 }
 
 // Output staging. Each lane computes one window's blocks; records are written to LDS
@@ -1207,11 +1317,11 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
     if (act) {
       st_state<T, NX>(S, tid - s, m, P);
       const T* lv = M.level(p);
-      T F[NX][NX], D[NX][NX], Z[NX][NX];
+      T F[NX][NX], D[NX][NX], J[NX][NX];
       load(F, lv + M.lay.o_F);
       load(D, lv + M.lay.o_D);
-      load(Z, lv + M.lay.o_Z);
-      if (!state_combine_z(m, P, F, dl, D, el, Z)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      load(J, lv + M.lay.o_J);
+      if (!state_combine(m, P, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
       st_state<T, NX>(S, tid, m, P);
     }
     __syncthreads();
@@ -1232,11 +1342,11 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
   }
   {
     const T* lv = M.level(0);
-    T F[NX][NX], D[NX][NX], Z[NX][NX];
+    T F[NX][NX], D[NX][NX], J[NX][NX];
     load(F, lv + M.lay.o_F);
     load(D, lv + M.lay.o_D);
-    load(Z, lv + M.lay.o_Z);
-    if (!state_combine_z(m, P, F, d, D, e, Z)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    load(J, lv + M.lay.o_J);
+    if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
   if (k < N) {
 #pragma unroll
@@ -1689,7 +1799,7 @@ struct Events {
 size_t constants_lds_bytes(int nx, int ny, int L) {
   const int nn = nx * nx, nxy = nx * ny;
   const int w2s = nn > 2 * nxy ? nn : 2 * nxy;
-  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy));
+  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy) + 16 * nn);
 }
 
 #define SRTM_CHECK_LAUNCH()                    \
@@ -1738,12 +1848,13 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
     if (bytes > 65536) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   };
 
+  const ScanPlan plan = make_scan_plan(N);
   const size_t lds0 = constants_lds_bytes(NX, NY, L);
   allow((const void*)k_constants<T, NX, NY>, lds0);
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(1), dim3(256), lds0, st, static_cast<const T*>(p.F),
-                     static_cast<const T*>(p.Q), static_cast<const T*>(p.H), static_cast<const T*>(p.R), L, cst,
-                     p.info);
+                     static_cast<const T*>(p.Q), static_cast<const T*>(p.H), static_cast<const T*>(p.R), L,
+                     plan.nlev, cst, p.info);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -1752,11 +1863,11 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  const size_t lds_ft = sizeof(T) * (size_t)TREE * (3 * NN + 2 * NX);
-  allow((const void*)k_fwd_tiles<T, NX, NY>, lds_ft);
+  const size_t lds_ft = sizeof(T) * (size_t)KS * (NX + NN);
+  allow((const void*)k_fwd_tiles_ks<T, NX, NY>, lds_ft);
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_ft, st, ftagg, nt, cst, L, m0, P0, ftst,
-                     p.info);
+  hipLaunchKernelGGL((k_fwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_ft, st, ftagg, nt, plan.lchunk, plan.steps,
+                     cst, L, m0, P0, ftst, p.info);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -1794,10 +1905,16 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  const size_t lds_bt = sizeof(T) * (size_t)TREE * (2 * NN + NX);
-  allow((const void*)k_bwd_tiles<T, NX, NY>, lds_bt);
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_bt, st, btagg, nt, btst);
+  if (nt <= KS) {
+    const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
+    allow((const void*)k_bwd_tiles_ks<T, NX, NY>, lds_bk);
+    hipLaunchKernelGGL((k_bwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_bk, st, btagg, nt, btst);
+  } else {
+    const size_t lds_bt = sizeof(T) * (size_t)TREE * (2 * NN + NX);
+    allow((const void*)k_bwd_tiles<T, NX, NY>, lds_bt);
+    hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_bt, st, btagg, nt, btst);
+  }
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 

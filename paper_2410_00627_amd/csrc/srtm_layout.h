@@ -8,8 +8,34 @@ namespace srtm {
 
 constexpr int TILE = 256;       // windows per workgroup in the per-tile kernels
 constexpr int LOG_TILE = 8;
-constexpr int NLEV = LOG_TILE + 1;  // scan-table levels p = 0..LOG_TILE (segments of 2^p windows)
-constexpr int TREE = 256;       // threads of the single-workgroup tile-level scans
+constexpr int TREE = 256;       // threads of the tree-form tile-level scans (many tiles)
+constexpr int KS = 512;         // threads of the Kogge-Stone tile-level scans
+constexpr int LOG_KS = 9;
+
+inline __host__ __device__ int ceil_log2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+// Tile-level forward scan plan: each of the KS threads folds `chunk` (a power of two)
+// tiles, `active` threads take part in ceil_log2(active) Kogge-Stone steps, and the
+// constants kernel provides scan levels 0 .. nlev-1 (segments of 2^p windows).
+struct ScanPlan {
+  int64_t nt;
+  int lchunk, active, steps, nlev;
+};
+
+inline __host__ __device__ ScanPlan make_scan_plan(int64_t N) {
+  ScanPlan s;
+  s.nt = (N + TILE - 1) / TILE;
+  s.lchunk = ceil_log2((s.nt + KS - 1) / KS);
+  s.active = (int)((s.nt + (int64_t(1) << s.lchunk) - 1) >> s.lchunk);
+  s.steps = ceil_log2(s.active);
+  const int need = LOG_TILE + s.lchunk + s.steps + 1;
+  s.nlev = need > LOG_TILE + 1 ? need : LOG_TILE + 1;
+  return s;
+}
 
 // Offsets (in scalars) into the constants block written by the constants kernel.
 struct ConstLayout {
@@ -17,12 +43,12 @@ struct ConstLayout {
   int A, Q, Cbar, Rx, K, Heta;   // model and slow-rate constants
   int per_i, per_i_stride;       // per fast step i = 1..L: A^i, Q_ii, Q_iL, c_i
   int o_Ai, o_Qii, o_QiL, o_ci;
-  int lev, lev_stride;           // per level p: F, D, J of 2^p merged windows, a factor
-  int o_F, o_D, o_J, o_Z, o_G1, o_G2, o_G3, o_G4;  // Z Z^T = J, and the vector-combine coefficients
+  int lev, lev_stride;           // per level p: F, D, J of 2^p merged windows and
+  int o_F, o_D, o_J, o_G1, o_G2, o_G3, o_G4;  // the vector-combine coefficients
   int total;
 };
 
-inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L) {
+inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L, int nlev = 0) {
   ConstLayout c;
   const int nn = nx * nx, nxy = nx * ny;
   c.nx = nx; c.ny = ny; c.L = L;
@@ -37,10 +63,10 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L) 
   c.o_Ai = 0; c.o_Qii = nn; c.o_QiL = 2 * nn; c.o_ci = 3 * nn;
   c.per_i_stride = (3 * nn + nxy + 7) & ~7;
   c.per_i = o; o += L * c.per_i_stride;
-  c.o_F = 0; c.o_D = nn; c.o_J = 2 * nn; c.o_Z = 3 * nn;
-  c.o_G1 = 4 * nn; c.o_G2 = 5 * nn; c.o_G3 = 6 * nn; c.o_G4 = 7 * nn;
-  c.lev_stride = (8 * nn + 7) & ~7;
-  c.lev = o; o += NLEV * c.lev_stride;
+  c.o_F = 0; c.o_D = nn; c.o_J = 2 * nn;
+  c.o_G1 = 3 * nn; c.o_G2 = 4 * nn; c.o_G3 = 5 * nn; c.o_G4 = 6 * nn;
+  c.lev_stride = (7 * nn + 7) & ~7;
+  c.lev = o; o += nlev * c.lev_stride;
   c.total = o;
   return c;
 }
@@ -57,7 +83,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother) {
   WorkLayout w;
-  const ConstLayout c = make_const_layout(nx, ny, L);
+  const ConstLayout c = make_const_layout(nx, ny, L, make_scan_plan(N).nlev);
   const int64_t nt = (N + TILE - 1) / TILE;
   const size_t nn = (size_t)nx * nx;
   size_t o = 0;

@@ -103,6 +103,14 @@ def test_edge_lengths(N):
     check_smoother(m, y, torch.float64, f"N={N}")
 
 
+def test_many_tiles_general_paths():
+    """N = 140000 windows (547 tiles of 256): the forward tile scan folds two tiles per thread
+    and the reverse tile scan takes its tree form."""
+    m = wl.random_stable_model(2, 1, 3, 61)
+    y = wl.simulate(m, 140000, 62)
+    check_smoother(m, y, torch.float64, "N=140000")
+
+
 def test_general_model_nonzero_prior():
     """Non-orthogonal A, full Q, R, P0 and nonzero m0."""
     m = wl.random_general_model(4, 2, 6, 21)
