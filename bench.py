@@ -35,13 +35,12 @@ def algorithmic_bytes(nx, ny, L, N, esz):
     (the carry is read once; both window neighbours come from the same array).
     """
     st = nx + nx * nx
-    vws = nx + nx * (nx + 1) // 2
+    sf = nx * nx + nx + nx * (nx + 1) // 2   # per-window smoother-correction record
     total = N * (ny + 2 * st + st + L * st) * esz
     return dict(total=total,
-                k_recover=N * (ny + st + vws + st + L * st) * esz,    # reads y, carry, (v, W); writes outputs
-                k_fwd_final=N * (ny + st) * esz,                      # reads y; writes the carry
-                k_bwd_reduce=N * (ny + 2 * st) * esz,
-                k_bwd_scan=N * (ny + 2 * st + vws) * esz,
+                k_recover=N * (ny + st + sf + st + L * st) * esz,  # reads y, carry, record; writes outputs
+                k_fwd_bwd=N * (ny + st + sf) * esz,                # reads y; writes the carry and the record
+                k_fwd_final=N * (ny + st) * esz,                   # reads y; writes the carry
                 k_fwd_reduce=N * ny * esz)
 
 

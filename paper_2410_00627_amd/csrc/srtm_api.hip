@@ -58,8 +58,8 @@ srtm_status run_common(const srtm_shape* sh, const srtm::Ptrs& p, bool smoother,
 }
 
 const char* const kFilterKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles", "k_fwd_final", "k_recover"};
-const char* const kSmoothKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles", "k_fwd_final",
-                                      "k_bwd_reduce", "k_bwd_tiles", "k_bwd_scan",  "k_recover"};
+const char* const kSmoothKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles",
+                                      "k_fwd_bwd",   "k_bwd_tiles",  "k_recover"};
 
 }  // namespace
 

@@ -798,11 +798,11 @@ SRTM_DEV void load_prior(const T* __restrict__ carry, const T* __restrict__ m0, 
 // Smoother element of window k (eq. parallel-ak-smoothing, transposed S_k):
 //   P^- = A P^f_{k,l} A^T + Q,  E = P^f_{k,1,l} A^T (P^-)^{-1},  g = m^f_{k,1} - E A m^f_{k,l},
 //   S = P^f_{k,1} - E A (P^f_{k,1,l})^T = P^f_{k,1} - E P^- E^T;   last window: (0, m^f_{N,1}, P^f_{N,1}).
-// Also returns (P^-)^{-1} and A m^f_{k,l}, which the fast-rate recovery reuses.
+// Also returns P^-, (P^-)^{-1} and A m^f_{k,l}, which the smoother correction reuses.
 template <typename T, int NX, int NY>
 SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, bool last,
                               const T (&mL)[NX], const T (&PL)[NX][NX], SElem<T, NX>& el,
-                              T (&Pmi)[NX][NX], T (&mpred)[NX]) {
+                              T (&Pmi)[NX][NX], T (&mpred)[NX], T (&Pm)[NX][NX]) {
   T mf1[NX], Pf11[NX][NX], Pf1L[NX][NX];
   window_step<T, NX, NY, true>(M, w, 1, mf1, Pf11, Pf1L);
   int flag = 0;
@@ -816,6 +816,7 @@ SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, 
         el.E[r][c] = T(0);
         el.S[r][c] = Pf11[r][c];
         Pmi[r][c] = T(0);
+        Pm[r][c] = T(0);
       }
     }
     return 0;
@@ -823,7 +824,6 @@ SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, 
   T A[NX][NX], Qm[NX][NX];
   load(A, M.cst + M.lay.A);
   load(Qm, M.cst + M.lay.Q);
-  T Pm[NX][NX];
   sandwich(A, PL, Qm, Pm);
   if (!spd_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
   mv(A, mL, mpred);
@@ -1268,20 +1268,15 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
   return ok;
 }
 
-// K3: per tile, down-sweep from the tile's exclusive state to every window, giving the
-// slow-rate carry (m^f_{k,l}, P^f_{k,l}) and, when requested, the slow-rate filter outputs.
+// Per tile, down-sweep from the tile's exclusive state to every window: lane k ends with
+// the exclusive state (m^f_{k-1,l}, P^f_{k-1,l}) in (mprev, Pprev) and the inclusive one
+// (m^f_{k,l}, P^f_{k,l}) in (m, P). S needs TILE * max(2 nx, nx + nx^2) scalars.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TILE)
-k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
-            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
-            T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
-  constexpr int NN = NX * NX, ST = NX + NN;
-  extern __shared__ char smraw[];
-  T* smem = reinterpret_cast<T*>(smraw);
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
-  const Slots<T> S{smem, TILE};
+SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T* __restrict__ y, int64_t k,
+                             int64_t N, const T* __restrict__ m0, const T* __restrict__ P0,
+                             const T* __restrict__ tile_state, T (&mprev)[NX], T (&Pprev)[NX][NX], T (&m)[NX],
+                             T (&P)[NX][NX]) {
   const int tid = threadIdx.x;
-  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
   int flag = 0;
   T d[NX], e[NX];
   fwd_element(M, y, k, N, d, e);
@@ -1294,40 +1289,39 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
   fwd_upsweep(M, S, tid);
   // down-sweep with states; slot TILE-1 <- the tile's exclusive state
   if (tid == TILE - 1) {
-    T m[NX], P[NX][NX];
-    loadv(m, tstate + blockIdx.x * ST);
-    load(P, tstate + blockIdx.x * ST + NX);
-    st_state<T, NX>(S, tid, m, P);
+    T mt[NX], Pt[NX][NX];
+    loadv(mt, tile_state);
+    load(Pt, tile_state + NX);
+    st_state<T, NX>(S, tid, mt, Pt);
   }
   __syncthreads();
 #pragma unroll 1
   for (int p = LOG_TILE - 1; p >= 0; --p) {
     const int s = 1 << p;
     const bool act = ((tid + 1) & (2 * s - 1)) == 0;
-    T dl[NX], el[NX], m[NX], P[NX][NX];
+    T dl[NX], el[NX], ma[NX], Pa[NX][NX];
     if (act) {
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         dl[r] = S.at(r, tid - s);
         el[r] = S.at(NX + r, tid - s);
       }
-      ld_state<T, NX>(S, tid, m, P);
+      ld_state<T, NX>(S, tid, ma, Pa);
     }
     __syncthreads();
     if (act) {
-      st_state<T, NX>(S, tid - s, m, P);
+      st_state<T, NX>(S, tid - s, ma, Pa);
       const T* lv = M.level(p);
       T F[NX][NX], D[NX][NX], J[NX][NX];
       load(F, lv + M.lay.o_F);
       load(D, lv + M.lay.o_D);
       load(J, lv + M.lay.o_J);
-      if (!state_combine(m, P, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
-      st_state<T, NX>(S, tid, m, P);
+      if (!state_combine(ma, Pa, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      st_state<T, NX>(S, tid, ma, Pa);
     }
     __syncthreads();
   }
   // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
-  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
   ld_state<T, NX>(S, tid, mprev, Pprev);
   if (k == 0) {  // the prior itself, not a rounded copy through the tree
     loadv(mprev, m0);
@@ -1348,64 +1342,50 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
     load(J, lv + M.lay.o_J);
     if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
-  if (k < N) {
+  return flag;
+}
+
+// Writes the slow-rate carry (m^f_{k,l}, P^f_{k,l}) and, when requested, the slow-rate
+// filter outputs of window k < N.
+template <typename T, int NX>
+SRTM_DEV int store_carry(int64_t k, const T (&m)[NX], const T (&P)[NX][NX], T* __restrict__ carry,
+                         T* __restrict__ m_slow, T* __restrict__ P_slow) {
+  constexpr int NN = NX * NX, ST = NX + NN;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) carry[k * ST + r] = m[r];
+  for (int r = 0; r < NX; ++r) carry[k * ST + r] = m[r];
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) carry[k * ST + NX + r * NX + c] = P[r][c];
-    if (m_slow) {
+    for (int c = 0; c < NX; ++c) carry[k * ST + NX + r * NX + c] = P[r][c];
+  if (m_slow) {
 #pragma unroll
-      for (int r = 0; r < NX; ++r) m_slow[k * NX + r] = m[r];
-    }
-    if (P_slow) {
-#pragma unroll
-      for (int r = 0; r < NN; ++r) P_slow[k * NN + r] = P[r / NX][r % NX];
-    }
-    if (!finite_state(m, P)) flag |= SRTM_INFO_NONFINITE;
+    for (int r = 0; r < NX; ++r) m_slow[k * NX + r] = m[r];
   }
+  if (P_slow) {
+#pragma unroll
+    for (int r = 0; r < NN; ++r) P_slow[k * NN + r] = P[r / NX][r % NX];
+  }
+  return finite_state(m, P) ? 0 : SRTM_INFO_NONFINITE;
+}
+
+// K3 (filter only): per tile, the slow-rate carry and the slow-rate filter outputs.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE)
+k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
+            T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
+  constexpr int ST = NX + NX * NX;
+  extern __shared__ char smraw[];
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+  const int64_t k = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
+  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, tstate + blockIdx.x * ST, mprev, Pprev, m, P);
+  if (k < N) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if (flag && info) atomicOr(info, flag);
 }
 
 // ============================================================================ backward
-// Builds the smoother element of window k (zero element past the end).
-template <typename T, int NX, int NY>
-SRTM_DEV int bwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N, int L,
-                         const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
-                         SElem<T, NX>& el, Window<T, NX, NY>& w, T (&Pmi)[NX][NX], T (&mpred)[NX]) {
-  constexpr int ST = NX + NX * NX;
-  int flag = 0;
-  if (k < N) {
-    T m[NX], P[NX][NX], mL[NX], PL[NX][NX], yk[NY];
-    load_prior<T, NX, NY>(carry, m0, P0, k, m, P);
-    loadv(mL, carry + k * ST);
-    load(PL, carry + k * ST + NX);
-    loadv(yk, y + k * NY);
-    if (!window_setup(M, L, m, P, yk, w)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
-    flag |= smoother_element(M, L, w, k == N - 1, mL, PL, el, Pmi, mpred);
-  } else {  // past the last window: a zero element and a zero window (never stored)
-    T z[NX], Z[NX][NX], zy[NY];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      z[r] = T(0);
-      mpred[r] = T(0);
-      el.g[r] = T(0);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        Z[r][c] = (r == c) ? T(1) : T(0);
-        el.E[r][c] = T(0);
-        el.S[r][c] = T(0);
-        Pmi[r][c] = T(0);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NY; ++r) zy[r] = T(0);
-    window_setup(M, L, z, Z, zy, w);
-  }
-  return flag;
-}
-
 // Reversed in-place up-sweep: slot r holds window (tile end - r); combining slot j - s
 // (later windows) with slot j (earlier windows) gives  a_j (x) a_{j-s}.
 template <typename T, int NX>
@@ -1423,26 +1403,147 @@ SRTM_DEV void bwd_upsweep(const Slots<T>& S, int tid, int n) {
   }
 }
 
-// K4: per-tile smoother aggregate a_first (x) ... (x) a_last.
+// K3s (smoother): per tile, the forward down-sweep of K3; then, from the exclusive and
+// inclusive filter states of window k, its smoother element (eq. parallel-ak-smoothing), an
+// in-tile reverse Kogge-Stone scan of those elements under eq. op-smoother, the tile's
+// aggregate a_first (x) ... (x) a_last, and per window the smoother correction of eq.
+// seq-smoothing-all written as terms linear in the smoothed state (m_in, P_in) that enters
+// the tile from the right (the first window after it). With B = (P^-)^{-1} A and the
+// in-tile exclusive suffix (E', g', S') = a_{k+1} (x) ... (x) a_{last of tile}:
+//   v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}) = Et m_in + gt,
+//   W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A = Et P_in Et^T + St,
+//   Et = B^T E',  gt = B^T (g' - A m^f_{k,l}),  St = B^T (S' - P^-) B;
+// all three are zero for the last window, whose smoothed blocks equal the filtered ones.
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(TILE)
-k_bwd_reduce(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
-             const T* __restrict__ P0, const T* __restrict__ carry, T* __restrict__ tagg, int32_t* info) {
-  constexpr int NN = NX * NX, SE = 2 * NN + NX;
+k_fwd_bwd(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
+          const T* __restrict__ P0, const T* __restrict__ ftstate, T* __restrict__ carry, T* __restrict__ m_slow,
+          T* __restrict__ P_slow, T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
   extern __shared__ char smraw[];
-  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const int tid = threadIdx.x;
   const int64_t k = (int64_t)blockIdx.x * TILE + tid;
-  SElem<T, NX> el;
-  Window<T, NX, NY> w;
-  T Pmi[NX][NX], mpred[NX];
-  const int flag = bwd_element(M, y, k, N, L, m0, P0, carry, el, w, Pmi, mpred);
-  st_selem(S, TILE - 1 - tid, el);
+  const bool valid = k < N;
+  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
+  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, ftstate + blockIdx.x * ST, mprev, Pprev, m, P);
+  if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
+
+  SElem<T, NX> x;
+  T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T A m^f_{k,l}, B^T P^- B
+  {
+    T yk[NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) yk[r] = valid ? y[k * NY + r] : T(0);
+    Window<T, NX, NY> w;
+    if (!window_setup(M, L, mprev, Pprev, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    T Pmi[NX][NX], mpred[NX], Pm[NX][NX];
+    const int f = smoother_element(M, L, w, k == N - 1, m, P, x, Pmi, mpred, Pm);
+    if (valid) flag |= f;
+    T A[NX][NX];
+    load(A, M.cst + M.lay.A);
+    mm(Pmi, A, B);
+    mtv(B, mpred, Bm);
+    T PB[NX][NX];
+    mm(Pm, B, PB);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T t = T(0);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(B[q][r], PB[q][c], t);
+        BPB[r][c] = t;
+        BPB[c][r] = t;
+      }
+  }
+  if (!valid) {  // past the last window: a zero element (finite, and absorbed by E_N = 0)
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      x.g[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        x.E[r][c] = T(0);
+        x.S[r][c] = T(0);
+      }
+    }
+  }
+  __syncthreads();  // the slots switch from forward states to smoother elements
+  // lane j ends with a_j (x) a_{j+1} (x) ... (x) a_{TILE-1}
+#pragma unroll 1
+  for (int s = 1; s < TILE; s *= 2) {
+    st_selem(S, tid, x);
+    __syncthreads();
+    SElem<T, NX> later;
+    if (tid + s < TILE) ld_selem(S, tid + s, later);
+    __syncthreads();
+    if (tid + s < TILE) selem_combine(x, later, x);
+  }
+  st_selem(S, tid, x);
   __syncthreads();
-  bwd_upsweep<T, NX>(S, tid, TILE);
   if (tid == 0) {
-    for (int f = 0; f < SE; ++f) tagg[blockIdx.x * SE + f] = S.at(f, TILE - 1);
+    T* dst = btagg + blockIdx.x * SE;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      dst[NN + r] = x.g[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        dst[r * NX + c] = x.E[r][c];
+        dst[NN + NX + r * NX + c] = x.S[r][c];
+      }
+    }
+  }
+  SElem<T, NX> nxt;  // exclusive suffix; the identity (I, 0, 0) for the tile's last lane
+  if (tid + 1 < TILE) {
+    ld_selem(S, tid + 1, nxt);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      nxt.g[r] = T(0);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        nxt.E[r][c] = (r == c) ? T(1) : T(0);
+        nxt.S[r][c] = T(0);
+      }
+    }
+  }
+  if (valid) {
+    T rec[SF];
+    if (k < N - 1) {
+      T SB[NX][NX];
+      mm(nxt.S, B, SB);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = -Bm[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(B[q][r], nxt.g[q], t);
+        rec[NN + r] = t;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T e = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) e = my_fma(B[q][r], nxt.E[q][c], e);
+          rec[r * NX + c] = e;
+        }
+      }
+      int o = NN + NX;
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = -BPB[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(B[q][r], SB[q][c], t);
+          rec[o++] = t;
+        }
+    } else {
+#pragma unroll
+      for (int r = 0; r < SF; ++r) rec[r] = T(0);
+    }
+    T* dst = sfx + k * SF;
+#pragma unroll
+    for (int r = 0; r < SF; ++r) dst[r] = rec[r];
   }
   if (flag && info) atomicOr(info, flag);
 }
@@ -1549,112 +1650,11 @@ k_bwd_tiles(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
   }
 }
 
-// K6: per tile, down-sweep of smoothed states. For every window k < N it writes the
-// correction that turns its filter blocks into smoothed ones (eq. seq-smoothing-all):
-//   v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}),  W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A,
-// so that m^s_{k,i} = m^f_{k,i} + P^f_{k,i,l} v and P^s_{k,i} = P^f_{k,i,i} + P^f_{k,i,l} W P^f_{k,i,l}^T;
-// (v, W) = 0 for the last window, whose smoothed blocks equal the filtered ones.
-template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TILE)
-k_bwd_scan(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
-           const T* __restrict__ P0, const T* __restrict__ carry, const T* __restrict__ tstate,
-           T* __restrict__ vw, int32_t* info) {
-  constexpr int NN = NX * NX, ST = NX + NN, VWS = vw_stride(NX);
-  extern __shared__ char smraw[];
-  T* smem = reinterpret_cast<T*>(smraw);
-  const Slots<T> S{smem, TILE};
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
-  const int tid = threadIdx.x;
-  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
-  SElem<T, NX> el;
-  Window<T, NX, NY> w;
-  T Pmi[NX][NX], mpred[NX];
-  int flag = bwd_element(M, y, k, N, L, m0, P0, carry, el, w, Pmi, mpred);
-  st_selem(S, TILE - 1 - tid, el);
-  __syncthreads();
-  bwd_upsweep<T, NX>(S, tid, TILE);
-  if (tid == TILE - 1) {
-    T m[NX], P[NX][NX];
-    loadv(m, tstate + blockIdx.x * ST);
-    load(P, tstate + blockIdx.x * ST + NX);
-    st_state<T, NX>(S, tid, m, P);
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int s = TILE / 2; s >= 1; s /= 2) {
-    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
-    SElem<T, NX> later;
-    T m[NX], P[NX][NX];
-    if (act) {
-      ld_selem(S, tid - s, later);
-      ld_state<T, NX>(S, tid, m, P);
-    }
-    __syncthreads();
-    if (act) {
-      st_state<T, NX>(S, tid - s, m, P);
-      sstate_combine(later, m, P);
-      st_state<T, NX>(S, tid, m, P);
-    }
-    __syncthreads();
-  }
-  // exclusive suffix state of window k = smoothed state of window k+1, block 1
-  T msn[NX], Psn[NX][NX];
-  ld_state<T, NX>(S, TILE - 1 - tid, msn, Psn);
-  T v[NX], W[NX][NX];
-  if (k < N - 1) {
-    T A[NX][NX], PL[NX][NX], Qm[NX][NX];
-    load(A, cst + M.lay.A);
-    load(Qm, cst + M.lay.Q);
-    load(PL, carry + k * ST + NX);
-    T Pm[NX][NX];
-    sandwich(A, PL, Qm, Pm);
-    T B[NX][NX];  // B = (P^-)^{-1} A
-    mm(Pmi, A, B);
-    T dm[NX], Dm[NX][NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      dm[r] = msn[r] - mpred[r];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) Dm[r][c] = Psn[r][c] - Pm[r][c];
-    }
-    mtv(B, dm, v);
-    T DB[NX][NX];
-    mm(Dm, B, DB);
-#pragma unroll
-    for (int r = 0; r < NX; ++r)
-#pragma unroll
-      for (int c = r; c < NX; ++c) {
-        T s = T(0);
-#pragma unroll
-        for (int q = 0; q < NX; ++q) s = my_fma(B[q][r], DB[q][c], s);
-        W[r][c] = s;
-        W[c][r] = s;
-      }
-  } else {
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      v[r] = T(0);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) W[r][c] = T(0);
-    }
-  }
-  if (k < N) {
-    T* dst = vw + k * VWS;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) dst[r] = v[r];
-    int o = NX;
-#pragma unroll
-    for (int r = 0; r < NX; ++r)
-#pragma unroll
-      for (int c = r; c < NX; ++c) dst[o++] = W[r][c];
-  }
-  if (flag && info) atomicOr(info, flag);
-}
-
 // K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
 // MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
-// from the (v, W) of K6 (and the smoother's slow state, block i = 1). `ilim` is L when
-// fast-rate outputs are requested and 1 when only the slow smoothed state is.
+// (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
+// terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
+// `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
 constexpr int REC_G = 4;  // fast steps whose means are gathered into one record
 #ifndef SRTM_REC_DIRECT
 #define SRTM_REC_DIRECT 0
@@ -1665,10 +1665,11 @@ template <typename T, int NX, int NY, int MODE>
 __global__ void __launch_bounds__(256)
 k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
           const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
-          const T* __restrict__ vw, T* __restrict__ mf_fast, T* __restrict__ Pf_fast,
+          const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast, T* __restrict__ Pf_fast,
           T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow,
           T* __restrict__ Ps_slow, int32_t* info) {
-  constexpr int NN = NX * NX, VWS = vw_stride(NX);
+  constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX);
+  static_assert(TILE == 256, "one recovery workgroup per tile");
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
   using Stg = OutStage<T, NX, REC_G>;
   extern __shared__ char smraw[];
@@ -1688,17 +1689,31 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
   T v[NX], W[NX][NX];
-  if (SMOOTH) {
-    const T* src = vw + kc * VWS;
+  if (SMOOTH) {  // v = Et m_in + gt,  W = Et P_in Et^T + St
+    const T* src = sfx + kc * SF;
+    const T* ti = tin + (int64_t)blockIdx.x * ST;
+    T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
+    load(Et, src);
+    loadv(mi, ti);
+    load(Pi, ti + NX);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) v[r] = src[r];
-    int o = NX;
+    for (int r = 0; r < NX; ++r) {
+      T t = src[NN + r];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
+      v[r] = t;
+    }
+    mm(Et, Pi, EP);
+    int o = NN + NX;
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = r; c < NX; ++c) {
-        W[r][c] = src[o++];
-        W[c][r] = W[r][c];
+        T t = src[o++];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
+        W[r][c] = t;
+        W[c][r] = t;
       }
   }
   bool fin = true;
@@ -1815,13 +1830,13 @@ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 template <typename T, int NX, int NY, int MODE>
 srtm_status launch_recover(const Ptrs& p, const T* y, int64_t N, int L, int ilim, const T* cst, const T* m0,
-                           const T* P0, const T* carry, const T* vw, hipStream_t st) {
+                           const T* P0, const T* carry, const T* sfx, const T* tin, hipStream_t st) {
   const size_t lds = (size_t)4 * OutStage<T, NX, REC_G>::BYTES * ((MODE == 3) ? 2 : 1);
   if (lds > 65536)
     hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const unsigned grid = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL((k_recover<T, NX, NY, MODE>), dim3(grid), dim3(256), lds, st, y, N, L, ilim, cst, m0, P0,
-                     carry, vw, static_cast<T*>(p.mf_fast), static_cast<T*>(p.Pf_fast),
+                     carry, sfx, tin, static_cast<T*>(p.mf_fast), static_cast<T*>(p.Pf_fast),
                      static_cast<T*>(p.ms_fast), static_cast<T*>(p.Ps_fast), static_cast<T*>(p.ms_slow),
                      static_cast<T*>(p.Ps_slow), p.info);
   SRTM_CHECK_LAUNCH();
@@ -1874,20 +1889,19 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   T* mf_slow = static_cast<T*>(p.mf_slow);
   T* Pf_slow = static_cast<T*>(p.Pf_slow);
   const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
-  allow((const void*)k_fwd_final<T, NX, NY>, lds_ff);
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0, ftst,
-                     carry, mf_slow, Pf_slow, p.info);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
-
   const bool want_f = p.mf_fast || p.Pf_fast;
   const bool want_sfast = p.ms_fast || p.Ps_fast;
   const bool want_sslow = p.ms_slow || p.Ps_slow;
   if (!smoother) {
+    allow((const void*)k_fwd_final<T, NX, NY>, lds_ff);
+    SRTM_EV(ev.pre(st));
+    hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0,
+                       ftst, carry, mf_slow, Pf_slow, p.info);
+    SRTM_CHECK_LAUNCH();
+    SRTM_EV(ev.post(st));
     SRTM_EV(ev.pre(st));
     if (want_f) {
-      srtm_status s = launch_recover<T, NX, NY, 1>(p, y, N, L, L, cst, m0, P0, carry, nullptr, st);
+      srtm_status s = launch_recover<T, NX, NY, 1>(p, y, N, L, L, cst, m0, P0, carry, nullptr, nullptr, st);
       if (s != SRTM_OK) return s;
     }
     SRTM_EV(ev.post(st));
@@ -1896,12 +1910,12 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
 
   T* btagg = reinterpret_cast<T*>(ws + wl.btile_agg);
   T* btst = reinterpret_cast<T*>(ws + wl.btile_state);
-  T* vw = reinterpret_cast<T*>(ws + wl.vw);
-  const size_t lds_br = sizeof(T) * (size_t)TILE * (2 * NN + NX);
-  allow((const void*)k_bwd_reduce<T, NX, NY>, lds_br);
+  T* sfx = reinterpret_cast<T*>(ws + wl.sfx);
+  const size_t lds_fb = sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN);
+  allow((const void*)k_fwd_bwd<T, NX, NY>, lds_fb);
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_reduce<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_br, st, y, N, L, cst, m0, P0,
-                     carry, btagg, p.info);
+  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_fb, st, y, N, L, cst, m0, P0, ftst,
+                     carry, mf_slow, Pf_slow, btagg, sfx, p.info);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -1918,18 +1932,11 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  allow((const void*)k_bwd_scan<T, NX, NY>, lds_br);
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_scan<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_br, st, y, N, L, cst, m0, P0,
-                     carry, btst, vw, p.info);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
-
   SRTM_EV(ev.pre(st));
   const int ilim = (want_f || want_sfast) ? L : (want_sslow ? 1 : 0);
   if (ilim > 0) {
-    srtm_status s = want_f ? launch_recover<T, NX, NY, 3>(p, y, N, L, ilim, cst, m0, P0, carry, vw, st)
-                           : launch_recover<T, NX, NY, 2>(p, y, N, L, ilim, cst, m0, P0, carry, vw, st);
+    srtm_status s = want_f ? launch_recover<T, NX, NY, 3>(p, y, N, L, ilim, cst, m0, P0, carry, sfx, btst, st)
+                           : launch_recover<T, NX, NY, 2>(p, y, N, L, ilim, cst, m0, P0, carry, sfx, btst, st);
     if (s != SRTM_OK) return s;
   }
   SRTM_EV(ev.post(st));

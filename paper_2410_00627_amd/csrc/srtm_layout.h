@@ -73,11 +73,11 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L, 
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, vw, total;
+  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, total;
 };
 
-// Per-window smoother correction (v, W) with W stored as its upper triangle.
-inline __host__ __device__ constexpr int vw_stride(int nx) { return nx + nx * (nx + 1) / 2; }
+// Per-window smoother-correction record: Et (nx^2), gt (nx), St (upper triangle).
+inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + nx + nx * (nx + 1) / 2; }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -94,9 +94,9 @@ inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz,
   if (smoother) {
     w.btile_agg = o; o = align256(o + (size_t)nt * (2 * nn + nx) * esz);
     w.btile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
-    w.vw = o; o = align256(o + (size_t)N * vw_stride(nx) * esz);
+    w.sfx = o; o = align256(o + (size_t)N * sfx_stride(nx) * esz);
   } else {
-    w.btile_agg = w.btile_state = w.vw = 0;
+    w.btile_agg = w.btile_state = w.sfx = 0;
   }
   w.total = o;
   return w;
