@@ -1148,16 +1148,29 @@ k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
 // and copied out by the whole wave so that consecutive lanes store consecutive 16-byte
 // chunks. Covariance records (nx^2 scalars) are flushed every fast step; means are
 // gathered over G consecutive fast steps so that a record fills whole cache lines.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <int CH> struct Chunk;
-template <> struct Chunk<16> { using type = uint4; };
-template <> struct Chunk<8> { using type = uint2; };
+template <> struct Chunk<16> { using type = u32x4; };
+template <> struct Chunk<8> { using type = u32x2; };
 template <> struct Chunk<4> { using type = unsigned int; };
+
+// Store of one output chunk. Outputs are written once and never read back by the library;
+// when a flush writes whole 128-byte lines they are stored non-temporally (streamed past the
+// L2), otherwise normally, so that partial lines can merge in the L2 first.
+template <bool NT, typename V>
+SRTM_DEV void put_chunk(char* p, const V& v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+  else
+    *reinterpret_cast<V*>(p) = v;
+}
 
 // Copies records w = 0..nvalid-1 of RB bytes (stride SB bytes in LDS) to dst + w * gstride
 // bytes in chunks of CH bytes. When a record holds a power-of-two number of chunks, lane l
 // always moves chunk (l mod PER) of windows l / PER + r * 64 / PER: every store address is
 // a wave-uniform base plus one loop-invariant 32-bit lane offset.
-template <int RB, int SB>
+template <int RB, int SB, bool NT = false>
 SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, char* __restrict__ dst,
                             int64_t gstride) {
   constexpr int CH = (RB % 16 == 0 && SB % 16 == 0) ? 16 : ((RB % 8 == 0 && SB % 8 == 0) ? 8 : 4);
@@ -1174,11 +1187,17 @@ SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, 
   const int wl = lane / PER, pl = lane - wl * PER;
   const unsigned int lo = (unsigned int)(wl * gstride) + (unsigned int)(pl * CH);
   const char* lsrc = lds + wl * SB + pl * CH;
+  // all LDS reads first, so that the stores leave back to back
+  V v[PER];
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const V v = *reinterpret_cast<const V*>(lsrc + r * WPI * SB);
-    char* ub = dst + (int64_t)r * WPI * gstride;
-    if (wl + r * WPI < nvalid) *reinterpret_cast<V*>(ub + lo) = v;
+  for (int r = 0; r < PER; ++r) v[r] = *reinterpret_cast<const V*>(lsrc + r * WPI * SB);
+  if (nvalid == 64) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (wl + r * WPI < nvalid) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
   }
 }
 
@@ -1192,60 +1211,59 @@ SRTM_DEV void flush_records_rt(int lane, int nvalid, const char* __restrict__ ld
   }
 }
 
-// Stores one lane's record of N scalars at dst (16-byte chunks when N * sizeof(T) allows).
-template <typename T, int N>
-SRTM_DEV void store_record(T* __restrict__ dst, const T* vals) {
-  if constexpr ((N * sizeof(T)) % 16 == 0) {
-    constexpr int PER = N * sizeof(T) / 16, E = 16 / sizeof(T);
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      uint4 u;
-      __builtin_memcpy(&u, vals + r * E, 16);
-      reinterpret_cast<uint4*>(dst)[r] = u;
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < N; ++r) dst[r] = vals[r];
-  }
+// Fast steps gathered into one output record: the largest power of two (at most 8) for
+// which the record still fits in one 128-byte line.
+constexpr int line_group(int bytes) {
+  int g = 1;
+  while (g < 8 && 2 * g * bytes <= 128) g *= 2;
+  return g;
 }
 
-template <typename T, int NX, int G>
+template <typename T, int NX>
 struct OutStage {
   static constexpr int NN = NX * NX;
-  static constexpr int SBP = ((NN * (int)sizeof(T) + 15) / 16) * 16 + 16;      // bytes per P record
-  static constexpr int SBM = ((G * NX * (int)sizeof(T) + 15) / 16) * 16 + 16;  // bytes per m record
-  static constexpr int BYTES = 64 * (SBP + SBM);                                // per wave
+  static constexpr int GM = line_group(NX * (int)sizeof(T));   // means per record
+  static constexpr int GP = line_group(NN * (int)sizeof(T));   // covariances per record
+  static constexpr int RBM = GM * NX * (int)sizeof(T), RBP = GP * NN * (int)sizeof(T);
+  static constexpr int SBP = ((RBP + 15) / 16) * 16 + 16;   // LDS bytes per lane (padded)
+  static constexpr int SBM = ((RBM + 15) / 16) * 16 + 16;
+  static constexpr int BYTES = 64 * (SBP + SBM);             // per wave
   char* pbuf;
   char* mbuf;
   SRTM_DEV OutStage(char* base) : pbuf(base), mbuf(base + 64 * SBP) {}
-  SRTM_DEV void put(int lane, int slot, const T (&m)[NX], const T (&P)[NX][NX]) const {
-    T* pp = reinterpret_cast<T*>(pbuf + lane * SBP);
+  // blocks of fast step i (1-based)
+  SRTM_DEV void put(int lane, int i, const T (&m)[NX], const T (&P)[NX][NX]) const {
+    T* pp = reinterpret_cast<T*>(pbuf + lane * SBP) + ((i - 1) % GP) * NN;
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = 0; c < NX; ++c) pp[r * NX + c] = P[r][c];
-    T* mp = reinterpret_cast<T*>(mbuf + lane * SBM) + slot * NX;
+    T* mp = reinterpret_cast<T*>(mbuf + lane * SBM) + ((i - 1) % GM) * NX;
 #pragma unroll
     for (int r = 0; r < NX; ++r) mp[r] = m[r];
   }
-  // covariance of fast step i (1-based) for windows w0 + w: P_out[((w0 + w) L + i - 1) nx^2]
-  SRTM_DEV void flush_P(int lane, int nvalid, T* P_out, int64_t w0, int L, int i) const {
-    if (!P_out) return;
-    T* dst = P_out + (w0 * L + (i - 1)) * NN;
-    flush_records<NN * (int)sizeof(T), SBP>(lane, nvalid, pbuf, reinterpret_cast<char*>(dst),
-                                            (int64_t)L * NN * sizeof(T));
+  // After put(i): flush the covariance and mean groups that step i completes. The record of
+  // window w0 + w for fast steps i0 .. i0+g-1 starts at out[((w0 + w) L + i0 - 1) * size].
+  SRTM_DEV void flush(int lane, int nvalid, T* m_out, T* P_out, int64_t w0, int L, int i, int ilim) const {
+    const int sp = (i - 1) % GP, sm = (i - 1) % GM;
+    if (P_out && (sp == GP - 1 || i == ilim)) {
+      T* dst = P_out + (w0 * L + (i - sp - 1)) * NN;
+      if (sp == GP - 1)
+        flush_records<RBP, SBP, RBP % 128 == 0>(lane, nvalid, pbuf, reinterpret_cast<char*>(dst),
+                                                (int64_t)L * NN * sizeof(T));
+      else
+        flush_records_rt<T>(lane, nvalid, pbuf, SBP, dst, (int64_t)L * NN, (sp + 1) * NN);
+    }
+    if (m_out && (sm == GM - 1 || i == ilim)) {
+      T* dst = m_out + (w0 * L + (i - sm - 1)) * NX;
+      if (sm == GM - 1)
+        flush_records<RBM, SBM, RBM % 128 == 0>(lane, nvalid, mbuf, reinterpret_cast<char*>(dst),
+                                                (int64_t)L * NX * sizeof(T));
+      else
+        flush_records_rt<T>(lane, nvalid, mbuf, SBM, dst, (int64_t)L * NX, (sm + 1) * NX);
+    }
   }
-  // means of fast steps i0 .. i0+g-1 (1-based) held in slots 0 .. g-1
-  SRTM_DEV void flush_m(int lane, int nvalid, T* m_out, int64_t w0, int L, int i0, int g) const {
-    if (!m_out) return;
-    T* dst = m_out + (w0 * L + (i0 - 1)) * NX;
-    if (g == G)
-      flush_records<G * NX * (int)sizeof(T), SBM>(lane, nvalid, mbuf, reinterpret_cast<char*>(dst),
-                                                  (int64_t)L * NX * sizeof(T));
-    else
-      flush_records_rt<T>(lane, nvalid, mbuf, SBM, dst, (int64_t)L * NX, g * NX);
-  }
-  // slow-rate output from slot 0 and the current covariance record (contiguous windows)
+  // slow-rate output: the blocks of fast step 1 (call right after put(1)), contiguous windows
   SRTM_DEV void flush_slow(int lane, int nvalid, T* m_out, T* P_out, int64_t w0) const {
     if (m_out)
       flush_records<NX * (int)sizeof(T), SBM>(lane, nvalid, mbuf, reinterpret_cast<char*>(m_out + w0 * NX),
@@ -1655,12 +1673,6 @@ k_bwd_tiles(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
-constexpr int REC_G = 4;  // fast steps whose means are gathered into one record
-#ifndef SRTM_REC_DIRECT
-#define SRTM_REC_DIRECT 0
-#endif
-constexpr bool REC_DIRECT = SRTM_REC_DIRECT != 0;  // smoothed records stored by their own lane
-
 template <typename T, int NX, int NY, int MODE>
 __global__ void __launch_bounds__(256)
 k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
@@ -1671,7 +1683,7 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX);
   static_assert(TILE == 256, "one recovery workgroup per tile");
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
-  using Stg = OutStage<T, NX, REC_G>;
+  using Stg = OutStage<T, NX>;
   extern __shared__ char smraw[];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1719,12 +1731,11 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   bool fin = true;
 #pragma unroll 1
   for (int i = 1; i <= ilim; ++i) {
-    const int slot = (i - 1) % REC_G;
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
     window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
     if (FILT) {
       fin = fin && finite_state(mf, Pii);
-      fst.put(lane, slot, mf, Pii);
+      fst.put(lane, i, mf, Pii);
     }
     if (SMOOTH) {
       T ms[NX], Ps[NX][NX];
@@ -1752,33 +1763,13 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
         }
       }
       fin = fin && finite_state(ms, Ps);
-      if (REC_DIRECT) {
-        if (valid) {
-          T pv[NN];
-#pragma unroll
-          for (int r = 0; r < NX; ++r)
-#pragma unroll
-            for (int c = 0; c < NX; ++c) pv[r * NX + c] = Ps[r][c];
-          if (Ps_fast) store_record<T, NN>(Ps_fast + (k * L + i - 1) * NN, pv);
-          if (ms_fast) store_record<T, NX>(ms_fast + (k * L + i - 1) * NX, ms);
-          if (i == 1 && Ps_slow) store_record<T, NN>(Ps_slow + k * NN, pv);
-          if (i == 1 && ms_slow) store_record<T, NX>(ms_slow + k * NX, ms);
-        }
-      } else {
-        sst.put(lane, slot, ms, Ps);
-      }
+      sst.put(lane, i, ms, Ps);
     }
-    if (REC_DIRECT && !FILT) continue;
     wave_sync();
-    const bool group_end = (slot == REC_G - 1) || (i == ilim);
-    if (FILT) {
-      fst.flush_P(lane, nvalid, Pf_fast, w0, L, i);
-      if (group_end) fst.flush_m(lane, nvalid, mf_fast, w0, L, i - slot, slot + 1);
-    }
-    if (SMOOTH && !REC_DIRECT) {
-      sst.flush_P(lane, nvalid, Ps_fast, w0, L, i);
+    if (FILT) fst.flush(lane, nvalid, mf_fast, Pf_fast, w0, L, i, ilim);
+    if (SMOOTH) {
       if (i == 1) sst.flush_slow(lane, nvalid, ms_slow, Ps_slow, w0);
-      if (group_end) sst.flush_m(lane, nvalid, ms_fast, w0, L, i - slot, slot + 1);
+      sst.flush(lane, nvalid, ms_fast, Ps_fast, w0, L, i, ilim);
     }
     wave_sync();
   }
@@ -1831,7 +1822,7 @@ size_t constants_lds_bytes(int nx, int ny, int L) {
 template <typename T, int NX, int NY, int MODE>
 srtm_status launch_recover(const Ptrs& p, const T* y, int64_t N, int L, int ilim, const T* cst, const T* m0,
                            const T* P0, const T* carry, const T* sfx, const T* tin, hipStream_t st) {
-  const size_t lds = (size_t)4 * OutStage<T, NX, REC_G>::BYTES * ((MODE == 3) ? 2 : 1);
+  const size_t lds = (size_t)4 * OutStage<T, NX>::BYTES * ((MODE == 3) ? 2 : 1);
   if (lds > 65536)
     hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const unsigned grid = (unsigned)((N + 255) / 256);
