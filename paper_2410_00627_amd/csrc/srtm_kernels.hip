@@ -31,6 +31,34 @@
 namespace srtm {
 
 // ============================================================================ constants
+// Cofactor (r, c) of the NX x NX row-major matrix M: (-1)^{r+c} times the determinant of M
+// without row r and column c.
+template <int NX>
+SRTM_DEV double cofactor(const double* M, int r, int c) {
+  constexpr int K = NX - 1;
+  if constexpr (K == 0) {
+    return 1.0;
+  } else {
+    double a[K][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int ri = i < r ? i : i + 1;
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[i][j] = M[ri * NX + (j < c ? j : j + 1)];
+    }
+    double d;
+    if constexpr (K == 1) {
+      d = a[0][0];
+    } else if constexpr (K == 2) {
+      d = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+    } else {
+      d = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+          a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    }
+    return ((r + c) & 1) ? -d : d;
+  }
+}
+
 // One workgroup, float64 throughout. Per-step tables are built in LDS by parallel
 // loops; the slow-rate constants and the level tables by one lane in registers.
 //
@@ -57,7 +85,7 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
   double* W1 = Qii + (L + 1) * NN;      // (L+1) NN scratch
   double* W2 = W1 + (L + 1) * NN;       // (L+1) W2S scratch
   double* ci = W2 + (L + 1) * W2S;      // (L+1) NXY, ci[i] = c_i
-  double* chain = ci + (L + 1) * NXY;   // 16 NN: level-chain matrices
+  double* chain = ci + (L + 1) * NXY;   // 19 NN: level-chain records and scratch
 
   for (int e = tid; e < NN; e += nthr) {
     sA[e] = (double)Fm[e];
@@ -192,19 +220,15 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
   }
   __syncthreads();
   if (tid >= 64) return;  // the rest is done by wave 0
-  double* cF = chain;            // current Theta(2^p): F, D, J
-  double* cD = chain + NN;
-  double* cJ = chain + 2 * NN;
-  double* nF = chain + 3 * NN;   // next level
-  double* nD = chain + 4 * NN;
-  double* nJ = chain + 5 * NN;
-  double* cM = chain + 6 * NN;
-  double* cW = chain + 7 * NN;
-  double* cWF = chain + 8 * NN;
-  double* cG1 = chain + 9 * NN;
-  double* cXD = chain + 10 * NN;
-  double* cG2 = chain + 11 * NN;
-  double* cG4 = chain + 12 * NN;
+  // Level records (F, D, J, G1, G2, G3, G4 of Theta(2^p), the global layout of one level),
+  // double-buffered: the next level's F, D, J are formed directly in the other record.
+  double* rec = chain;
+  double* nrec = chain + 7 * NN;
+  double* sM = chain + 14 * NN;
+  double* sCof = sM + NN;
+  double* sW = sCof + NN;
+  double* sWF = sW + NN;
+  double* sXD = sWF + NN;
   int lflag = 0;
   if (tid == 0) {
     // ------------------------------------------------------------ generic element (one lane)
@@ -246,104 +270,97 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
       }
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) {
-        cF[r * NX + c] = F[r][c];
-        cD[r * NX + c] = D[r][c];
-        cJ[r * NX + c] = J[r][c];
+        rec[r * NX + c] = F[r][c];
+        rec[NN + r * NX + c] = D[r][c];
+        rec[2 * NN + r * NX + c] = J[r][c];
       }
   }
   wave_sync();
-  // ------------------------------------------------------------ level chain (wave 0, one lane per entry)
-  // Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, W = (I + D J)^{-1},
-  // and the coefficients that combine the vector parts of two runs of 2^p elements:
+  // ------------------------------------------------------------ level chain (wave 0)
+  // Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, W = (I + D J)^{-1}, and the
+  // coefficients that combine the vector parts of two runs of 2^p elements:
   //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
-  //   G1 = F W, G2 = F W D, G3 = F^T W^T, G4 = F^T W^T J.
-  const int e = tid, er = (e % NN) / NX, ec = e % NX, part = e / NN;
+  //   G1 = F W, G2 = F W D, G3 = (W F)^T, G4 = (W F)^T J.
+  // One lane per matrix entry; W is the adjugate of I + D J over its determinant, with one
+  // cofactor per lane.
+  const int e = tid, o = e % NN, er = o / NX, ec = o % NX, part = e / NN;
   for (int p = 0; p < nlev; ++p) {
+    const double* F = rec;
+    const double* D = rec + NN;
+    const double* J = rec + 2 * NN;
     if (e < NN) {  // M = I + D J
       double acc = (er == ec) ? 1.0 : 0.0;
-      for (int k = 0; k < NX; ++k) acc += cD[er * NX + k] * cJ[k * NX + ec];
-      cM[e] = acc;
+      for (int k = 0; k < NX; ++k) acc += D[er * NX + k] * J[k * NX + ec];
+      sM[e] = acc;
     }
     wave_sync();
-    if (e < NN) {  // W = M^{-1} (every lane forms the adjugate, keeps its entry)
-      double Mr[NX][NX], Wr[NX][NX];
-      for (int r = 0; r < NX; ++r)
-        for (int c = 0; c < NX; ++c) Mr[r][c] = cM[r * NX + c];
-      if (!inv_adj(Mr, Wr) && e == 0) lflag |= SRTM_INFO_COMBINE_SINGULAR;
-      double w = 0.0;
-      for (int r = 0; r < NX; ++r)
-        for (int c = 0; c < NX; ++c)
-          if (r == er && c == ec) w = Wr[r][c];
-      cW[e] = w;
+    if (e < NN) sCof[e] = cofactor<NX>(sM, er, ec);
+    wave_sync();
+    if (e < NN) {  // W = adj(M) / det(M), adj(M)[r][c] = C[c][r]
+      double det = 0.0;
+      for (int c = 0; c < NX; ++c) det += sM[c] * sCof[c];
+      const double id = rcp_nr(det);
+      if (e == 0 && !(det != 0.0 && isfinite(id))) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+      sW[e] = sCof[ec * NX + er] * id;
     }
     wave_sync();
-    if (part < 3) {  // W F, F W, sym(W D)
+    if (part < 3) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
       double acc = 0.0;
       if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += cW[er * NX + k] * cF[k * NX + ec];
-        cWF[e % NN] = acc;
+        for (int k = 0; k < NX; ++k) acc += sW[er * NX + k] * F[k * NX + ec];
+        sWF[o] = acc;
+        rec[5 * NN + ec * NX + er] = acc;
       } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cW[k * NX + ec];
-        cG1[e % NN] = acc;
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sW[k * NX + ec];
+        rec[3 * NN + o] = acc;
       } else {
         double acc2 = 0.0;
         for (int k = 0; k < NX; ++k) {
-          acc += cW[er * NX + k] * cD[k * NX + ec];
-          acc2 += cW[ec * NX + k] * cD[k * NX + er];
+          acc += sW[er * NX + k] * D[k * NX + ec];
+          acc2 += sW[ec * NX + k] * D[k * NX + er];
         }
-        cXD[e % NN] = 0.5 * (acc + acc2);
+        sXD[o] = 0.5 * (acc + acc2);
       }
     }
     wave_sync();
     if (part < 3) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
       double acc = 0.0;
       if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cXD[k * NX + ec];
-        cG2[e % NN] = acc;
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sXD[k * NX + ec];
+        rec[4 * NN + o] = acc;
       } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += cWF[k * NX + er] * cJ[k * NX + ec];
-        cG4[e % NN] = acc;
+        for (int k = 0; k < NX; ++k) acc += sWF[k * NX + er] * J[k * NX + ec];
+        rec[6 * NN + o] = acc;
       } else {
-        for (int k = 0; k < NX; ++k) acc += cF[er * NX + k] * cWF[k * NX + ec];
-        nF[e % NN] = acc;
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sWF[k * NX + ec];
+        nrec[o] = acc;
       }
     }
     wave_sync();
     if (part < 2) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+      const double* G2 = rec + 4 * NN;
+      const double* G4 = rec + 6 * NN;
       double acc = 0.0, acc2 = 0.0;
       if (part == 0) {
         for (int k = 0; k < NX; ++k) {
-          acc += cG2[er * NX + k] * cF[ec * NX + k];
-          acc2 += cG2[ec * NX + k] * cF[er * NX + k];
+          acc += G2[er * NX + k] * F[ec * NX + k];
+          acc2 += G2[ec * NX + k] * F[er * NX + k];
         }
-        nD[e % NN] = 0.5 * (acc + acc2) + cD[e % NN];
+        nrec[NN + o] = 0.5 * (acc + acc2) + D[o];
       } else {
         for (int k = 0; k < NX; ++k) {
-          acc += cG4[er * NX + k] * cF[k * NX + ec];
-          acc2 += cG4[ec * NX + k] * cF[k * NX + er];
+          acc += G4[er * NX + k] * F[k * NX + ec];
+          acc2 += G4[ec * NX + k] * F[k * NX + er];
         }
-        nJ[e % NN] = 0.5 * (acc + acc2) + cJ[e % NN];
+        nrec[2 * NN + o] = 0.5 * (acc + acc2) + J[o];
       }
     }
-    T* dst = cst + lay.lev + p * lay.lev_stride;
-    for (int q = e; q < 7 * NN; q += 64) {
-      const int which = q / NN, o = q % NN, r = o / NX, c = o % NX;
-      double v;
-      switch (which) {
-        case 0: v = cF[o]; dst[lay.o_F + o] = (T)v; break;
-        case 1: v = cD[o]; dst[lay.o_D + o] = (T)v; break;
-        case 2: v = cJ[o]; dst[lay.o_J + o] = (T)v; break;
-        case 3: v = cG1[o]; dst[lay.o_G1 + o] = (T)v; break;
-        case 4: v = cG2[o]; dst[lay.o_G2 + o] = (T)v; break;
-        case 5: v = cWF[c * NX + r]; dst[lay.o_G3 + o] = (T)v; break;
-        default: v = cG4[o]; dst[lay.o_G4 + o] = (T)v; break;
-      }
-    }
+    T* dst = cst + lay.lev + p * lay.lev_stride;  // the level record, as laid out in LDS
+    for (int q = e; q < 7 * NN; q += 64) dst[q] = (T)rec[q];
     wave_sync();
-    double* t;
-    t = cF; cF = nF; nF = t;
-    t = cD; cD = nD; nD = t;
-    t = cJ; cJ = nJ; nJ = t;
+    double* t = rec;
+    rec = nrec;
+    nrec = t;
   }
   if (lflag && info) atomicOr(info, lflag);
 }
@@ -970,6 +987,19 @@ k_fwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, co
       d[r] = (t0 < nt) ? tagg[t0 * 2 * NX + r] : T(0);
       e[r] = (t0 < nt) ? tagg[t0 * 2 * NX + NX + r] : T(0);
     }
+  } else if (c == 2) {  // two runs of 2^LOG_TILE windows: vector parts only
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      d[r] = (t0 + 1 < nt) ? tagg[(t0 + 1) * 2 * NX + r] : T(0);
+      e[r] = (t0 + 1 < nt) ? tagg[(t0 + 1) * 2 * NX + NX + r] : T(0);
+    }
+    T di[NX], ei[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      di[r] = (t0 < nt) ? tagg[t0 * 2 * NX + r] : T(0);
+      ei[r] = (t0 < nt) ? tagg[t0 * 2 * NX + NX + r] : T(0);
+    }
+    level_vec_combine(M.level(LOG_TILE), M.lay, di, ei, d, e);
   } else {  // fold the chunk with full combines (tiles past the end carry zero vectors)
     const T* lv = M.level(LOG_TILE);
     FElem<T, NX> acc, b;
@@ -1086,42 +1116,64 @@ k_fwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, co
   if (flag && info) atomicOr(info, flag);
 }
 
-// K5 (Kogge-Stone form, nt <= KS): reverse tile-level scan, one tile per thread in reversed
-// order (thread r holds tile nt-1-r). Step s: thread r merges its run with the later run
-// held by thread r - s (eq. op-smoother: earlier (x) later). Every run reaching the last
-// window has E = 0, i.e. is the smoothed state at its first window.
+// K5 (Kogge-Stone form): reverse tile-level scan in one workgroup of KS threads. Thread r
+// holds the aggregate of its chunk of 2^lchunk consecutive tiles, counted from the end
+// (thread 0 holds the last tiles), folded under eq. op-smoother (earlier (x) later). Step s:
+// thread r merges its run with the later run held by thread r - s. Every run reaching the
+// last window has E = 0, i.e. is the smoothed state at its first window; thread r then walks
+// its chunk backwards from the state after it, writing per tile the smoothed state of the
+// first window after the tile (zero after the last tile).
+template <typename T, int NX>
+SRTM_DEV void ld_selem_global(const T* __restrict__ src, SElem<T, NX>& x) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    x.g[i] = src[NN + i];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      x.E[i][c] = src[i * NX + c];
+      x.S[i][c] = src[NN + NX + i * NX + c];
+    }
+  }
+}
+
+template <typename T, int NX>
+SRTM_DEV void selem_identity(SElem<T, NX>& x) {
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    x.g[i] = T(0);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      x.E[i][c] = (i == c) ? T(1) : T(0);
+      x.S[i][c] = T(0);
+    }
+  }
+}
+
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(KS)
-k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
+k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, T* __restrict__ tstate) {
   constexpr int NN = NX * NX, SE = 2 * NN + NX, ST = NX + NN;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
   const int tid = threadIdx.x;
+  const int64_t c = int64_t(1) << lchunk;
+  const int64_t thi = nt - 1 - tid * c;  // the chunk is tiles thi - c + 1 .. thi (those >= 0)
   SElem<T, NX> x;
-  if (tid < nt) {
-    const T* src = tagg + (nt - 1 - tid) * SE;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      x.g[i] = src[NN + i];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        x.E[i][c] = src[i * NX + c];
-        x.S[i][c] = src[NN + NX + i * NX + c];
-      }
+  if (thi >= 0) {
+    ld_selem_global(tagg + thi * SE, x);
+#pragma unroll 1
+    for (int64_t t = thi - 1; t > thi - c && t >= 0; --t) {
+      SElem<T, NX> a;
+      ld_selem_global(tagg + t * SE, a);
+      selem_combine(a, x, x);
     }
   } else {
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      x.g[i] = T(0);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        x.E[i][c] = (i == c) ? T(1) : T(0);
-        x.S[i][c] = T(0);
-      }
-    }
+    selem_identity(x);
   }
 #pragma unroll 1
-  for (int s = 1; s < nt; s *= 2) {
+  for (int q = 0; q < steps; ++q) {
+    const int s = 1 << q;
     st_selem(S, tid, x);
     __syncthreads();
     SElem<T, NX> later;
@@ -1131,16 +1183,39 @@ k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
   }
   st_selem(S, tid, x);
   __syncthreads();
-  if (tid < nt) {
-    const int64_t t = nt - 1 - tid;
-    SElem<T, NX> nxt;
-    if (tid > 0) ld_selem(S, tid - 1, nxt);
+  if (thi >= 0) {
+    T m[NX], P[NX][NX];
+    if (tid > 0) {
+      SElem<T, NX> nxt;
+      ld_selem(S, tid - 1, nxt);
 #pragma unroll
-    for (int i = 0; i < NX; ++i) tstate[t * ST + i] = (tid > 0) ? nxt.g[i] : T(0);
+      for (int i = 0; i < NX; ++i) {
+        m[i] = nxt.g[i];
 #pragma unroll
-    for (int i = 0; i < NX; ++i)
+        for (int cc = 0; cc < NX; ++cc) P[i][cc] = nxt.S[i][cc];
+      }
+    } else {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + i * NX + c] = (tid > 0) ? nxt.S[i][c] : T(0);
+      for (int i = 0; i < NX; ++i) {
+        m[i] = T(0);
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) P[i][cc] = T(0);
+      }
+    }
+#pragma unroll 1
+    for (int64_t t = thi; t > thi - c && t >= 0; --t) {
+#pragma unroll
+      for (int i = 0; i < NX; ++i) tstate[t * ST + i] = m[i];
+#pragma unroll
+      for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) tstate[t * ST + NX + i * NX + cc] = P[i][cc];
+      if (t - 1 > thi - c && t - 1 >= 0) {
+        SElem<T, NX> a;
+        ld_selem_global(tagg + t * SE, a);
+        sstate_combine(a, m, P);
+      }
+    }
   }
 }
 
@@ -1404,23 +1479,6 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
 }
 
 // ============================================================================ backward
-// Reversed in-place up-sweep: slot r holds window (tile end - r); combining slot j - s
-// (later windows) with slot j (earlier windows) gives  a_j (x) a_{j-s}.
-template <typename T, int NX>
-SRTM_DEV void bwd_upsweep(const Slots<T>& S, int tid, int n) {
-#pragma unroll 1
-  for (int s = 1; s < n; s *= 2) {
-    if (((tid + 1) & (2 * s - 1)) == 0) {
-      SElem<T, NX> later, earlier;
-      ld_selem(S, tid - s, later);
-      ld_selem(S, tid, earlier);
-      selem_combine(earlier, later, earlier);
-      st_selem(S, tid, earlier);
-    }
-    __syncthreads();
-  }
-}
-
 // K3s (smoother): per tile, the forward down-sweep of K3; then, from the exclusive and
 // inclusive filter states of window k, its smoother element (eq. parallel-ak-smoothing), an
 // in-tile reverse Kogge-Stone scan of those elements under eq. op-smoother, the tile's
@@ -1566,108 +1624,6 @@ k_fwd_bwd(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, 
   if (flag && info) atomicOr(info, flag);
 }
 
-// K5: one workgroup scans the tile aggregates in reverse and writes, per tile, the
-// smoothed state of the first window after it (m^s_{k+1,1}, P^s_{k+1,1}).
-template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TREE)
-k_bwd_tiles(const T* __restrict__ tagg, int64_t nt, T* __restrict__ tstate) {
-  constexpr int NN = NX * NX, SE = 2 * NN + NX, ST = NX + NN;
-  extern __shared__ char smraw[];
-  const Slots<T> S{reinterpret_cast<T*>(smraw), TREE};
-  const int tid = threadIdx.x;
-  const int64_t per = (nt + TREE - 1) / TREE;
-  const int64_t r0 = tid * per;  // reversed tile indices r0 .. r0+per-1 (tile = nt-1-r)
-  SElem<T, NX> acc;
-  bool have = false;
-#pragma unroll 1
-  for (int64_t r = r0; r < r0 + per && r < nt; ++r) {
-    const T* src = tagg + (nt - 1 - r) * SE;
-    SElem<T, NX> b;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      b.g[i] = src[NN + i];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        b.E[i][c] = src[i * NX + c];
-        b.S[i][c] = src[NN + NX + i * NX + c];
-      }
-    }
-    if (have) {
-      selem_combine(b, acc, acc);  // earlier tile (x) later aggregate
-    } else {
-      acc = b;
-      have = true;
-    }
-  }
-  if (!have) {  // identity (I, 0, 0)
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      acc.g[i] = T(0);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        acc.E[i][c] = (i == c) ? T(1) : T(0);
-        acc.S[i][c] = T(0);
-      }
-    }
-  }
-  st_selem(S, tid, acc);
-  __syncthreads();
-  bwd_upsweep<T, NX>(S, tid, TREE);
-  // down-sweep with states; the state after the last window is irrelevant (E_N = 0)
-  if (tid == TREE - 1) {
-    T m[NX], P[NX][NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      m[r] = T(0);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) P[r][c] = T(0);
-    }
-    st_state<T, NX>(S, tid, m, P);
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int s = TREE / 2; s >= 1; s /= 2) {
-    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
-    SElem<T, NX> later;
-    T m[NX], P[NX][NX];
-    if (act) {
-      ld_selem(S, tid - s, later);
-      ld_state<T, NX>(S, tid, m, P);
-    }
-    __syncthreads();
-    if (act) {
-      st_state<T, NX>(S, tid - s, m, P);
-      sstate_combine(later, m, P);
-      st_state<T, NX>(S, tid, m, P);
-    }
-    __syncthreads();
-  }
-  T m[NX], P[NX][NX];
-  ld_state<T, NX>(S, tid, m, P);
-#pragma unroll 1
-  for (int64_t r = r0; r < r0 + per && r < nt; ++r) {
-    const int64_t t = nt - 1 - r;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) tstate[t * ST + i] = m[i];
-#pragma unroll
-    for (int i = 0; i < NX; ++i)
-#pragma unroll
-      for (int c = 0; c < NX; ++c) tstate[t * ST + NX + i * NX + c] = P[i][c];
-    const T* src = tagg + t * SE;
-    SElem<T, NX> b;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      b.g[i] = src[NN + i];
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        b.E[i][c] = src[i * NX + c];
-        b.S[i][c] = src[NN + NX + i * NX + c];
-      }
-    }
-    sstate_combine(b, m, P);
-  }
-}
-
 // K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
 // MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
@@ -1805,7 +1761,7 @@ struct Events {
 size_t constants_lds_bytes(int nx, int ny, int L) {
   const int nn = nx * nx, nxy = nx * ny;
   const int w2s = nn > 2 * nxy ? nn : 2 * nxy;
-  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy) + 16 * nn);
+  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy) + 19 * nn);
 }
 
 #define SRTM_CHECK_LAUNCH()                    \
@@ -1823,8 +1779,9 @@ template <typename T, int NX, int NY, int MODE>
 srtm_status launch_recover(const Ptrs& p, const T* y, int64_t N, int L, int ilim, const T* cst, const T* m0,
                            const T* P0, const T* carry, const T* sfx, const T* tin, hipStream_t st) {
   const size_t lds = (size_t)4 * OutStage<T, NX>::BYTES * ((MODE == 3) ? 2 : 1);
-  if (lds > 65536)
-    hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536 && hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return SRTM_E_HIP;
   const unsigned grid = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL((k_recover<T, NX, NY, MODE>), dim3(grid), dim3(256), lds, st, y, N, L, ilim, cst, m0, P0,
                      carry, sfx, tin, static_cast<T*>(p.mf_fast), static_cast<T*>(p.Pf_fast),
@@ -1851,12 +1808,12 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   const T* P0 = static_cast<const T*>(p.P0);
   // Dynamic LDS above 64 KiB must be allowed per kernel before launching.
   auto allow = [](const void* f, size_t bytes) {
-    if (bytes > 65536) hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return bytes <= 65536 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
   };
 
   const ScanPlan plan = make_scan_plan(N);
   const size_t lds0 = constants_lds_bytes(NX, NY, L);
-  allow((const void*)k_constants<T, NX, NY>, lds0);
+  if (!allow((const void*)k_constants<T, NX, NY>, lds0)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(1), dim3(256), lds0, st, static_cast<const T*>(p.F),
                      static_cast<const T*>(p.Q), static_cast<const T*>(p.H), static_cast<const T*>(p.R), L,
@@ -1870,7 +1827,7 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   SRTM_EV(ev.post(st));
 
   const size_t lds_ft = sizeof(T) * (size_t)KS * (NX + NN);
-  allow((const void*)k_fwd_tiles_ks<T, NX, NY>, lds_ft);
+  if (!allow((const void*)k_fwd_tiles_ks<T, NX, NY>, lds_ft)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_fwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_ft, st, ftagg, nt, plan.lchunk, plan.steps,
                      cst, L, m0, P0, ftst, p.info);
@@ -1884,7 +1841,7 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   const bool want_sfast = p.ms_fast || p.Ps_fast;
   const bool want_sslow = p.ms_slow || p.Ps_slow;
   if (!smoother) {
-    allow((const void*)k_fwd_final<T, NX, NY>, lds_ff);
+    if (!allow((const void*)k_fwd_final<T, NX, NY>, lds_ff)) return SRTM_E_HIP;
     SRTM_EV(ev.pre(st));
     hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0,
                        ftst, carry, mf_slow, Pf_slow, p.info);
@@ -1903,23 +1860,18 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   T* btst = reinterpret_cast<T*>(ws + wl.btile_state);
   T* sfx = reinterpret_cast<T*>(ws + wl.sfx);
   const size_t lds_fb = sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN);
-  allow((const void*)k_fwd_bwd<T, NX, NY>, lds_fb);
+  if (!allow((const void*)k_fwd_bwd<T, NX, NY>, lds_fb)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_fb, st, y, N, L, cst, m0, P0, ftst,
                      carry, mf_slow, Pf_slow, btagg, sfx, p.info);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
+  const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
+  if (!allow((const void*)k_bwd_tiles_ks<T, NX, NY>, lds_bk)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  if (nt <= KS) {
-    const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
-    allow((const void*)k_bwd_tiles_ks<T, NX, NY>, lds_bk);
-    hipLaunchKernelGGL((k_bwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_bk, st, btagg, nt, btst);
-  } else {
-    const size_t lds_bt = sizeof(T) * (size_t)TREE * (2 * NN + NX);
-    allow((const void*)k_bwd_tiles<T, NX, NY>, lds_bt);
-    hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(1), dim3(TREE), lds_bt, st, btagg, nt, btst);
-  }
+  hipLaunchKernelGGL((k_bwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_bk, st, btagg, nt, plan.lchunk, plan.steps,
+                     btst);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 

@@ -8,9 +8,8 @@ namespace srtm {
 
 constexpr int TILE = 256;       // windows per workgroup in the per-tile kernels
 constexpr int LOG_TILE = 8;
-constexpr int TREE = 256;       // threads of the tree-form tile-level scans (many tiles)
-constexpr int KS = 512;         // threads of the Kogge-Stone tile-level scans
-constexpr int LOG_KS = 9;
+constexpr int KS = 256;         // threads of the Kogge-Stone tile-level scans
+constexpr int LOG_KS = 8;
 
 inline __host__ __device__ int ceil_log2(int64_t x) {
   int l = 0;
