@@ -76,12 +76,139 @@ def cpu_baseline(model, y, n_windows, max_seconds=30.0):
                        f"with dense windows, one BLAS thread), {dt:.2f} s")
 
 
+def run_batched(args):
+    """256 independent sequences (nx in {2,4,6}, L in {5,10,20}, N log-uniform in [2^8, 2^14],
+    ny = 1): the autotuned batched path against one srtm_smooth call per sequence."""
+    import torch
+    from paper_2410_00627_amd import batching, srtm, workloads as wl
+    dt = torch.float64 if (args.dtype or "f32") == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    specs = wl.batched_specs()
+    problems = []
+    for nx, L, N, seed in specs:
+        m = wl.batched_model(nx, L, seed)
+        y = wl.simulate(m, N, seed + 1)
+        F, Q, H, R, m0, P0 = srtm.model_tensors(m, dev, dt)
+        problems.append((F, Q, H, R, L, m0, P0, torch.as_tensor(y, dtype=torch.float64).to(dev, dt)))
+    fast_states = sum(pr[7].shape[0] * pr[4] for pr in problems)
+    log = []
+    runner = batching.autotune(problems, reps=5, log=log)
+    for _ in range(args.warmup):
+        runner.run()
+    torch.cuda.synchronize()
+    steps = args.steps
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        runner.run()
+    b.record()
+    b.synchronize()
+    t_batch = a.elapsed_time(b) / 1e3 / steps
+    runner.zero_info()
+    runner.run()
+    runner.check()
+    # plain: one srtm_smooth per sequence on one stream, buffers preallocated
+    plain = []
+    for pr in problems:
+        F, Q, H, R, L, m0, P0, y = pr
+        N, nx = y.shape[0], F.shape[0]
+        ws = torch.empty(srtm.workspace_size(nx, 1, L, N, dt, True), device=dev, dtype=torch.uint8)
+        out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+               "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+               "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+               "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
+        plain.append((pr, ws, out, torch.zeros(1, device=dev, dtype=torch.int32)))
+
+    def plain_pass():
+        for pr, ws, out, info in plain:
+            srtm.smooth(*pr, workspace=ws, out=out, info=info, check=False)
+    plain_pass()
+    torch.cuda.synchronize()
+    psteps = max(1, min(steps, 5))
+    a.record()
+    for _ in range(psteps):
+        plain_pass()
+    b.record()
+    b.synchronize()
+    t_plain = a.elapsed_time(b) / 1e3 / psteps
+    # the two paths must agree bitwise (same kernels on the same tiles)
+    same = all(torch.equal(runner.outputs[j][k], plain[j][2][k]) for j in range(len(problems))
+               for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"))
+    line = {"metric": "fast-rate smoothed states/sec (filter+smoother), 256 uneven sequences batched",
+            "value": round(fast_states / t_batch), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
+            "steps": steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+            "config": {"workload": "256 independent sequences, nx in {2,4,6}, ny=1, L in {5,10,20}, "
+                                   "N = round(2^U(8,14)), A=0.99*Haar, Q=0.01I, C Gaussian, R=0.1",
+                       "sequences": len(problems), "fast_states": int(fast_states),
+                       "windows": int(sum(pr[7].shape[0] for pr in problems))},
+            "tuned": runner.describe(), "candidates": log,
+            "plain_per_sequence": {"ms_per_pass": round(t_plain * 1e3, 4),
+                                   "value": round(fast_states / t_plain), "bitwise_equal_to_batched": same},
+            "speedup_vs_plain": round(t_plain / t_batch, 2)}
+    print(json.dumps(line))
+
+
+def run_serving(args):
+    """Requests arriving as a Poisson process (nx=4, ny=2, L=10, N = round(10^U(2,5)) windows,
+    the headline model's construction), served with continuous batching under an HBM budget;
+    reports p50/p99 latency (arrival to observed completion) beside throughput."""
+    import numpy as np
+    import torch
+    from paper_2410_00627_amd import serving, workloads as wl
+    dt = torch.float64 if (args.dtype or "f32") == "f64" else torch.float32
+    torch.cuda.set_device(0)
+    model = wl.random_stable_model(4, 2, 10, 2024, rho=0.99, q=0.01, r=0.05)
+    rng = np.random.default_rng(4040)
+    pools = [wl.simulate(model, 100000, 4100 + j) for j in range(4)]
+    reqs, t = [], 0.0
+    n = int(args.rate * args.serve_seconds)
+    for j in range(n):
+        t += rng.exponential(1.0 / args.rate)
+        N = int(round(10.0 ** rng.uniform(2.0, 5.0)))
+        pool = pools[j % len(pools)]
+        off = int(rng.integers(0, pool.shape[0] - N + 1))
+        reqs.append(serving.Request(rid=j, arrival=t, F=model.A, Q=model.Q, H=model.C, R=model.R, L=10,
+                                    m0=model.m0, P0=model.P0, y=pool[off:off + N]))
+    srv = serving.Server(4, 2, dt, hbm_budget=int(args.hbm_budget_gb * (1 << 30)), streams=args.streams,
+                         max_batch=64, keep_outputs=False)
+    # warm-up: a few requests through the same server (kernels loaded, allocator primed)
+    serving.serve(srv, [serving.Request(rid=-1 - k, arrival=0.0, F=model.A, Q=model.Q, H=model.C, R=model.R,
+                                        L=10, m0=model.m0, P0=model.P0, y=pools[0][:1000]) for k in range(4)])
+    srv.batches_launched = 0
+    st = serving.serve(srv, reqs)
+    line = {"metric": "fast-rate smoothed states/sec served; p50/p99 latency",
+            "value": round(st["fast_states_per_s"]), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+            "config": {"workload": f"Poisson arrivals at {args.rate:g}/s for {args.serve_seconds:g} s, nx=4 ny=2 "
+                                   "L=10, N=round(10^U(2,5)), A=0.99*Haar, Q=0.01I, C Gaussian, R=0.05I",
+                       "requests": st["requests"], "hbm_budget_gb": args.hbm_budget_gb,
+                       "streams": args.streams, "max_batch": 64},
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
+            "max_ms": round(st["max_ms"], 3), "batches": st["batches"],
+            "requests_per_batch": round(st["requests"] / max(st["batches"], 1), 2),
+            "offered_fast_states_per_s": round(st["fast_states"] / args.serve_seconds),
+            "failed_requests": len(st["failed"])}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--workload", choices=["headline", "batched", "serving"], default="headline",
+                    help="headline: one long sequence (default); batched: 256 uneven sequences; "
+                         "serving: Poisson arrivals with continuous batching")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: length of the arrival process")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: arrivals per second")
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0, help="serving: device arena for requests")
+    ap.add_argument("--streams", type=int, default=4, help="serving: concurrent batches")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default=None,
+                    help="default f64 for the headline workload, f32 for the batched one")
     ap.add_argument("--N", type=int, default=None, help="override the number of windows")
     ap.add_argument("--cpu-windows", type=int, default=None, help="windows timed on the CPU (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +220,11 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's multi-GPU sharding is "
                                    "described in the design notes but not built (use --gpus 1)"}))
         sys.exit(2)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "serving":
+        return run_serving(args)
+    args.dtype = args.dtype or "f64"
 
     import numpy as np
     import torch

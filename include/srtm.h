@@ -122,6 +122,67 @@ srtm_status srtm_smooth_profiled(const srtm_shape* shape,
                                  void* workspace, size_t workspace_bytes, int32_t* info,
                                  void* stream, void* const* events, int32_t n_events);
 
+/* ------------------------------------------------------------------ log-likelihood and gradient
+ * Marginal log-likelihood of the measurements, log p(y_{1:N}) = sum_k log N(y_k; C_bar m, S_k)
+ * with the slow-rate filter's one-step prediction of y_k (eq. m-h-k-l; the Gaussian elements
+ * of Sec. IV drop their normalisers, so it is accumulated from the innovations), written to
+ * ll[0]. Workspace: srtm_workspace_size(shape, 0) bytes. */
+srtm_status srtm_loglik(const srtm_shape* shape,
+                        const void* F, const void* Q, const void* H, const void* R,
+                        const void* m0, const void* P0, const void* y,
+                        void* ll, void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
+/* log p(y_{1:N}) and its gradient with respect to F (dF [nx][nx]), Q and R (dQ [nx][nx],
+ * dR [ny][ny]: symmetric-matrix gradients G, i.e. a small symmetric change E of Q changes
+ * ll by tr(G E)).
+ * Computed by Fisher's identity: the expected gradient of the complete-data log-density
+ * under the smoothing distribution, whose second moments (including lag-one cross terms
+ * between consecutive fast states) come from the same forward and reverse scans as
+ * srtm_smooth, recomputed per window rather than stored. Workspace:
+ * srtm_workspace_size(shape, 1) bytes. All outputs are device arrays of the shape's dtype. */
+srtm_status srtm_loglik_grad(const srtm_shape* shape,
+                             const void* F, const void* Q, const void* H, const void* R,
+                             const void* m0, const void* P0, const void* y,
+                             void* ll, void* dF, void* dQ, void* dR,
+                             void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
+/* ------------------------------------------------------------------ many sequences
+ * One sequence of a batch: its own model (F, Q, H, R, m0, P0), measurements y [N][ny],
+ * window length L and output arrays (each may be NULL), all DEVICE pointers of the batch's
+ * dtype with the layouts of srtm_smooth. The sequences of a batch are independent problems
+ * (each is the problem of Sec. III); they share only nx, ny and the dtype. */
+typedef struct {
+  const void *F, *Q, *H, *R, *m0, *P0, *y;
+  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow;
+  int64_t N;
+  int32_t L;
+  int32_t reserved; /* must be 0 */
+} srtm_seq;
+
+/* Plans a batch on the host. Validates every sequence (as srtm_smooth would), then returns
+ * in *table_size the bytes of the batch table, in *workspace_size the device workspace the
+ * batch needs, in *ntiles the number of 256-window tiles over all sequences and in *max_L
+ * the largest window length. When `table` is not NULL and table_bytes >= *table_size, it
+ * also writes the table there (host memory): per sequence a descriptor with its pointers
+ * and its place in the workspace, then the sequence index of every tile. The caller copies
+ * the table unchanged to device memory (16-byte aligned) before srtm_smooth_batch. Any
+ * output pointer may be NULL (other outputs are written as usual). */
+srtm_status srtm_batch_plan(int32_t nx, int32_t ny, int32_t dtype, const srtm_seq* seqs, int32_t nseq,
+                            void* table, size_t table_bytes, size_t* table_size, size_t* workspace_size,
+                            int64_t* ntiles, int32_t* max_L);
+
+/* Smooths every sequence of a planned batch with one set of kernel launches: kernels over
+ * sequences run one workgroup per sequence, kernels over tiles one workgroup per tile of
+ * any sequence, so short and long sequences share the device. Each sequence's results are
+ * bitwise equal to an srtm_smooth call on it alone. `table_host` is the plan's table and
+ * `table_dev` its unchanged copy in device memory (16-byte aligned); the host copy is read
+ * to check the workspace (at least the plan's size, 256-byte aligned) and to size the
+ * launches. `info` holds one device int32 per sequence (zeroed by the caller; may be NULL).
+ * Enqueues kernels only, so the call can be captured in a HIP graph. */
+srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                              const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                              void* stream);
+
 /* Number of kernels one srtm_filter (smoother = 0) or srtm_smooth (smoother = 1) call
  * enqueues, and the name of kernel j of that sequence (static string, or NULL). */
 int32_t srtm_kernel_count(int32_t smoother);

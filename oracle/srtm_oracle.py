@@ -210,3 +210,46 @@ def slow_rate_smoother(A, Q, C, R, L, m0, P0, y):
         ms[k] = mf1 + G1 @ (ms[k + 1] - m_pred)
         Ps[k] = _sym(Pf1 + G1 @ (Ps[k + 1] - P_pred) @ G1.T)
     return ms, Ps
+
+
+def loglik_grad_fd(A, Q, C, R, L, m0, P0, y, h=1e-6):
+    """Central finite differences of the IMKF log-likelihood (imkf) with respect to the model.
+
+    Returns (dA, dQ, dR): dA[i, j] = d loglik / d A[i, j]; Q and R are perturbed as symmetric
+    matrices (entries (i, j) and (j, i) together), and the returned dQ, dR are the symmetric
+    gradients G with d loglik = tr(G E) for a small symmetric change E, i.e. half the paired
+    difference off the diagonal. Step h is relative to max(1, |entry|).
+    """
+    def ll(a, q, r):
+        return imkf(a, q, C, r, L, m0, P0, y)[2]
+
+    A, Q, R = (np.array(x, dtype=float) for x in (A, Q, R))
+    nx, ny = A.shape[0], R.shape[0]
+    dA = np.zeros_like(A)
+    for i in range(nx):
+        for j in range(nx):
+            s = h * max(1.0, abs(A[i, j]))
+            Ap, Am = A.copy(), A.copy()
+            Ap[i, j] += s
+            Am[i, j] -= s
+            dA[i, j] = (ll(Ap, Q, R) - ll(Am, Q, R)) / (2 * s)
+
+    def sym_grad(M, which):
+        n = M.shape[0]
+        G = np.zeros_like(M)
+        for i in range(n):
+            for j in range(i, n):
+                s = h * max(1.0, abs(M[i, j]))
+                Mp, Mm = M.copy(), M.copy()
+                Mp[i, j] += s
+                Mm[i, j] -= s
+                if i != j:
+                    Mp[j, i] += s
+                    Mm[j, i] -= s
+                fp = ll(A, Mp, R) if which == "Q" else ll(A, Q, Mp)
+                fm = ll(A, Mm, R) if which == "Q" else ll(A, Q, Mm)
+                d = (fp - fm) / (2 * s)
+                G[i, j] = G[j, i] = d if i == j else 0.5 * d
+        return G
+
+    return dA, sym_grad(Q, "Q"), sym_grad(R, "R")

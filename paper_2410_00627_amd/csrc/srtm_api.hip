@@ -21,6 +21,10 @@ bool pair_supported(int nx, int ny);
 srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, hipEvent_t const* ev,
                      int nev);
 size_t constants_lds_bytes(int nx, int ny, int L);
+srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
+                           void* ws, int32_t* info, hipStream_t st);
+srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* ll, void* dF, void* dQ, void* dR,
+                         hipStream_t st);
 }  // namespace srtm
 
 namespace {
@@ -102,6 +106,124 @@ srtm_status srtm_smooth_profiled(const srtm_shape* shape, const void* F, const v
   const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
                      mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
   return run_common(shape, p, true, workspace_bytes, stream, events, n_events);
+}
+
+srtm_status srtm_batch_plan(int32_t nx, int32_t ny, int32_t dtype, const srtm_seq* seqs, int32_t nseq,
+                            void* table, size_t table_bytes, size_t* table_size, size_t* workspace_size,
+                            int64_t* ntiles, int32_t* max_L) {
+  if (!seqs || !table_size || !workspace_size || !ntiles || !max_L) return SRTM_E_NULL;
+  if (nseq < 1) return SRTM_E_SHAPE;
+  const size_t esz = dtype == SRTM_F64 ? 8 : 4;
+  int64_t tiles = 0;
+  size_t ws = 0;
+  int32_t lmax = 1;
+  for (int32_t s = 0; s < nseq; ++s) {
+    const srtm_seq& q = seqs[s];
+    const srtm_shape sh{nx, ny, q.L, (srtm_dtype)dtype, q.N};
+    srtm_status st = check_shape(&sh);
+    if (st != SRTM_OK) return st;
+    if (q.reserved != 0) return SRTM_E_SHAPE;
+    if (!q.F || !q.Q || !q.H || !q.R || !q.m0 || !q.P0 || !q.y) return SRTM_E_NULL;
+    const void* all[] = {q.F, q.Q, q.H, q.R, q.m0, q.P0, q.y, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow};
+    for (const void* p : all)
+      if (!aligned(p, 16)) return SRTM_E_ALIGN;
+    tiles += (q.N + srtm::TILE - 1) / srtm::TILE;
+    ws += srtm::align256(srtm::make_work_layout(nx, ny, q.L, q.N, esz, true).total);
+    if (q.L > lmax) lmax = q.L;
+  }
+  if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
+  const size_t map_off = srtm::batch_tile_map_offset(nseq);
+  const size_t need = map_off + (size_t)tiles * sizeof(int32_t);
+  *table_size = need;
+  *workspace_size = ws;
+  *ntiles = tiles;
+  *max_L = lmax;
+  if (!table || table_bytes < need) return SRTM_OK;
+  srtm::SeqDesc* d = static_cast<srtm::SeqDesc*>(table);
+  int32_t* map = reinterpret_cast<int32_t*>(static_cast<char*>(table) + map_off);
+  int64_t t0 = 0;
+  size_t off = 0;
+  for (int32_t s = 0; s < nseq; ++s) {
+    const srtm_seq& q = seqs[s];
+    srtm::SeqDesc e{};
+    e.F = q.F; e.Q = q.Q; e.H = q.H; e.R = q.R; e.m0 = q.m0; e.P0 = q.P0; e.y = q.y;
+    e.ms_fast = q.ms_fast; e.Ps_fast = q.Ps_fast; e.ms_slow = q.ms_slow; e.Ps_slow = q.Ps_slow;
+    e.N = q.N;
+    e.tile0 = t0;
+    e.ws_off = off;
+    e.L = q.L;
+    e.smoother = 1;
+    d[s] = e;
+    const int64_t nt = (q.N + srtm::TILE - 1) / srtm::TILE;
+    for (int64_t t = 0; t < nt; ++t) map[t0 + t] = s;
+    t0 += nt;
+    off += srtm::align256(srtm::make_work_layout(nx, ny, q.L, q.N, esz, true).total);
+  }
+  return SRTM_OK;
+}
+
+srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                              const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                              void* stream) {
+  if (!table_host || !table_dev || !workspace) return SRTM_E_NULL;
+  if (dtype != SRTM_F32 && dtype != SRTM_F64) return SRTM_E_DTYPE;
+  if (nseq < 1) return SRTM_E_SHAPE;
+  if (!srtm::pair_supported(nx, ny)) return SRTM_E_UNSUPPORTED;
+  if (!aligned(table_dev, 16) || !aligned(workspace, 256) || !aligned(info, 4)) return SRTM_E_ALIGN;
+  const size_t esz = dtype == SRTM_F64 ? 8 : 4;
+  const srtm::SeqDesc* d = static_cast<const srtm::SeqDesc*>(table_host);
+  int64_t tiles = 0;
+  int32_t lmax = 1;
+  for (int32_t s = 0; s < nseq; ++s) {
+    const srtm_shape sh{nx, ny, d[s].L, (srtm_dtype)dtype, d[s].N};
+    srtm_status st = check_shape(&sh);
+    if (st != SRTM_OK) return st;
+    if (d[s].tile0 != tiles || d[s].smoother != 1) return SRTM_E_SHAPE;
+    const int32_t* map = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) +
+                                                          srtm::batch_tile_map_offset(nseq));
+    const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;
+    for (int64_t t = 0; t < nt; ++t)
+      if (map[tiles + t] != s) return SRTM_E_SHAPE;
+    const size_t end = d[s].ws_off + srtm::make_work_layout(nx, ny, d[s].L, d[s].N, esz, true).total;
+    if (d[s].ws_off % 256 != 0 || end > workspace_bytes) return SRTM_E_WORKSPACE;
+    tiles += (d[s].N + srtm::TILE - 1) / srtm::TILE;
+    if (d[s].L > lmax) lmax = d[s].L;
+  }
+  if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
+  return srtm::dispatch_batch(nx, ny, dtype, table_dev, nseq, tiles, lmax, workspace, info,
+                              static_cast<hipStream_t>(stream));
+}
+
+static srtm_status lik_common(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                              const void* m0, const void* P0, const void* y, void* ll, void* dF, void* dQ, void* dR,
+                              void* workspace, size_t workspace_bytes, int32_t* info, void* stream, bool grad) {
+  srtm_status s = check_shape(shape);
+  if (s != SRTM_OK) return s;
+  if (!F || !Q || !H || !R || !m0 || !P0 || !y || !ll || !workspace) return SRTM_E_NULL;
+  if (grad && (!dF || !dQ || !dR)) return SRTM_E_NULL;
+  const void* all[] = {F, Q, H, R, m0, P0, y, ll, dF, dQ, dR};
+  for (const void* q : all)
+    if (!aligned(q, 16)) return SRTM_E_ALIGN;
+  if (!aligned(workspace, 256) || !aligned(info, 4)) return SRTM_E_ALIGN;
+  const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
+  if (workspace_bytes < srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, grad).total)
+    return SRTM_E_WORKSPACE;
+  const srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, nullptr, nullptr, workspace, info};
+  return srtm::dispatch_lik(*shape, p, grad, ll, dF, dQ, dR, static_cast<hipStream_t>(stream));
+}
+
+srtm_status srtm_loglik(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                        const void* m0, const void* P0, const void* y, void* ll, void* workspace,
+                        size_t workspace_bytes, int32_t* info, void* stream) {
+  return lik_common(shape, F, Q, H, R, m0, P0, y, ll, nullptr, nullptr, nullptr, workspace, workspace_bytes, info,
+                    stream, false);
+}
+
+srtm_status srtm_loglik_grad(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                             const void* m0, const void* P0, const void* y, void* ll, void* dF, void* dQ, void* dR,
+                             void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
+  return lik_common(shape, F, Q, H, R, m0, P0, y, ll, dF, dQ, dR, workspace, workspace_bytes, info, stream, true);
 }
 
 int32_t srtm_kernel_count(int32_t smoother) {

@@ -273,6 +273,25 @@ SRTM_DEV bool inv_adj(const T (&a)[N][N], T (&b)[N][N]) {
   return det != T(0) && isfinite(id);
 }
 
+// Inverse of a small general matrix: adjugate for N <= 4, Gaussian elimination with partial
+// pivoting against the identity otherwise. Returns false when the matrix is singular.
+template <typename T, int N>
+SRTM_DEV bool inv_small(const T (&a)[N][N], T (&b)[N][N]) {
+  if constexpr (N <= 4) {
+    return inv_adj(a, b);
+  } else {
+    T A[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        A[r][c] = a[r][c];
+        b[r][c] = (r == c) ? T(1) : T(0);
+      }
+    return solve_pp(A, b);
+  }
+}
+
 // Inverse of a symmetric positive-definite matrix (N <= 4: adjugate, exactly symmetrised;
 // larger N: Cholesky). Returns false when the matrix is not numerically positive definite.
 template <typename T, int N>

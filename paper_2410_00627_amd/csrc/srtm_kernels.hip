@@ -68,9 +68,8 @@ SRTM_DEV double cofactor(const double* M, int r, int c) {
 //   C_bar = (C/l) sum_{i=1..l} A^i,  R_x = (1/l) sum_i C c_i + R,  G_bar Q~ M_bar^T = c_l,
 //   Q_bar = Q_ll, A_bar = A^l   (eq. h-k-l-2, eq. y-k-l-2 and eq. a-k-f).
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(256)
-k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
-            const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst, int32_t* info) {
+SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
+                             const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst, int32_t* info) {
   constexpr int NN = NX * NX, NXY = NX * NY;
   constexpr int W2S = (NN > 2 * NXY ? NN : 2 * NXY);
   extern __shared__ double sm[];
@@ -283,28 +282,41 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
   //   G1 = F W, G2 = F W D, G3 = (W F)^T, G4 = (W F)^T J.
   // One lane per matrix entry; W is the adjugate of I + D J over its determinant, with one
   // cofactor per lane.
-  const int e = tid, o = e % NN, er = o / NX, ec = o % NX, part = e / NN;
+  const int e = tid;
   for (int p = 0; p < nlev; ++p) {
     const double* F = rec;
     const double* D = rec + NN;
     const double* J = rec + 2 * NN;
-    if (e < NN) {  // M = I + D J
+    for (int o = e; o < NN; o += 64) {  // M = I + D J
+      const int er = o / NX, ec = o % NX;
       double acc = (er == ec) ? 1.0 : 0.0;
       for (int k = 0; k < NX; ++k) acc += D[er * NX + k] * J[k * NX + ec];
-      sM[e] = acc;
+      sM[o] = acc;
     }
     wave_sync();
-    if (e < NN) sCof[e] = cofactor<NX>(sM, er, ec);
-    wave_sync();
-    if (e < NN) {  // W = adj(M) / det(M), adj(M)[r][c] = C[c][r]
-      double det = 0.0;
-      for (int c = 0; c < NX; ++c) det += sM[c] * sCof[c];
-      const double id = rcp_nr(det);
-      if (e == 0 && !(det != 0.0 && isfinite(id))) lflag |= SRTM_INFO_COMBINE_SINGULAR;
-      sW[e] = sCof[ec * NX + er] * id;
+    if constexpr (NX <= 4) {
+      if (e < NN) sCof[e] = cofactor<NX>(sM, e / NX, e % NX);
+      wave_sync();
+      if (e < NN) {  // W = adj(M) / det(M), adj(M)[r][c] = C[c][r]
+        double det = 0.0;
+        for (int c = 0; c < NX; ++c) det += sM[c] * sCof[c];
+        const double id = rcp_nr(det);
+        if (e == 0 && !(det != 0.0 && isfinite(id))) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+        sW[e] = sCof[(e % NX) * NX + e / NX] * id;
+      }
+    } else {  // larger states: one lane, Gaussian elimination with partial pivoting
+      if (e == 0) {
+        double Mr[NX][NX], Wr[NX][NX];
+        for (int r = 0; r < NX; ++r)
+          for (int c = 0; c < NX; ++c) Mr[r][c] = sM[r * NX + c];
+        if (!inv_small(Mr, Wr)) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+        for (int r = 0; r < NX; ++r)
+          for (int c = 0; c < NX; ++c) sW[r * NX + c] = Wr[r][c];
+      }
     }
     wave_sync();
-    if (part < 3) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
+    for (int q = e; q < 3 * NN; q += 64) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
       double acc = 0.0;
       if (part == 0) {
         for (int k = 0; k < NX; ++k) acc += sW[er * NX + k] * F[k * NX + ec];
@@ -323,7 +335,8 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
       }
     }
     wave_sync();
-    if (part < 3) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
+    for (int q = e; q < 3 * NN; q += 64) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
       double acc = 0.0;
       if (part == 0) {
         for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sXD[k * NX + ec];
@@ -337,7 +350,8 @@ k_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restr
       }
     }
     wave_sync();
-    if (part < 2) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+    for (int q = e; q < 2 * NN; q += 64) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
       const double* G2 = rec + 4 * NN;
       const double* G4 = rec + 6 * NN;
       double acc = 0.0, acc2 = 0.0;
@@ -387,7 +401,7 @@ SRTM_DEV bool state_combine(T (&m)[NX], T (&P)[NX][NX], const T (&F)[NX][NX], co
   mm(P, J, M);
 #pragma unroll
   for (int r = 0; r < NX; ++r) M[r][r] += T(1);
-  const bool ok = inv_adj(M, W);
+  const bool ok = inv_small(M, W);
   T u[NX], Wu[NX], WP[NX][NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -433,7 +447,7 @@ SRTM_DEV bool elem_combine(const FElem<T, NX>& a, const FElem<T, NX>& b, FElem<T
   mm(a.D, b.J, M);
 #pragma unroll
   for (int r = 0; r < NX; ++r) M[r][r] += T(1);
-  const bool ok = inv_adj(M, W);
+  const bool ok = inv_small(M, W);
   T XF[NX][NX], u[NX], Xu[NX], XD[NX][NX];
   mm(W, a.F, XF);
 #pragma unroll
@@ -938,13 +952,13 @@ SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, in
 
 // K1: per-tile aggregate of the vector parts (d, eta) of the filter elements.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TILE)
-k_fwd_reduce(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L, T* __restrict__ tagg) {
+SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L,
+                              T* __restrict__ tagg, int64_t tile) {
   __shared__ T smem[2 * NX * TILE];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const Slots<T> S{smem, TILE};
   const int tid = threadIdx.x;
-  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  const int64_t k = tile * TILE + tid;
   T d[NX], e[NX];
   fwd_element(M, y, k, N, d, e);
 #pragma unroll
@@ -956,7 +970,7 @@ k_fwd_reduce(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int 
   fwd_upsweep(M, S, tid);
   if (tid == TILE - 1) {
 #pragma unroll
-    for (int r = 0; r < 2 * NX; ++r) tagg[blockIdx.x * 2 * NX + r] = S.at(r, TILE - 1);
+    for (int r = 0; r < 2 * NX; ++r) tagg[tile * 2 * NX + r] = S.at(r, TILE - 1);
   }
 }
 
@@ -968,9 +982,9 @@ k_fwd_reduce(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int 
 // with the shared level coefficients. Thread tau then walks its chunk from its exclusive
 // state, writing each tile's incoming state.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(KS)
-k_fwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, const T* __restrict__ cst, int L,
-               const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate, int32_t* info) {
+SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, const T* __restrict__ cst,
+                             int L, const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate,
+                             int32_t* info) {
   constexpr int NN = NX * NX, ST = NX + NN;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
@@ -1151,8 +1165,7 @@ SRTM_DEV void selem_identity(SElem<T, NX>& x) {
 }
 
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(KS)
-k_bwd_tiles_ks(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, T* __restrict__ tstate) {
+SRTM_DEV void bwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, T* __restrict__ tstate) {
   constexpr int NN = NX * NX, SE = 2 * NN + NX, ST = NX + NN;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
@@ -1463,17 +1476,17 @@ SRTM_DEV int store_carry(int64_t k, const T (&m)[NX], const T (&P)[NX][NX], T* _
 
 // K3 (filter only): per tile, the slow-rate carry and the slow-rate filter outputs.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TILE)
-k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
-            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
-            T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info) {
+SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                             const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
+                             T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info,
+                             int64_t tile) {
   constexpr int ST = NX + NX * NX;
   extern __shared__ char smraw[];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
-  const int64_t k = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  const int64_t k = tile * TILE + threadIdx.x;
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, tstate + blockIdx.x * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, tstate + tile * ST, mprev, Pprev, m, P);
   if (k < N) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if (flag && info) atomicOr(info, flag);
 }
@@ -1491,19 +1504,19 @@ k_fwd_final(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst
 //   Et = B^T E',  gt = B^T (g' - A m^f_{k,l}),  St = B^T (S' - P^-) B;
 // all three are zero for the last window, whose smoothed blocks equal the filtered ones.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(TILE)
-k_fwd_bwd(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, const T* __restrict__ m0,
-          const T* __restrict__ P0, const T* __restrict__ ftstate, T* __restrict__ carry, T* __restrict__ m_slow,
-          T* __restrict__ P_slow, T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info) {
+SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                           const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ ftstate,
+                           T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
+                           T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info, int64_t tile) {
   constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
   extern __shared__ char smraw[];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const int tid = threadIdx.x;
-  const int64_t k = (int64_t)blockIdx.x * TILE + tid;
+  const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, ftstate + blockIdx.x * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
 
   SElem<T, NX> x;
@@ -1559,7 +1572,7 @@ k_fwd_bwd(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, 
   st_selem(S, tid, x);
   __syncthreads();
   if (tid == 0) {
-    T* dst = btagg + blockIdx.x * SE;
+    T* dst = btagg + tile * SE;
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       dst[NN + r] = x.g[r];
@@ -1630,12 +1643,11 @@ k_fwd_bwd(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, 
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
 template <typename T, int NX, int NY, int MODE>
-__global__ void __launch_bounds__(256)
-k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
-          const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
-          const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast, T* __restrict__ Pf_fast,
-          T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow,
-          T* __restrict__ Ps_slow, int32_t* info) {
+SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
+                           const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+                           const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast,
+                           T* __restrict__ Pf_fast, T* __restrict__ ms_fast, T* __restrict__ Ps_fast,
+                           T* __restrict__ ms_slow, T* __restrict__ Ps_slow, int32_t* info, int64_t tile) {
   constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX);
   static_assert(TILE == 256, "one recovery workgroup per tile");
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
@@ -1643,8 +1655,8 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   extern __shared__ char smraw[];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t k = (int64_t)blockIdx.x * 256 + tid;
-  const int64_t w0 = (int64_t)blockIdx.x * 256 + wv * 64;
+  const int64_t k = tile * TILE + tid;
+  const int64_t w0 = tile * TILE + wv * 64;
   const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
   const Stg fst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
   const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
@@ -1659,7 +1671,7 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   T v[NX], W[NX][NX];
   if (SMOOTH) {  // v = Et m_in + gt,  W = Et P_in Et^T + St
     const T* src = sfx + kc * SF;
-    const T* ti = tin + (int64_t)blockIdx.x * ST;
+    const T* ti = tin + tile * ST;
     T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
     load(Et, src);
     loadv(mi, ti);
@@ -1733,6 +1745,526 @@ k_recover(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restri
   if (flag && info) atomicOr(info, flag);
 }
 
+// ============================================================================ log-likelihood and gradient
+// Marginal log-likelihood log p(y_{1:N}) = sum_k log N(y_k; C_bar m^f_{k-1,l}, S_k) (the IMKF
+// prediction of y_k, eq. m-h-k-l), and its gradient with respect to F, Q and R by Fisher's
+// identity: the gradient of log p(y | theta) is the expectation, under the smoothing
+// distribution p(x_{0:Nl} | y_{1:N}), of the gradient of the complete-data log-density
+//   log p(x_0) + sum_t log N(x_t; F x_{t-1}, Q) + sum_k log N(y_k; (H/l) sum_i x_{k,i}, R).
+// With T = N l transitions and the smoothed sums S11 = sum_{t>=1} E[x_t x_t^T],
+// S10 = sum_{t>=1} E[x_t x_{t-1}^T], S00 = E[x_0 x_0^T] + S11 - E[x_T x_T^T] and
+// SY = sum_k E[(y_k - H xbar_k)(y_k - H xbar_k)^T]:
+//   dll/dF = Q^{-1} (S10 - F S00),
+//   dll/dQ = 1/2 Q^{-1} (S11 - F S10^T - S10 F^T + F S00 F^T - T Q) Q^{-1},
+//   dll/dR = 1/2 R^{-1} (SY - N R) R^{-1}
+// (symmetric-matrix gradients for Q and R: dll = tr(G dQ) for symmetric dQ).
+//
+// Per-tile record (float64): ll, S11, S10, SY summed over the tile's windows, and in the
+// records of the first and last tiles E[x_0 x_0^T] and E[x_T x_T^T].
+template <int NX, int NY>
+struct StatLayout {
+  static constexpr int NN = NX * NX;
+  static constexpr int LL = 0, S11 = 1, S10 = 1 + NN, SY = 1 + 2 * NN, X0 = 1 + 2 * NN + NY * NY,
+                       XT = X0 + NN, SIZE = XT + NN;
+};
+
+template <typename T, int N>
+SRTM_DEV T det_small(const T (&a)[N][N]) {
+  static_assert(N >= 1 && N <= 2, "det_small: N <= 2");
+  if constexpr (N == 1)
+    return a[0][0];
+  else
+    return a[0][0] * a[1][1] - a[0][1] * a[1][0];
+}
+
+// Wave-wide sum (fixed butterfly order, identical on every lane).
+SRTM_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, int NX, int NY, bool GRAD>
+SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                         const T* __restrict__ Rm, const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+                         const T* __restrict__ sfx, const T* __restrict__ tin, double* __restrict__ parts,
+                         int32_t* info, int64_t tile, int64_t nt) {
+  using SL = StatLayout<NX, NY>;
+  constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX), NR = SL::X0;  // reduced components
+  __shared__ double red[TILE / 64][NR];
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t k = tile * TILE + tid;
+  const bool valid = k < N;
+  const int64_t kc = valid ? k : 0;
+  double* part = parts + tile * SL::SIZE;
+  T m[NX], P[NX][NX], yk[NY];
+  load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
+  loadv(yk, y + kc * NY);
+  Window<T, NX, NY> w;
+  int flag = 0;
+  if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  T e[NY];
+  double ll;
+  {
+    T Cb[NY][NX];
+    load(Cb, M.cst + M.lay.Cbar);
+    double quad = 0.0;
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+      T s = yk[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) s = my_fma(-Cb[r][c], m[c], s);
+      e[r] = s;
+      quad += (double)s * (double)w.Se[r];
+    }
+    const double logdetS = -log((double)det_small(w.Si));
+    ll = -0.5 * (quad + logdetS + NY * 1.8378770664093453);  // log(2 pi)
+  }
+  T S11[NX][NX], S10[NX][NX], SY[NY][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) S11[r][c] = S10[r][c] = T(0);
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) SY[r][c] = T(0);
+  if constexpr (GRAD) {
+    // (v, W) of the smoother correction, from the window's record and its tile's incoming state
+    T v[NX], W[NX][NX];
+    {
+      const T* src = sfx + kc * SF;
+      const T* ti = tin + tile * ST;
+      T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
+      load(Et, src);
+      loadv(mi, ti);
+      load(Pi, ti + NX);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = src[NN + r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
+        v[r] = t;
+      }
+      mm(Et, Pi, EP);
+      int o = NN + NX;
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = src[o++];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
+          W[r][c] = t;
+          W[c][r] = t;
+        }
+    }
+    T A[NX][NX];
+    load(A, M.cst + M.lay.A);
+    T Pprev[NX][NX], PLprev[NX][NX], Uprev[NX][NY], msprev[NX];
+#pragma unroll 1
+    for (int i = 1; i <= L; ++i) {
+      T mf[NX], Pii[NX][NX], PiL[NX][NX];
+      window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
+      T ms[NX], Ps[NX][NX], PLW[NX][NX];
+      mm(PiL, W, PLW);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T s = mf[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
+        ms[r] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = Pii[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(PLW[r][q], PiL[c][q], t);
+          Ps[r][c] = t;
+          Ps[c][r] = t;
+        }
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) S11[r][c] += my_fma(ms[r], ms[c], Ps[r][c]);
+      // U_i = A^i V + c_i (the cross-covariance of x_{k,i} with y_k given y_{1:k-1})
+      const T* pi = M.per_i(i);
+      T Ui[NX][NY];
+      {
+        T Ai[NX][NX], ci[NX][NY];
+        load(Ai, pi + M.lay.o_Ai);
+        load(ci, pi + M.lay.o_ci);
+        mm(Ai, w.V, Ui);
+#pragma unroll
+        for (int r = 0; r < NX; ++r)
+#pragma unroll
+          for (int c = 0; c < NY; ++c) Ui[r][c] += ci[r][c];
+      }
+      if (i == 1) {
+        // across the window boundary: x_{k-1,l} (or x_0) given x_{k,1} has the one-step smoother
+        // gain G = P A^T (A P A^T + Q)^{-1}, with (m, P) the filter state of x_{k-1,l}
+        T Qq[NX][NX], Pm[NX][NX], Pmi[NX][NX], PA[NX][NX], G[NX][NX];
+        load(Qq, M.cst + M.lay.Q);
+        sandwich(A, P, Qq, Pm);
+        if (!spd_inv(Pm, Pmi) && valid) flag |= SRTM_INFO_PRED_SINGULAR;
+        mm_nt(P, A, PA);
+        mm(PA, Pmi, G);
+        T Am[NX], dm[NX], mb[NX];
+        mv(A, m, Am);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) dm[r] = ms[r] - Am[r];
+        mv(G, dm, mb);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) mb[r] += m[r];   // E[x_{k-1,l} | y_{1:N}]
+        T PsG[NX][NX];
+        mm_nt(Ps, G, PsG);
+#pragma unroll
+        for (int r = 0; r < NX; ++r)
+#pragma unroll
+          for (int c = 0; c < NX; ++c) S10[r][c] += my_fma(ms[r], mb[c], PsG[r][c]);
+        if (valid && k == 0) {  // E[x_0 x_0^T] = P0 + G (P^s_{1,1} - P^-) G^T + mb mb^T
+          T D[NX][NX], GD[NX][NX];
+#pragma unroll
+          for (int r = 0; r < NX; ++r)
+#pragma unroll
+            for (int c = 0; c < NX; ++c) D[r][c] = Ps[r][c] - Pm[r][c];
+          mm(G, D, GD);
+#pragma unroll
+          for (int r = 0; r < NX; ++r)
+#pragma unroll
+            for (int c = 0; c < NX; ++c) {
+              T t = my_fma(mb[r], mb[c], P[r][c]);
+#pragma unroll
+              for (int q = 0; q < NX; ++q) t = my_fma(GD[r][q], G[c][q], t);
+              part[SL::X0 + r * NX + c] = (double)t;
+            }
+        }
+      } else {
+        // within the window: Cov(x_{k,i}, x_{k,i-1} | y_{1:k}) = A P^f_{i-1,i-1} + (A c_{i-1} - c_i) S^{-1} U_{i-1}^T,
+        // plus the smoothing term P^f_{i,l} W P^f_{i-1,l}^T
+        T Dc[NX][NY], SU[NY][NX], C[NX][NX];
+        {
+          T cp[NX][NY], ci[NX][NY];
+          load(cp, M.per_i(i - 1) + M.lay.o_ci);
+          load(ci, pi + M.lay.o_ci);
+          mm(A, cp, Dc);
+#pragma unroll
+          for (int r = 0; r < NX; ++r)
+#pragma unroll
+            for (int c = 0; c < NY; ++c) Dc[r][c] -= ci[r][c];
+        }
+#pragma unroll
+        for (int r = 0; r < NY; ++r)
+#pragma unroll
+          for (int c = 0; c < NX; ++c) {
+            T t = T(0);
+#pragma unroll
+            for (int q = 0; q < NY; ++q) t = my_fma(symget(w.Si, r, q), Uprev[c][q], t);
+            SU[r][c] = t;
+          }
+        mm(A, Pprev, C);
+#pragma unroll
+        for (int r = 0; r < NX; ++r)
+#pragma unroll
+          for (int c = 0; c < NX; ++c) {
+            T t = C[r][c];
+#pragma unroll
+            for (int q = 0; q < NY; ++q) t = my_fma(Dc[r][q], SU[q][c], t);
+#pragma unroll
+            for (int q = 0; q < NX; ++q) t = my_fma(PLW[r][q], PLprev[c][q], t);
+            S10[r][c] += my_fma(ms[r], msprev[c], t);
+          }
+      }
+      if (valid && k == N - 1 && i == L) {  // E[x_T x_T^T]
+#pragma unroll
+        for (int r = 0; r < NX; ++r)
+#pragma unroll
+          for (int c = 0; c < NX; ++c) part[SL::XT + r * NX + c] = (double)my_fma(ms[r], ms[c], Ps[r][c]);
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        msprev[r] = ms[r];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          Pprev[r][c] = Pii[r][c];
+          PLprev[r][c] = PiL[r][c];
+        }
+#pragma unroll
+        for (int c = 0; c < NY; ++c) Uprev[r][c] = Ui[r][c];
+      }
+    }
+    // measurement statistic: y_k - H xbar = R S^{-1} e - Z v, Cov = R - R S^{-1} R + Z W Z^T, Z = R S^{-1} U_l^T
+    {
+      T R[NY][NY], RSi[NY][NY], Z[NY][NX], d[NY], ZW[NY][NX];
+      load(R, Rm);
+      mm(R, w.Si, RSi);
+      mm(R, w.Y2, Z);
+      mm(Z, W, ZW);
+#pragma unroll
+      for (int r = 0; r < NY; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int q = 0; q < NY; ++q) s = my_fma(RSi[r][q], e[q], s);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) s = my_fma(-Z[r][q], v[q], s);
+        d[r] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < NY; ++r)
+#pragma unroll
+        for (int c = 0; c < NY; ++c) {
+          T t = my_fma(d[r], d[c], R[r][c]);
+#pragma unroll
+          for (int q = 0; q < NY; ++q) t = my_fma(-RSi[r][q], R[q][c], t);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(ZW[r][q], Z[c][q], t);
+          SY[r][c] = t;
+        }
+    }
+  }
+  // tile sums of the reduced components (fixed order: butterfly per wave, then waves 0..3)
+  auto comp = [&](int c) -> double {
+    if (!valid) return 0.0;
+    if (c == SL::LL) return ll;
+    if (c < SL::S10) return (double)S11[(c - SL::S11) / NX][(c - SL::S11) % NX];
+    if (c < SL::SY) return (double)S10[(c - SL::S10) / NX][(c - SL::S10) % NX];
+    return (double)SY[(c - SL::SY) / NY][(c - SL::SY) % NY];
+  };
+  const int ncomp = GRAD ? NR : 1;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    if (c >= ncomp) break;
+    const double s = wave_sum(comp(c));
+    if (lane == 0) red[wv][c] = s;
+  }
+  __syncthreads();
+  for (int c = tid; c < ncomp; c += blockDim.x) {
+    double s = red[0][c];
+    for (int q = 1; q < TILE / 64; ++q) s += red[q][c];
+    part[c] = s;
+  }
+  (void)nt;
+  if (flag && info) atomicOr(info, flag);
+}
+
+// One workgroup per sequence: sums the tile records in a fixed order and forms the outputs.
+template <typename T, int NX, int NY, bool GRAD>
+SRTM_DEV void stats_final_body(int64_t N, int L, int64_t nt, const T* __restrict__ Fm, const T* __restrict__ Qm,
+                               const T* __restrict__ Rm, const double* __restrict__ parts, T* __restrict__ ll_out,
+                               T* __restrict__ dF, T* __restrict__ dQ, T* __restrict__ dR, int32_t* info) {
+  using SL = StatLayout<NX, NY>;
+  constexpr int NN = NX * NX, NR = SL::X0, G = 16;
+  __shared__ double red[256][G];
+  __shared__ double tot[NR];
+  const int tid = threadIdx.x;
+  const int ncomp = GRAD ? NR : 1;
+  for (int c0 = 0; c0 < ncomp; c0 += G) {
+    double acc[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) acc[j] = 0.0;
+    for (int64_t t = tid; t < nt; t += 256) {  // lane tid: tiles tid, tid + 256, ... in order
+      const double* p = parts + t * SL::SIZE + c0;
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (c0 + j < ncomp) acc[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) red[tid][j] = acc[j];
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if (tid < s) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) red[tid][j] += red[tid + s][j];
+      }
+      __syncthreads();
+    }
+    if (tid < G && c0 + tid < ncomp) tot[c0 + tid] = red[0][tid];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  if (ll_out) ll_out[0] = (T)tot[SL::LL];
+  if constexpr (GRAD) {
+    double F[NX][NX], Q[NX][NX], R[NY][NY], Qi[NX][NX], Ri[NY][NY];
+    double S11[NX][NX], S10[NX][NX], S00[NX][NX], SY[NY][NY];
+    const double* first = parts;
+    const double* last = parts + (nt - 1) * SL::SIZE;
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        F[r][c] = (double)Fm[r * NX + c];
+        Q[r][c] = (double)Qm[r * NX + c];
+        S11[r][c] = tot[SL::S11 + r * NX + c];
+        S10[r][c] = tot[SL::S10 + r * NX + c];
+        S00[r][c] = first[SL::X0 + r * NX + c] + S11[r][c] - last[SL::XT + r * NX + c];
+      }
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NY; ++c) {
+        R[r][c] = (double)Rm[r * NY + c];
+        SY[r][c] = tot[SL::SY + r * NY + c];
+      }
+    symmetrize(Q);
+    symmetrize(R);
+    int flag = 0;
+    if (!spd_inv(Q, Qi)) flag |= SRTM_INFO_PRED_SINGULAR;
+    if (!spd_inv(R, Ri)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    const double Tn = (double)N * (double)L;
+    // dF = Q^{-1} (S10 - F S00)
+    double FS00[NX][NX], B[NX][NX], Sig[NX][NX], FS10t[NX][NX], tmp[NX][NX];
+    mm(F, S00, FS00);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) B[r][c] = S10[r][c] - FS00[r][c];
+    mm(Qi, B, tmp);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) dF[r * NX + c] = (T)tmp[r][c];
+    // Sig = S11 - F S10^T - S10 F^T + F S00 F^T - T Q
+    mm_nt(F, S10, FS10t);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) {
+        double t = S11[r][c] - FS10t[r][c] - FS10t[c][r] - Tn * Q[r][c];
+        for (int q = 0; q < NX; ++q) t += FS00[r][q] * F[c][q];
+        Sig[r][c] = t;
+      }
+    symmetrize(Sig);
+    double QS[NX][NX], G2[NX][NX];
+    mm(Qi, Sig, QS);
+    mm(QS, Qi, G2);
+    symmetrize(G2);
+    for (int r = 0; r < NX; ++r)
+      for (int c = 0; c < NX; ++c) dQ[r * NX + c] = (T)(0.5 * G2[r][c]);
+    double SR[NY][NY], RS[NY][NY], GR[NY][NY];
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NY; ++c) SR[r][c] = SY[r][c] - (double)N * R[r][c];
+    symmetrize(SR);
+    mm(Ri, SR, RS);
+    mm(RS, Ri, GR);
+    symmetrize(GR);
+    for (int r = 0; r < NY; ++r)
+      for (int c = 0; c < NY; ++c) dR[r * NY + c] = (T)(0.5 * GR[r][c]);
+    if (flag && info) atomicOr(info, flag);
+  }
+  (void)NN;
+}
+
+// ============================================================================ kernels
+// Every kernel takes the call's Batch. Kernels over sequences run one workgroup per sequence;
+// kernels over tiles run one workgroup per tile of any sequence.
+template <typename T, int NX, int NY>
+struct Seq {  // one sequence's typed arrays and scan plan
+  const T *F, *Q, *H, *R, *m0, *P0, *y;
+  T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
+  T *cst, *ftagg, *ftst, *carry, *btagg, *btst, *sfx;
+  double* stats;
+  int64_t N, tile0;
+  int L;
+  ScanPlan plan;
+  int32_t* info;
+};
+
+template <typename T, int NX, int NY>
+SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
+  const SeqDesc d = b.table ? b.table[s] : b.one;
+  Seq<T, NX, NY> q;
+  q.F = static_cast<const T*>(d.F);
+  q.Q = static_cast<const T*>(d.Q);
+  q.H = static_cast<const T*>(d.H);
+  q.R = static_cast<const T*>(d.R);
+  q.m0 = static_cast<const T*>(d.m0);
+  q.P0 = static_cast<const T*>(d.P0);
+  q.y = static_cast<const T*>(d.y);
+  q.ms_fast = static_cast<T*>(d.ms_fast);
+  q.Ps_fast = static_cast<T*>(d.Ps_fast);
+  q.ms_slow = static_cast<T*>(d.ms_slow);
+  q.Ps_slow = static_cast<T*>(d.Ps_slow);
+  q.mf_fast = static_cast<T*>(d.mf_fast);
+  q.Pf_fast = static_cast<T*>(d.Pf_fast);
+  q.mf_slow = static_cast<T*>(d.mf_slow);
+  q.Pf_slow = static_cast<T*>(d.Pf_slow);
+  q.N = d.N;
+  q.tile0 = d.tile0;
+  q.L = d.L;
+  q.plan = make_scan_plan(d.N);
+  const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0);
+  char* base = b.ws + d.ws_off;
+  q.cst = reinterpret_cast<T*>(base + wl.consts);
+  q.ftagg = reinterpret_cast<T*>(base + wl.ftile_agg);
+  q.ftst = reinterpret_cast<T*>(base + wl.ftile_state);
+  q.carry = reinterpret_cast<T*>(base + wl.carry);
+  q.btagg = reinterpret_cast<T*>(base + wl.btile_agg);
+  q.btst = reinterpret_cast<T*>(base + wl.btile_state);
+  q.sfx = reinterpret_cast<T*>(base + wl.sfx);
+  q.stats = reinterpret_cast<double*>(base + wl.stats);
+  q.info = b.info ? b.info + s : nullptr;
+  return q;
+}
+
+SRTM_DEV int tile_sequence(const Batch& b) { return b.tile_seq ? b.tile_seq[blockIdx.x] : 0; }
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(256) k_constants(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.info);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  fwd_reduce_body<T, NX, NY>(q.y, q.N, q.cst, q.L, q.ftagg, (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  fwd_tiles_body<T, NX, NY>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.cst, q.L, q.m0, q.P0, q.ftst,
+                            q.info);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE) k_fwd_final(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  fwd_final_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.info,
+                            (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE) k_fwd_bwd(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  fwd_bwd_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
+                          q.info, (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(KS) k_bwd_tiles(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  bwd_tiles_body<T, NX, NY>(q.btagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.btst);
+}
+
+// MODE 1: filter outputs only; 2: smoother outputs; 3: both. Fast-rate outputs take all L
+// steps; with only the slow smoothed state requested, step 1 suffices.
+template <typename T, int NX, int NY, int MODE>
+__global__ void __launch_bounds__(TILE) k_recover(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
+  if (!fast && !q.ms_slow && !q.Ps_slow) return;
+  recover_body<T, NX, NY, MODE>(q.y, q.N, q.L, fast ? q.L : 1, q.cst, q.m0, q.P0, q.carry, q.sfx, q.btst,
+                                q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
+                                (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY, bool GRAD>
+__global__ void __launch_bounds__(TILE) k_stats(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  stats_body<T, NX, NY, GRAD>(q.y, q.N, q.L, q.cst, q.R, q.m0, q.P0, q.carry, q.sfx, q.btst, q.stats, q.info,
+                              (int64_t)blockIdx.x - q.tile0, q.plan.nt);
+}
+
+template <typename T, int NX, int NY, bool GRAD>
+__global__ void __launch_bounds__(256) k_stats_final(Batch b, T* ll, T* dF, T* dQ, T* dR) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  stats_final_body<T, NX, NY, GRAD>(q.N, q.L, q.plan.nt, q.F, q.Q, q.R, q.stats, ll, dF, dQ, dR, q.info);
+}
+
 // ============================================================================ launchers
 struct Ptrs {
   const void *F, *Q, *H, *R, *m0, *P0, *y;
@@ -1775,121 +2307,162 @@ size_t constants_lds_bytes(int nx, int ny, int L) {
     if ((call) != hipSuccess) return SRTM_E_HIP; \
   } while (0)
 
-template <typename T, int NX, int NY, int MODE>
-srtm_status launch_recover(const Ptrs& p, const T* y, int64_t N, int L, int ilim, const T* cst, const T* m0,
-                           const T* P0, const T* carry, const T* sfx, const T* tin, hipStream_t st) {
-  const size_t lds = (size_t)4 * OutStage<T, NX>::BYTES * ((MODE == 3) ? 2 : 1);
-  if (lds > 65536 && hipFuncSetAttribute((const void*)k_recover<T, NX, NY, MODE>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return SRTM_E_HIP;
-  const unsigned grid = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL((k_recover<T, NX, NY, MODE>), dim3(grid), dim3(256), lds, st, y, N, L, ilim, cst, m0, P0,
-                     carry, sfx, tin, static_cast<T*>(p.mf_fast), static_cast<T*>(p.Pf_fast),
-                     static_cast<T*>(p.ms_fast), static_cast<T*>(p.Ps_fast), static_cast<T*>(p.ms_slow),
-                     static_cast<T*>(p.Ps_slow), p.info);
-  SRTM_CHECK_LAUNCH();
-  return SRTM_OK;
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+
+// Dynamic LDS above 64 KiB must be allowed per kernel before launching.
+inline bool allow_lds(const void* f, size_t bytes) {
+  return bytes <= 65536 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
 }
 
-template <typename T, int NX, int NY>
-srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, Events ev) {
-  constexpr int NN = NX * NX;
-  const int L = sh.L;
-  const int64_t N = sh.N;
-  const int64_t nt = (N + TILE - 1) / TILE;
-  const WorkLayout wl = make_work_layout(NX, NY, L, N, sizeof(T), smoother);
-  char* ws = static_cast<char*>(p.ws);
-  T* cst = reinterpret_cast<T*>(ws + wl.consts);
-  T* ftagg = reinterpret_cast<T*>(ws + wl.ftile_agg);
-  T* ftst = reinterpret_cast<T*>(ws + wl.ftile_state);
-  T* carry = reinterpret_cast<T*>(ws + wl.carry);
-  const T* y = static_cast<const T*>(p.y);
-  const T* m0 = static_cast<const T*>(p.m0);
-  const T* P0 = static_cast<const T*>(p.P0);
-  // Dynamic LDS above 64 KiB must be allowed per kernel before launching.
-  auto allow = [](const void* f, size_t bytes) {
-    return bytes <= 65536 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
-  };
+// Grid shape of one call: `nseq` sequences, `ntiles` tiles in all, the largest window length.
+struct Launch {
+  unsigned nseq;
+  unsigned ntiles;
+  int max_L;
+};
 
-  const ScanPlan plan = make_scan_plan(N);
-  const size_t lds0 = constants_lds_bytes(NX, NY, L);
-  if (!allow((const void*)k_constants<T, NX, NY>, lds0)) return SRTM_E_HIP;
+// What follows the scans: the fast-rate recovery (modes 1-3, see k_recover), the
+// log-likelihood alone (REC_LL, after the forward scan) or the log-likelihood and its gradient
+// (REC_GRAD, after both scans); `lo` receives the latter two.
+constexpr int REC_LL = 4, REC_GRAD = 5;
+template <typename T>
+struct LikOut {
+  T *ll, *dF, *dQ, *dR;
+};
+
+template <typename T, int NX, int NY>
+srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_mode, hipStream_t st, Events ev,
+                       LikOut<T> lo = LikOut<T>{nullptr, nullptr, nullptr, nullptr}) {
+  constexpr int NN = NX * NX;
+  const size_t lds0 = constants_lds_bytes(NX, NY, g.max_L);
+  if (!allow_lds((const void*)k_constants<T, NX, NY>, lds0)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(1), dim3(256), lds0, st, static_cast<const T*>(p.F),
-                     static_cast<const T*>(p.Q), static_cast<const T*>(p.H), static_cast<const T*>(p.R), L,
-                     plan.nlev, cst, p.info);
+  hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(g.nseq), dim3(256), lds0, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), 0, st, y, N, cst, L, ftagg);
+  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY>), dim3(g.ntiles), dim3(TILE), 0, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
   const size_t lds_ft = sizeof(T) * (size_t)KS * (NX + NN);
-  if (!allow((const void*)k_fwd_tiles_ks<T, NX, NY>, lds_ft)) return SRTM_E_HIP;
+  if (!allow_lds((const void*)k_fwd_tiles<T, NX, NY>, lds_ft)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_ft, st, ftagg, nt, plan.lchunk, plan.steps,
-                     cst, L, m0, P0, ftst, p.info);
+  hipLaunchKernelGGL((k_fwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ft, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  T* mf_slow = static_cast<T*>(p.mf_slow);
-  T* Pf_slow = static_cast<T*>(p.Pf_slow);
-  const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
-  const bool want_f = p.mf_fast || p.Pf_fast;
-  const bool want_sfast = p.ms_fast || p.Ps_fast;
-  const bool want_sslow = p.ms_slow || p.Ps_slow;
+  const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES * ((rec_mode == 3) ? 2 : 1);
   if (!smoother) {
-    if (!allow((const void*)k_fwd_final<T, NX, NY>, lds_ff)) return SRTM_E_HIP;
+    const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
+    if (!allow_lds((const void*)k_fwd_final<T, NX, NY>, lds_ff)) return SRTM_E_HIP;
     SRTM_EV(ev.pre(st));
-    hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_ff, st, y, N, L, cst, m0, P0,
-                       ftst, carry, mf_slow, Pf_slow, p.info);
+    hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds_ff, st, b);
     SRTM_CHECK_LAUNCH();
     SRTM_EV(ev.post(st));
     SRTM_EV(ev.pre(st));
-    if (want_f) {
-      srtm_status s = launch_recover<T, NX, NY, 1>(p, y, N, L, L, cst, m0, P0, carry, nullptr, nullptr, st);
-      if (s != SRTM_OK) return s;
+    if (rec_mode == 1) {
+      if (!allow_lds((const void*)k_recover<T, NX, NY, 1>, lds_rec)) return SRTM_E_HIP;
+      hipLaunchKernelGGL((k_recover<T, NX, NY, 1>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+      SRTM_CHECK_LAUNCH();
+    } else if (rec_mode == REC_LL) {
+      hipLaunchKernelGGL((k_stats<T, NX, NY, false>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+      SRTM_CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_stats_final<T, NX, NY, false>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
+                         lo.dR);
+      SRTM_CHECK_LAUNCH();
     }
     SRTM_EV(ev.post(st));
     return SRTM_OK;
   }
 
-  T* btagg = reinterpret_cast<T*>(ws + wl.btile_agg);
-  T* btst = reinterpret_cast<T*>(ws + wl.btile_state);
-  T* sfx = reinterpret_cast<T*>(ws + wl.sfx);
   const size_t lds_fb = sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN);
-  if (!allow((const void*)k_fwd_bwd<T, NX, NY>, lds_fb)) return SRTM_E_HIP;
+  if (!allow_lds((const void*)k_fwd_bwd<T, NX, NY>, lds_fb)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY>), dim3((unsigned)nt), dim3(TILE), lds_fb, st, y, N, L, cst, m0, P0, ftst,
-                     carry, mf_slow, Pf_slow, btagg, sfx, p.info);
+  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds_fb, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
   const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
-  if (!allow((const void*)k_bwd_tiles_ks<T, NX, NY>, lds_bk)) return SRTM_E_HIP;
+  if (!allow_lds((const void*)k_bwd_tiles<T, NX, NY>, lds_bk)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_tiles_ks<T, NX, NY>), dim3(1), dim3(KS), lds_bk, st, btagg, nt, plan.lchunk, plan.steps,
-                     btst);
+  hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_bk, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
   SRTM_EV(ev.pre(st));
-  const int ilim = (want_f || want_sfast) ? L : (want_sslow ? 1 : 0);
-  if (ilim > 0) {
-    srtm_status s = want_f ? launch_recover<T, NX, NY, 3>(p, y, N, L, ilim, cst, m0, P0, carry, sfx, btst, st)
-                           : launch_recover<T, NX, NY, 2>(p, y, N, L, ilim, cst, m0, P0, carry, sfx, btst, st);
-    if (s != SRTM_OK) return s;
+  if (rec_mode == REC_GRAD) {
+    hipLaunchKernelGGL((k_stats<T, NX, NY, true>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+    SRTM_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
+                       lo.dR);
+    SRTM_CHECK_LAUNCH();
+  } else if (rec_mode == 2) {
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 2>, lds_rec)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 2>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+    SRTM_CHECK_LAUNCH();
+  } else if (rec_mode == 3 && lds_rec <= kMaxLdsBytes) {
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 3>, lds_rec)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 3>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+    SRTM_CHECK_LAUNCH();
+  } else if (rec_mode == 3) {  // filter and smoother staging do not fit together: two passes
+    const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES;
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 1>, lds1)) return SRTM_E_HIP;
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 2>, lds1)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 1>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+    SRTM_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 2>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+    SRTM_CHECK_LAUNCH();
   }
   SRTM_EV(ev.post(st));
   return SRTM_OK;
 }
 
+// One sequence (srtm_filter / srtm_smooth).
+template <typename T, int NX, int NY>
+srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, Events ev, int lik_mode = 0,
+                void* ll = nullptr, void* dF = nullptr, void* dQ = nullptr, void* dR = nullptr) {
+  Batch b{};
+  b.table = nullptr;
+  b.tile_seq = nullptr;
+  b.ws = static_cast<char*>(p.ws);
+  b.info = p.info;
+  SeqDesc& d = b.one;
+  d.F = p.F; d.Q = p.Q; d.H = p.H; d.R = p.R; d.m0 = p.m0; d.P0 = p.P0; d.y = p.y;
+  d.ms_fast = p.ms_fast; d.Ps_fast = p.Ps_fast; d.ms_slow = p.ms_slow; d.Ps_slow = p.Ps_slow;
+  d.mf_fast = p.mf_fast; d.Pf_fast = p.Pf_fast; d.mf_slow = p.mf_slow; d.Pf_slow = p.Pf_slow;
+  d.N = sh.N;
+  d.tile0 = 0;
+  d.ws_off = 0;
+  d.L = sh.L;
+  d.smoother = smoother ? 1 : 0;
+  const Launch g{1u, (unsigned)((sh.N + TILE - 1) / TILE), (int)sh.L};
+  const bool want_f = p.mf_fast || p.Pf_fast;
+  const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
+  const int mode = lik_mode ? lik_mode : (smoother ? (want_f ? 3 : (want_s ? 2 : 0)) : (want_f ? 1 : 0));
+  const LikOut<T> lo{static_cast<T*>(ll), static_cast<T*>(dF), static_cast<T*>(dQ), static_cast<T*>(dR)};
+  return launch_all<T, NX, NY>(b, g, smoother, mode, st, ev, lo);
+}
+
+// Many sequences (srtm_smooth_batch): `table` holds nseq descriptors followed by the sequence
+// index of every tile, in device memory.
+template <typename T, int NX, int NY>
+srtm_status run_batch(const void* table, int nseq, int64_t ntiles, int max_L, void* ws, int32_t* info,
+                      hipStream_t st) {
+  Batch b{};
+  b.table = static_cast<const SeqDesc*>(table);
+  b.tile_seq = reinterpret_cast<const int32_t*>(static_cast<const char*>(table) + batch_tile_map_offset(nseq));
+  b.ws = static_cast<char*>(ws);
+  b.info = info;
+  const Launch g{(unsigned)nseq, (unsigned)ntiles, max_L};
+  return launch_all<T, NX, NY>(b, g, true, 2, st, Events{nullptr, 0, 0});
+}
+
 }  // namespace srtm
 
 // ---------------------------------------------------------------- dispatch (C++ linkage)
-#define SRTM_PAIRS(X) X(1, 1) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2)
+#define SRTM_PAIRS(X) X(1, 1) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2) X(6, 1)
 
 namespace srtm {
 bool pair_supported(int nx, int ny) {
@@ -1909,6 +2482,30 @@ srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStre
   }
   SRTM_PAIRS(SRTM_DISP)
 #undef SRTM_DISP
+  return SRTM_E_UNSUPPORTED;
+}
+srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* ll, void* dF, void* dQ, void* dR,
+                         hipStream_t st) {
+  Events E{nullptr, 0, 0};
+#define SRTM_DISPL(a, b)                                                                                  \
+  if (sh.nx == a && sh.ny == b) {                                                                        \
+    if (sh.dtype == SRTM_F64) return run<double, a, b>(sh, p, grad, st, E, grad ? REC_GRAD : REC_LL, ll, dF, dQ, dR); \
+    return run<float, a, b>(sh, p, grad, st, E, grad ? REC_GRAD : REC_LL, ll, dF, dQ, dR);               \
+  }
+  SRTM_PAIRS(SRTM_DISPL)
+#undef SRTM_DISPL
+  return SRTM_E_UNSUPPORTED;
+}
+
+srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
+                           void* ws, int32_t* info, hipStream_t st) {
+#define SRTM_DISPB(a, b)                                                                            \
+  if (nx == a && ny == b) {                                                                        \
+    if (dtype == SRTM_F64) return run_batch<double, a, b>(table, nseq, ntiles, max_L, ws, info, st); \
+    return run_batch<float, a, b>(table, nseq, ntiles, max_L, ws, info, st);                        \
+  }
+  SRTM_PAIRS(SRTM_DISPB)
+#undef SRTM_DISPB
   return SRTM_E_UNSUPPORTED;
 }
 }  // namespace srtm

@@ -72,15 +72,18 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L, 
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, total;
+  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, total;
 };
+
+// Scalars (float64) of one tile's log-likelihood / gradient record.
+inline __host__ __device__ constexpr int stat_size(int nx, int ny) { return 1 + 4 * nx * nx + ny * ny; }
 
 // Per-window smoother-correction record: Et (nx^2), gt (nx), St (upper triangle).
 inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + nx + nx * (nx + 1) / 2; }
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother) {
+inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother) {
   WorkLayout w;
   const ConstLayout c = make_const_layout(nx, ny, L, make_scan_plan(N).nlev);
   const int64_t nt = (N + TILE - 1) / TILE;
@@ -97,8 +100,36 @@ inline WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz,
   } else {
     w.btile_agg = w.btile_state = w.sfx = 0;
   }
+  w.stats = o; o = align256(o + (size_t)nt * stat_size(nx, ny) * sizeof(double));
   w.total = o;
   return w;
+}
+
+// One sequence of a call: device pointers of its model, data and outputs (typed by the call's
+// dtype; outputs nullable), its place in the call's tile numbering and its workspace block.
+struct SeqDesc {
+  const void *F, *Q, *H, *R, *m0, *P0, *y;
+  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
+  int64_t N;
+  int64_t tile0;     // first tile of the sequence among the call's tiles
+  uint64_t ws_off;   // byte offset of the sequence's workspace block (256-byte aligned)
+  int32_t L;
+  int32_t smoother;  // the block holds the smoother regions
+};
+
+// What every kernel receives: either one sequence (`table` null) or a device table of
+// sequences with the sequence index of every tile.
+struct Batch {
+  const SeqDesc* table;
+  const int32_t* tile_seq;
+  char* ws;
+  int32_t* info;  // one status word per sequence, nullable
+  SeqDesc one;
+};
+
+// Byte offset of the tile-to-sequence map behind nseq descriptors in a batch table.
+inline __host__ __device__ size_t batch_tile_map_offset(int nseq) {
+  return (((size_t)nseq * sizeof(SeqDesc)) + 15) & ~size_t(15);
 }
 
 }  // namespace srtm

@@ -30,6 +30,13 @@ class Shape(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("N", ctypes.c_int64)]
 
 
+class SeqC(ctypes.Structure):
+    """srtm_seq: one sequence of a batch (device pointers)."""
+    _fields_ = ([(n, ctypes.c_void_p) for n in ("F", "Q", "H", "R", "m0", "P0", "y",
+                                                 "ms_fast", "Ps_fast", "ms_slow", "Ps_slow")] +
+                [("N", ctypes.c_int64), ("L", ctypes.c_int32), ("reserved", ctypes.c_int32)])
+
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -53,6 +60,18 @@ def lib():
     L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
                                        [ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_int32])
     L.srtm_smooth_profiled.restype = ctypes.c_int
+    L.srtm_batch_plan.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SeqC),
+                                  ctypes.c_int32, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
+                                  ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.srtm_batch_plan.restype = ctypes.c_int
+    L.srtm_smooth_batch.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth_batch.restype = ctypes.c_int
+    L.srtm_loglik.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 9 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_loglik.restype = ctypes.c_int
+    L.srtm_loglik_grad.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_loglik_grad.restype = ctypes.c_int
     L.srtm_kernel_count.argtypes = [ctypes.c_int32]
     L.srtm_kernel_count.restype = ctypes.c_int32
     L.srtm_kernel_name.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -210,6 +229,153 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
         _raise_info(info, "srtm_smooth")
     out["info"] = info
     return out
+
+
+def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool):
+    ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    dev, dt = y.device, y.dtype
+    ll = torch.empty(1, device=dev, dtype=dt)
+    dF = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None
+    dQ = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None
+    dR = torch.empty((ny, ny), device=dev, dtype=dt) if grad else None
+    ws = torch.empty(workspace_size(nx, ny, L, N, dt, grad), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+    sh = shape_of(nx, ny, L, N, dt)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    ins = [_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")]
+    if grad:
+        code = lib().srtm_loglik_grad(ctypes.byref(sh), *ins, _ptr(ll), _ptr(dF), _ptr(dQ), _ptr(dR), _ptr(ws),
+                                      ws.numel(), _ptr(info), stream)
+        _check(code, "srtm_loglik_grad")
+    else:
+        code = lib().srtm_loglik(ctypes.byref(sh), *ins, _ptr(ll), _ptr(ws), ws.numel(), _ptr(info), stream)
+        _check(code, "srtm_loglik")
+    if check:
+        _raise_info(info, "srtm_loglik_grad" if grad else "srtm_loglik")
+    return ll[0], dF, dQ, dR
+
+
+def loglik(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True) -> torch.Tensor:
+    """log p(y_{1:N}) (a 0-d tensor on the device)."""
+    return _lik(F, Q, H, R, L, m0, P0, y, False, check)[0]
+
+
+def loglik_grad(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True):
+    """(log p(y_{1:N}), d/dF, d/dQ, d/dR); the Q and R gradients are symmetric-matrix gradients."""
+    return _lik(F, Q, H, R, L, m0, P0, y, True, check)
+
+
+class LogLikelihood(torch.autograd.Function):
+    """log p(y_{1:N}) as a differentiable function of F, Q and R. The forward pass runs the
+    filter scan only; the backward pass runs both scans again (nothing from the forward pass is
+    stored) and returns the gradient from the library."""
+
+    @staticmethod
+    def forward(ctx, F, Q, R, H, m0, P0, y, L):
+        ctx.save_for_backward(F, Q, R, H, m0, P0, y)
+        ctx.L = int(L)
+        return loglik(F.detach(), Q.detach(), H.detach(), R.detach(), int(L), m0.detach(), P0.detach(), y.detach())
+
+    @staticmethod
+    def backward(ctx, g):
+        F, Q, R, H, m0, P0, y = ctx.saved_tensors
+        _, dF, dQ, dR = loglik_grad(F.detach(), Q.detach(), H.detach(), R.detach(), ctx.L, m0.detach(),
+                                    P0.detach(), y.detach())
+        return g * dF, g * dQ, g * dR, None, None, None, None, None
+
+
+def log_likelihood(F, Q, R, H, L: int, m0, P0, y) -> torch.Tensor:
+    """Differentiable log p(y_{1:N}) with respect to F, Q and R (see LogLikelihood)."""
+    return LogLikelihood.apply(F, Q, R, H, m0, P0, y, L)
+
+
+class Batch:
+    """A planned batch: the host and device copies of the plan's table, the workspace, the
+    per-sequence status words and output tensors. Reusable for repeated calls (and graph
+    capture) on the same inputs."""
+
+    def __init__(self, problems, *, fast: bool = True, slow: bool = True, outputs=None, alloc=None):
+        items = []
+        for pr in problems:
+            F, Q, H, R, L, m0, P0, y = pr
+            ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+            items.append((ts, int(L), N, nx, ny))
+        if not items:
+            raise SrtmError("empty batch")
+        nx, ny = items[0][3], items[0][4]
+        dev, dt = items[0][0]["y"].device, items[0][0]["y"].dtype
+        for ts, L, N, a, b in items:
+            if (a, b) != (nx, ny) or ts["y"].device != dev or ts["y"].dtype != dt:
+                raise SrtmError("all sequences of a batch share nx, ny, device and dtype")
+        self.nx, self.ny, self.dtype, self.device = nx, ny, dt, dev
+        self.inputs = [it[0] for it in items]
+        self.outputs = []
+        arr = (SeqC * len(items))()
+        for j, (ts, L, N, _, _) in enumerate(items):
+            out = {} if outputs is None else outputs[j]
+            if outputs is not None:
+                for k, shp in (("ms_fast", (N, L, nx)), ("Ps_fast", (N, L, nx, nx)), ("ms_slow", (N, nx)),
+                               ("Ps_slow", (N, nx, nx))):
+                    t = out.get(k)
+                    if t is not None and (tuple(t.shape) != shp or t.dtype != dt or t.device != dev or
+                                          not t.is_contiguous()):
+                        raise SrtmError(f"sequence {j}: output {k} must be a contiguous {shp} tensor")
+            elif fast:
+                out["ms_fast"] = torch.empty((N, L, nx), device=dev, dtype=dt)
+                out["Ps_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
+            if outputs is None and slow:
+                out["ms_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
+                out["Ps_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+            self.outputs.append(out)
+            e = arr[j]
+            for k in ("F", "Q", "H", "R", "m0", "P0", "y"):
+                setattr(e, k, ts[k].data_ptr())
+            for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+                setattr(e, k, out[k].data_ptr() if k in out else None)
+            e.N, e.L, e.reserved = N, L, 0
+        self.nseq = len(items)
+        tsz, wsz = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        ntiles, max_L = ctypes.c_int64(0), ctypes.c_int32(0)
+        code = _dtype_code(dt)
+        _check(lib().srtm_batch_plan(nx, ny, code, arr, self.nseq, None, 0, ctypes.byref(tsz), ctypes.byref(wsz),
+                                     ctypes.byref(ntiles), ctypes.byref(max_L)), "srtm_batch_plan")
+        self.table_host = torch.empty(tsz.value, dtype=torch.uint8, pin_memory=True)
+        _check(lib().srtm_batch_plan(nx, ny, code, arr, self.nseq, _ptr(self.table_host), tsz.value,
+                                     ctypes.byref(tsz), ctypes.byref(wsz), ctypes.byref(ntiles),
+                                     ctypes.byref(max_L)), "srtm_batch_plan")
+        # device buffers: from `alloc(nbytes) -> uint8 device tensor` when given (an arena), else torch
+        get = alloc if alloc is not None else (lambda n: torch.empty(n, device=dev, dtype=torch.uint8))
+        self.table_dev = get(tsz.value)
+        self.table_dev.copy_(self.table_host, non_blocking=True)
+        self.workspace = get(max(wsz.value, 256))
+        self.info = get(4 * self.nseq).view(torch.int32)
+        self.info.zero_()
+        self.ntiles, self.max_L = int(ntiles.value), int(max_L.value)
+
+    def launch(self, stream=None):
+        """Enqueue the batch on `stream` (default: the current stream); no allocation, no sync."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().srtm_smooth_batch(self.nx, self.ny, _dtype_code(self.dtype), self.nseq, _ptr(self.table_host),
+                                       _ptr(self.table_dev), _ptr(self.workspace), self.workspace.numel(),
+                                       _ptr(self.info), ctypes.c_void_p(stream)), "srtm_smooth_batch")
+
+    def check(self):
+        v = self.info.cpu()
+        bad = [(j, int(x)) for j, x in enumerate(v.tolist()) if x]
+        if bad:
+            raise SrtmError(f"srtm_smooth_batch: numerical failure in sequences {bad[:8]}")
+
+
+def smooth_batch(problems, *, fast: bool = True, slow: bool = True, check: bool = True):
+    """Smooths many independent sequences (tuples (F, Q, H, R, L, m0, P0, y) of device tensors
+    sharing nx, ny and dtype) with one set of launches; returns one output dict per sequence."""
+    b = Batch(problems, fast=fast, slow=slow)
+    b.info.zero_()
+    b.launch()
+    if check:
+        b.check()
+    return [dict(o, info=b.info[j:j + 1]) for j, o in enumerate(b.outputs)]
 
 
 def model_tensors(model, device="cuda", dtype=torch.float64):

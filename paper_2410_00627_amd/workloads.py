@@ -98,6 +98,24 @@ HEADLINE_N = 1 << 17
 WNA_N = 100
 
 
+def batched_specs(n_seq: int = 256, seed: int = 3030):
+    """Many independent sequences of uneven length: per sequence nx in {2, 4, 6}, L in
+    {5, 10, 20}, N = round(2^U(8, 14)) windows, ny = 1; returns (nx, L, N, model seed) tuples."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for j in range(n_seq):
+        nx = int(rng.choice([2, 4, 6]))
+        L = int(rng.choice([5, 10, 20]))
+        N = int(round(2.0 ** rng.uniform(8.0, 14.0)))
+        out.append((nx, L, N, seed * 1000 + j))
+    return out
+
+
+def batched_model(nx: int, L: int, seed: int) -> Model:
+    """One sequence of the batched workload: A = 0.99 U, Q = 0.01 I, C Gaussian 1 x nx, R = 0.1."""
+    return random_stable_model(nx, 1, L, seed, rho=0.99, q=0.01, r=0.1)
+
+
 def _chol_psd(S: np.ndarray) -> np.ndarray:
     w, V = np.linalg.eigh(S)
     return V * np.sqrt(np.clip(w, 0.0, None))[None, :]

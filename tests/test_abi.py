@@ -71,12 +71,21 @@ def test_workspace_size_errors(L, nx, ny, Lw, N, dtype, code):
 
 
 def test_supported_pairs(L):
-    for nx, ny in [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2)]:
+    for nx, ny in [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (6, 1)]:
         assert L.srtm_supported(nx, ny) == 1
-    assert L.srtm_supported(9, 9) == 0
+    assert L.srtm_supported(9, 9) == 0 and L.srtm_supported(5, 1) == 0
+
+
+def _no_gpu():
+    # These calls pass fake device addresses: they must fail validation on the host, and as a
+    # second line of defence they never run where a GPU could execute a launch.
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-validation test with fake device pointers; skipped where a GPU is visible")
 
 
 def _call(fn, sh, ptrs, ws_bytes, n_out):
+    _no_gpu()
     P = [ctypes.c_void_p(p) if p else None for p in ptrs]
     args = [ctypes.byref(sh)] + P[:7] + [None] * n_out + [P[7], ws_bytes, None, None]
     return fn(*args)
@@ -130,3 +139,82 @@ def test_python_binding_refuses_cpu_tensors():
     y = torch.zeros(5, 1, dtype=torch.float64)
     with pytest.raises(srtm.SrtmError, match="GPU"):
         srtm.smooth(*t[:4], m.L, t[4], t[5], y)
+
+
+# ----------------------------------------------------------------------------- batch plan (host only)
+def _seqs(specs, base=0x100000):
+    """srtm_seq entries with fake, 16-byte aligned addresses (never dereferenced on the host)."""
+    arr = (srtm.SeqC * len(specs))()
+    a = base
+    for j, (N, Lw) in enumerate(specs):
+        e = arr[j]
+        for k in ("F", "Q", "H", "R", "m0", "P0", "y", "ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+            setattr(e, k, a)
+            a += 4096
+        e.N, e.L, e.reserved = N, Lw, 0
+    return arr
+
+
+def _plan(arr, nx=4, ny=2, dtype=1, table=None, nbytes=0):
+    t, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    nt, ml = ctypes.c_int64(0), ctypes.c_int32(0)
+    code = srtm.lib().srtm_batch_plan(nx, ny, dtype, arr, len(arr), table, nbytes, ctypes.byref(t), ctypes.byref(w),
+                                      ctypes.byref(nt), ctypes.byref(ml))
+    return code, t.value, w.value, nt.value, ml.value
+
+
+def test_batch_plan_sizes_and_tile_map(L):
+    specs = [(1, 20), (300, 5), (256, 10), (257, 20), (5000, 3)]
+    arr = _seqs(specs)
+    code, tsz, wsz, nt, ml = _plan(arr)
+    assert code == 0 and ml == 20
+    assert nt == sum((N + 255) // 256 for N, _ in specs)
+    # the workspace is the sum of the per-sequence smoother workspaces (256-byte aligned blocks)
+    assert wsz == sum(((_ws(4, 2, Lw, N)[1] + 255) // 256) * 256 for N, Lw in specs)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    tile_map = (ctypes.c_int32 * nt).from_buffer(buf, tsz - 4 * nt)
+    expect = [j for j, (N, _) in enumerate(specs) for _ in range((N + 255) // 256)]
+    assert list(tile_map) == expect
+    # a table that is too small is not written, and the sizes are still returned
+    small = (ctypes.c_uint8 * 8)()
+    assert _plan(arr, table=ctypes.cast(small, ctypes.c_void_p), nbytes=8)[:2] == (0, tsz)
+    assert bytes(small) == bytes(8)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda a: setattr(a[1], "N", 0), 2),
+    (lambda a: setattr(a[0], "L", 0), 2),
+    (lambda a: setattr(a[2], "reserved", 1), 2),
+    (lambda a: setattr(a[1], "y", None), 1),
+    (lambda a: setattr(a[0], "Ps_fast", 0x100008), 5),
+    (lambda a: setattr(a[2], "L", 1000), 4),
+])
+def test_batch_plan_errors(L, mutate, code):
+    arr = _seqs([(10, 4), (20, 5), (30, 6)])
+    mutate(arr)
+    assert _plan(arr)[0] == code
+
+
+def test_batch_plan_unsupported_pair(L):
+    assert _plan(_seqs([(10, 4)]), nx=9, ny=9)[0] == 4
+
+
+def test_smooth_batch_rejects_small_workspace_and_bad_table(L):
+    _no_gpu()
+    specs = [(300, 5), (600, 7)]
+    arr = _seqs(specs)
+    _, tsz, wsz, nt, _ = _plan(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    fake_dev = ctypes.c_void_p(0x4000000)
+    fake_ws = ctypes.c_void_p(0x8000000)
+    host = ctypes.cast(buf, ctypes.c_void_p)
+    # workspace smaller than planned: rejected before anything is enqueued
+    assert L.srtm_smooth_batch(4, 2, 1, 2, host, fake_dev, fake_ws, wsz - 256, None, None) == 6
+    # a tile map that does not match the descriptors
+    tile_map = (ctypes.c_int32 * nt).from_buffer(buf, tsz - 4 * nt)
+    tile_map[0] = 1
+    assert L.srtm_smooth_batch(4, 2, 1, 2, host, fake_dev, fake_ws, wsz, None, None) == 2
+    assert L.srtm_smooth_batch(4, 2, 1, 2, None, fake_dev, fake_ws, wsz, None, None) == 1
+    assert L.srtm_smooth_batch(4, 2, 1, 2, host, ctypes.c_void_p(0x4000008), fake_ws, wsz, None, None) == 5

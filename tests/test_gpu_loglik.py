@@ -1,0 +1,94 @@
+"""Log-likelihood and its gradient on the GPU (srtm_loglik, srtm_loglik_grad, autograd).
+
+The log-likelihood is compared with the float64 IMKF reference; the gradient with central
+finite differences of that reference (h = 1e-6), including the parameterisation
+theta = (log q, log r, entries of F) with Q = q I and R = r I.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_00627_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _srtm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_00627_amd import srtm
+    srtm.lib()
+    return srtm
+
+
+def _t(a, dtype):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64)).to("cuda", dtype).contiguous()
+
+
+def _rounded(a, dtype):
+    a = np.asarray(a, dtype=np.float64)
+    return a if dtype == torch.float64 else a.astype(np.float32).astype(np.float64)
+
+
+CASES = [(2, 1, 3, 60, 81), (4, 2, 5, 150, 82), (4, 1, 10, 120, 83), (3, 2, 1, 80, 84)]
+
+
+@pytest.mark.parametrize("nx,ny,L,N,seed", CASES, ids=[f"nx{c[0]}ny{c[1]}L{c[2]}N{c[3]}" for c in CASES])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_loglik_and_gradient_against_finite_differences(nx, ny, L, N, seed, dtype):
+    srtm = _srtm()
+    m = wl.random_general_model(nx, ny, L, seed)
+    y = wl.simulate(m, N, seed + 1)
+    args = [_t(x, dtype) for x in (m.A, m.Q, m.C, m.R)] + [L] + [_t(x, dtype) for x in (m.m0, m.P0, y)]
+    print(f"[gpu] loglik_grad nx={nx} ny={ny} L={L} N={N} {dtype}", flush=True)
+    ll, dF, dQ, dR = srtm.loglik_grad(*args)
+    ll_only = srtm.loglik(*args)
+    torch.cuda.synchronize()
+    r = {k: _rounded(v, dtype) for k, v in dict(A=m.A, Q=m.Q, C=m.C, R=m.R, m0=m.m0, P0=m.P0, y=y).items()}
+    ref_ll = oracle.imkf(r["A"], r["Q"], r["C"], r["R"], L, r["m0"], r["P0"], r["y"])[2]
+    tol_ll = 1e-10 if dtype == torch.float64 else 2e-5
+    assert abs(float(ll) - ref_ll) <= tol_ll * max(1.0, abs(ref_ll))
+    assert abs(float(ll_only) - ref_ll) <= tol_ll * max(1.0, abs(ref_ll))
+    gA, gQ, gR = oracle.loglik_grad_fd(r["A"], r["Q"], r["C"], r["R"], L, r["m0"], r["P0"], r["y"])
+    tol = 1e-6 if dtype == torch.float64 else 2e-3
+    for name, got, want in (("F", dF, gA), ("Q", dQ, gQ), ("R", dR, gR)):
+        got = got.double().cpu().numpy()
+        scale = max(1.0, np.max(np.abs(want)))
+        err = np.max(np.abs(got - want)) / scale
+        print(f"[gpu]   d/d{name}: max rel err {err:.2e} (scale {scale:.3g})", flush=True)
+        assert err <= tol, f"d/d{name}: {err:.3e}"
+
+
+def test_autograd_log_parameters_match_finite_differences():
+    """theta = (log q, log r, vec F) with Q = q I, R = r I, through torch.autograd."""
+    srtm = _srtm()
+    nx, ny, L, N = 4, 1, 10, 200
+    m = wl.random_stable_model(nx, ny, L, 91, rho=0.99, q=0.01, r=0.1)
+    y = wl.simulate(m, N, 92)
+    dt = torch.float64
+    logq = torch.tensor(np.log(0.01), dtype=dt, device="cuda", requires_grad=True)
+    logr = torch.tensor(np.log(0.1), dtype=dt, device="cuda", requires_grad=True)
+    F = _t(m.A, dt).requires_grad_(True)
+    eye_x = torch.eye(nx, dtype=dt, device="cuda")
+    eye_y = torch.eye(ny, dtype=dt, device="cuda")
+    ll = srtm.log_likelihood(F, torch.exp(logq) * eye_x, torch.exp(logr) * eye_y, _t(m.C, dt), L, _t(m.m0, dt),
+                             _t(m.P0, dt), _t(y, dt))
+    ll.backward()
+
+    def ref(theta):
+        A = theta[2:].reshape(nx, nx)
+        return oracle.imkf(A, np.exp(theta[0]) * np.eye(nx), m.C, np.exp(theta[1]) * np.eye(ny), L, m.m0, m.P0,
+                           y)[2]
+
+    th = np.concatenate([[np.log(0.01), np.log(0.1)], m.A.ravel()])
+    fd = np.zeros_like(th)
+    for i in range(th.size):
+        e = np.zeros_like(th)
+        e[i] = 1e-6
+        fd[i] = (ref(th + e) - ref(th - e)) / 2e-6
+    got = np.concatenate([[logq.grad.item(), logr.grad.item()], F.grad.cpu().numpy().ravel()])
+    assert abs(ll.item() - ref(th)) <= 1e-10 * abs(ref(th))
+    err = np.max(np.abs(got - fd)) / max(1.0, np.max(np.abs(fd)))
+    print(f"[gpu] autograd theta grad max rel err {err:.2e}", flush=True)
+    assert err <= 1e-6

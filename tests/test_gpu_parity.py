@@ -85,6 +85,7 @@ CASES = [
     (1, 1, 3, 513, 5),
     (2, 2, 1, 700, 6),      # l = 1: Kalman filter + RTS smoother
     (3, 1, 16, 257, 7),
+    (6, 1, 5, 300, 8),      # nx > 4: Gaussian elimination instead of the adjugate
 ]
 
 
