@@ -183,6 +183,14 @@ srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nse
                               const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
                               void* stream);
 
+/* srtm_loglik_grad for every sequence of a planned batch, in one set of launches. Here the
+ * four output pointers of each srtm_seq given to srtm_batch_plan receive that sequence's
+ * ll [1], dF [nx][nx], dQ [nx][nx] and dR [ny][ny] (all four required); everything else is as
+ * in srtm_smooth_batch. */
+srtm_status srtm_loglik_grad_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                                   const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                                   void* stream);
+
 /* Number of kernels one srtm_filter (smoother = 0) or srtm_smooth (smoother = 1) call
  * enqueues, and the name of kernel j of that sequence (static string, or NULL). */
 int32_t srtm_kernel_count(int32_t smoother);

@@ -22,7 +22,7 @@ srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStre
                      int nev);
 size_t constants_lds_bytes(int nx, int ny, int L);
 srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
-                           void* ws, int32_t* info, hipStream_t st);
+                           void* ws, int32_t* info, hipStream_t st, bool grad);
 srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* ll, void* dF, void* dQ, void* dR,
                          hipStream_t st);
 }  // namespace srtm
@@ -162,9 +162,9 @@ srtm_status srtm_batch_plan(int32_t nx, int32_t ny, int32_t dtype, const srtm_se
   return SRTM_OK;
 }
 
-srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
-                              const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
-                              void* stream) {
+static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                                const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                                void* stream, bool grad) {
   if (!table_host || !table_dev || !workspace) return SRTM_E_NULL;
   if (dtype != SRTM_F32 && dtype != SRTM_F64) return SRTM_E_DTYPE;
   if (nseq < 1) return SRTM_E_SHAPE;
@@ -190,8 +190,23 @@ srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nse
     if (d[s].L > lmax) lmax = d[s].L;
   }
   if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
+  if (grad)  // the four output slots receive ll, dF, dQ, dR: all required
+    for (int32_t s = 0; s < nseq; ++s)
+      if (!d[s].ms_fast || !d[s].Ps_fast || !d[s].ms_slow || !d[s].Ps_slow) return SRTM_E_NULL;
   return srtm::dispatch_batch(nx, ny, dtype, table_dev, nseq, tiles, lmax, workspace, info,
-                              static_cast<hipStream_t>(stream));
+                              static_cast<hipStream_t>(stream), grad);
+}
+
+srtm_status srtm_smooth_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                              const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                              void* stream) {
+  return batch_common(nx, ny, dtype, nseq, table_host, table_dev, workspace, workspace_bytes, info, stream, false);
+}
+
+srtm_status srtm_loglik_grad_batch(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
+                                   const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
+                                   void* stream) {
+  return batch_common(nx, ny, dtype, nseq, table_host, table_dev, workspace, workspace_bytes, info, stream, true);
 }
 
 static srtm_status lik_common(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,

@@ -2259,10 +2259,14 @@ __global__ void __launch_bounds__(TILE) k_stats(Batch b) {
                               (int64_t)blockIdx.x - q.tile0, q.plan.nt);
 }
 
+// Outputs: the given arrays (one sequence), or else, per sequence of a batch, its four output
+// slots (ms_fast, Ps_fast, ms_slow, Ps_slow) hold ll, dF, dQ and dR.
 template <typename T, int NX, int NY, bool GRAD>
 __global__ void __launch_bounds__(256) k_stats_final(Batch b, T* ll, T* dF, T* dQ, T* dR) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  stats_final_body<T, NX, NY, GRAD>(q.N, q.L, q.plan.nt, q.F, q.Q, q.R, q.stats, ll, dF, dQ, dR, q.info);
+  const bool own = ll == nullptr;
+  stats_final_body<T, NX, NY, GRAD>(q.N, q.L, q.plan.nt, q.F, q.Q, q.R, q.stats, own ? q.ms_fast : ll,
+                                    own ? q.Ps_fast : dF, own ? q.ms_slow : dQ, own ? q.Ps_slow : dR, q.info);
 }
 
 // ============================================================================ launchers
@@ -2449,14 +2453,14 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
 // index of every tile, in device memory.
 template <typename T, int NX, int NY>
 srtm_status run_batch(const void* table, int nseq, int64_t ntiles, int max_L, void* ws, int32_t* info,
-                      hipStream_t st) {
+                      hipStream_t st, bool grad) {
   Batch b{};
   b.table = static_cast<const SeqDesc*>(table);
   b.tile_seq = reinterpret_cast<const int32_t*>(static_cast<const char*>(table) + batch_tile_map_offset(nseq));
   b.ws = static_cast<char*>(ws);
   b.info = info;
   const Launch g{(unsigned)nseq, (unsigned)ntiles, max_L};
-  return launch_all<T, NX, NY>(b, g, true, 2, st, Events{nullptr, 0, 0});
+  return launch_all<T, NX, NY>(b, g, true, grad ? REC_GRAD : 2, st, Events{nullptr, 0, 0});
 }
 
 }  // namespace srtm
@@ -2498,11 +2502,11 @@ srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* l
 }
 
 srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
-                           void* ws, int32_t* info, hipStream_t st) {
-#define SRTM_DISPB(a, b)                                                                            \
-  if (nx == a && ny == b) {                                                                        \
-    if (dtype == SRTM_F64) return run_batch<double, a, b>(table, nseq, ntiles, max_L, ws, info, st); \
-    return run_batch<float, a, b>(table, nseq, ntiles, max_L, ws, info, st);                        \
+                           void* ws, int32_t* info, hipStream_t st, bool grad) {
+#define SRTM_DISPB(a, b)                                                                                  \
+  if (nx == a && ny == b) {                                                                              \
+    if (dtype == SRTM_F64) return run_batch<double, a, b>(table, nseq, ntiles, max_L, ws, info, st, grad); \
+    return run_batch<float, a, b>(table, nseq, ntiles, max_L, ws, info, st, grad);                        \
   }
   SRTM_PAIRS(SRTM_DISPB)
 #undef SRTM_DISPB

@@ -68,6 +68,8 @@ def lib():
     L.srtm_smooth_batch.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp, _vp]
     L.srtm_smooth_batch.restype = ctypes.c_int
+    L.srtm_loglik_grad_batch.argtypes = L.srtm_smooth_batch.argtypes
+    L.srtm_loglik_grad_batch.restype = ctypes.c_int
     L.srtm_loglik.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 9 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_loglik.restype = ctypes.c_int
     L.srtm_loglik_grad.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
@@ -294,7 +296,8 @@ class Batch:
     per-sequence status words and output tensors. Reusable for repeated calls (and graph
     capture) on the same inputs."""
 
-    def __init__(self, problems, *, fast: bool = True, slow: bool = True, outputs=None, alloc=None):
+    def __init__(self, problems, *, fast: bool = True, slow: bool = True, outputs=None, alloc=None,
+                 grad: bool = False):
         items = []
         for pr in problems:
             F, Q, H, R, L, m0, P0, y = pr
@@ -311,9 +314,14 @@ class Batch:
         self.inputs = [it[0] for it in items]
         self.outputs = []
         arr = (SeqC * len(items))()
+        self.grad = grad
+        if grad:   # per sequence: ll, dF, dQ, dR in the four output slots
+            outputs = [{"ll": torch.empty(1, device=dev, dtype=dt), "dF": torch.empty((nx, nx), device=dev, dtype=dt),
+                        "dQ": torch.empty((nx, nx), device=dev, dtype=dt),
+                        "dR": torch.empty((ny, ny), device=dev, dtype=dt)} for _ in items]
         for j, (ts, L, N, _, _) in enumerate(items):
             out = {} if outputs is None else outputs[j]
-            if outputs is not None:
+            if outputs is not None and not grad:
                 for k, shp in (("ms_fast", (N, L, nx)), ("Ps_fast", (N, L, nx, nx)), ("ms_slow", (N, nx)),
                                ("Ps_slow", (N, nx, nx))):
                     t = out.get(k)
@@ -330,8 +338,10 @@ class Batch:
             e = arr[j]
             for k in ("F", "Q", "H", "R", "m0", "P0", "y"):
                 setattr(e, k, ts[k].data_ptr())
+            slots = dict(zip(("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"), ("ll", "dF", "dQ", "dR"))) if grad else {}
             for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
-                setattr(e, k, out[k].data_ptr() if k in out else None)
+                src = slots.get(k, k)
+                setattr(e, k, out[src].data_ptr() if src in out else None)
             e.N, e.L, e.reserved = N, L, 0
         self.nseq = len(items)
         tsz, wsz = ctypes.c_size_t(0), ctypes.c_size_t(0)
@@ -356,9 +366,10 @@ class Batch:
         """Enqueue the batch on `stream` (default: the current stream); no allocation, no sync."""
         if stream is None:
             stream = torch.cuda.current_stream(self.device).cuda_stream
-        _check(lib().srtm_smooth_batch(self.nx, self.ny, _dtype_code(self.dtype), self.nseq, _ptr(self.table_host),
-                                       _ptr(self.table_dev), _ptr(self.workspace), self.workspace.numel(),
-                                       _ptr(self.info), ctypes.c_void_p(stream)), "srtm_smooth_batch")
+        fn = lib().srtm_loglik_grad_batch if self.grad else lib().srtm_smooth_batch
+        _check(fn(self.nx, self.ny, _dtype_code(self.dtype), self.nseq, _ptr(self.table_host), _ptr(self.table_dev),
+                  _ptr(self.workspace), self.workspace.numel(), _ptr(self.info), ctypes.c_void_p(stream)),
+               "srtm_loglik_grad_batch" if self.grad else "srtm_smooth_batch")
 
     def check(self):
         v = self.info.cpu()

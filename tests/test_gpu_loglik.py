@@ -92,3 +92,24 @@ def test_autograd_log_parameters_match_finite_differences():
     err = np.max(np.abs(got - fd)) / max(1.0, np.max(np.abs(fd)))
     print(f"[gpu] autograd theta grad max rel err {err:.2e}", flush=True)
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batched_gradient_equals_single_calls(dtype):
+    srtm = _srtm()
+    specs = [(4, 1, 10, 50, 101), (4, 1, 10, 300, 102), (4, 1, 5, 1, 103), (4, 1, 10, 257, 104), (4, 1, 20, 900, 105)]
+    probs = []
+    for nx, ny, L, N, seed in specs:
+        m = wl.random_stable_model(nx, ny, L, seed, rho=0.99, q=0.01, r=0.1)
+        y = wl.simulate(m, N, seed + 1)
+        probs.append(tuple(_t(x, dtype) for x in (m.A, m.Q, m.C, m.R)) + (L,) +
+                     tuple(_t(x, dtype) for x in (m.m0, m.P0, y)))
+    b = srtm.Batch(probs, grad=True)
+    b.launch()
+    torch.cuda.synchronize()
+    b.check()
+    for j, pr in enumerate(probs):
+        ll, dF, dQ, dR = srtm.loglik_grad(*pr)
+        o = b.outputs[j]
+        for got, want in ((o["ll"][0], ll), (o["dF"], dF), (o["dQ"], dQ), (o["dR"], dR)):
+            assert torch.equal(got, want), f"sequence {j}"
