@@ -27,6 +27,27 @@ SRTM_DEV void loadv(T (&a)[R], const T* __restrict__ p) {
   for (int r = 0; r < R; ++r) a[r] = p[r];
 }
 
+// Loads from device (global) memory through a global-address-space pointer, for arrays whose
+// pointers were read from memory (generic) but always live in device memory. Never for LDS.
+template <typename T>
+SRTM_DEV T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T, int R, int C>
+SRTM_DEV void gload(T (&a)[R][C], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[r][c] = gld(p + r * C + c);
+}
+
+template <typename T, int R>
+SRTM_DEV void gloadv(T (&a)[R], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = gld(p + r);
+}
+
 // C = A B
 template <typename T, int M, int K, int N>
 SRTM_DEV void mm(const T (&A)[M][K], const T (&B)[K][N], T (&C)[M][N]) {

@@ -30,6 +30,25 @@
 
 namespace srtm {
 
+// Every array of a call is device (global) memory. Pointers read from a descriptor are
+// generic; passing them through the global address space lets the compiler emit global
+// instead of flat loads and stores.
+template <typename T>
+SRTM_DEV T* as_global(T* p) {
+  using G = __attribute__((address_space(1))) T*;
+  return (T*)((G)p);
+}
+template <typename T>
+SRTM_DEV T* as_global(const void* p) {
+  return as_global(static_cast<T*>(const_cast<void*>(p)));
+}
+
+// Store of one scalar to device memory through a global pointer.
+template <typename T>
+SRTM_DEV void put_global(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // ============================================================================ constants
 // Cofactor (r, c) of the NX x NX row-major matrix M: (-1)^{r+c} times the determinant of M
 // without row r and column c.
@@ -818,11 +837,11 @@ SRTM_DEV void load_prior(const T* __restrict__ carry, const T* __restrict__ m0, 
                          int64_t k, T (&m)[NX], T (&P)[NX][NX]) {
   constexpr int ST = NX + NX * NX;
   if (k == 0) {
-    loadv(m, m0);
-    load(P, P0);
+    gloadv(m, m0);
+    gload(P, P0);
   } else {
-    loadv(m, carry + (k - 1) * ST);
-    load(P, carry + (k - 1) * ST + NX);
+    gloadv(m, carry + (k - 1) * ST);
+    gload(P, carry + (k - 1) * ST + NX);
   }
 }
 
@@ -942,7 +961,7 @@ SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, in
                           T (&d)[NX], T (&e)[NX]) {
   T yk[NY];
 #pragma unroll
-  for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? y[k * NY + r] : T(0);
+  for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? gld(y + k * NY + r) : T(0);
   T K[NX][NY], He[NX][NY];
   load(K, M.cst + M.lay.K);
   load(He, M.cst + M.lay.Heta);
@@ -998,20 +1017,20 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   if (c == 1) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      d[r] = (t0 < nt) ? tagg[t0 * 2 * NX + r] : T(0);
-      e[r] = (t0 < nt) ? tagg[t0 * 2 * NX + NX + r] : T(0);
+      d[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + r) : T(0);
+      e[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + NX + r) : T(0);
     }
   } else if (c == 2) {  // two runs of 2^LOG_TILE windows: vector parts only
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      d[r] = (t0 + 1 < nt) ? tagg[(t0 + 1) * 2 * NX + r] : T(0);
-      e[r] = (t0 + 1 < nt) ? tagg[(t0 + 1) * 2 * NX + NX + r] : T(0);
+      d[r] = (t0 + 1 < nt) ? gld(tagg + (t0 + 1) * 2 * NX + r) : T(0);
+      e[r] = (t0 + 1 < nt) ? gld(tagg + (t0 + 1) * 2 * NX + NX + r) : T(0);
     }
     T di[NX], ei[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      di[r] = (t0 < nt) ? tagg[t0 * 2 * NX + r] : T(0);
-      ei[r] = (t0 < nt) ? tagg[t0 * 2 * NX + NX + r] : T(0);
+      di[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + r) : T(0);
+      ei[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + NX + r) : T(0);
     }
     level_vec_combine(M.level(LOG_TILE), M.lay, di, ei, d, e);
   } else {  // fold the chunk with full combines (tiles past the end carry zero vectors)
@@ -1042,8 +1061,8 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   }
   T m[NX], P[NX][NX];
   if (tid == 0) {
-    loadv(m, m0);
-    load(P, P0);
+    gloadv(m, m0);
+    gload(P, P0);
     symmetrize(P);
     const T* lv = M.level(l0);
     T F[NX][NX], D[NX][NX], J[NX][NX];
@@ -1100,8 +1119,8 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   if (t0 < nt) {
     T X[NX], XP[NX][NX];
     if (tid == 0) {
-      loadv(X, m0);
-      load(XP, P0);
+      gloadv(X, m0);
+      gload(XP, P0);
       symmetrize(XP);
     } else {
       ld_state<T, NX>(S, tid - 1, X, XP);
@@ -1121,8 +1140,8 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
         for (int cc = 0; cc < NX; ++cc) tstate[t * ST + NX + r * NX + cc] = XP[r][cc];
       if (t + 1 < t0 + c && t + 1 < nt) {
         T dt[NX], et[NX];
-        loadv(dt, tagg + t * 2 * NX);
-        loadv(et, tagg + t * 2 * NX + NX);
+        gloadv(dt, tagg + t * 2 * NX);
+        gloadv(et, tagg + t * 2 * NX + NX);
         if (!state_combine(X, XP, F, dt, D, et, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
       }
     }
@@ -1142,11 +1161,11 @@ SRTM_DEV void ld_selem_global(const T* __restrict__ src, SElem<T, NX>& x) {
   constexpr int NN = NX * NX;
 #pragma unroll
   for (int i = 0; i < NX; ++i) {
-    x.g[i] = src[NN + i];
+    x.g[i] = gld(src + NN + i);
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      x.E[i][c] = src[i * NX + c];
-      x.S[i][c] = src[NN + NX + i * NX + c];
+      x.E[i][c] = gld(src + i * NX + c);
+      x.S[i][c] = gld(src + NN + NX + i * NX + c);
     }
   }
 }
@@ -1248,11 +1267,13 @@ template <> struct Chunk<4> { using type = unsigned int; };
 // L2), otherwise normally, so that partial lines can merge in the L2 first.
 template <bool NT, typename V>
 SRTM_DEV void put_chunk(char* p, const V& v) {
+  using G = __attribute__((address_space(1))) V*;  // outputs are device memory: global stores
   if constexpr (NT)
-    __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+    __builtin_nontemporal_store(v, (G)p);
   else
-    *reinterpret_cast<V*>(p) = v;
+    *(G)p = v;
 }
+
 
 // Copies records w = 0..nvalid-1 of RB bytes (stride SB bytes in LDS) to dst + w * gstride
 // bytes in chunks of CH bytes. When a record holds a power-of-two number of chunks, lane l
@@ -1267,7 +1288,8 @@ SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, 
   if (((reinterpret_cast<uintptr_t>(dst) | (uintptr_t)gstride) % CH) != 0 || (64 % PER) != 0) {
     for (int c = lane; c < nvalid * (RB / 4); c += 64) {  // generic: 4-byte words
       const int w = c / (RB / 4), e = c - w * (RB / 4);
-      reinterpret_cast<unsigned int*>(dst + w * gstride)[e] = reinterpret_cast<const unsigned int*>(lds + w * SB)[e];
+      put_global(reinterpret_cast<unsigned int*>(dst + w * gstride) + e,
+                 reinterpret_cast<const unsigned int*>(lds + w * SB)[e]);
     }
     return;
   }
@@ -1295,7 +1317,7 @@ SRTM_DEV void flush_records_rt(int lane, int nvalid, const char* __restrict__ ld
                                int64_t gstride_elems, int nel) {
   for (int c = lane; c < nvalid * nel; c += 64) {
     const int w = c / nel, e = c - w * nel;
-    dst[w * gstride_elems + e] = reinterpret_cast<const T*>(lds + w * SB)[e];
+    put_global(dst + w * gstride_elems + e, reinterpret_cast<const T*>(lds + w * SB)[e]);
   }
 }
 
@@ -1396,8 +1418,8 @@ SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const
   // down-sweep with states; slot TILE-1 <- the tile's exclusive state
   if (tid == TILE - 1) {
     T mt[NX], Pt[NX][NX];
-    loadv(mt, tile_state);
-    load(Pt, tile_state + NX);
+    gloadv(mt, tile_state);
+    gload(Pt, tile_state + NX);
     st_state<T, NX>(S, tid, mt, Pt);
   }
   __syncthreads();
@@ -1430,8 +1452,8 @@ SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const
   // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
   ld_state<T, NX>(S, tid, mprev, Pprev);
   if (k == 0) {  // the prior itself, not a rounded copy through the tree
-    loadv(mprev, m0);
-    load(Pprev, P0);
+    gloadv(mprev, m0);
+    gload(Pprev, P0);
     symmetrize(Pprev);
   }
 #pragma unroll
@@ -1458,18 +1480,18 @@ SRTM_DEV int store_carry(int64_t k, const T (&m)[NX], const T (&P)[NX][NX], T* _
                          T* __restrict__ m_slow, T* __restrict__ P_slow) {
   constexpr int NN = NX * NX, ST = NX + NN;
 #pragma unroll
-  for (int r = 0; r < NX; ++r) carry[k * ST + r] = m[r];
+  for (int r = 0; r < NX; ++r) put_global(carry + k * ST + r, m[r]);
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
-    for (int c = 0; c < NX; ++c) carry[k * ST + NX + r * NX + c] = P[r][c];
+    for (int c = 0; c < NX; ++c) put_global(carry + k * ST + NX + r * NX + c, P[r][c]);
   if (m_slow) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m_slow[k * NX + r] = m[r];
+    for (int r = 0; r < NX; ++r) put_global(m_slow + k * NX + r, m[r]);
   }
   if (P_slow) {
 #pragma unroll
-    for (int r = 0; r < NN; ++r) P_slow[k * NN + r] = P[r / NX][r % NX];
+    for (int r = 0; r < NN; ++r) put_global(P_slow + k * NN + r, P[r / NX][r % NX]);
   }
   return finite_state(m, P) ? 0 : SRTM_INFO_NONFINITE;
 }
@@ -1524,7 +1546,7 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
   {
     T yk[NY];
 #pragma unroll
-    for (int r = 0; r < NY; ++r) yk[r] = valid ? y[k * NY + r] : T(0);
+    for (int r = 0; r < NY; ++r) yk[r] = valid ? gld(y + k * NY + r) : T(0);
     Window<T, NX, NY> w;
     if (!window_setup(M, L, mprev, Pprev, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
     T Pmi[NX][NX], mpred[NX], Pm[NX][NX];
@@ -1632,7 +1654,7 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
     }
     T* dst = sfx + k * SF;
 #pragma unroll
-    for (int r = 0; r < SF; ++r) dst[r] = rec[r];
+    for (int r = 0; r < SF; ++r) put_global(dst + r, rec[r]);
   }
   if (flag && info) atomicOr(info, flag);
 }
@@ -1664,7 +1686,7 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   const int64_t kc = valid ? k : 0;   // clamped index for loads of padding lanes
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
-  loadv(yk, y + kc * NY);
+  gloadv(yk, y + kc * NY);
   Window<T, NX, NY> w;
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
@@ -1673,12 +1695,12 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
     const T* src = sfx + kc * SF;
     const T* ti = tin + tile * ST;
     T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
-    load(Et, src);
-    loadv(mi, ti);
-    load(Pi, ti + NX);
+    gload(Et, src);
+    gloadv(mi, ti);
+    gload(Pi, ti + NX);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      T t = src[NN + r];
+      T t = gld(src + NN + r);
 #pragma unroll
       for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
       v[r] = t;
@@ -1689,7 +1711,7 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = r; c < NX; ++c) {
-        T t = src[o++];
+        T t = gld(src + o++);
 #pragma unroll
         for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
         W[r][c] = t;
@@ -1800,7 +1822,7 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
   double* part = parts + tile * SL::SIZE;
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
-  loadv(yk, y + kc * NY);
+  gloadv(yk, y + kc * NY);
   Window<T, NX, NY> w;
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
@@ -1837,12 +1859,12 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
       const T* src = sfx + kc * SF;
       const T* ti = tin + tile * ST;
       T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
-      load(Et, src);
-      loadv(mi, ti);
-      load(Pi, ti + NX);
+      gload(Et, src);
+      gloadv(mi, ti);
+      gload(Pi, ti + NX);
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
-        T t = src[NN + r];
+        T t = gld(src + NN + r);
 #pragma unroll
         for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
         v[r] = t;
@@ -1853,7 +1875,7 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
       for (int r = 0; r < NX; ++r)
 #pragma unroll
         for (int c = r; c < NX; ++c) {
-          T t = src[o++];
+          T t = gld(src + o++);
 #pragma unroll
           for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
           W[r][c] = t;
@@ -1999,7 +2021,7 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
     // measurement statistic: y_k - H xbar = R S^{-1} e - Z v, Cov = R - R S^{-1} R + Z W Z^T, Z = R S^{-1} U_l^T
     {
       T R[NY][NY], RSi[NY][NY], Z[NY][NX], d[NY], ZW[NY][NX];
-      load(R, Rm);
+      gload(R, Rm);
       mm(R, w.Si, RSi);
       mm(R, w.Y2, Z);
       mm(Z, W, ZW);
@@ -2166,27 +2188,27 @@ template <typename T, int NX, int NY>
 SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   const SeqDesc d = b.table ? b.table[s] : b.one;
   Seq<T, NX, NY> q;
-  q.F = static_cast<const T*>(d.F);
-  q.Q = static_cast<const T*>(d.Q);
-  q.H = static_cast<const T*>(d.H);
-  q.R = static_cast<const T*>(d.R);
-  q.m0 = static_cast<const T*>(d.m0);
-  q.P0 = static_cast<const T*>(d.P0);
-  q.y = static_cast<const T*>(d.y);
-  q.ms_fast = static_cast<T*>(d.ms_fast);
-  q.Ps_fast = static_cast<T*>(d.Ps_fast);
-  q.ms_slow = static_cast<T*>(d.ms_slow);
-  q.Ps_slow = static_cast<T*>(d.Ps_slow);
-  q.mf_fast = static_cast<T*>(d.mf_fast);
-  q.Pf_fast = static_cast<T*>(d.Pf_fast);
-  q.mf_slow = static_cast<T*>(d.mf_slow);
-  q.Pf_slow = static_cast<T*>(d.Pf_slow);
+  q.F = as_global<T>(d.F);
+  q.Q = as_global<T>(d.Q);
+  q.H = as_global<T>(d.H);
+  q.R = as_global<T>(d.R);
+  q.m0 = as_global<T>(d.m0);
+  q.P0 = as_global<T>(d.P0);
+  q.y = as_global<T>(d.y);
+  q.ms_fast = as_global<T>(d.ms_fast);
+  q.Ps_fast = as_global<T>(d.Ps_fast);
+  q.ms_slow = as_global<T>(d.ms_slow);
+  q.Ps_slow = as_global<T>(d.Ps_slow);
+  q.mf_fast = as_global<T>(d.mf_fast);
+  q.Pf_fast = as_global<T>(d.Pf_fast);
+  q.mf_slow = as_global<T>(d.mf_slow);
+  q.Pf_slow = as_global<T>(d.Pf_slow);
   q.N = d.N;
   q.tile0 = d.tile0;
   q.L = d.L;
   q.plan = make_scan_plan(d.N);
   const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0);
-  char* base = b.ws + d.ws_off;
+  char* base = as_global(b.ws) + d.ws_off;
   q.cst = reinterpret_cast<T*>(base + wl.consts);
   q.ftagg = reinterpret_cast<T*>(base + wl.ftile_agg);
   q.ftst = reinterpret_cast<T*>(base + wl.ftile_state);
