@@ -26,8 +26,14 @@ def _mpow(A, i):
     return np.linalg.matrix_power(A, i)
 
 
-def slow_rate_model(A, Q, C, L):
+def slow_rate_model(A, Q, C, L, B=None):
     """Slow-rate dynamic and measurement model of Sec. III-A.
+
+    With inputs (x_t = A x_{t-1} + B u_{t-1} + w_{t-1}, eq. original-linear-SSM) the stacked
+    window input u_bar_k = [u_{k,0}; ...; u_{k,l-1}] (u_{k,i-1} drives x_{k,i}) enters as
+    B_bar u_bar_k in the state equation and D_bar u_bar_k in the measurement equation, with
+    B_bar = G_bar (I_l (x) B) and D_bar = M_bar (I_l (x) B) (the input rides the same
+    propagation as the process noise).
 
     eq. h-k-l-2:  x_{k,l} = A_bar x_{k-1,l} + G_bar w_bar_k,
                   A_bar = A^l, G_bar = [A^{l-1} ... A I], Q_bar = G_bar Q~ G_bar^T.
@@ -42,12 +48,15 @@ def slow_rate_model(A, Q, C, L):
     Qbar = Gbar @ Qtilde @ Gbar.T
     Cbar = (C / L) @ sum(_mpow(A, i) for i in range(1, L + 1))
     Mbar = (C / L) @ np.hstack([sum(_mpow(A, i) for i in range(0, L - j)) for j in range(L)])
-    return dict(Abar=Abar, Gbar=Gbar, Qtilde=Qtilde, Qbar=Qbar, Cbar=Cbar, Mbar=Mbar,
-                nx=nx, L=L)
+    out = dict(Abar=Abar, Gbar=Gbar, Qtilde=Qtilde, Qbar=Qbar, Cbar=Cbar, Mbar=Mbar, nx=nx, L=L)
+    if B is not None:
+        Btilde = np.kron(np.eye(L), B)
+        out.update(Bbar=Gbar @ Btilde, Dbar=Mbar @ Btilde)
+    return out
 
 
-def batch_model(A, Q, C, L):
-    """Stacked fast-rate window model of Sec. III-B.
+def batch_model(A, Q, C, L, B=None):
+    """Stacked fast-rate window model of Sec. III-B (with inputs: calB = calG (I_l (x) B)).
 
     eq. params-fast:   calA = [A; A^2; ...; A^l] (l nx x nx),
                        calG = lower block-triangular Toeplitz with blocks A^{r-c}.
@@ -61,15 +70,19 @@ def batch_model(A, Q, C, L):
             calG[r * nx:(r + 1) * nx, c * nx:(c + 1) * nx] = _mpow(A, r - c)
     calH = np.hstack([C] * L) / L
     Qtilde = np.kron(np.eye(L), Q)
-    return dict(calA=calA, calG=calG, calH=calH, Qtilde=Qtilde, nx=nx, L=L)
+    out = dict(calA=calA, calG=calG, calH=calH, Qtilde=Qtilde, nx=nx, L=L)
+    if B is not None:
+        out["calB"] = calG @ np.kron(np.eye(L), B)
+    return out
 
 
-def imkf(A, Q, C, R, L, m0, P0, y):
+def imkf(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     """Sequential slow-rate IMKF, eq. prediction and eq. m-h-k-l (Sec. III-A).
 
+    Optional inputs: B (nx x nu) and u [N][l][nu], u[k-1][i-1] driving x_{k,i}.
     Returns (m, P, loglik) with m[k-1] = m^f_{k,l}, P[k-1] = P^f_{k,l} for k = 1..N.
     """
-    sr = slow_rate_model(A, Q, C, L)
+    sr = slow_rate_model(A, Q, C, L, B)
     Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[k] for k in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
     N = y.shape[0]
     nx, ny = A.shape[0], C.shape[0]
@@ -78,13 +91,14 @@ def imkf(A, Q, C, R, L, m0, P0, y):
     m, P = np.array(m0, dtype=float), np.array(P0, dtype=float)
     ll = 0.0
     for k in range(N):
+        ub = None if B is None else np.asarray(u[k], dtype=float).reshape(-1)
         # prediction (eq. prediction)
-        m_pred = Abar @ m
+        m_pred = Abar @ m + (0.0 if ub is None else sr["Bbar"] @ ub)
         P_pred = Abar @ P @ Abar.T + Qbar
         # update (eq. m-h-k-l): gain from the cross-covariance with the correlated noise term
         cross = Abar @ P @ Cbar.T + Gbar @ Qt @ Mbar.T
         S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + R
-        innov = y[k] - Cbar @ m
+        innov = y[k] - Cbar @ m - (0.0 if ub is None else sr["Dbar"] @ ub)
         gain = np.linalg.solve(S.T, cross.T).T
         m = m_pred + gain @ innov
         P = _sym(P_pred - gain @ cross.T)
@@ -94,7 +108,7 @@ def imkf(A, Q, C, R, L, m0, P0, y):
     return ms, Ps, ll
 
 
-def fast_filter_window(bm, R, m_prev, P_prev, yk):
+def fast_filter_window(bm, R, m_prev, P_prev, yk, uk=None):
     """Window posterior p(X_{k,1:l} | y_{1:k}), eq. predict-fast and eq. update-fast.
 
     (m_prev, P_prev) = (m^f_{k-1,l}, P^f_{k-1,l}); returns the dense (l nx) mean and
@@ -102,6 +116,8 @@ def fast_filter_window(bm, R, m_prev, P_prev, yk):
     """
     calA, calG, calH, Qt = bm["calA"], bm["calG"], bm["calH"], bm["Qtilde"]
     M_pred = calA @ m_prev
+    if uk is not None:   # stacked window input u_{k,0..l-1}
+        M_pred = M_pred + bm["calB"] @ np.asarray(uk, dtype=float).reshape(-1)
     P_pred = calA @ P_prev @ calA.T + calG @ Qt @ calG.T
     S = calH @ P_pred @ calH.T + R
     gain = np.linalg.solve(S.T, (P_pred @ calH.T).T).T
@@ -116,7 +132,7 @@ def _blocks(M, P, nx, L):
     return m, Pd
 
 
-def srtm_filter(A, Q, C, R, L, m0, P0, y):
+def srtm_filter(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     """Fast- and slow-rate filtering marginals (Sec. III-A, III-B and Remark fast-par-filter).
 
     Returns dict with
@@ -124,18 +140,18 @@ def srtm_filter(A, Q, C, R, L, m0, P0, y):
       m_slow[k-1] = m^f_{k,l},  P_slow[k-1] = P^f_{k,l}  (the IMKF carry), and loglik.
     """
     nx, N = A.shape[0], y.shape[0]
-    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y)
-    bm = batch_model(A, Q, C, L)
+    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y, B, u)
+    bm = batch_model(A, Q, C, L, B)
     m_fast = np.zeros((N, L, nx))
     P_fast = np.zeros((N, L, nx, nx))
     for k in range(N):
         mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k])
+        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k], None if B is None else u[k])
         m_fast[k], P_fast[k] = _blocks(M_f, P_f, nx, L)
     return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
 
 
-def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
+def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None):
     """Fast- and slow-rate smoothing marginals by the proposed sequential smoother.
 
     eq. smoothing-dynamic / eq. seq-smoothing-all (Sec. III-C): for k = N-1..1,
@@ -145,13 +161,14 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
       P^s_k = P^f_k + G_k (P^s_{k+1,1} - P^-_{k+1,1}) G_k^T,
     with A_hat = [0 ... 0 A]; window N is smoothed = filtered. The window filter
     (M^f_k, P^f_k) is recomputed from the stored slow carry (Remark fast-par-filter).
+    With inputs the prediction of x_{k+1,1} adds B u_{k+1,0} (the input driving it).
 
     Returns dict with ms_fast/Ps_fast [N, L, ...] = p(x_{k,i} | y_{1:N}) and
     ms_slow/Ps_slow [N, ...] = p(x_{k,1} | y_{1:N}) (the smoother's slow state).
     """
     nx, N = A.shape[0], y.shape[0]
-    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y)
-    bm = batch_model(A, Q, C, L)
+    m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y, B, u)
+    bm = batch_model(A, Q, C, L, B)
     Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A])
     ms_fast = np.zeros((N, L, nx))
     Ps_fast = np.zeros((N, L, nx, nx))
@@ -162,13 +179,13 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
     ms1 = Ps1 = None
     for k in range(N - 1, -1, -1):
         mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k])
+        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k], None if B is None else u[k])
         if with_filter:
             out["m_fast"][k], out["P_fast"][k] = _blocks(M_f, P_f, nx, L)
         if k == N - 1:
             M_s, P_s = M_f, P_f
         else:
-            m_pred = Ahat @ M_f
+            m_pred = Ahat @ M_f + (0.0 if B is None else B @ np.asarray(u[k + 1][0], dtype=float))
             P_pred = Ahat @ P_f @ Ahat.T + Q
             G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
             M_s = M_f + G @ (ms1 - m_pred)

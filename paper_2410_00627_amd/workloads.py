@@ -98,6 +98,16 @@ HEADLINE_N = 1 << 17
 WNA_N = 100
 
 
+def random_inputs(nx: int, nu: int, L: int, N: int, seed: int, scale: float = 0.5):
+    """Input matrix B ~ N(0,1)^{nx x nu} and inputs u [N][L][nu]: a slow sinusoid plus
+    N(0, scale^2) noise per fast step."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = rng.standard_normal((nx, nu))
+    t = np.arange(N * L).reshape(N, L, 1)
+    u = np.sin(2 * np.pi * t / (7.0 * L) + np.arange(nu)) + scale * rng.standard_normal((N, L, nu))
+    return B, u
+
+
 def batched_specs(n_seq: int = 256, seed: int = 3030):
     """Many independent sequences of uneven length: per sequence nx in {2, 4, 6}, L in
     {5, 10, 20}, N = round(2^U(8, 14)) windows, ny = 1; returns (nx, L, N, model seed) tuples."""
@@ -121,8 +131,9 @@ def _chol_psd(S: np.ndarray) -> np.ndarray:
     return V * np.sqrt(np.clip(w, 0.0, None))[None, :]
 
 
-def simulate(model: Model, N: int, seed: int, *, return_states: bool = False):
-    """Draw x_0..x_{NL} and y_1..y_N from the model (float64).
+def simulate(model: Model, N: int, seed: int, *, return_states: bool = False, B=None, u=None):
+    """Draw x_0..x_{NL} and y_1..y_N from the model (float64); with inputs, B (nx x nu) and
+    u [N][L][nu] add B u[k-1][i-1] to the step into x_{k,i}.
 
     The fast-rate recursion is evaluated blockwise: within blocks of b steps it runs
     vectorised over all blocks from a zero start, then block-start states are chained
@@ -135,6 +146,8 @@ def simulate(model: Model, N: int, seed: int, *, return_states: bool = False):
     x0 = model.m0 + _chol_psd(model.P0) @ rng.standard_normal(nx)
     w = rng.standard_normal((T, nx)) @ _chol_psd(model.Q).T      # w_{t-1} drives x_t
     v = rng.standard_normal((N, ny)) @ _chol_psd(model.R).T
+    if B is not None:
+        w = w + np.asarray(u, dtype=float).reshape(T, -1) @ np.asarray(B, dtype=float).T
     A = model.A
     b = max(1, min(T, int(np.sqrt(T)) + 1))
     nb = -(-T // b)

@@ -11,7 +11,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def joint_prior(A, Q, C, R, L, m0, P0, N):
+def joint_prior(A, Q, C, R, L, m0, P0, N, B=None, u=None):
     nx, ny = A.shape[0], C.shape[0]
     T = N * L
     dim = (T + 1) * nx
@@ -25,6 +25,8 @@ def joint_prior(A, Q, C, R, L, m0, P0, N):
         for s in range(1, t + 1):          # w_{s-1} enters x_s
             Gam[t * nx:(t + 1) * nx, (s - 1) * nx:s * nx] = powers[t - s]
     muZ = Phi @ m0
+    if B is not None:   # u_{s-1} enters x_s like w_{s-1}: mean shift Gam (I_T (x) B) u
+        muZ = muZ + Gam @ np.kron(np.eye(T), B) @ np.asarray(u, dtype=float).reshape(-1)
     SZ = Phi @ P0 @ Phi.T + Gam @ np.kron(np.eye(T), Q) @ Gam.T
     Psi = np.zeros((N * ny, dim))
     for k in range(N):
@@ -44,7 +46,7 @@ def _condition(muZ, SZ, Psi, SY, y, rows):
     return muZ + K @ r, SZ - K @ SZY.T
 
 
-def posteriors(A, Q, C, R, L, m0, P0, y):
+def posteriors(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     """Exact filter and smoother marginals of every fast state x_{k,i}.
 
     Returns dict: m_fast/P_fast = p(x_{k,i} | y_{1:k}), ms_fast/Ps_fast = p(x_{k,i} | y_{1:N}),
@@ -52,7 +54,7 @@ def posteriors(A, Q, C, R, L, m0, P0, y):
     """
     nx, ny = A.shape[0], C.shape[0]
     N = y.shape[0]
-    muZ, SZ, Psi, SY = joint_prior(A, Q, C, R, L, m0, P0, N)
+    muZ, SZ, Psi, SY = joint_prior(A, Q, C, R, L, m0, P0, N, B, u)
     m_fast = np.zeros((N, L, nx))
     P_fast = np.zeros((N, L, nx, nx))
     for k in range(N):

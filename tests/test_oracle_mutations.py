@@ -25,8 +25,8 @@ MUTATIONS = [
      "Gbar = np.hstack([_mpow(A, L - j) for j in range(L)])"),
     ("C_bar sum from 0", "Cbar = (C / L) @ sum(_mpow(A, i) for i in range(1, L + 1))",
      "Cbar = (C / L) @ sum(_mpow(A, i) for i in range(0, L))"),
-    ("M_bar blocks reversed", "for j in range(L)])\n    return dict(Abar",
-     "for j in reversed(range(L))])\n    return dict(Abar"),
+    ("M_bar blocks reversed", "for j in range(L)])\n    out = dict(Abar",
+     "for j in reversed(range(L))])\n    out = dict(Abar"),
     ("calG transposed", "P_pred = calA @ P_prev @ calA.T + calG @ Qt @ calG.T",
      "P_pred = calA @ P_prev @ calA.T + calG.T @ Qt @ calG"),
     ("fast update sign", "M_f = M_pred + gain @ (yk - calH @ M_pred)", "M_f = M_pred - gain @ (yk - calH @ M_pred)"),
