@@ -5,7 +5,8 @@
  *
  * Method: Yaghoobi & Sarkka, "Parallel state estimation for systems with integrated
  * measurements", arXiv 2410.00627. The problem is the one stated in Sec. III
- * (eq. original-linear-SSM and eq. dual-rate-ssm1) without inputs (B = 0):
+ * (eq. original-linear-SSM and eq. dual-rate-ssm1); the plain entry points take it without
+ * inputs (B = 0), the *_inputs ones with known inputs B u_{t-1} added to the dynamics:
  *
  *     x_t = F x_{t-1} + w_{t-1},        w ~ N(0, Q)          (F is the paper's A)
  *     y_k = (H / L) sum_{i=1..L} x_{k,i} + v_k,  v ~ N(0, R)  (H is the paper's C)
@@ -77,6 +78,9 @@ typedef struct {
 #define SRTM_MAX_L 128
 #define SRTM_MAX_N (1LL << 26)
 
+/* Largest input size of the *_inputs entry points. */
+#define SRTM_MAX_NU 4
+
 /* Bytes of device workspace srtm_filter (smoother = 0) or srtm_smooth (smoother = 1)
  * needs for `shape`. Returns SRTM_OK and writes *bytes, or an argument error. */
 srtm_status srtm_workspace_size(const srtm_shape* shape, int32_t smoother, size_t* bytes);
@@ -121,6 +125,42 @@ srtm_status srtm_smooth_profiled(const srtm_shape* shape,
                                  void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
                                  void* workspace, size_t workspace_bytes, int32_t* info,
                                  void* stream, void* const* events, int32_t n_events);
+
+/* ------------------------------------------------------------------ known inputs
+ * The model of eq. original-linear-SSM with its input term:
+ *     x_t = F x_{t-1} + B u_{t-1} + w_{t-1},
+ * so the input u_{k,i-1} of window k drives the fast state x_{k,i}. Over one window the
+ * inputs add the deterministic response z_{k,i} = sum_{j=1..i} F^{i-j} B u_{k,j-1} to the
+ * fast states, i.e. B_bar u_bar_k to the slow state equation (eq. h-k-l-2) and
+ * (H / L) sum_i z_{k,i} to the measurement (eq. y-k-l-2); the smoother's prediction of
+ * x_{k+1,1} (eq. seq-smoothing-all) gains B u_{k+1,0}. Covariances do not change.
+ *  B: device [nx][nu];  u: device [N][L][nu], u[k-1][i-1] = u_{k,i-1} (both of the call's
+ *  dtype, 16-byte aligned);  1 <= nu <= SRTM_MAX_NU;  reserved must be 0. */
+typedef struct {
+  const void* B;
+  const void* u;
+  int32_t nu;
+  int32_t reserved;
+} srtm_inputs;
+
+/* srtm_filter, srtm_smooth and srtm_loglik with known inputs (same outputs, workspace sizes
+ * and errors; `inputs` NULL or with a NULL array -> SRTM_E_NULL, nu out of range or
+ * reserved != 0 -> SRTM_E_SHAPE). */
+srtm_status srtm_filter_inputs(const srtm_shape* shape, const srtm_inputs* inputs,
+                               const void* F, const void* Q, const void* H, const void* R,
+                               const void* m0, const void* P0, const void* y,
+                               void* m_fast, void* P_fast, void* m_slow, void* P_slow,
+                               void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+srtm_status srtm_smooth_inputs(const srtm_shape* shape, const srtm_inputs* inputs,
+                               const void* F, const void* Q, const void* H, const void* R,
+                               const void* m0, const void* P0, const void* y,
+                               void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                               void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
+                               void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+srtm_status srtm_loglik_inputs(const srtm_shape* shape, const srtm_inputs* inputs,
+                               const void* F, const void* Q, const void* H, const void* R,
+                               const void* m0, const void* P0, const void* y,
+                               void* ll, void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
 /* ------------------------------------------------------------------ log-likelihood and gradient
  * Marginal log-likelihood of the measurements, log p(y_{1:N}) = sum_k log N(y_k; C_bar m, S_k)

@@ -6,25 +6,37 @@
 
 #include <cstdint>
 
+#include "srtm_entry.h"
 #include "srtm_layout.h"
-#include "../../include/srtm.h"
 
 namespace srtm {
-struct Ptrs {
-  const void *F, *Q, *H, *R, *m0, *P0, *y;
-  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow;
-  void *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
-  void* ws;
-  int32_t* info;
-};
-bool pair_supported(int nx, int ny);
+bool pair_supported(int nx, int ny) {
+#define SRTM_SUP(a, b) \
+  if (nx == a && ny == b) return true;
+  SRTM_PAIRS(SRTM_SUP)
+#undef SRTM_SUP
+  return false;
+}
+
+// Routes a call to the object compiled for its (nx, ny) pair (lik_mode: 0, REC_LL or REC_GRAD).
 srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, hipEvent_t const* ev,
-                     int nev);
-size_t constants_lds_bytes(int nx, int ny, int L);
+                     int nev, int lik_mode = 0, void* ll = nullptr, void* dF = nullptr, void* dQ = nullptr,
+                     void* dR = nullptr) {
+#define SRTM_DISP(a, b) \
+  if (sh.nx == a && sh.ny == b) return run_pair_##a##_##b(sh.dtype, sh, p, smoother, st, ev, nev, lik_mode, ll, dF, dQ, dR);
+  SRTM_PAIRS(SRTM_DISP)
+#undef SRTM_DISP
+  return SRTM_E_UNSUPPORTED;
+}
+
 srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
-                           void* ws, int32_t* info, hipStream_t st, bool grad);
-srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* ll, void* dF, void* dQ, void* dR,
-                         hipStream_t st);
+                           void* ws, int32_t* info, hipStream_t st, bool grad) {
+#define SRTM_DISPB(a, b) \
+  if (nx == a && ny == b) return run_batch_pair_##a##_##b(dtype, table, nseq, ntiles, max_L, ws, info, st, grad);
+  SRTM_PAIRS(SRTM_DISPB)
+#undef SRTM_DISPB
+  return SRTM_E_UNSUPPORTED;
+}
 }  // namespace srtm
 
 namespace {
@@ -61,6 +73,17 @@ srtm_status run_common(const srtm_shape* sh, const srtm::Ptrs& p, bool smoother,
                         reinterpret_cast<hipEvent_t const*>(events), events ? n_events : 0);
 }
 
+// Adds validated known inputs to `p`.
+srtm_status with_inputs(const srtm_inputs* in, srtm::Ptrs& p) {
+  if (!in || !in->B || !in->u) return SRTM_E_NULL;
+  if (in->nu < 1 || in->nu > SRTM_MAX_NU || in->reserved != 0) return SRTM_E_SHAPE;
+  if (!aligned(in->B, 16) || !aligned(in->u, 16)) return SRTM_E_ALIGN;
+  p.B = in->B;
+  p.u = in->u;
+  p.nu = in->nu;
+  return SRTM_OK;
+}
+
 const char* const kFilterKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles", "k_fwd_final", "k_recover"};
 const char* const kSmoothKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles",
                                       "k_fwd_bwd",   "k_bwd_tiles",  "k_recover"};
@@ -94,6 +117,29 @@ srtm_status srtm_smooth(const srtm_shape* shape, const void* F, const void* Q, c
                         void* Pf_slow, void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
   const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
                      mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
+  return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_filter_inputs(const srtm_shape* shape, const srtm_inputs* inputs, const void* F, const void* Q,
+                               const void* H, const void* R, const void* m0, const void* P0, const void* y,
+                               void* m_fast, void* P_fast, void* m_slow, void* P_slow, void* workspace,
+                               size_t workspace_bytes, int32_t* info, void* stream) {
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
+               m_fast, P_fast, m_slow, P_slow, workspace, info};
+  const srtm_status s = with_inputs(inputs, p);
+  if (s != SRTM_OK) return s;
+  return run_common(shape, p, false, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_smooth_inputs(const srtm_shape* shape, const srtm_inputs* inputs, const void* F, const void* Q,
+                               const void* H, const void* R, const void* m0, const void* P0, const void* y,
+                               void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow, void* mf_fast,
+                               void* Pf_fast, void* mf_slow, void* Pf_slow, void* workspace,
+                               size_t workspace_bytes, int32_t* info, void* stream) {
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
+               mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
+  const srtm_status s = with_inputs(inputs, p);
+  if (s != SRTM_OK) return s;
   return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
 }
 
@@ -179,6 +225,7 @@ static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t n
     srtm_status st = check_shape(&sh);
     if (st != SRTM_OK) return st;
     if (d[s].tile0 != tiles || d[s].smoother != 1) return SRTM_E_SHAPE;
+    if (d[s].B || d[s].u || d[s].nu || d[s].reserved) return SRTM_E_SHAPE;  // batches carry no inputs
     const int32_t* map = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) +
                                                           srtm::batch_tile_map_offset(nseq));
     const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;
@@ -211,7 +258,8 @@ srtm_status srtm_loglik_grad_batch(int32_t nx, int32_t ny, int32_t dtype, int32_
 
 static srtm_status lik_common(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
                               const void* m0, const void* P0, const void* y, void* ll, void* dF, void* dQ, void* dR,
-                              void* workspace, size_t workspace_bytes, int32_t* info, void* stream, bool grad) {
+                              void* workspace, size_t workspace_bytes, int32_t* info, void* stream, bool grad,
+                              const srtm_inputs* inputs = nullptr) {
   srtm_status s = check_shape(shape);
   if (s != SRTM_OK) return s;
   if (!F || !Q || !H || !R || !m0 || !P0 || !y || !ll || !workspace) return SRTM_E_NULL;
@@ -223,9 +271,14 @@ static srtm_status lik_common(const srtm_shape* shape, const void* F, const void
   const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
   if (workspace_bytes < srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, grad).total)
     return SRTM_E_WORKSPACE;
-  const srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, nullptr, nullptr, workspace, info};
-  return srtm::dispatch_lik(*shape, p, grad, ll, dF, dQ, dR, static_cast<hipStream_t>(stream));
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
+               nullptr, nullptr, nullptr, nullptr, workspace, info};
+  if (inputs) {
+    const srtm_status si = with_inputs(inputs, p);
+    if (si != SRTM_OK) return si;
+  }
+  return srtm::dispatch(*shape, p, grad, static_cast<hipStream_t>(stream), nullptr, 0,
+                        grad ? srtm::REC_GRAD : srtm::REC_LL, ll, dF, dQ, dR);
 }
 
 srtm_status srtm_loglik(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
@@ -233,6 +286,14 @@ srtm_status srtm_loglik(const srtm_shape* shape, const void* F, const void* Q, c
                         size_t workspace_bytes, int32_t* info, void* stream) {
   return lik_common(shape, F, Q, H, R, m0, P0, y, ll, nullptr, nullptr, nullptr, workspace, workspace_bytes, info,
                     stream, false);
+}
+
+srtm_status srtm_loglik_inputs(const srtm_shape* shape, const srtm_inputs* inputs, const void* F, const void* Q,
+                               const void* H, const void* R, const void* m0, const void* P0, const void* y,
+                               void* ll, void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
+  if (!inputs) return SRTM_E_NULL;
+  return lik_common(shape, F, Q, H, R, m0, P0, y, ll, nullptr, nullptr, nullptr, workspace, workspace_bytes, info,
+                    stream, false, inputs);
 }
 
 srtm_status srtm_loglik_grad(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,

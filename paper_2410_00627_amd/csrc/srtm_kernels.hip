@@ -25,8 +25,8 @@
 //    A^i, Q_ii, Q_il, c_i, instead of the dense (l nx)^2 window covariance.
 
 #include "srtm_device.h"
+#include "srtm_entry.h"
 #include "srtm_layout.h"
-#include "../../include/srtm.h"
 
 namespace srtm {
 
@@ -399,10 +399,20 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
 }
 
 // ============================================================================ helpers
+// Known inputs of a call (all null and nu = 0 without inputs).
+template <typename T>
+struct InputView {
+  const T* B;  // [nx][nu]
+  const T* u;  // [N][l][nu], u[k-1][i-1] drives x_{k,i}
+  const T* H;  // [ny][nx], the measurement matrix C
+  int nu;
+};
+
 template <typename T, int NX, int NY>
 struct Model {
   const T* __restrict__ cst;
   ConstLayout lay;
+  InputView<T> in{};
   SRTM_DEV const T* per_i(int i) const { return cst + lay.per_i + (i - 1) * lay.per_i_stride; }
   SRTM_DEV const T* level(int p) const { return cst + lay.lev + p * lay.lev_stride; }
 };
@@ -845,16 +855,91 @@ SRTM_DEV void load_prior(const T* __restrict__ carry, const T* __restrict__ m0, 
   }
 }
 
+// ---------------------------------------------------------------- known inputs
+// With x_t = A x_{t-1} + B u_{t-1} + w_{t-1} (eq. original-linear-SSM), window k's own
+// inputs add the deterministic response z_{k,i} = A z_{k,i-1} + B u_{k,i-1}, z_{k,0} = 0, to
+// its fast states given x_{k-1,l}: in eq. h-k-l-2 B_bar u_bar_k = z_{k,l}, and in eq. y-k-l-2
+// D_bar u_bar_k = mu_k = (C/l) sum_i z_{k,i}. Hence the filter element's d gains z_{k,l}, every
+// innovation uses y_k - mu_k, m^f_{k,i} gains z_{k,i}, and the smoother's prediction of
+// x_{k+1,1} gains B u_{k+1,0}. No covariance depends on the inputs.
+
+// B u of one fast step (uk: that step's nu inputs).
+template <typename T, int NX>
+SRTM_DEV void input_drive(const InputView<T>& in, const T* __restrict__ uk, T (&bu)[NX]) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) bu[r] = T(0);
+#pragma unroll
+  for (int j = 0; j < NU_MAX; ++j) {
+    if (j < in.nu) {
+      const T uj = gld(uk + j);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) bu[r] = my_fma(gld(in.B + r * in.nu + j), uj, bu[r]);
+    }
+  }
+}
+
+// z <- A z + B u  (one fast step of the input response)
+template <typename T, int NX>
+SRTM_DEV void input_step(const InputView<T>& in, const T (&A)[NX][NX], const T* __restrict__ uk, T (&z)[NX]) {
+  T nz[NX];
+  input_drive(in, uk, nz);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int q = 0; q < NX; ++q) nz[r] = my_fma(A[r][q], z[q], nz[r]);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) z[r] = nz[r];
+}
+
+// Window k's measurement y_k (zero past the last window) and, with inputs, y_k - mu_k and z_{k,l}
+// (zL = 0 without inputs).
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N, int L,
+                          T (&yt)[NY], T (&zL)[NX]) {
+#pragma unroll
+  for (int r = 0; r < NY; ++r) yt[r] = (k < N) ? gld(y + k * NY + r) : T(0);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) zL[r] = T(0);
+  if constexpr (INP) {
+    if (k < N) {
+      T A[NX][NX], zs[NX];
+      load(A, M.cst + M.lay.A);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) zs[r] = T(0);
+      const T* uk = M.in.u + k * L * M.in.nu;
+#pragma unroll 1
+      for (int i = 0; i < L; ++i) {
+        input_step(M.in, A, uk + i * M.in.nu, zL);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) zs[r] += zL[r];
+      }
+      const T inv_l = T(1) / T(L);
+#pragma unroll
+      for (int r = 0; r < NY; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) s = my_fma(gld(M.in.H + r * NX + c), zs[c], s);
+        yt[r] -= s * inv_l;
+      }
+    }
+  }
+}
+
 // Smoother element of window k (eq. parallel-ak-smoothing, transposed S_k):
 //   P^- = A P^f_{k,l} A^T + Q,  E = P^f_{k,1,l} A^T (P^-)^{-1},  g = m^f_{k,1} - E A m^f_{k,l},
 //   S = P^f_{k,1} - E A (P^f_{k,1,l})^T = P^f_{k,1} - E P^- E^T;   last window: (0, m^f_{N,1}, P^f_{N,1}).
-// Also returns P^-, (P^-)^{-1} and A m^f_{k,l}, which the smoother correction reuses.
-template <typename T, int NX, int NY>
+// Also returns P^-, (P^-)^{-1} and the predicted mean A m^f_{k,l}, which the smoother correction
+// reuses. With inputs, z1 = B u_{k,0} is added to m^f_{k,1} and bnext = B u_{k+1,0} to the prediction.
+template <bool INP, typename T, int NX, int NY>
 SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, bool last,
-                              const T (&mL)[NX], const T (&PL)[NX][NX], SElem<T, NX>& el,
-                              T (&Pmi)[NX][NX], T (&mpred)[NX], T (&Pm)[NX][NX]) {
+                              const T (&mL)[NX], const T (&PL)[NX][NX], const T (&z1)[NX], const T (&bnext)[NX],
+                              SElem<T, NX>& el, T (&Pmi)[NX][NX], T (&mpred)[NX], T (&Pm)[NX][NX]) {
   T mf1[NX], Pf11[NX][NX], Pf1L[NX][NX];
   window_step<T, NX, NY, true>(M, w, 1, mf1, Pf11, Pf1L);
+  if constexpr (INP) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) mf1[r] += z1[r];
+  }
   int flag = 0;
   if (last) {
 #pragma unroll
@@ -877,6 +962,10 @@ SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, 
   sandwich(A, PL, Qm, Pm);
   if (!spd_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
   mv(A, mL, mpred);
+  if constexpr (INP) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) mpred[r] += bnext[r];
+  }
   T PA[NX][NX];
   mm_nt(Pf1L, A, PA);
   mm(PA, Pmi, el.E);
@@ -956,30 +1045,34 @@ SRTM_DEV void fwd_upsweep(const Model<T, NX, NY>& M, const Slots<T>& S, int tid)
   }
 }
 
-template <typename T, int NX, int NY>
-SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N,
-                          T (&d)[NX], T (&e)[NX]) {
-  T yk[NY];
-#pragma unroll
-  for (int r = 0; r < NY; ++r) yk[r] = (k < N) ? gld(y + k * NY + r) : T(0);
+// Vector part (d, eta) of window k's filter element from its measurement yt (y_k - mu_k with
+// inputs) and its input response zL = z_{k,l}.
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T (&yt)[NY], const T (&zL)[NX], T (&d)[NX],
+                          T (&e)[NX]) {
   T K[NX][NY], He[NX][NY];
   load(K, M.cst + M.lay.K);
   load(He, M.cst + M.lay.Heta);
-  mv(K, yk, d);
-  mv(He, yk, e);
+  mv(K, yt, d);
+  mv(He, yt, e);
+  if constexpr (INP) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) d[r] += zL[r];
+  }
 }
 
 // K1: per-tile aggregate of the vector parts (d, eta) of the filter elements.
-template <typename T, int NX, int NY>
+template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L,
-                              T* __restrict__ tagg, int64_t tile) {
+                              InputView<T> in, T* __restrict__ tagg, int64_t tile) {
   __shared__ T smem[2 * NX * TILE];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{smem, TILE};
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
-  T d[NX], e[NX];
-  fwd_element(M, y, k, N, d, e);
+  T yt[NY], zL[NX], d[NX], e[NX];
+  window_meas<INP>(M, y, k, N, L, yt, zL);
+  fwd_element<INP>(M, yt, zL, d, e);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     S.at(r, tid) = d[r];
@@ -1399,15 +1492,16 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
 // Per tile, down-sweep from the tile's exclusive state to every window: lane k ends with
 // the exclusive state (m^f_{k-1,l}, P^f_{k-1,l}) in (mprev, Pprev) and the inclusive one
 // (m^f_{k,l}, P^f_{k,l}) in (m, P). S needs TILE * max(2 nx, nx + nx^2) scalars.
-template <typename T, int NX, int NY>
-SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T* __restrict__ y, int64_t k,
-                             int64_t N, const T* __restrict__ m0, const T* __restrict__ P0,
+// (yt, zL): window k's measurement and input response (window_meas).
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T (&yt)[NY], const T (&zL)[NX],
+                             int64_t k, const T* __restrict__ m0, const T* __restrict__ P0,
                              const T* __restrict__ tile_state, T (&mprev)[NX], T (&Pprev)[NX][NX], T (&m)[NX],
                              T (&P)[NX][NX]) {
   const int tid = threadIdx.x;
   int flag = 0;
   T d[NX], e[NX];
-  fwd_element(M, y, k, N, d, e);
+  fwd_element<INP>(M, yt, zL, d, e);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     S.at(r, tid) = d[r];
@@ -1497,18 +1591,20 @@ SRTM_DEV int store_carry(int64_t k, const T (&m)[NX], const T (&P)[NX][NX], T* _
 }
 
 // K3 (filter only): per tile, the slow-rate carry and the slow-rate filter outputs.
-template <typename T, int NX, int NY>
-SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
                              const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
                              T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info,
                              int64_t tile) {
   constexpr int ST = NX + NX * NX;
   extern __shared__ char smraw[];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const int64_t k = tile * TILE + threadIdx.x;
+  T yt[NY], zL[NX];
+  window_meas<INP>(M, y, k, N, L, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, tstate + tile * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, tstate + tile * ST, mprev, Pprev, m, P);
   if (k < N) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if (flag && info) atomicOr(info, flag);
 }
@@ -1525,32 +1621,38 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
 //   W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A = Et P_in Et^T + St,
 //   Et = B^T E',  gt = B^T (g' - A m^f_{k,l}),  St = B^T (S' - P^-) B;
 // all three are zero for the last window, whose smoothed blocks equal the filtered ones.
-template <typename T, int NX, int NY>
-SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ ftstate,
                            T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
                            T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info, int64_t tile) {
   constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
   extern __shared__ char smraw[];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
+  T yt[NY], zL[NX];
+  window_meas<INP>(M, y, k, N, L, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states(M, S, y, k, N, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
 
   SElem<T, NX> x;
-  T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T A m^f_{k,l}, B^T P^- B
+  T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T (predicted mean), B^T P^- B
   {
-    T yk[NY];
-#pragma unroll
-    for (int r = 0; r < NY; ++r) yk[r] = valid ? gld(y + k * NY + r) : T(0);
     Window<T, NX, NY> w;
-    if (!window_setup(M, L, mprev, Pprev, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    if (!window_setup(M, L, mprev, Pprev, yt, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    T z1[NX], bnext[NX];  // B u_{k,0} and B u_{k+1,0}
+#pragma unroll
+    for (int r = 0; r < NX; ++r) z1[r] = bnext[r] = T(0);
+    if constexpr (INP) {
+      if (valid) input_drive(M.in, M.in.u + k * L * M.in.nu, z1);
+      if (k + 1 < N) input_drive(M.in, M.in.u + (k + 1) * L * M.in.nu, bnext);
+    }
     T Pmi[NX][NX], mpred[NX], Pm[NX][NX];
-    const int f = smoother_element(M, L, w, k == N - 1, m, P, x, Pmi, mpred, Pm);
+    const int f = smoother_element<INP>(M, L, w, k == N - 1, m, P, z1, bnext, x, Pmi, mpred, Pm);
     if (valid) flag |= f;
     T A[NX][NX];
     load(A, M.cst + M.lay.A);
@@ -1664,8 +1766,9 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
-template <typename T, int NX, int NY, int MODE>
+template <typename T, int NX, int NY, int MODE, bool INP>
 SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
+                           InputView<T> in,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                            const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast,
                            T* __restrict__ Pf_fast, T* __restrict__ ms_fast, T* __restrict__ Ps_fast,
@@ -1675,7 +1778,7 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
   using Stg = OutStage<T, NX>;
   extern __shared__ char smraw[];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const int64_t w0 = tile * TILE + wv * 64;
@@ -1686,10 +1789,18 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   const int64_t kc = valid ? k : 0;   // clamped index for loads of padding lanes
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
-  gloadv(yk, y + kc * NY);
+  if constexpr (INP) {
+    T zL[NX];
+    window_meas<true>(M, y, kc, N, L, yk, zL);
+  } else {
+    gloadv(yk, y + kc * NY);
+  }
   Window<T, NX, NY> w;
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  T z[NX];  // input response z_{k,i} (inputs only)
+#pragma unroll
+  for (int r = 0; r < NX; ++r) z[r] = T(0);
   T v[NX], W[NX][NX];
   if (SMOOTH) {  // v = Et m_in + gt,  W = Et P_in Et^T + St
     const T* src = sfx + kc * SF;
@@ -1723,6 +1834,13 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   for (int i = 1; i <= ilim; ++i) {
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
     window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
+    if constexpr (INP) {
+      T A[NX][NX];
+      load(A, M.cst + M.lay.A);
+      input_step(M.in, A, M.in.u + (kc * L + (i - 1)) * M.in.nu, z);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) mf[r] += z[r];
+    }
     if (FILT) {
       fin = fin && finite_state(mf, Pii);
       fst.put(lane, i, mf, Pii);
@@ -1806,15 +1924,15 @@ SRTM_DEV double wave_sum(double v) {
   return v;
 }
 
-template <typename T, int NX, int NY, bool GRAD>
-SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+template <typename T, int NX, int NY, bool GRAD, bool INP>
+SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
                          const T* __restrict__ Rm, const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                          const T* __restrict__ sfx, const T* __restrict__ tin, double* __restrict__ parts,
                          int32_t* info, int64_t tile, int64_t nt) {
   using SL = StatLayout<NX, NY>;
   constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX), NR = SL::X0;  // reduced components
   __shared__ double red[TILE / 64][NR];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
@@ -1822,7 +1940,13 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
   double* part = parts + tile * SL::SIZE;
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
-  gloadv(yk, y + kc * NY);
+  static_assert(!(GRAD && INP), "the gradient is built without inputs");
+  if constexpr (INP) {
+    T zL[NX];
+    window_meas<true>(M, y, kc, N, L, yk, zL);
+  } else {
+    gloadv(yk, y + kc * NY);
+  }
   Window<T, NX, NY> w;
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
@@ -2182,6 +2306,7 @@ struct Seq {  // one sequence's typed arrays and scan plan
   int L;
   ScanPlan plan;
   int32_t* info;
+  InputView<T> in;
 };
 
 template <typename T, int NX, int NY>
@@ -2218,6 +2343,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.sfx = reinterpret_cast<T*>(base + wl.sfx);
   q.stats = reinterpret_cast<double*>(base + wl.stats);
   q.info = b.info ? b.info + s : nullptr;
+  q.in = InputView<T>{as_global<T>(d.B), as_global<T>(d.u), q.H, d.nu};
   return q;
 }
 
@@ -2229,10 +2355,10 @@ __global__ void __launch_bounds__(256) k_constants(Batch b) {
   constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.info);
 }
 
-template <typename T, int NX, int NY>
+template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_reduce_body<T, NX, NY>(q.y, q.N, q.cst, q.L, q.ftagg, (int64_t)blockIdx.x - q.tile0);
+  fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, (int64_t)blockIdx.x - q.tile0);
 }
 
 template <typename T, int NX, int NY>
@@ -2242,17 +2368,17 @@ __global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
                             q.info);
 }
 
-template <typename T, int NX, int NY>
+template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_final(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_final_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.info,
+  fwd_final_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.info,
                             (int64_t)blockIdx.x - q.tile0);
 }
 
-template <typename T, int NX, int NY>
+template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_bwd(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_bwd_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
+  fwd_bwd_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
                           q.info, (int64_t)blockIdx.x - q.tile0);
 }
 
@@ -2264,20 +2390,20 @@ __global__ void __launch_bounds__(KS) k_bwd_tiles(Batch b) {
 
 // MODE 1: filter outputs only; 2: smoother outputs; 3: both. Fast-rate outputs take all L
 // steps; with only the slow smoothed state requested, step 1 suffices.
-template <typename T, int NX, int NY, int MODE>
+template <typename T, int NX, int NY, int MODE, bool INP>
 __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
   const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
   if (!fast && !q.ms_slow && !q.Ps_slow) return;
-  recover_body<T, NX, NY, MODE>(q.y, q.N, q.L, fast ? q.L : 1, q.cst, q.m0, q.P0, q.carry, q.sfx, q.btst,
+  recover_body<T, NX, NY, MODE, INP>(q.y, q.N, q.L, fast ? q.L : 1, q.cst, q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
                                 q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
                                 (int64_t)blockIdx.x - q.tile0);
 }
 
-template <typename T, int NX, int NY, bool GRAD>
+template <typename T, int NX, int NY, bool GRAD, bool INP>
 __global__ void __launch_bounds__(TILE) k_stats(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  stats_body<T, NX, NY, GRAD>(q.y, q.N, q.L, q.cst, q.R, q.m0, q.P0, q.carry, q.sfx, q.btst, q.stats, q.info,
+  stats_body<T, NX, NY, GRAD, INP>(q.y, q.N, q.L, q.cst, q.in, q.R, q.m0, q.P0, q.carry, q.sfx, q.btst, q.stats, q.info,
                               (int64_t)blockIdx.x - q.tile0, q.plan.nt);
 }
 
@@ -2292,13 +2418,6 @@ __global__ void __launch_bounds__(256) k_stats_final(Batch b, T* ll, T* dF, T* d
 }
 
 // ============================================================================ launchers
-struct Ptrs {
-  const void *F, *Q, *H, *R, *m0, *P0, *y;
-  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow;
-  void *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
-  void* ws;
-  int32_t* info;
-};
 
 struct Events {
   hipEvent_t const* ev;
@@ -2315,12 +2434,6 @@ struct Events {
     return e;
   }
 };
-
-size_t constants_lds_bytes(int nx, int ny, int L) {
-  const int nn = nx * nx, nxy = nx * ny;
-  const int w2s = nn > 2 * nxy ? nn : 2 * nxy;
-  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy) + 19 * nn);
-}
 
 #define SRTM_CHECK_LAUNCH()                    \
   do {                                         \
@@ -2350,13 +2463,13 @@ struct Launch {
 // What follows the scans: the fast-rate recovery (modes 1-3, see k_recover), the
 // log-likelihood alone (REC_LL, after the forward scan) or the log-likelihood and its gradient
 // (REC_GRAD, after both scans); `lo` receives the latter two.
-constexpr int REC_LL = 4, REC_GRAD = 5;
 template <typename T>
 struct LikOut {
   T *ll, *dF, *dQ, *dR;
 };
 
-template <typename T, int NX, int NY>
+// INP: the call has known inputs (every sequence of it).
+template <typename T, int NX, int NY, bool INP>
 srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_mode, hipStream_t st, Events ev,
                        LikOut<T> lo = LikOut<T>{nullptr, nullptr, nullptr, nullptr}) {
   constexpr int NN = NX * NX;
@@ -2368,7 +2481,7 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   SRTM_EV(ev.post(st));
 
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -2382,18 +2495,18 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES * ((rec_mode == 3) ? 2 : 1);
   if (!smoother) {
     const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
-    if (!allow_lds((const void*)k_fwd_final<T, NX, NY>, lds_ff)) return SRTM_E_HIP;
+    if (!allow_lds((const void*)k_fwd_final<T, NX, NY, INP>, lds_ff)) return SRTM_E_HIP;
     SRTM_EV(ev.pre(st));
-    hipLaunchKernelGGL((k_fwd_final<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds_ff, st, b);
+    hipLaunchKernelGGL((k_fwd_final<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_ff, st, b);
     SRTM_CHECK_LAUNCH();
     SRTM_EV(ev.post(st));
     SRTM_EV(ev.pre(st));
     if (rec_mode == 1) {
-      if (!allow_lds((const void*)k_recover<T, NX, NY, 1>, lds_rec)) return SRTM_E_HIP;
-      hipLaunchKernelGGL((k_recover<T, NX, NY, 1>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+      if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds_rec)) return SRTM_E_HIP;
+      hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
       SRTM_CHECK_LAUNCH();
     } else if (rec_mode == REC_LL) {
-      hipLaunchKernelGGL((k_stats<T, NX, NY, false>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+      hipLaunchKernelGGL((k_stats<T, NX, NY, false, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
       SRTM_CHECK_LAUNCH();
       hipLaunchKernelGGL((k_stats_final<T, NX, NY, false>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
                          lo.dR);
@@ -2404,9 +2517,9 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   }
 
   const size_t lds_fb = sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN);
-  if (!allow_lds((const void*)k_fwd_bwd<T, NX, NY>, lds_fb)) return SRTM_E_HIP;
+  if (!allow_lds((const void*)k_fwd_bwd<T, NX, NY, INP>, lds_fb)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds_fb, st, b);
+  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_fb, st, b);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -2419,26 +2532,30 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
 
   SRTM_EV(ev.pre(st));
   if (rec_mode == REC_GRAD) {
-    hipLaunchKernelGGL((k_stats<T, NX, NY, true>), dim3(g.ntiles), dim3(TILE), 0, st, b);
-    SRTM_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
-                       lo.dR);
-    SRTM_CHECK_LAUNCH();
+    if constexpr (INP) {
+      return SRTM_E_UNSUPPORTED;  // the gradient is built without inputs
+    } else {
+      hipLaunchKernelGGL((k_stats<T, NX, NY, true, false>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+      SRTM_CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
+                         lo.dR);
+      SRTM_CHECK_LAUNCH();
+    }
   } else if (rec_mode == 2) {
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 2>, lds_rec)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 2>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds_rec)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
     SRTM_CHECK_LAUNCH();
   } else if (rec_mode == 3 && lds_rec <= kMaxLdsBytes) {
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 3>, lds_rec)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 3>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 3, INP>, lds_rec)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 3, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
     SRTM_CHECK_LAUNCH();
   } else if (rec_mode == 3) {  // filter and smoother staging do not fit together: two passes
     const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES;
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 1>, lds1)) return SRTM_E_HIP;
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 2>, lds1)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 1>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds1)) return SRTM_E_HIP;
+    if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds1)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
     SRTM_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 2>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+    hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
     SRTM_CHECK_LAUNCH();
   }
   SRTM_EV(ev.post(st));
@@ -2463,12 +2580,17 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   d.ws_off = 0;
   d.L = sh.L;
   d.smoother = smoother ? 1 : 0;
+  d.B = p.B;
+  d.u = p.u;
+  d.nu = p.B ? p.nu : 0;
+  d.reserved = 0;
   const Launch g{1u, (unsigned)((sh.N + TILE - 1) / TILE), (int)sh.L};
   const bool want_f = p.mf_fast || p.Pf_fast;
   const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
   const int mode = lik_mode ? lik_mode : (smoother ? (want_f ? 3 : (want_s ? 2 : 0)) : (want_f ? 1 : 0));
   const LikOut<T> lo{static_cast<T*>(ll), static_cast<T*>(dF), static_cast<T*>(dQ), static_cast<T*>(dR)};
-  return launch_all<T, NX, NY>(b, g, smoother, mode, st, ev, lo);
+  if (p.B) return launch_all<T, NX, NY, true>(b, g, smoother, mode, st, ev, lo);
+  return launch_all<T, NX, NY, false>(b, g, smoother, mode, st, ev, lo);
 }
 
 // Many sequences (srtm_smooth_batch): `table` holds nseq descriptors followed by the sequence
@@ -2482,56 +2604,31 @@ srtm_status run_batch(const void* table, int nseq, int64_t ntiles, int max_L, vo
   b.ws = static_cast<char*>(ws);
   b.info = info;
   const Launch g{(unsigned)nseq, (unsigned)ntiles, max_L};
-  return launch_all<T, NX, NY>(b, g, true, grad ? REC_GRAD : 2, st, Events{nullptr, 0, 0});
+  return launch_all<T, NX, NY, false>(b, g, true, grad ? REC_GRAD : 2, st, Events{nullptr, 0, 0});
 }
 
 }  // namespace srtm
 
-// ---------------------------------------------------------------- dispatch (C++ linkage)
-#define SRTM_PAIRS(X) X(1, 1) X(2, 1) X(2, 2) X(3, 1) X(3, 2) X(4, 1) X(4, 2) X(6, 1)
+// ---------------------------------------------------------------- this object's (nx, ny) pair
+#if !defined(SRTM_NX) || !defined(SRTM_NY)
+#error "srtm_kernels.hip is compiled once per (nx, ny) pair: define SRTM_NX and SRTM_NY"
+#endif
+#define SRTM_NAME2(p, a, b) p##a##_##b
+#define SRTM_NAME(p, a, b) SRTM_NAME2(p, a, b)
 
 namespace srtm {
-bool pair_supported(int nx, int ny) {
-#define SRTM_SUP(a, b) if (nx == a && ny == b) return true;
-  SRTM_PAIRS(SRTM_SUP)
-#undef SRTM_SUP
-  return false;
+srtm_status SRTM_NAME(run_pair_, SRTM_NX, SRTM_NY)(int dtype, const srtm_shape& sh, const Ptrs& p, bool smoother,
+                                                   hipStream_t st, hipEvent_t const* ev, int nev, int lik_mode,
+                                                   void* ll, void* dF, void* dQ, void* dR) {
+  const Events E{ev, nev, 0};
+  if (dtype == SRTM_F64) return run<double, SRTM_NX, SRTM_NY>(sh, p, smoother, st, E, lik_mode, ll, dF, dQ, dR);
+  return run<float, SRTM_NX, SRTM_NY>(sh, p, smoother, st, E, lik_mode, ll, dF, dQ, dR);
 }
 
-srtm_status dispatch(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, hipEvent_t const* ev,
-                     int nev) {
-  Events E{ev, nev, 0};
-#define SRTM_DISP(a, b)                                                            \
-  if (sh.nx == a && sh.ny == b) {                                                  \
-    if (sh.dtype == SRTM_F64) return run<double, a, b>(sh, p, smoother, st, E);   \
-    return run<float, a, b>(sh, p, smoother, st, E);                               \
-  }
-  SRTM_PAIRS(SRTM_DISP)
-#undef SRTM_DISP
-  return SRTM_E_UNSUPPORTED;
-}
-srtm_status dispatch_lik(const srtm_shape& sh, const Ptrs& p, bool grad, void* ll, void* dF, void* dQ, void* dR,
-                         hipStream_t st) {
-  Events E{nullptr, 0, 0};
-#define SRTM_DISPL(a, b)                                                                                  \
-  if (sh.nx == a && sh.ny == b) {                                                                        \
-    if (sh.dtype == SRTM_F64) return run<double, a, b>(sh, p, grad, st, E, grad ? REC_GRAD : REC_LL, ll, dF, dQ, dR); \
-    return run<float, a, b>(sh, p, grad, st, E, grad ? REC_GRAD : REC_LL, ll, dF, dQ, dR);               \
-  }
-  SRTM_PAIRS(SRTM_DISPL)
-#undef SRTM_DISPL
-  return SRTM_E_UNSUPPORTED;
-}
-
-srtm_status dispatch_batch(int nx, int ny, int dtype, const void* table, int nseq, int64_t ntiles, int max_L,
-                           void* ws, int32_t* info, hipStream_t st, bool grad) {
-#define SRTM_DISPB(a, b)                                                                                  \
-  if (nx == a && ny == b) {                                                                              \
-    if (dtype == SRTM_F64) return run_batch<double, a, b>(table, nseq, ntiles, max_L, ws, info, st, grad); \
-    return run_batch<float, a, b>(table, nseq, ntiles, max_L, ws, info, st, grad);                        \
-  }
-  SRTM_PAIRS(SRTM_DISPB)
-#undef SRTM_DISPB
-  return SRTM_E_UNSUPPORTED;
+srtm_status SRTM_NAME(run_batch_pair_, SRTM_NX, SRTM_NY)(int dtype, const void* table, int nseq, int64_t ntiles,
+                                                         int max_L, void* ws, int32_t* info, hipStream_t st,
+                                                         bool grad) {
+  if (dtype == SRTM_F64) return run_batch<double, SRTM_NX, SRTM_NY>(table, nseq, ntiles, max_L, ws, info, st, grad);
+  return run_batch<float, SRTM_NX, SRTM_NY>(table, nseq, ntiles, max_L, ws, info, st, grad);
 }
 }  // namespace srtm

@@ -70,6 +70,13 @@ inline __host__ __device__ ConstLayout make_const_layout(int nx, int ny, int L, 
   return c;
 }
 
+// Dynamic LDS of the constants kernel (float64 per-step tables and level-chain scratch).
+inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
+  const int nn = nx * nx, nxy = nx * ny;
+  const int w2s = nn > 2 * nxy ? nn : 2 * nxy;
+  return sizeof(double) * (size_t)(2 * nn + nxy + ny * ny + (L + 1) * (3 * nn + w2s + nxy) + 19 * nn);
+}
+
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
   size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, total;
@@ -115,6 +122,9 @@ struct SeqDesc {
   uint64_t ws_off;   // byte offset of the sequence's workspace block (256-byte aligned)
   int32_t L;
   int32_t smoother;  // the block holds the smoother regions
+  const void *B, *u;  // known inputs (null without)
+  int32_t nu;
+  int32_t reserved;
 };
 
 // What every kernel receives: either one sequence (`table` null) or a device table of

@@ -37,6 +37,12 @@ class SeqC(ctypes.Structure):
                 [("N", ctypes.c_int64), ("L", ctypes.c_int32), ("reserved", ctypes.c_int32)])
 
 
+class InputsC(ctypes.Structure):
+    """srtm_inputs: known inputs B [nx][nu] and u [N][L][nu] (device pointers)."""
+    _fields_ = [("B", ctypes.c_void_p), ("u", ctypes.c_void_p), ("nu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+MAX_NU = 4
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -74,6 +80,13 @@ def lib():
     L.srtm_loglik.restype = ctypes.c_int
     L.srtm_loglik_grad.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_loglik_grad.restype = ctypes.c_int
+    _si = [ctypes.POINTER(Shape), ctypes.POINTER(InputsC)]
+    L.srtm_filter_inputs.argtypes = _si + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_filter_inputs.restype = ctypes.c_int
+    L.srtm_smooth_inputs.argtypes = _si + [_vp] * 16 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth_inputs.restype = ctypes.c_int
+    L.srtm_loglik_inputs.argtypes = _si + [_vp] * 9 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_loglik_inputs.restype = ctypes.c_int
     L.srtm_kernel_count.argtypes = [ctypes.c_int32]
     L.srtm_kernel_count.restype = ctypes.c_int32
     L.srtm_kernel_name.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -139,6 +152,23 @@ def _prep(F, Q, H, R, L, m0, P0, y):
     return ts, nx, ny, N
 
 
+def _prep_inputs(B, u, nx: int, L: int, N: int, y: torch.Tensor):
+    """Validated (contiguous B, contiguous u, srtm_inputs) for known inputs, or None without."""
+    if B is None and u is None:
+        return None
+    if B is None or u is None:
+        raise SrtmError("known inputs need both B [nx, nu] and u [N, L, nu]")
+    for k, t in (("B", B), ("u", u)):
+        if not isinstance(t, torch.Tensor) or t.device != y.device or t.dtype != y.dtype:
+            raise SrtmError(f"{k} must be a tensor on {y.device} of dtype {y.dtype}")
+    nu = B.shape[1] if B.dim() == 2 else -1
+    if tuple(B.shape) != (nx, nu) or tuple(u.shape) != (N, L, nu) or not 1 <= nu <= MAX_NU:
+        raise SrtmError(f"inputs: B {tuple(B.shape)} and u {tuple(u.shape)} must be [{nx}, nu] and "
+                        f"[{N}, {L}, nu] with 1 <= nu <= {MAX_NU}")
+    B, u = B.contiguous(), u.contiguous()
+    return B, u, InputsC(B.data_ptr(), u.data_ptr(), nu, 0)
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -152,9 +182,12 @@ def _raise_info(info: torch.Tensor, what: str):
 
 def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = True,
            workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
-           check: bool = True) -> Dict[str, torch.Tensor]:
-    """p(x_{k,i} | y_{1:k}) as m_fast [N,L,nx], P_fast [N,L,nx,nx]; p(x_{k,L} | y_{1:k}) as m_slow, P_slow."""
+           check: bool = True, B=None, u=None) -> Dict[str, torch.Tensor]:
+    """p(x_{k,i} | y_{1:k}) as m_fast [N,L,nx], P_fast [N,L,nx,nx]; p(x_{k,L} | y_{1:k}) as m_slow, P_slow.
+
+    B [nx, nu] and u [N, L, nu] add known inputs (u[k-1, i-1] drives x_{k,i})."""
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    inp = _prep_inputs(B, u, nx, L, N, y)
     dev, dt = y.device, y.dtype
     out = {}
     if fast:
@@ -170,11 +203,13 @@ def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
         info = torch.zeros(1, device=dev, dtype=torch.int32)
     sh = shape_of(nx, ny, L, N, dt)
     stream = torch.cuda.current_stream(dev).cuda_stream
-    code = lib().srtm_filter(ctypes.byref(sh), *(_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")),
-                             _ptr(out.get("m_fast")), _ptr(out.get("P_fast")), _ptr(out.get("m_slow")),
-                             _ptr(out.get("P_slow")), _ptr(workspace), workspace.numel(), _ptr(info),
-                             ctypes.c_void_p(stream))
-    _check(code, "srtm_filter")
+    args = ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
+            [_ptr(out.get(k)) for k in ("m_fast", "P_fast", "m_slow", "P_slow")] +
+            [_ptr(workspace), workspace.numel(), _ptr(info), ctypes.c_void_p(stream)])
+    if inp is None:
+        _check(lib().srtm_filter(ctypes.byref(sh), *args), "srtm_filter")
+    else:
+        _check(lib().srtm_filter_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *args), "srtm_filter_inputs")
     if check:
         _raise_info(info, "srtm_filter")
     out["info"] = info
@@ -191,14 +226,17 @@ def _smooth_args(ts, out, workspace, info):
 def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = True, with_filter: bool = False,
            workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
            out: Optional[Dict[str, torch.Tensor]] = None, check: bool = True,
-           events=None) -> Dict[str, torch.Tensor]:
+           events=None, B=None, u=None) -> Dict[str, torch.Tensor]:
     """p(x_{k,i} | y_{1:N}) as ms_fast [N,L,nx], Ps_fast [N,L,nx,nx]; p(x_{k,1} | y_{1:N}) as ms_slow, Ps_slow.
 
     with_filter also returns the filter outputs (mf_fast, Pf_fast, mf_slow, Pf_slow). `out` may
     supply preallocated output tensors; `events` (a ctypes array of hipEvent_t) selects the
-    profiling entry point.
+    profiling entry point. B [nx, nu] and u [N, L, nu] add known inputs (u[k-1, i-1] drives x_{k,i}).
     """
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    inp = _prep_inputs(B, u, nx, L, N, y)
+    if inp is not None and events is not None:
+        raise SrtmError("the profiling entry point takes no inputs")
     dev, dt = y.device, y.dtype
     if out is None:
         out = {}
@@ -221,7 +259,10 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     sh = shape_of(nx, ny, L, N, dt)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     args = _smooth_args(ts, out, workspace, info)
-    if events is None:
+    if inp is not None:
+        code = lib().srtm_smooth_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *args, stream)
+        _check(code, "srtm_smooth_inputs")
+    elif events is None:
         code = lib().srtm_smooth(ctypes.byref(sh), *args, stream)
         _check(code, "srtm_smooth")
     else:
@@ -233,8 +274,11 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     return out
 
 
-def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool):
+def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    inp = _prep_inputs(B, u, nx, L, N, y)
+    if inp is not None and grad:
+        raise SrtmError("the log-likelihood gradient takes no inputs")
     dev, dt = y.device, y.dtype
     ll = torch.empty(1, device=dev, dtype=dt)
     dF = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None
@@ -249,6 +293,10 @@ def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool):
         code = lib().srtm_loglik_grad(ctypes.byref(sh), *ins, _ptr(ll), _ptr(dF), _ptr(dQ), _ptr(dR), _ptr(ws),
                                       ws.numel(), _ptr(info), stream)
         _check(code, "srtm_loglik_grad")
+    elif inp is not None:
+        code = lib().srtm_loglik_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *ins, _ptr(ll), _ptr(ws), ws.numel(),
+                                        _ptr(info), stream)
+        _check(code, "srtm_loglik_inputs")
     else:
         code = lib().srtm_loglik(ctypes.byref(sh), *ins, _ptr(ll), _ptr(ws), ws.numel(), _ptr(info), stream)
         _check(code, "srtm_loglik")
@@ -257,9 +305,9 @@ def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool):
     return ll[0], dF, dQ, dR
 
 
-def loglik(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True) -> torch.Tensor:
-    """log p(y_{1:N}) (a 0-d tensor on the device)."""
-    return _lik(F, Q, H, R, L, m0, P0, y, False, check)[0]
+def loglik(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True, B=None, u=None) -> torch.Tensor:
+    """log p(y_{1:N}) (a 0-d tensor on the device); B, u: optional known inputs as in filter()."""
+    return _lik(F, Q, H, R, L, m0, P0, y, False, check, B, u)[0]
 
 
 def loglik_grad(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True):

@@ -124,6 +124,41 @@ def test_rejects_bad_shape_and_dtype(L):
     assert L.srtm_smooth(None, *([None] * 16), 0, None, None) == 1
 
 
+def _call_inputs(fn, sh, inp, ptrs, ws_bytes, n_out):
+    _no_gpu()
+    P = [ctypes.c_void_p(p) if p else None for p in ptrs]
+    args = [ctypes.byref(sh), None if inp is None else ctypes.byref(inp)] + P[:7] + [None] * n_out
+    return fn(*args, P[7], ws_bytes, None, None)
+
+
+@pytest.mark.parametrize("name,n_out", [("srtm_filter_inputs", 4), ("srtm_smooth_inputs", 8)])
+def test_inputs_entry_points_validate(L, name, n_out):
+    fn = getattr(L, name)
+    sh = srtm.Shape(2, 1, 10, 1, 5)
+    ok = srtm.InputsC(0x9000, 0xA000, 2, 0)
+    assert _call_inputs(fn, sh, None, FAKE, 1 << 30, n_out) == 1                                # no inputs struct
+    assert _call_inputs(fn, sh, srtm.InputsC(0, 0xA000, 2, 0), FAKE, 1 << 30, n_out) == 1       # B missing
+    assert _call_inputs(fn, sh, srtm.InputsC(0x9000, 0, 2, 0), FAKE, 1 << 30, n_out) == 1       # u missing
+    assert _call_inputs(fn, sh, srtm.InputsC(0x9000, 0xA000, 0, 0), FAKE, 1 << 30, n_out) == 2  # nu = 0
+    assert _call_inputs(fn, sh, srtm.InputsC(0x9000, 0xA000, 5, 0), FAKE, 1 << 30, n_out) == 2  # nu > max
+    assert _call_inputs(fn, sh, srtm.InputsC(0x9000, 0xA000, 2, 1), FAKE, 1 << 30, n_out) == 2  # reserved
+    assert _call_inputs(fn, sh, srtm.InputsC(0x9008, 0xA000, 2, 0), FAKE, 1 << 30, n_out) == 5  # misaligned B
+    assert _call_inputs(fn, sh, ok, FAKE, 16, n_out) == 6                                        # workspace
+    assert _call_inputs(fn, srtm.Shape(7, 1, 10, 1, 5), ok, FAKE, 1 << 30, n_out) == 4          # pair
+
+
+def test_loglik_inputs_validates(L):
+    _no_gpu()
+    sh = srtm.Shape(2, 1, 10, 1, 5)
+    P = [ctypes.c_void_p(p) for p in FAKE]
+    ll = ctypes.c_void_p(0xB000)
+    assert L.srtm_loglik_inputs(ctypes.byref(sh), None, *P[:7], ll, P[7], 1 << 30, None, None) == 1
+    bad = srtm.InputsC(0x9000, 0xA000, 9, 0)
+    assert L.srtm_loglik_inputs(ctypes.byref(sh), ctypes.byref(bad), *P[:7], ll, P[7], 1 << 30, None, None) == 2
+    ok = srtm.InputsC(0x9000, 0xA000, 1, 0)
+    assert L.srtm_loglik_inputs(ctypes.byref(sh), ctypes.byref(ok), *P[:7], ll, P[7], 16, None, None) == 6
+
+
 def test_profiled_requires_events(L):
     sh = srtm.Shape(2, 1, 10, 1, 5)
     P = [ctypes.c_void_p(p) for p in FAKE]
@@ -218,3 +253,19 @@ def test_smooth_batch_rejects_small_workspace_and_bad_table(L):
     assert L.srtm_smooth_batch(4, 2, 1, 2, host, fake_dev, fake_ws, wsz, None, None) == 2
     assert L.srtm_smooth_batch(4, 2, 1, 2, None, fake_dev, fake_ws, wsz, None, None) == 1
     assert L.srtm_smooth_batch(4, 2, 1, 2, host, ctypes.c_void_p(0x4000008), fake_ws, wsz, None, None) == 5
+
+
+def test_smooth_batch_rejects_descriptors_with_inputs(L):
+    """Batch descriptors carry no inputs: a table whose descriptor names inputs is refused."""
+    _no_gpu()
+    arr = _seqs([(300, 5)])
+    _, tsz, wsz, nt, _ = _plan(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    # descriptor layout: 15 pointers, N, tile0, ws_off (8 bytes each), L, smoother (4 each), then B
+    off_B = 15 * 8 + 3 * 8 + 2 * 4
+    assert bytes(buf[off_B:off_B + 8]) == bytes(8)
+    ctypes.c_uint64.from_buffer(buf, off_B).value = 0x9000
+    host = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.srtm_smooth_batch(4, 2, 1, 1, host, ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x8000000), wsz,
+                               None, None) == 2
