@@ -135,6 +135,27 @@ def run_batched(args):
     # the two paths must agree bitwise (same kernels on the same tiles)
     same = all(torch.equal(runner.outputs[j][k], plain[j][2][k]) for j in range(len(problems))
                for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"))
+    check64 = None
+    if dt == torch.float32:
+        # FP64 check run: the same batch (inputs as rounded to float32) on the float64 path
+        p64 = [tuple(t.double() if isinstance(t, torch.Tensor) else t for t in pr) for pr in problems]
+        r64 = batching.BatchRunner(p64)
+        r64.zero_info()
+        r64.run()
+        r64.check()
+        out64 = r64.outputs
+        torch.cuda.synchronize()
+        em = ep = 0.0
+        for j, o in enumerate(out64):
+            a, r = runner.outputs[j], o
+            m32, P32 = a["ms_fast"].double(), a["Ps_fast"].double()
+            m64, P64 = r["ms_fast"], r["Ps_fast"]
+            tr = torch.diagonal(P64, dim1=-2, dim2=-1).sum(-1).clamp_min(0).sqrt()
+            den = torch.maximum(m64.norm(dim=-1), tr)
+            em = max(em, float(((m32 - m64).norm(dim=-1) / den).max()))
+            ep = max(ep, float(((P32 - P64).flatten(-2).norm(dim=-1) / P64.flatten(-2).norm(dim=-1)).max()))
+        check64 = {"max_rel_err_mean": em, "max_rel_err_cov": ep, "tol": 1e-3,
+                   "metric": "per fast state: |m - m64| / max(|m64|, sqrt tr P64), |P - P64|_F / |P64|_F"}
     line = {"metric": "fast-rate smoothed states/sec (filter+smoother), 256 uneven sequences batched",
             "value": round(fast_states / t_batch), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
             "steps": steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 4),
@@ -147,7 +168,64 @@ def run_batched(args):
             "tuned": runner.describe(), "candidates": log,
             "plain_per_sequence": {"ms_per_pass": round(t_plain * 1e3, 4),
                                    "value": round(fast_states / t_plain), "bitwise_equal_to_batched": same},
-            "speedup_vs_plain": round(t_plain / t_batch, 2)}
+            "speedup_vs_plain": round(t_plain / t_batch, 2), "fp64_check": check64}
+    print(json.dumps(line))
+
+
+def run_inputs(args):
+    """The long-sequence workload (nx=4, ny=2, L=20, N=2^17) with two known inputs per fast step
+    (x_t = A x_{t-1} + B u_{t-1} + w_{t-1}), against the same call without inputs."""
+    import torch
+    from paper_2410_00627_amd import srtm, workloads as wl
+    dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m = wl.headline_model()
+    N = args.N or wl.HEADLINE_N
+    nu = 2
+    B, u = wl.random_inputs(m.nx, nu, m.L, N, 2025)
+    y = wl.simulate(m, N, 2026, B=B, u=u)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, dev, dt)
+    conv = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev, dt).contiguous()  # noqa: E731
+    yt, Bt, ut = conv(y), conv(B), conv(u)
+    nx, L = m.nx, m.L
+    out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+           "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+           "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+           "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
+    ws = torch.empty(srtm.workspace_size(nx, m.ny, L, N, dt, True), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+
+    def timed(with_inputs):
+        kw = dict(B=Bt, u=ut) if with_inputs else {}
+        for _ in range(args.warmup):
+            srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, **kw)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, **kw)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / args.steps
+
+    t_plain = timed(False)
+    t_in = timed(True)
+    if int(info.item()) != 0:
+        raise RuntimeError(f"numerical failure: info={int(info.item())}")
+    esz = 8 if dt == torch.float64 else 4
+    fast_states = N * L
+    line = {"metric": "fast-rate smoothed states/sec (filter+smoother) with known inputs",
+            "value": round(fast_states / t_in), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_in * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+            "config": {"workload": "one sequence, nx=4, ny=2, L=20, N=2^17, A=0.99*Haar, Q=0.01I, C Gaussian, "
+                                   "R=0.05I, nu=2 inputs: B ~ N(0,1), u = sin + 0.5 N(0,1)",
+                       "N": N, "L": L, "nu": nu, "fast_states": fast_states,
+                       "input_bytes_per_call": int(N * L * nu * esz)},
+            "without_inputs_ms_per_step": round(t_plain * 1e3, 4),
+            "cost_of_inputs": round(t_in / t_plain, 3)}
     print(json.dumps(line))
 
 
@@ -250,7 +328,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs"], default="headline",
                     help="headline: one long sequence (default); batched: 256 uneven sequences; "
                          "serving: Poisson arrivals with continuous batching")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: length of the arrival process")
@@ -274,6 +352,8 @@ def main():
         return run_batched(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "inputs":
+        return run_inputs(args)
     if args.workload == "gradient":
         return run_gradient(args)
     args.dtype = args.dtype or "f64"

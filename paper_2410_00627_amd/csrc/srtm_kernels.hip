@@ -78,6 +78,150 @@ SRTM_DEV double cofactor(const double* M, int r, int c) {
   }
 }
 
+// Level chain over levels p0 .. p1-1, run by wave 0 of a workgroup (one lane per matrix entry).
+// `chain` is 19 nx^2 doubles of LDS whose first 3 nx^2 hold F, D, J of Theta(2^p0). Writes the
+// level records p0 .. p1-1 and, when p1 < nlev, F, D, J of Theta(2^p1) in float64 to `hand`
+// (3 nx^2 doubles), where a continuation of the chain in a later launch picks them up.
+//   Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, W = (I + D J)^{-1}, and the
+// coefficients that combine the vector parts of two runs of 2^p elements:
+//   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
+//   G1 = F W, G2 = F W D, G3 = (W F)^T, G4 = (W F)^T J.
+// W is the adjugate of I + D J over its determinant, with one cofactor per lane (nx <= 4).
+template <typename T, int NX>
+SRTM_DEV int level_chain(double* chain, T* __restrict__ cst, const ConstLayout& lay, int p0, int p1, int nlev,
+                         double* __restrict__ hand) {
+  constexpr int NN = NX * NX;
+  double* rec = chain;
+  double* nrec = chain + 7 * NN;
+  double* sM = chain + 14 * NN;
+  double* sCof = sM + NN;
+  double* sW = sCof + NN;
+  double* sWF = sW + NN;
+  double* sXD = sWF + NN;
+  int lflag = 0;
+  const int e = threadIdx.x;
+  for (int p = p0; p < p1; ++p) {
+    const double* F = rec;
+    const double* D = rec + NN;
+    const double* J = rec + 2 * NN;
+    for (int o = e; o < NN; o += 64) {  // M = I + D J
+      const int er = o / NX, ec = o % NX;
+      double acc = (er == ec) ? 1.0 : 0.0;
+      for (int k = 0; k < NX; ++k) acc += D[er * NX + k] * J[k * NX + ec];
+      sM[o] = acc;
+    }
+    wave_sync();
+    if constexpr (NX <= 4) {
+      if (e < NN) sCof[e] = cofactor<NX>(sM, e / NX, e % NX);
+      wave_sync();
+      if (e < NN) {  // W = adj(M) / det(M), adj(M)[r][c] = C[c][r]
+        double det = 0.0;
+        for (int c = 0; c < NX; ++c) det += sM[c] * sCof[c];
+        const double id = rcp_nr(det);
+        if (e == 0 && !(det != 0.0 && isfinite(id))) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+        sW[e] = sCof[(e % NX) * NX + e / NX] * id;
+      }
+    } else {  // larger states: one lane, Gaussian elimination with partial pivoting
+      if (e == 0) {
+        double Mr[NX][NX], Wr[NX][NX];
+        for (int r = 0; r < NX; ++r)
+          for (int c = 0; c < NX; ++c) Mr[r][c] = sM[r * NX + c];
+        if (!inv_small(Mr, Wr)) lflag |= SRTM_INFO_COMBINE_SINGULAR;
+        for (int r = 0; r < NX; ++r)
+          for (int c = 0; c < NX; ++c) sW[r * NX + c] = Wr[r][c];
+      }
+    }
+    wave_sync();
+    for (int q = e; q < 3 * NN; q += 64) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
+      double acc = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) acc += sW[er * NX + k] * F[k * NX + ec];
+        sWF[o] = acc;
+        rec[5 * NN + ec * NX + er] = acc;
+      } else if (part == 1) {
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sW[k * NX + ec];
+        rec[3 * NN + o] = acc;
+      } else {
+        double acc2 = 0.0;
+        for (int k = 0; k < NX; ++k) {
+          acc += sW[er * NX + k] * D[k * NX + ec];
+          acc2 += sW[ec * NX + k] * D[k * NX + er];
+        }
+        sXD[o] = 0.5 * (acc + acc2);
+      }
+    }
+    wave_sync();
+    for (int q = e; q < 3 * NN; q += 64) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
+      double acc = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sXD[k * NX + ec];
+        rec[4 * NN + o] = acc;
+      } else if (part == 1) {
+        for (int k = 0; k < NX; ++k) acc += sWF[k * NX + er] * J[k * NX + ec];
+        rec[6 * NN + o] = acc;
+      } else {
+        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sWF[k * NX + ec];
+        nrec[o] = acc;
+      }
+    }
+    wave_sync();
+    for (int q = e; q < 2 * NN; q += 64) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
+      const double* G2 = rec + 4 * NN;
+      const double* G4 = rec + 6 * NN;
+      double acc = 0.0, acc2 = 0.0;
+      if (part == 0) {
+        for (int k = 0; k < NX; ++k) {
+          acc += G2[er * NX + k] * F[ec * NX + k];
+          acc2 += G2[ec * NX + k] * F[er * NX + k];
+        }
+        nrec[NN + o] = 0.5 * (acc + acc2) + D[o];
+      } else {
+        for (int k = 0; k < NX; ++k) {
+          acc += G4[er * NX + k] * F[k * NX + ec];
+          acc2 += G4[ec * NX + k] * F[k * NX + er];
+        }
+        nrec[2 * NN + o] = 0.5 * (acc + acc2) + J[o];
+      }
+    }
+    T* dst = cst + lay.lev + p * lay.lev_stride;  // the level record, as laid out in LDS
+    for (int q = e; q < 7 * NN; q += 64) dst[q] = (T)rec[q];
+    wave_sync();
+    double* t = rec;
+    rec = nrec;
+    nrec = t;
+  }
+  if (p1 < nlev) {
+    for (int q = threadIdx.x; q < 3 * NN; q += 64) put_global(hand + q, rec[q]);
+  }
+  return lflag;
+}
+
+// Levels 0 .. CHAIN_SPLIT-1 come from the constants kernel (the in-tile scans need levels below
+// LOG_TILE); the rest, which only the tile-level scan uses, from one workgroup of the
+// tile-reduction launch, so that they are computed while the tiles are reduced.
+constexpr int CHAIN_SPLIT = LOG_TILE + 2;
+static_assert(CHAIN_SPLIT >= LOG_TILE, "the tile reductions read levels below LOG_TILE");
+
+// The rest of the level chain (levels CHAIN_SPLIT .. nlev-1), continued from the handed-over
+// Theta(2^CHAIN_SPLIT). The wave runs at raised priority: it shares its SIMD with reductions.
+template <typename T, int NX, int NY>
+SRTM_DEV void chain_tail_body(T* __restrict__ cst, const double* __restrict__ hand, int L, int nlev,
+                              int32_t* info) {
+  constexpr int NN = NX * NX;
+  __shared__ double chain[19 * NN];
+  const int tid = threadIdx.x;
+  if (tid >= 64 || nlev <= CHAIN_SPLIT) return;
+  __builtin_amdgcn_s_setprio(3);
+  for (int q = tid; q < 3 * NN; q += 64) chain[q] = gld(hand + q);
+  wave_sync();
+  const ConstLayout lay = make_const_layout(NX, NY, L, nlev);
+  const int f = level_chain<T, NX>(chain, cst, lay, CHAIN_SPLIT, nlev, nlev, nullptr);
+  if (f && info) atomicOr(info, f);
+}
+
 // One workgroup, float64 throughout. Per-step tables are built in LDS by parallel
 // loops; the slow-rate constants and the level tables by one lane in registers.
 //
@@ -88,7 +232,8 @@ SRTM_DEV double cofactor(const double* M, int r, int c) {
 //   Q_bar = Q_ll, A_bar = A^l   (eq. h-k-l-2, eq. y-k-l-2 and eq. a-k-f).
 template <typename T, int NX, int NY>
 SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
-                             const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst, int32_t* info) {
+                             const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst,
+                             double* __restrict__ hand, int32_t* info) {
   constexpr int NN = NX * NX, NXY = NX * NY;
   constexpr int W2S = (NN > 2 * NXY ? NN : 2 * NXY);
   extern __shared__ double sm[];
@@ -238,16 +383,8 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
   }
   __syncthreads();
   if (tid >= 64) return;  // the rest is done by wave 0
-  // Level records (F, D, J, G1, G2, G3, G4 of Theta(2^p), the global layout of one level),
-  // double-buffered: the next level's F, D, J are formed directly in the other record.
-  double* rec = chain;
-  double* nrec = chain + 7 * NN;
-  double* sM = chain + 14 * NN;
-  double* sCof = sM + NN;
-  double* sW = sCof + NN;
-  double* sWF = sW + NN;
-  double* sXD = sWF + NN;
   int lflag = 0;
+  double* rec = chain;  // the chain's F, D, J of Theta(1): the generic element
   if (tid == 0) {
     // ------------------------------------------------------------ generic element (one lane)
     double Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
@@ -294,107 +431,9 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
       }
   }
   wave_sync();
-  // ------------------------------------------------------------ level chain (wave 0)
-  // Theta(2^{p+1}) = Theta(2^p) (x) Theta(2^p) under eq. op-filter, W = (I + D J)^{-1}, and the
-  // coefficients that combine the vector parts of two runs of 2^p elements:
-  //   d_ij = G1 d_i + G2 eta_j + d_j,   eta_ij = G3 eta_j - G4 d_i + eta_i,
-  //   G1 = F W, G2 = F W D, G3 = (W F)^T, G4 = (W F)^T J.
-  // One lane per matrix entry; W is the adjugate of I + D J over its determinant, with one
-  // cofactor per lane.
-  const int e = tid;
-  for (int p = 0; p < nlev; ++p) {
-    const double* F = rec;
-    const double* D = rec + NN;
-    const double* J = rec + 2 * NN;
-    for (int o = e; o < NN; o += 64) {  // M = I + D J
-      const int er = o / NX, ec = o % NX;
-      double acc = (er == ec) ? 1.0 : 0.0;
-      for (int k = 0; k < NX; ++k) acc += D[er * NX + k] * J[k * NX + ec];
-      sM[o] = acc;
-    }
-    wave_sync();
-    if constexpr (NX <= 4) {
-      if (e < NN) sCof[e] = cofactor<NX>(sM, e / NX, e % NX);
-      wave_sync();
-      if (e < NN) {  // W = adj(M) / det(M), adj(M)[r][c] = C[c][r]
-        double det = 0.0;
-        for (int c = 0; c < NX; ++c) det += sM[c] * sCof[c];
-        const double id = rcp_nr(det);
-        if (e == 0 && !(det != 0.0 && isfinite(id))) lflag |= SRTM_INFO_COMBINE_SINGULAR;
-        sW[e] = sCof[(e % NX) * NX + e / NX] * id;
-      }
-    } else {  // larger states: one lane, Gaussian elimination with partial pivoting
-      if (e == 0) {
-        double Mr[NX][NX], Wr[NX][NX];
-        for (int r = 0; r < NX; ++r)
-          for (int c = 0; c < NX; ++c) Mr[r][c] = sM[r * NX + c];
-        if (!inv_small(Mr, Wr)) lflag |= SRTM_INFO_COMBINE_SINGULAR;
-        for (int r = 0; r < NX; ++r)
-          for (int c = 0; c < NX; ++c) sW[r * NX + c] = Wr[r][c];
-      }
-    }
-    wave_sync();
-    for (int q = e; q < 3 * NN; q += 64) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
-      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
-      double acc = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += sW[er * NX + k] * F[k * NX + ec];
-        sWF[o] = acc;
-        rec[5 * NN + ec * NX + er] = acc;
-      } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sW[k * NX + ec];
-        rec[3 * NN + o] = acc;
-      } else {
-        double acc2 = 0.0;
-        for (int k = 0; k < NX; ++k) {
-          acc += sW[er * NX + k] * D[k * NX + ec];
-          acc2 += sW[ec * NX + k] * D[k * NX + er];
-        }
-        sXD[o] = 0.5 * (acc + acc2);
-      }
-    }
-    wave_sync();
-    for (int q = e; q < 3 * NN; q += 64) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
-      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
-      double acc = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sXD[k * NX + ec];
-        rec[4 * NN + o] = acc;
-      } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += sWF[k * NX + er] * J[k * NX + ec];
-        rec[6 * NN + o] = acc;
-      } else {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sWF[k * NX + ec];
-        nrec[o] = acc;
-      }
-    }
-    wave_sync();
-    for (int q = e; q < 2 * NN; q += 64) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
-      const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
-      const double* G2 = rec + 4 * NN;
-      const double* G4 = rec + 6 * NN;
-      double acc = 0.0, acc2 = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) {
-          acc += G2[er * NX + k] * F[ec * NX + k];
-          acc2 += G2[ec * NX + k] * F[er * NX + k];
-        }
-        nrec[NN + o] = 0.5 * (acc + acc2) + D[o];
-      } else {
-        for (int k = 0; k < NX; ++k) {
-          acc += G4[er * NX + k] * F[k * NX + ec];
-          acc2 += G4[ec * NX + k] * F[k * NX + er];
-        }
-        nrec[2 * NN + o] = 0.5 * (acc + acc2) + J[o];
-      }
-    }
-    T* dst = cst + lay.lev + p * lay.lev_stride;  // the level record, as laid out in LDS
-    for (int q = e; q < 7 * NN; q += 64) dst[q] = (T)rec[q];
-    wave_sync();
-    double* t = rec;
-    rec = nrec;
-    nrec = t;
-  }
+  // Levels below CHAIN_SPLIT; the others continue in the tile-reduction launch.
+  const int p1 = nlev < CHAIN_SPLIT ? nlev : CHAIN_SPLIT;
+  lflag |= level_chain<T, NX>(chain, cst, lay, 0, p1, nlev, hand);
   if (lflag && info) atomicOr(info, lflag);
 }
 
@@ -2301,7 +2340,7 @@ struct Seq {  // one sequence's typed arrays and scan plan
   const T *F, *Q, *H, *R, *m0, *P0, *y;
   T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
   T *cst, *ftagg, *ftst, *carry, *btagg, *btst, *sfx;
-  double* stats;
+  double *hand, *stats;
   int64_t N, tile0;
   int L;
   ScanPlan plan;
@@ -2335,6 +2374,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0);
   char* base = as_global(b.ws) + d.ws_off;
   q.cst = reinterpret_cast<T*>(base + wl.consts);
+  q.hand = reinterpret_cast<double*>(base + wl.chain);
   q.ftagg = reinterpret_cast<T*>(base + wl.ftile_agg);
   q.ftst = reinterpret_cast<T*>(base + wl.ftile_state);
   q.carry = reinterpret_cast<T*>(base + wl.carry);
@@ -2352,13 +2392,21 @@ SRTM_DEV int tile_sequence(const Batch& b) { return b.tile_seq ? b.tile_seq[bloc
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(256) k_constants(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.info);
+  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.hand, q.info);
 }
 
+// Workgroups 0 .. nseq-1 continue the level chains of the sequences; the others reduce tile
+// blockIdx.x - nseq of the call.
 template <typename T, int NX, int NY, bool INP>
-__global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, (int64_t)blockIdx.x - q.tile0);
+__global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b, int nseq) {
+  if ((int)blockIdx.x < nseq) {
+    const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+    chain_tail_body<T, NX, NY>(q.cst, q.hand, q.L, q.plan.nlev, q.info);
+    return;
+  }
+  const int64_t t = (int64_t)blockIdx.x - nseq;
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, b.tile_seq ? b.tile_seq[t] : 0);
+  fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, t - q.tile0);
 }
 
 template <typename T, int NX, int NY>
@@ -2481,7 +2529,7 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   SRTM_EV(ev.post(st));
 
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles + g.nseq), dim3(TILE), 0, st, b, (int)g.nseq);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 

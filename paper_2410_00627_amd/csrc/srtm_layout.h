@@ -79,7 +79,7 @@ inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, total;
+  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, total;
 };
 
 // Scalars (float64) of one tile's log-likelihood / gradient record.
@@ -97,6 +97,7 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
   const size_t nn = (size_t)nx * nx;
   size_t o = 0;
   w.consts = o; o = align256(o + (size_t)c.total * esz);
+  w.chain = o; o = align256(o + 3 * nn * sizeof(double));  // float64 F, D, J handed between launches
   w.ftile_agg = o; o = align256(o + (size_t)nt * 2 * nx * esz);
   w.ftile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
   w.carry = o; o = align256(o + (size_t)N * (nx + nn) * esz);
