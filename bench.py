@@ -193,7 +193,7 @@ def run_inputs(args):
            "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
            "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
            "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
-    ws = torch.empty(srtm.workspace_size(nx, m.ny, L, N, dt, True), device=dev, dtype=torch.uint8)
+    ws = torch.empty(srtm.workspace_size(nx, m.ny, L, N, dt, True, inputs=True), device=dev, dtype=torch.uint8)
     info = torch.zeros(1, device=dev, dtype=torch.int32)
 
     def timed(with_inputs):

@@ -143,9 +143,14 @@ typedef struct {
   int32_t reserved;
 } srtm_inputs;
 
-/* srtm_filter, srtm_smooth and srtm_loglik with known inputs (same outputs, workspace sizes
- * and errors; `inputs` NULL or with a NULL array -> SRTM_E_NULL, nu out of range or
- * reserved != 0 -> SRTM_E_SHAPE). */
+/* Bytes of device workspace the *_inputs entry points need: srtm_workspace_size plus one
+ * per-window record (N (nx + ny) scalars) of the measurement with the input response removed. */
+srtm_status srtm_workspace_size_inputs(const srtm_shape* shape, int32_t smoother, size_t* bytes);
+
+/* srtm_filter, srtm_smooth and srtm_loglik with known inputs (same outputs and errors; the
+ * workspace is srtm_workspace_size_inputs(shape, 0) bytes for the filter and the
+ * log-likelihood and srtm_workspace_size_inputs(shape, 1) for the smoother; `inputs` NULL or
+ * with a NULL array -> SRTM_E_NULL, nu out of range or reserved != 0 -> SRTM_E_SHAPE). */
 srtm_status srtm_filter_inputs(const srtm_shape* shape, const srtm_inputs* inputs,
                                const void* F, const void* Q, const void* H, const void* R,
                                const void* m0, const void* P0, const void* y,

@@ -66,7 +66,7 @@ srtm_status run_common(const srtm_shape* sh, const srtm::Ptrs& p, bool smoother,
     if (!aligned(q, 16)) return SRTM_E_ALIGN;
   if (!aligned(p.ws, 256) || !aligned(p.info, 4)) return SRTM_E_ALIGN;
   const size_t esz = sh->dtype == SRTM_F64 ? 8 : 4;
-  const srtm::WorkLayout wl = srtm::make_work_layout(sh->nx, sh->ny, sh->L, sh->N, esz, smoother);
+  const srtm::WorkLayout wl = srtm::make_work_layout(sh->nx, sh->ny, sh->L, sh->N, esz, smoother, p.B != nullptr);
   if (ws_bytes < wl.total) return SRTM_E_WORKSPACE;
   if (events && n_events < 2 * srtm_kernel_count(smoother ? 1 : 0)) return SRTM_E_SHAPE;
   return srtm::dispatch(*sh, p, smoother, static_cast<hipStream_t>(stream),
@@ -98,6 +98,15 @@ srtm_status srtm_workspace_size(const srtm_shape* shape, int32_t smoother, size_
   if (!bytes) return SRTM_E_NULL;
   const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
   *bytes = srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, smoother != 0).total;
+  return SRTM_OK;
+}
+
+srtm_status srtm_workspace_size_inputs(const srtm_shape* shape, int32_t smoother, size_t* bytes) {
+  srtm_status s = check_shape(shape);
+  if (s != SRTM_OK) return s;
+  if (!bytes) return SRTM_E_NULL;
+  const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
+  *bytes = srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, smoother != 0, true).total;
   return SRTM_OK;
 }
 
@@ -269,7 +278,8 @@ static srtm_status lik_common(const srtm_shape* shape, const void* F, const void
     if (!aligned(q, 16)) return SRTM_E_ALIGN;
   if (!aligned(workspace, 256) || !aligned(info, 4)) return SRTM_E_ALIGN;
   const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
-  if (workspace_bytes < srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, grad).total)
+  if (workspace_bytes <
+      srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, grad, inputs != nullptr).total)
     return SRTM_E_WORKSPACE;
   srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
                nullptr, nullptr, nullptr, nullptr, workspace, info};

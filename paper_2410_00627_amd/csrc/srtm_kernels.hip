@@ -444,6 +444,7 @@ struct InputView {
   const T* B;  // [nx][nu]
   const T* u;  // [N][l][nu], u[k-1][i-1] drives x_{k,i}
   const T* H;  // [ny][nx], the measurement matrix C
+  T* rec;      // workspace [N][ny + nx]: y_k - mu_k and z_{k,l}, written by the tile reductions
   int nu;
 };
 
@@ -930,37 +931,74 @@ SRTM_DEV void input_step(const InputView<T>& in, const T (&A)[NX][NX], const T* 
   for (int r = 0; r < NX; ++r) z[r] = nz[r];
 }
 
-// Window k's measurement y_k (zero past the last window) and, with inputs, y_k - mu_k and z_{k,l}
-// (zL = 0 without inputs).
-template <bool INP, typename T, int NX, int NY>
-SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N, int L,
-                          T (&yt)[NY], T (&zL)[NX]) {
+// Input response of window k < N from its inputs: zL = z_{k,l} and yt = y_k - mu_k. The inputs
+// of 8 fast steps are loaded together before they are used, so that their loads are in flight
+// at once.
+template <typename T, int NX, int NY>
+SRTM_DEV void window_input_pass(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int L,
+                                T (&yt)[NY], T (&zL)[NX]) {
+  constexpr int CH = 8;
+  T A[NX][NX], zs[NX];
+  load(A, M.cst + M.lay.A);
 #pragma unroll
-  for (int r = 0; r < NY; ++r) yt[r] = (k < N) ? gld(y + k * NY + r) : T(0);
+  for (int r = 0; r < NX; ++r) zs[r] = zL[r] = T(0);
+  const int nu = M.in.nu;
+  const T* uk = M.in.u + k * L * nu;
+#pragma unroll 1
+  for (int i0 = 0; i0 < L; i0 += CH) {
+    T ub[CH][NU_MAX];
+#pragma unroll
+    for (int t = 0; t < CH; ++t)
+#pragma unroll
+      for (int j = 0; j < NU_MAX; ++j) ub[t][j] = (i0 + t < L && j < nu) ? gld(uk + (i0 + t) * nu + j) : T(0);
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      if (i0 + t < L) {
+        T nz[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          T a = T(0);
+#pragma unroll
+          for (int j = 0; j < NU_MAX; ++j)
+            if (j < nu) a = my_fma(gld(M.in.B + r * nu + j), ub[t][j], a);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) a = my_fma(A[r][q], zL[q], a);
+          nz[r] = a;
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          zL[r] = nz[r];
+          zs[r] += nz[r];
+        }
+      }
+    }
+  }
+  const T inv_l = T(1) / T(L);
+#pragma unroll
+  for (int r = 0; r < NY; ++r) {
+    T s = T(0);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) s = my_fma(gld(M.in.H + r * NX + c), zs[c], s);
+    yt[r] = gld(y + k * NY + r) - s * inv_l;
+  }
+}
+
+// Window k's measurement (zero past the last window): y_k itself without inputs, and with inputs
+// y_k - mu_k and z_{k,l} from the per-window record (zL = 0 without inputs).
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, int64_t k, int64_t N,
+                          T (&yt)[NY], T (&zL)[NX]) {
+  constexpr int RS = NX + NY;
 #pragma unroll
   for (int r = 0; r < NX; ++r) zL[r] = T(0);
   if constexpr (INP) {
-    if (k < N) {
-      T A[NX][NX], zs[NX];
-      load(A, M.cst + M.lay.A);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) zs[r] = T(0);
-      const T* uk = M.in.u + k * L * M.in.nu;
-#pragma unroll 1
-      for (int i = 0; i < L; ++i) {
-        input_step(M.in, A, uk + i * M.in.nu, zL);
+    for (int r = 0; r < NY; ++r) yt[r] = (k < N) ? gld(M.in.rec + k * RS + r) : T(0);
 #pragma unroll
-        for (int r = 0; r < NX; ++r) zs[r] += zL[r];
-      }
-      const T inv_l = T(1) / T(L);
+    for (int r = 0; r < NX; ++r) zL[r] = (k < N) ? gld(M.in.rec + k * RS + NY + r) : T(0);
+  } else {
 #pragma unroll
-      for (int r = 0; r < NY; ++r) {
-        T s = T(0);
-#pragma unroll
-        for (int c = 0; c < NX; ++c) s = my_fma(gld(M.in.H + r * NX + c), zs[c], s);
-        yt[r] -= s * inv_l;
-      }
-    }
+    for (int r = 0; r < NY; ++r) yt[r] = (k < N) ? gld(y + k * NY + r) : T(0);
   }
 }
 
@@ -1110,7 +1148,23 @@ SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __res
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
   T yt[NY], zL[NX], d[NX], e[NX];
-  window_meas<INP>(M, y, k, N, L, yt, zL);
+  if constexpr (INP) {  // one pass over the window's inputs; later kernels read the record
+    if (k < N) {
+      window_input_pass(M, y, k, L, yt, zL);
+      constexpr int RS = NX + NY;
+#pragma unroll
+      for (int r = 0; r < NY; ++r) put_global(M.in.rec + k * RS + r, yt[r]);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) put_global(M.in.rec + k * RS + NY + r, zL[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < NY; ++r) yt[r] = T(0);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) zL[r] = T(0);
+    }
+  } else {
+    window_meas<false>(M, y, k, N, yt, zL);
+  }
   fwd_element<INP>(M, yt, zL, d, e);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -1641,7 +1695,7 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const int64_t k = tile * TILE + threadIdx.x;
   T yt[NY], zL[NX];
-  window_meas<INP>(M, y, k, N, L, yt, zL);
+  window_meas<INP>(M, y, k, N, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
   int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, tstate + tile * ST, mprev, Pprev, m, P);
   if (k < N) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
@@ -1673,7 +1727,7 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
   T yt[NY], zL[NX];
-  window_meas<INP>(M, y, k, N, L, yt, zL);
+  window_meas<INP>(M, y, k, N, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
   int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
@@ -1830,16 +1884,21 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
   if constexpr (INP) {
     T zL[NX];
-    window_meas<true>(M, y, kc, N, L, yk, zL);
+    window_meas<true>(M, y, kc, N, yk, zL);
   } else {
     gloadv(yk, y + kc * NY);
   }
   Window<T, NX, NY> w;
   int flag = 0;
   if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
-  T z[NX];  // input response z_{k,i} (inputs only)
+  T z[NX], un[NU_MAX];  // input response z_{k,i} and the next step's inputs (inputs only)
 #pragma unroll
   for (int r = 0; r < NX; ++r) z[r] = T(0);
+  const T* uk = INP ? M.in.u + kc * L * M.in.nu : nullptr;
+  if constexpr (INP) {
+#pragma unroll
+    for (int j = 0; j < NU_MAX; ++j) un[j] = (j < M.in.nu) ? gld(uk + j) : T(0);
+  }
   T v[NX], W[NX][NX];
   if (SMOOTH) {  // v = Et m_in + gt,  W = Et P_in Et^T + St
     const T* src = sfx + kc * SF;
@@ -1873,12 +1932,30 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   for (int i = 1; i <= ilim; ++i) {
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
     window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
-    if constexpr (INP) {
-      T A[NX][NX];
-      load(A, M.cst + M.lay.A);
-      input_step(M.in, A, M.in.u + (kc * L + (i - 1)) * M.in.nu, z);
+    if constexpr (INP) {  // z_i = A z_{i-1} + B u_{k,i-1}, the loads of step i+1 issued first
+      T uc[NU_MAX];
 #pragma unroll
-      for (int r = 0; r < NX; ++r) mf[r] += z[r];
+      for (int j = 0; j < NU_MAX; ++j) {
+        uc[j] = un[j];
+        un[j] = (j < M.in.nu && i < L) ? gld(uk + i * M.in.nu + j) : T(0);
+      }
+      T A[NX][NX], nz[NX];
+      load(A, M.cst + M.lay.A);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = T(0);
+#pragma unroll
+        for (int j = 0; j < NU_MAX; ++j)
+          if (j < M.in.nu) t = my_fma(gld(M.in.B + r * M.in.nu + j), uc[j], t);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(A[r][q], z[q], t);
+        nz[r] = t;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        z[r] = nz[r];
+        mf[r] += z[r];
+      }
     }
     if (FILT) {
       fin = fin && finite_state(mf, Pii);
@@ -1982,7 +2059,7 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
   static_assert(!(GRAD && INP), "the gradient is built without inputs");
   if constexpr (INP) {
     T zL[NX];
-    window_meas<true>(M, y, kc, N, L, yk, zL);
+    window_meas<true>(M, y, kc, N, yk, zL);
   } else {
     gloadv(yk, y + kc * NY);
   }
@@ -2371,7 +2448,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.tile0 = d.tile0;
   q.L = d.L;
   q.plan = make_scan_plan(d.N);
-  const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0);
+  const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0, d.B != nullptr);
   char* base = as_global(b.ws) + d.ws_off;
   q.cst = reinterpret_cast<T*>(base + wl.consts);
   q.hand = reinterpret_cast<double*>(base + wl.chain);
@@ -2383,7 +2460,8 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.sfx = reinterpret_cast<T*>(base + wl.sfx);
   q.stats = reinterpret_cast<double*>(base + wl.stats);
   q.info = b.info ? b.info + s : nullptr;
-  q.in = InputView<T>{as_global<T>(d.B), as_global<T>(d.u), q.H, d.nu};
+  q.in = InputView<T>{as_global<T>(d.B), as_global<T>(d.u), q.H,
+                      d.B ? reinterpret_cast<T*>(base + wl.inp) : nullptr, d.nu};
   return q;
 }
 

@@ -79,7 +79,7 @@ inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, total;
+  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, inp, total;
 };
 
 // Scalars (float64) of one tile's log-likelihood / gradient record.
@@ -90,7 +90,10 @@ inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + n
 
 inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother) {
+// `inputs`: the call has known inputs, whose per-window record (y_k - mu_k, z_{k,l}) [N][ny + nx]
+// the tile reductions write for the later kernels.
+inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother,
+                                                       bool inputs = false) {
   WorkLayout w;
   const ConstLayout c = make_const_layout(nx, ny, L, make_scan_plan(N).nlev);
   const int64_t nt = (N + TILE - 1) / TILE;
@@ -109,6 +112,11 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
     w.btile_agg = w.btile_state = w.sfx = 0;
   }
   w.stats = o; o = align256(o + (size_t)nt * stat_size(nx, ny) * sizeof(double));
+  if (inputs) {
+    w.inp = o; o = align256(o + (size_t)N * (nx + ny) * esz);
+  } else {
+    w.inp = 0;
+  }
   w.total = o;
   return w;
 }

@@ -57,6 +57,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.srtm_workspace_size.argtypes = [ctypes.POINTER(Shape), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     L.srtm_workspace_size.restype = ctypes.c_int
+    L.srtm_workspace_size_inputs.argtypes = L.srtm_workspace_size.argtypes
+    L.srtm_workspace_size_inputs.restype = ctypes.c_int
     L.srtm_supported.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.srtm_supported.restype = ctypes.c_int32
     L.srtm_filter.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
@@ -120,10 +122,13 @@ def shape_of(nx: int, ny: int, L: int, N: int, dtype: torch.dtype) -> Shape:
     return Shape(nx, ny, L, _dtype_code(dtype), N)
 
 
-def workspace_size(nx: int, ny: int, L: int, N: int, dtype: torch.dtype, smoother: bool) -> int:
+def workspace_size(nx: int, ny: int, L: int, N: int, dtype: torch.dtype, smoother: bool,
+                   inputs: bool = False) -> int:
+    """Workspace bytes of srtm_filter (smoother False) or srtm_smooth, or of their *_inputs forms."""
     out = ctypes.c_size_t(0)
     sh = shape_of(nx, ny, L, N, dtype)
-    _check(lib().srtm_workspace_size(ctypes.byref(sh), int(smoother), ctypes.byref(out)), "srtm_workspace_size")
+    fn = lib().srtm_workspace_size_inputs if inputs else lib().srtm_workspace_size
+    _check(fn(ctypes.byref(sh), int(smoother), ctypes.byref(out)), "srtm_workspace_size")
     return int(out.value)
 
 
@@ -196,7 +201,7 @@ def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     if slow:
         out["m_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
         out["P_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
-    nbytes = workspace_size(nx, ny, L, N, dt, False)
+    nbytes = workspace_size(nx, ny, L, N, dt, False, inp is not None)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
     if info is None:
@@ -251,7 +256,7 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
             out["Pf_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
             out["mf_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
             out["Pf_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
-    nbytes = workspace_size(nx, ny, L, N, dt, True)
+    nbytes = workspace_size(nx, ny, L, N, dt, True, inp is not None)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
     if info is None:
@@ -284,7 +289,7 @@ def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):
     dF = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None
     dQ = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None
     dR = torch.empty((ny, ny), device=dev, dtype=dt) if grad else None
-    ws = torch.empty(workspace_size(nx, ny, L, N, dt, grad), device=dev, dtype=torch.uint8)
+    ws = torch.empty(workspace_size(nx, ny, L, N, dt, grad, inp is not None), device=dev, dtype=torch.uint8)
     info = torch.zeros(1, device=dev, dtype=torch.int32)
     sh = shape_of(nx, ny, L, N, dt)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)

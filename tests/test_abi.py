@@ -70,6 +70,14 @@ def test_workspace_size_errors(L, nx, ny, Lw, N, dtype, code):
     assert _ws(nx, ny, Lw, N, dtype)[0] == code
 
 
+def test_window_length_limits(L):
+    """L = 128, the build's maximum, is accepted for every pair (the constants kernel's float64
+    tables then still fit in 160 KiB of LDS for nx = 6); L = 129 is not."""
+    for nx, ny in [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (6, 1)]:
+        assert _ws(nx, ny, 128, 1000)[0] == 0
+        assert _ws(nx, ny, 129, 1000)[0] == 4
+
+
 def test_supported_pairs(L):
     for nx, ny in [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (6, 1)]:
         assert L.srtm_supported(nx, ny) == 1
@@ -269,3 +277,22 @@ def test_smooth_batch_rejects_descriptors_with_inputs(L):
     host = ctypes.cast(buf, ctypes.c_void_p)
     assert L.srtm_smooth_batch(4, 2, 1, 1, host, ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x8000000), wsz,
                                None, None) == 2
+
+
+def test_workspace_size_with_inputs(L):
+    """The *_inputs entry points need one more per-window record of nx + ny scalars."""
+    for dtype, esz in ((1, 8), (0, 4)):
+        for smoother in (0, 1):
+            sh = srtm.Shape(4, 2, 20, dtype, 1000)
+            a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+            assert L.srtm_workspace_size(ctypes.byref(sh), smoother, ctypes.byref(a)) == 0
+            assert L.srtm_workspace_size_inputs(ctypes.byref(sh), smoother, ctypes.byref(b)) == 0
+            assert b.value >= a.value + 1000 * 6 * esz
+            assert b.value - a.value < 1000 * 6 * esz + 512
+
+
+def test_inputs_call_rejects_plain_workspace_size(L):
+    sh = srtm.Shape(2, 1, 10, 1, 5)
+    plain = _ws(2, 1, 10, 5)[1]
+    ok = srtm.InputsC(0x9000, 0xA000, 1, 0)
+    assert _call_inputs(L.srtm_smooth_inputs, sh, ok, FAKE, plain, 8) == 6

@@ -205,3 +205,14 @@ def test_headline_full_size(dtype):
                         "smoother tail")
     em, eP = rel_errors(out["ms_fast"][N - n:], out["Ps_fast"][N - n:], tail["ms_fast"], tail["Ps_fast"])
     print(f"[gpu] headline {dtype}: tail max err mean {em.max():.2e} cov {eP.max():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("nx,ny,L,N", [(4, 2, 128, 12), (6, 1, 128, 10), (1, 1, 128, 300)],
+                         ids=["nx4ny2L128", "nx6ny1L128", "nx1ny1L128N300"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_longest_windows(nx, ny, L, N, dtype):
+    """The longest window the build accepts (L = 128; for nx = 6 the constants kernel's LDS tables
+    are then within 3 KiB of the 160 KiB limit)."""
+    m = wl.random_stable_model(nx, ny, L, 70 + nx)
+    y = wl.simulate(m, N, 71 + nx)
+    check_smoother(m, y, dtype, f"nx{nx} ny{ny} L{L} N{N}")
