@@ -1187,9 +1187,9 @@ SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __res
 // with the shared level coefficients. Thread tau then walks its chunk from its exclusive
 // state, writing each tile's incoming state.
 template <typename T, int NX, int NY>
-SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, const T* __restrict__ cst,
-                             int L, const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ tstate,
-                             int32_t* info) {
+SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, int nlev,
+                             const T* __restrict__ cst, int L, const T* __restrict__ m0, const T* __restrict__ P0,
+                             T* __restrict__ tstate, int32_t* info) {
   constexpr int NN = NX * NX, ST = NX + NN;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
@@ -1199,7 +1199,17 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   const int64_t t0 = tid * c;
   int flag = 0;
   const int l0 = LOG_TILE + lchunk;
+  // The level records this scan uses (LOG_TILE .. nlev-1) are copied to LDS behind the slots
+  // first, so that no step waits on a memory round trip for its coefficients.
+  T* slev = reinterpret_cast<T*>(smraw) + KS * (NX + NN);
+  {
+    const T* gl = M.level(LOG_TILE);
+    const int n = (nlev - LOG_TILE) * M.lay.lev_stride;
+    for (int q = tid; q < n; q += KS) slev[q] = gld(gl + q);
+  }
+  auto level = [&](int p) { return slev + (p - LOG_TILE) * M.lay.lev_stride; };
   T d[NX], e[NX];
+  T d0[NX], e0[NX];  // vector parts of tile t0 (c = 2), reused by the walk at the end
   if (c == 1) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
@@ -1212,15 +1222,16 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
       d[r] = (t0 + 1 < nt) ? gld(tagg + (t0 + 1) * 2 * NX + r) : T(0);
       e[r] = (t0 + 1 < nt) ? gld(tagg + (t0 + 1) * 2 * NX + NX + r) : T(0);
     }
-    T di[NX], ei[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      di[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + r) : T(0);
-      ei[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + NX + r) : T(0);
+      d0[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + r) : T(0);
+      e0[r] = (t0 < nt) ? gld(tagg + t0 * 2 * NX + NX + r) : T(0);
     }
-    level_vec_combine(M.level(LOG_TILE), M.lay, di, ei, d, e);
+    __syncthreads();  // the level copy is complete
+    level_vec_combine(level(LOG_TILE), M.lay, d0, e0, d, e);
   } else {  // fold the chunk with full combines (tiles past the end carry zero vectors)
-    const T* lv = M.level(LOG_TILE);
+    __syncthreads();  // the level copy is complete
+    const T* lv = level(LOG_TILE);
     FElem<T, NX> acc, b;
     load(b.F, lv + M.lay.o_F);
     load(b.D, lv + M.lay.o_D);
@@ -1245,12 +1256,13 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
       e[r] = acc.e[r];
     }
   }
+  if (c == 1) __syncthreads();  // the level copy is complete
   T m[NX], P[NX][NX];
   if (tid == 0) {
     gloadv(m, m0);
     gload(P, P0);
     symmetrize(P);
-    const T* lv = M.level(l0);
+    const T* lv = level(l0);
     T F[NX][NX], D[NX][NX], J[NX][NX];
     load(F, lv + M.lay.o_F);
     load(D, lv + M.lay.o_D);
@@ -1282,7 +1294,7 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
       }
     }
     __syncthreads();
-    const T* lv = M.level(l0 + q);
+    const T* lv = level(l0 + q);
     if (gets_state) {
       T F[NX][NX], D[NX][NX], J[NX][NX];
       load(F, lv + M.lay.o_F);
@@ -1311,7 +1323,7 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
     } else {
       ld_state<T, NX>(S, tid - 1, X, XP);
     }
-    const T* lv = M.level(LOG_TILE);
+    const T* lv = level(LOG_TILE);
     T F[NX][NX], D[NX][NX], J[NX][NX];
     load(F, lv + M.lay.o_F);
     load(D, lv + M.lay.o_D);
@@ -1326,8 +1338,16 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
         for (int cc = 0; cc < NX; ++cc) tstate[t * ST + NX + r * NX + cc] = XP[r][cc];
       if (t + 1 < t0 + c && t + 1 < nt) {
         T dt[NX], et[NX];
-        gloadv(dt, tagg + t * 2 * NX);
-        gloadv(et, tagg + t * 2 * NX + NX);
+        if (c == 2) {
+#pragma unroll
+          for (int r = 0; r < NX; ++r) {
+            dt[r] = d0[r];
+            et[r] = e0[r];
+          }
+        } else {
+          gloadv(dt, tagg + t * 2 * NX);
+          gloadv(et, tagg + t * 2 * NX + NX);
+        }
         if (!state_combine(X, XP, F, dt, D, et, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
       }
     }
@@ -1377,8 +1397,17 @@ SRTM_DEV void bwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   const int tid = threadIdx.x;
   const int64_t c = int64_t(1) << lchunk;
   const int64_t thi = nt - 1 - tid * c;  // the chunk is tiles thi - c + 1 .. thi (those >= 0)
-  SElem<T, NX> x;
-  if (thi >= 0) {
+  SElem<T, NX> x, xhi;  // xhi: the aggregate of tile thi itself (c = 2), reused by the walk
+  if (thi >= 0 && c == 2) {  // both loads in flight together
+    SElem<T, NX> a;
+    ld_selem_global(tagg + thi * SE, xhi);
+    if (thi - 1 >= 0) {
+      ld_selem_global(tagg + (thi - 1) * SE, a);
+      selem_combine(a, xhi, x);
+    } else {
+      x = xhi;
+    }
+  } else if (thi >= 0) {
     ld_selem_global(tagg + thi * SE, x);
 #pragma unroll 1
     for (int64_t t = thi - 1; t > thi - c && t >= 0; --t) {
@@ -1429,9 +1458,13 @@ SRTM_DEV void bwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
 #pragma unroll
         for (int cc = 0; cc < NX; ++cc) tstate[t * ST + NX + i * NX + cc] = P[i][cc];
       if (t - 1 > thi - c && t - 1 >= 0) {
-        SElem<T, NX> a;
-        ld_selem_global(tagg + t * SE, a);
-        sstate_combine(a, m, P);
+        if (c == 2) {
+          sstate_combine(xhi, m, P);
+        } else {
+          SElem<T, NX> a;
+          ld_selem_global(tagg + t * SE, a);
+          sstate_combine(a, m, P);
+        }
       }
     }
   }
@@ -2490,8 +2523,8 @@ __global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b, int nseq) {
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  fwd_tiles_body<T, NX, NY>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.cst, q.L, q.m0, q.P0, q.ftst,
-                            q.info);
+  fwd_tiles_body<T, NX, NY>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.plan.nlev, q.cst, q.L, q.m0, q.P0,
+                            q.ftst, q.info);
 }
 
 template <typename T, int NX, int NY, bool INP>
@@ -2611,7 +2644,10 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  const size_t lds_ft = sizeof(T) * (size_t)KS * (NX + NN);
+  // slots, then the level records LOG_TILE .. nlev-1 of the longest sequence of the call
+  const int nlev_max = make_scan_plan((int64_t)g.ntiles * TILE).nlev;
+  const size_t lds_ft = sizeof(T) * ((size_t)KS * (NX + NN) +
+                                     (size_t)(nlev_max - LOG_TILE) * make_const_layout(NX, NY, 1).lev_stride);
   if (!allow_lds((const void*)k_fwd_tiles<T, NX, NY>, lds_ft)) return SRTM_E_HIP;
   SRTM_EV(ev.pre(st));
   hipLaunchKernelGGL((k_fwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ft, st, b);
