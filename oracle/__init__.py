@@ -16,6 +16,6 @@ only the seeded input generators (paper_2410_00627_amd.workloads) feed both.
 """
 from .srtm_oracle import (  # noqa: F401
     slow_rate_model, batch_model, imkf, fast_filter_window, srtm_filter,
-    srtm_smoother, slow_rate_smoother, loglik_grad_fd,
+    srtm_smoother, slow_rate_smoother, loglik_grad_fd, imkf_tv, srtm_filter_tv, srtm_smoother_tv,
 )
 from . import scan_form  # noqa: F401

@@ -197,6 +197,96 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
     return out
 
 
+def _per_window(X, N):
+    X = np.asarray(X, dtype=float)
+    return X if X.ndim == 3 else np.broadcast_to(X, (N,) + X.shape)
+
+
+def imkf_tv(A, Q, C, R, L, m0, P0, y):
+    """IMKF with a time-varying model given per window (arrays [N, ...]).
+
+    Reading: window k's model (A_k, Q_k) drives its fast steps x_{k,1} .. x_{k,l} (the step
+    from x_{k-1,l} into x_{k,1} included) and (C_k, R_k) its measurement y_k, so that the
+    slow-rate model of eq. h-k-l-2 / eq. y-k-l-2 is built per window from that window's
+    matrices; the prediction and update steps are those of imkf.
+    Returns (m, P, loglik) as imkf.
+    """
+    N = y.shape[0]
+    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
+    nx, ny = As.shape[1], Cs.shape[1]
+    ms = np.zeros((N, nx))
+    Ps = np.zeros((N, nx, nx))
+    m, P = np.array(m0, dtype=float), np.array(P0, dtype=float)
+    ll = 0.0
+    for k in range(N):
+        sr = slow_rate_model(As[k], Qs[k], Cs[k], L)
+        Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[x] for x in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
+        m_pred = Abar @ m
+        P_pred = Abar @ P @ Abar.T + Qbar
+        cross = Abar @ P @ Cbar.T + Gbar @ Qt @ Mbar.T
+        S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + Rs[k]
+        innov = y[k] - Cbar @ m
+        gain = np.linalg.solve(S.T, cross.T).T
+        m = m_pred + gain @ innov
+        P = _sym(P_pred - gain @ cross.T)
+        ms[k], Ps[k] = m, P
+        _, logdet = np.linalg.slogdet(S)
+        ll += -0.5 * (innov @ np.linalg.solve(S, innov) + logdet + ny * np.log(2 * np.pi))
+    return ms, Ps, ll
+
+
+def srtm_filter_tv(A, Q, C, R, L, m0, P0, y):
+    """srtm_filter with a per-window model (imkf_tv; window k's window filter from its own
+    batch model of eq. params-fast and R_k)."""
+    N = y.shape[0]
+    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
+    nx = As.shape[1]
+    m_slow, P_slow, ll = imkf_tv(As, Qs, Cs, Rs, L, m0, P0, y)
+    m_fast = np.zeros((N, L, nx))
+    P_fast = np.zeros((N, L, nx, nx))
+    for k in range(N):
+        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
+        M_f, P_f = fast_filter_window(batch_model(As[k], Qs[k], Cs[k], L), Rs[k], mp, Pp, y[k])
+        m_fast[k], P_fast[k] = _blocks(M_f, P_f, nx, L)
+    return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
+
+
+def srtm_smoother_tv(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
+    """srtm_smoother with a per-window model: window k's filter from its own matrices, and the
+    smoother's prediction of x_{k+1,1} (eq. smoothing-dynamic) with the next window's A_{k+1}
+    and Q_{k+1}, the model of that step."""
+    N = y.shape[0]
+    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
+    nx = As.shape[1]
+    m_slow, P_slow, ll = imkf_tv(As, Qs, Cs, Rs, L, m0, P0, y)
+    ms_fast = np.zeros((N, L, nx))
+    Ps_fast = np.zeros((N, L, nx, nx))
+    out = {}
+    if with_filter:
+        out["m_fast"] = np.zeros((N, L, nx))
+        out["P_fast"] = np.zeros((N, L, nx, nx))
+    ms1 = Ps1 = None
+    for k in range(N - 1, -1, -1):
+        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
+        M_f, P_f = fast_filter_window(batch_model(As[k], Qs[k], Cs[k], L), Rs[k], mp, Pp, y[k])
+        if with_filter:
+            out["m_fast"][k], out["P_fast"][k] = _blocks(M_f, P_f, nx, L)
+        if k == N - 1:
+            M_s, P_s = M_f, P_f
+        else:
+            Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), As[k + 1]])
+            m_pred = Ahat @ M_f
+            P_pred = Ahat @ P_f @ Ahat.T + Qs[k + 1]
+            G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
+            M_s = M_f + G @ (ms1 - m_pred)
+            P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)
+        ms_fast[k], Ps_fast[k] = _blocks(M_s, P_s, nx, L)
+        ms1, Ps1 = ms_fast[k, 0].copy(), Ps_fast[k, 0].copy()
+    out.update(ms_fast=ms_fast, Ps_fast=Ps_fast, ms_slow=ms_fast[:, 0].copy(),
+               Ps_slow=Ps_fast[:, 0].copy(), m_slow=m_slow, P_slow=P_slow, loglik=ll)
+    return out
+
+
 def slow_rate_smoother(A, Q, C, R, L, m0, P0, y):
     """Slow-rate smoother for x_{k,1}, eq. seq-smoothing-1 (Sec. III-C).
 

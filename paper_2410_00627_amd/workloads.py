@@ -108,6 +108,85 @@ def random_inputs(nx: int, nu: int, L: int, N: int, seed: int, scale: float = 0.
     return B, u
 
 
+@dataclass
+class TVModel:
+    """A linear Gaussian SRTM model whose matrices change from window to window (float64):
+    window k's A[k-1], Q[k-1] drive its fast steps x_{k,1} .. x_{k,L} (the step from x_{k-1,L}
+    included) and C[k-1], R[k-1] give its measurement y_k."""
+    A: np.ndarray          # (N, nx, nx)
+    Q: np.ndarray          # (N, nx, nx)
+    C: np.ndarray          # (N, ny, nx)
+    R: np.ndarray          # (N, ny, ny)
+    L: int
+    m0: np.ndarray
+    P0: np.ndarray
+    name: str = ""
+
+    @property
+    def nx(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def ny(self) -> int:
+        return self.C.shape[1]
+
+    @property
+    def N(self) -> int:
+        return self.A.shape[0]
+
+
+def time_varying_model(nx: int, ny: int, L: int, N: int, seed: int, *, general: bool = False) -> TVModel:
+    """Per-window matrices. Default: a slowly drifting version of the long-sequence model,
+    A_k = rho_k U (U Haar orthogonal, rho_k = 0.97 + 0.02 sin(2 pi k / 50)),
+    Q_k = 0.01 (1 + 0.5 sin(2 pi k / 37)) I, C_k = C0 + 0.2 sin(2 pi k / 29) C1 (C0, C1
+    Gaussian), R_k = 0.05 (1 + 0.5 cos(2 pi k / 23)) I, m0 = 0, P0 = I. With general=True every
+    window draws an unrelated random model (non-orthogonal A with spectral radius 0.95, full Q,
+    R), with nonzero m0 and full P0: for pins that must not rely on structure."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if general:
+        A = np.empty((N, nx, nx))
+        Q = np.empty((N, nx, nx))
+        C = rng.standard_normal((N, ny, nx))
+        R = np.empty((N, ny, ny))
+        for k in range(N):
+            a = rng.standard_normal((nx, nx))
+            A[k] = a * (0.95 / max(abs(np.linalg.eigvals(a))))
+            Q[k] = random_spd(rng, nx, 0.05)
+            R[k] = random_spd(rng, ny, 0.2)
+        return TVModel(A, Q, C, R, L, rng.standard_normal(nx), random_spd(rng, nx, 1.0),
+                       name=f"tvgen_nx{nx}_ny{ny}_L{L}_s{seed}")
+    U = _haar_orthogonal(rng, nx)
+    C0 = rng.standard_normal((ny, nx))
+    C1 = rng.standard_normal((ny, nx))
+    k = np.arange(1, N + 1)
+    rho = 0.97 + 0.02 * np.sin(2 * np.pi * k / 50.0)
+    q = 0.01 * (1.0 + 0.5 * np.sin(2 * np.pi * k / 37.0))
+    r = 0.05 * (1.0 + 0.5 * np.cos(2 * np.pi * k / 23.0))
+    A = rho[:, None, None] * U[None]
+    Q = q[:, None, None] * np.eye(nx)[None]
+    C = C0[None] + 0.2 * np.sin(2 * np.pi * k / 29.0)[:, None, None] * C1[None]
+    R = r[:, None, None] * np.eye(ny)[None]
+    return TVModel(A, Q, C, R, L, np.zeros(nx), np.eye(nx), name=f"tv_nx{nx}_ny{ny}_L{L}_s{seed}")
+
+
+def simulate_tv(model: TVModel, seed: int, *, return_states: bool = False):
+    """Draw x_0..x_{NL} and y_1..y_N from a per-window model (plain loop over fast steps)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, L, N = model.nx, model.ny, model.L, model.N
+    x = model.m0 + _chol_psd(model.P0) @ rng.standard_normal(nx)
+    xs = [x]
+    y = np.zeros((N, ny))
+    for k in range(N):
+        cq = _chol_psd(model.Q[k])
+        acc = np.zeros(nx)
+        for _ in range(L):
+            x = model.A[k] @ x + cq @ rng.standard_normal(nx)
+            acc += x
+            xs.append(x)
+        y[k] = model.C[k] @ acc / L + _chol_psd(model.R[k]) @ rng.standard_normal(ny)
+    return (y, np.array(xs)) if return_states else y
+
+
 def batched_specs(n_seq: int = 256, seed: int = 3030):
     """Many independent sequences of uneven length: per sequence nx in {2, 4, 6}, L in
     {5, 10, 20}, N = round(2^U(8, 14)) windows, ny = 1; returns (nx, L, N, model seed) tuples."""

@@ -5,35 +5,53 @@ Z = [x_0; x_1; ...; x_{NL}] is written from x_t = A^t x_0 + sum_{s<=t} A^{t-s} w
 the measurements as Y = Psi Z + v with y_k = (C/L) sum_{i} x_{(k-1)L+i} (Sec. III,
 eq. original-linear-SSM), and marginals follow from the Gaussian conditioning rule.
 Only usable for tiny problems (dimension (N L + 1) nx).
+
+Time-varying models: A, Q, C, R may also be given per window as arrays [N, ...]; window k's
+A and Q then drive the fast steps into x_{k,1} .. x_{k,L} and its C, R give y_k.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
+def _per_window(X, N):
+    X = np.asarray(X, dtype=float)
+    return X if X.ndim == 3 else np.broadcast_to(X, (N,) + X.shape)
+
+
 def joint_prior(A, Q, C, R, L, m0, P0, N, B=None, u=None):
-    nx, ny = A.shape[0], C.shape[0]
+    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
+    nx, ny = As.shape[1], Cs.shape[1]
     T = N * L
     dim = (T + 1) * nx
+    # transition products Phi(t, s) = A_t ... A_{s+1}, with A_t the matrix of the window of step t
+    step_A = [None] + [As[(t - 1) // L] for t in range(1, T + 1)]
     Phi = np.zeros((dim, nx))
     Gam = np.zeros((dim, T * nx))
-    powers = [np.eye(nx)]
-    for _ in range(T):
-        powers.append(A @ powers[-1])
-    for t in range(T + 1):
-        Phi[t * nx:(t + 1) * nx] = powers[t]
-        for s in range(1, t + 1):          # w_{s-1} enters x_s
-            Gam[t * nx:(t + 1) * nx, (s - 1) * nx:s * nx] = powers[t - s]
+    for s in range(T + 1):
+        M = np.eye(nx)
+        for t in range(s, T + 1):
+            if t > s:
+                M = step_A[t] @ M
+            if s == 0:
+                Phi[t * nx:(t + 1) * nx] = M
+            else:                          # w_{s-1} enters x_s
+                Gam[t * nx:(t + 1) * nx, (s - 1) * nx:s * nx] = M
     muZ = Phi @ m0
     if B is not None:   # u_{s-1} enters x_s like w_{s-1}: mean shift Gam (I_T (x) B) u
         muZ = muZ + Gam @ np.kron(np.eye(T), B) @ np.asarray(u, dtype=float).reshape(-1)
-    SZ = Phi @ P0 @ Phi.T + Gam @ np.kron(np.eye(T), Q) @ Gam.T
+    Qw = np.zeros((T * nx, T * nx))       # Cov of the stacked w_0 .. w_{T-1}
+    for s in range(1, T + 1):
+        Qw[(s - 1) * nx:s * nx, (s - 1) * nx:s * nx] = Qs[(s - 1) // L]
+    SZ = Phi @ P0 @ Phi.T + Gam @ Qw @ Gam.T
     Psi = np.zeros((N * ny, dim))
+    Rv = np.zeros((N * ny, N * ny))
     for k in range(N):
         for i in range(1, L + 1):
             t = k * L + i
-            Psi[k * ny:(k + 1) * ny, t * nx:(t + 1) * nx] = C / L
-    SY = Psi @ SZ @ Psi.T + np.kron(np.eye(N), R)
+            Psi[k * ny:(k + 1) * ny, t * nx:(t + 1) * nx] = Cs[k] / L
+        Rv[k * ny:(k + 1) * ny, k * ny:(k + 1) * ny] = Rs[k]
+    SY = Psi @ SZ @ Psi.T + Rv
     return muZ, SZ, Psi, SY
 
 
@@ -52,7 +70,7 @@ def posteriors(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     Returns dict: m_fast/P_fast = p(x_{k,i} | y_{1:k}), ms_fast/Ps_fast = p(x_{k,i} | y_{1:N}),
     and loglik = log N(Y; Psi mu_Z, Psi S_Z Psi^T + I (x) R).
     """
-    nx, ny = A.shape[0], C.shape[0]
+    nx, ny = np.shape(A)[-1], np.shape(C)[-2]
     N = y.shape[0]
     muZ, SZ, Psi, SY = joint_prior(A, Q, C, R, L, m0, P0, N, B, u)
     m_fast = np.zeros((N, L, nx))
