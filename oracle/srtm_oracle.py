@@ -26,6 +26,11 @@ def _mpow(A, i):
     return np.linalg.matrix_power(A, i)
 
 
+def _per_window(X, N):
+    X = np.asarray(X, dtype=float)
+    return X if X.ndim == 3 else np.broadcast_to(X, (N,) + X.shape)
+
+
 def slow_rate_model(A, Q, C, L, B=None):
     """Slow-rate dynamic and measurement model of Sec. III-A.
 
@@ -80,24 +85,32 @@ def imkf(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     """Sequential slow-rate IMKF, eq. prediction and eq. m-h-k-l (Sec. III-A).
 
     Optional inputs: B (nx x nu) and u [N][l][nu], u[k-1][i-1] driving x_{k,i}.
+    Time-varying model: A, Q, C, R given per window as arrays [N, ...]. Reading: window k's
+    A_k, Q_k drive its fast steps x_{k,1} .. x_{k,l} (the step from x_{k-1,l} included) and
+    C_k, R_k its measurement, so each window's slow-rate model (eq. h-k-l-2, eq. y-k-l-2) is
+    built from its own matrices.
     Returns (m, P, loglik) with m[k-1] = m^f_{k,l}, P[k-1] = P^f_{k,l} for k = 1..N.
     """
-    sr = slow_rate_model(A, Q, C, L, B)
-    Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[k] for k in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
+    tv = np.ndim(A) == 3
+    sr = None if tv else slow_rate_model(A, Q, C, L, B)
     N = y.shape[0]
-    nx, ny = A.shape[0], C.shape[0]
+    nx, ny = np.shape(A)[-1], np.shape(C)[-2]
     ms = np.zeros((N, nx))
     Ps = np.zeros((N, nx, nx))
     m, P = np.array(m0, dtype=float), np.array(P0, dtype=float)
     ll = 0.0
     for k in range(N):
+        if tv:  # window k's own slow-rate model
+            sr = slow_rate_model(A[k], Q[k], C[k], L)
+        Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[x] for x in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
+        Rk = R[k] if tv else R
         ub = None if B is None else np.asarray(u[k], dtype=float).reshape(-1)
         # prediction (eq. prediction)
         m_pred = Abar @ m + (0.0 if ub is None else sr["Bbar"] @ ub)
         P_pred = Abar @ P @ Abar.T + Qbar
         # update (eq. m-h-k-l): gain from the cross-covariance with the correlated noise term
         cross = Abar @ P @ Cbar.T + Gbar @ Qt @ Mbar.T
-        S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + R
+        S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + Rk
         innov = y[k] - Cbar @ m - (0.0 if ub is None else sr["Dbar"] @ ub)
         gain = np.linalg.solve(S.T, cross.T).T
         m = m_pred + gain @ innov
@@ -138,15 +151,19 @@ def srtm_filter(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     Returns dict with
       m_fast[k-1, i-1] = E[x_{k,i} | y_{1:k}],  P_fast[k-1, i-1] = Cov[x_{k,i} | y_{1:k}],
       m_slow[k-1] = m^f_{k,l},  P_slow[k-1] = P^f_{k,l}  (the IMKF carry), and loglik.
+    Per-window (time-varying) arrays as in imkf: window k's filter uses its own batch model.
     """
-    nx, N = A.shape[0], y.shape[0]
+    tv = np.ndim(A) == 3
+    nx, N = np.shape(A)[-1], y.shape[0]
     m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y, B, u)
-    bm = batch_model(A, Q, C, L, B)
+    bm = None if tv else batch_model(A, Q, C, L, B)
     m_fast = np.zeros((N, L, nx))
     P_fast = np.zeros((N, L, nx, nx))
     for k in range(N):
         mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k], None if B is None else u[k])
+        if tv:
+            bm = batch_model(A[k], Q[k], C[k], L)
+        M_f, P_f = fast_filter_window(bm, R[k] if tv else R, mp, Pp, y[k], None if B is None else u[k])
         m_fast[k], P_fast[k] = _blocks(M_f, P_f, nx, L)
     return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
 
@@ -163,13 +180,17 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
     (M^f_k, P^f_k) is recomputed from the stored slow carry (Remark fast-par-filter).
     With inputs the prediction of x_{k+1,1} adds B u_{k+1,0} (the input driving it).
 
+    Per-window (time-varying) arrays as in imkf: window k's filter uses its own batch model,
+    and the prediction of x_{k+1,1} uses A_{k+1} and Q_{k+1}, the model of that step.
+
     Returns dict with ms_fast/Ps_fast [N, L, ...] = p(x_{k,i} | y_{1:N}) and
     ms_slow/Ps_slow [N, ...] = p(x_{k,1} | y_{1:N}) (the smoother's slow state).
     """
-    nx, N = A.shape[0], y.shape[0]
+    tv = np.ndim(A) == 3
+    nx, N = np.shape(A)[-1], y.shape[0]
     m_slow, P_slow, ll = imkf(A, Q, C, R, L, m0, P0, y, B, u)
-    bm = batch_model(A, Q, C, L, B)
-    Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A])
+    bm = None if tv else batch_model(A, Q, C, L, B)
+    Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A]) if not tv else None
     ms_fast = np.zeros((N, L, nx))
     Ps_fast = np.zeros((N, L, nx, nx))
     out = {}
@@ -179,14 +200,18 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
     ms1 = Ps1 = None
     for k in range(N - 1, -1, -1):
         mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(bm, R, mp, Pp, y[k], None if B is None else u[k])
+        if tv:
+            bm = batch_model(A[k], Q[k], C[k], L)
+        M_f, P_f = fast_filter_window(bm, R[k] if tv else R, mp, Pp, y[k], None if B is None else u[k])
         if with_filter:
             out["m_fast"][k], out["P_fast"][k] = _blocks(M_f, P_f, nx, L)
         if k == N - 1:
             M_s, P_s = M_f, P_f
         else:
+            if tv:  # the step into x_{k+1,1} belongs to window k+1
+                Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A[k + 1]])
             m_pred = Ahat @ M_f + (0.0 if B is None else B @ np.asarray(u[k + 1][0], dtype=float))
-            P_pred = Ahat @ P_f @ Ahat.T + Q
+            P_pred = Ahat @ P_f @ Ahat.T + (Q[k + 1] if tv else Q)
             G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
             M_s = M_f + G @ (ms1 - m_pred)
             P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)
@@ -195,96 +220,24 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
     out.update(ms_fast=ms_fast, Ps_fast=Ps_fast, ms_slow=ms_fast[:, 0].copy(),
                Ps_slow=Ps_fast[:, 0].copy(), m_slow=m_slow, P_slow=P_slow, loglik=ll)
     return out
-
-
-def _per_window(X, N):
-    X = np.asarray(X, dtype=float)
-    return X if X.ndim == 3 else np.broadcast_to(X, (N,) + X.shape)
 
 
 def imkf_tv(A, Q, C, R, L, m0, P0, y):
-    """IMKF with a time-varying model given per window (arrays [N, ...]).
-
-    Reading: window k's model (A_k, Q_k) drives its fast steps x_{k,1} .. x_{k,l} (the step
-    from x_{k-1,l} into x_{k,1} included) and (C_k, R_k) its measurement y_k, so that the
-    slow-rate model of eq. h-k-l-2 / eq. y-k-l-2 is built per window from that window's
-    matrices; the prediction and update steps are those of imkf.
-    Returns (m, P, loglik) as imkf.
-    """
+    """IMKF with a time-varying model given per window (arrays [N, ...]); see imkf."""
     N = y.shape[0]
-    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
-    nx, ny = As.shape[1], Cs.shape[1]
-    ms = np.zeros((N, nx))
-    Ps = np.zeros((N, nx, nx))
-    m, P = np.array(m0, dtype=float), np.array(P0, dtype=float)
-    ll = 0.0
-    for k in range(N):
-        sr = slow_rate_model(As[k], Qs[k], Cs[k], L)
-        Abar, Gbar, Qt, Qbar, Cbar, Mbar = (sr[x] for x in ("Abar", "Gbar", "Qtilde", "Qbar", "Cbar", "Mbar"))
-        m_pred = Abar @ m
-        P_pred = Abar @ P @ Abar.T + Qbar
-        cross = Abar @ P @ Cbar.T + Gbar @ Qt @ Mbar.T
-        S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + Rs[k]
-        innov = y[k] - Cbar @ m
-        gain = np.linalg.solve(S.T, cross.T).T
-        m = m_pred + gain @ innov
-        P = _sym(P_pred - gain @ cross.T)
-        ms[k], Ps[k] = m, P
-        _, logdet = np.linalg.slogdet(S)
-        ll += -0.5 * (innov @ np.linalg.solve(S, innov) + logdet + ny * np.log(2 * np.pi))
-    return ms, Ps, ll
+    return imkf(*(_per_window(X, N) for X in (A, Q, C, R)), L, m0, P0, y)
 
 
 def srtm_filter_tv(A, Q, C, R, L, m0, P0, y):
-    """srtm_filter with a per-window model (imkf_tv; window k's window filter from its own
-    batch model of eq. params-fast and R_k)."""
+    """srtm_filter with a per-window model (arrays [N, ...]); see srtm_filter."""
     N = y.shape[0]
-    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
-    nx = As.shape[1]
-    m_slow, P_slow, ll = imkf_tv(As, Qs, Cs, Rs, L, m0, P0, y)
-    m_fast = np.zeros((N, L, nx))
-    P_fast = np.zeros((N, L, nx, nx))
-    for k in range(N):
-        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(batch_model(As[k], Qs[k], Cs[k], L), Rs[k], mp, Pp, y[k])
-        m_fast[k], P_fast[k] = _blocks(M_f, P_f, nx, L)
-    return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
+    return srtm_filter(*(_per_window(X, N) for X in (A, Q, C, R)), L, m0, P0, y)
 
 
 def srtm_smoother_tv(A, Q, C, R, L, m0, P0, y, *, with_filter=False):
-    """srtm_smoother with a per-window model: window k's filter from its own matrices, and the
-    smoother's prediction of x_{k+1,1} (eq. smoothing-dynamic) with the next window's A_{k+1}
-    and Q_{k+1}, the model of that step."""
+    """srtm_smoother with a per-window model (arrays [N, ...]); see srtm_smoother."""
     N = y.shape[0]
-    As, Qs, Cs, Rs = (_per_window(X, N) for X in (A, Q, C, R))
-    nx = As.shape[1]
-    m_slow, P_slow, ll = imkf_tv(As, Qs, Cs, Rs, L, m0, P0, y)
-    ms_fast = np.zeros((N, L, nx))
-    Ps_fast = np.zeros((N, L, nx, nx))
-    out = {}
-    if with_filter:
-        out["m_fast"] = np.zeros((N, L, nx))
-        out["P_fast"] = np.zeros((N, L, nx, nx))
-    ms1 = Ps1 = None
-    for k in range(N - 1, -1, -1):
-        mp, Pp = (m0, P0) if k == 0 else (m_slow[k - 1], P_slow[k - 1])
-        M_f, P_f = fast_filter_window(batch_model(As[k], Qs[k], Cs[k], L), Rs[k], mp, Pp, y[k])
-        if with_filter:
-            out["m_fast"][k], out["P_fast"][k] = _blocks(M_f, P_f, nx, L)
-        if k == N - 1:
-            M_s, P_s = M_f, P_f
-        else:
-            Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), As[k + 1]])
-            m_pred = Ahat @ M_f
-            P_pred = Ahat @ P_f @ Ahat.T + Qs[k + 1]
-            G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
-            M_s = M_f + G @ (ms1 - m_pred)
-            P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)
-        ms_fast[k], Ps_fast[k] = _blocks(M_s, P_s, nx, L)
-        ms1, Ps1 = ms_fast[k, 0].copy(), Ps_fast[k, 0].copy()
-    out.update(ms_fast=ms_fast, Ps_fast=Ps_fast, ms_slow=ms_fast[:, 0].copy(),
-               Ps_slow=Ps_fast[:, 0].copy(), m_slow=m_slow, P_slow=P_slow, loglik=ll)
-    return out
+    return srtm_smoother(*(_per_window(X, N) for X in (A, Q, C, R)), L, m0, P0, y, with_filter=with_filter)
 
 
 def slow_rate_smoother(A, Q, C, R, L, m0, P0, y):

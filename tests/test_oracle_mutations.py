@@ -35,7 +35,7 @@ MUTATIONS = [
     ("A_hat picks first block", "Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A])",
      "Ahat = np.hstack([A, np.zeros((nx, (L - 1) * nx))])"),
     ("smoother gain sign", "M_s = M_f + G @ (ms1 - m_pred)", "M_s = M_f - G @ (ms1 - m_pred)"),
-    ("smoother drops Q", "P_pred = Ahat @ P_f @ Ahat.T + Q\n", "P_pred = Ahat @ P_f @ Ahat.T\n"),
+    ("smoother drops Q", "P_pred = Ahat @ P_f @ Ahat.T + (Q[k + 1] if tv else Q)\n", "P_pred = Ahat @ P_f @ Ahat.T\n"),
     ("smoother covariance correction sign", "P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)",
      "P_s = _sym(P_f + G @ (P_pred - Ps1) @ G.T)"),
     ("IMKF prediction with A_bar transposed", "P_pred = Abar @ P @ Abar.T + Qbar",

@@ -61,13 +61,13 @@ def test_constant_windows_equal_time_invariant():
 
 TV_MUTATIONS = [
     ("smoother predicts with the current window's A",
-     "Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), As[k + 1]])", "Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), As[k]])"),
-    ("smoother predicts with the current window's Q",
-     "P_pred = Ahat @ P_f @ Ahat.T + Qs[k + 1]", "P_pred = Ahat @ P_f @ Ahat.T + Qs[k]"),
-    ("IMKF update with the next window's R", "S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + Rs[k]",
-     "S = Cbar @ P @ Cbar.T + Mbar @ Qt @ Mbar.T + Rs[min(k + 1, len(Rs) - 1)]"),
-    ("IMKF uses the first window's model throughout", "sr = slow_rate_model(As[k], Qs[k], Cs[k], L)",
-     "sr = slow_rate_model(As[0], Qs[0], Cs[0], L)"),
+     "Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A[k + 1]])", "Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A[k]])"),
+    ("smoother predicts with the current window's Q", "(Q[k + 1] if tv else Q)", "(Q[k] if tv else Q)"),
+    ("IMKF update with the next window's R", "Rk = R[k] if tv else R", "Rk = R[min(k + 1, len(R) - 1)] if tv else R"),
+    ("IMKF uses the first window's model throughout", "sr = slow_rate_model(A[k], Q[k], C[k], L)",
+     "sr = slow_rate_model(A[0], Q[0], C[0], L)"),
+    ("window filter with the first window's model", "            bm = batch_model(A[k], Q[k], C[k], L)\n        M_f, P_f = fast_filter_window(bm, R[k] if tv else R, mp, Pp, y[k], None if B is None else u[k])\n        if with_filter:",
+     "            bm = batch_model(A[0], Q[0], C[0], L)\n        M_f, P_f = fast_filter_window(bm, R[k] if tv else R, mp, Pp, y[k], None if B is None else u[k])\n        if with_filter:"),
 ]
 
 
