@@ -172,6 +172,58 @@ def run_batched(args):
     print(json.dumps(line))
 
 
+def run_tv(args):
+    """The long-sequence shape (nx=4, ny=2, L=20, N=2^17) with a model that drifts from window to
+    window (srtm_smooth_tv), against the time-invariant path on the same shape."""
+    import torch
+    from paper_2410_00627_amd import srtm, workloads as wl
+    dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N = args.N or wl.HEADLINE_N
+    m = wl.time_varying_model(4, 2, 20, N, 2027)
+    y = wl.simulate_tv(m, 2028)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, dev, dt)
+    yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dt)
+    ti = wl.headline_model()
+    Fi, Qi, Hi, Ri, _, _ = srtm.model_tensors(ti, dev, dt)
+    nx, L = m.nx, m.L
+    out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+           "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+           "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+           "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
+    ws = torch.empty(srtm.workspace_size(nx, m.ny, L, N, dt, True, tv=True), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+
+    def timed(model):
+        for _ in range(args.warmup):
+            srtm.smooth(*model, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            srtm.smooth(*model, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / args.steps
+
+    t_ti = timed((Fi, Qi, Hi, Ri))
+    t_tv = timed((F, Q, H, R))
+    if int(info.item()) != 0:
+        raise RuntimeError(f"numerical failure: info={int(info.item())}")
+    fast_states = N * L
+    print(json.dumps({
+        "metric": "fast-rate smoothed states/sec (filter+smoother), per-window model",
+        "value": round(fast_states / t_tv), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_tv * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+        "config": {"workload": "one sequence, nx=4, ny=2, L=20, N=2^17, per-window model: A_k = rho_k U, "
+                               "Q_k = q_k I, C_k = C0 + 0.2 sin(.) C1, R_k = r_k I drifting with k",
+                   "N": N, "L": L, "fast_states": fast_states},
+        "time_invariant_ms_per_step": round(t_ti * 1e3, 4), "cost_of_per_window_model": round(t_tv / t_ti, 3)}))
+
+
 def run_inputs(args):
     """The long-sequence workload (nx=4, ny=2, L=20, N=2^17) with two known inputs per fast step
     (x_t = A x_{t-1} + B u_{t-1} + w_{t-1}), against the same call without inputs."""
@@ -328,7 +380,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs", "tv"],
+                    default="headline",
                     help="headline: one long sequence (default); batched: 256 uneven sequences; "
                          "serving: Poisson arrivals with continuous batching")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: length of the arrival process")
@@ -354,6 +407,8 @@ def main():
         return run_serving(args)
     if args.workload == "inputs":
         return run_inputs(args)
+    if args.workload == "tv":
+        return run_tv(args)
     if args.workload == "gradient":
         return run_gradient(args)
     args.dtype = args.dtype or "f64"

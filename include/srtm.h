@@ -167,6 +167,32 @@ srtm_status srtm_loglik_inputs(const srtm_shape* shape, const srtm_inputs* input
                                const void* m0, const void* P0, const void* y,
                                void* ll, void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
+/* ------------------------------------------------------------------ time-varying models
+ * The model given per window: window k's F_k, Q_k drive its fast steps x_{k,1} .. x_{k,L}
+ * (the step from x_{k-1,L} into x_{k,1} included) and H_k, R_k give its measurement y_k:
+ *     x_{k,i} = F_k x_{k,i-1} + w,  w ~ N(0, Q_k)   (x_{k,0} = x_{k-1,L}),
+ *     y_k = (H_k / L) sum_i x_{k,i} + v_k,  v_k ~ N(0, R_k).
+ * Each window's slow-rate model (Sec. III-A, eq. h-k-l-2 and eq. y-k-l-2) and window filter
+ * (Sec. III-B) are built from its own matrices, and the smoother's prediction of x_{k+1,1}
+ * (eq. seq-smoothing-all) uses F_{k+1}, Q_{k+1}. The scans combine whole filter elements
+ * (eq. op-filter), since the elements no longer share their matrices.
+ *  F [N][nx][nx], Q [N][nx][nx], H [N][ny][nx], R [N][ny][ny]: device arrays of the dtype;
+ *  m0, P0, y and all outputs as in srtm_filter / srtm_smooth. nx <= 4 (SRTM_E_UNSUPPORTED
+ *  otherwise). Workspace: srtm_workspace_size_tv(shape, 0) bytes for the filter and
+ *  srtm_workspace_size_tv(shape, 1) for the smoother (per-window constants included). */
+srtm_status srtm_workspace_size_tv(const srtm_shape* shape, int32_t smoother, size_t* bytes);
+srtm_status srtm_filter_tv(const srtm_shape* shape,
+                           const void* F, const void* Q, const void* H, const void* R,
+                           const void* m0, const void* P0, const void* y,
+                           void* m_fast, void* P_fast, void* m_slow, void* P_slow,
+                           void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+srtm_status srtm_smooth_tv(const srtm_shape* shape,
+                           const void* F, const void* Q, const void* H, const void* R,
+                           const void* m0, const void* P0, const void* y,
+                           void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                           void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
+                           void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
 /* ------------------------------------------------------------------ log-likelihood and gradient
  * Marginal log-likelihood of the measurements, log p(y_{1:N}) = sum_k log N(y_k; C_bar m, S_k)
  * with the slow-rate filter's one-step prediction of y_k (eq. m-h-k-l; the Gaussian elements

@@ -66,7 +66,9 @@ srtm_status run_common(const srtm_shape* sh, const srtm::Ptrs& p, bool smoother,
     if (!aligned(q, 16)) return SRTM_E_ALIGN;
   if (!aligned(p.ws, 256) || !aligned(p.info, 4)) return SRTM_E_ALIGN;
   const size_t esz = sh->dtype == SRTM_F64 ? 8 : 4;
-  const srtm::WorkLayout wl = srtm::make_work_layout(sh->nx, sh->ny, sh->L, sh->N, esz, smoother, p.B != nullptr);
+  if (p.tv && sh->nx > srtm::TV_NX_MAX) return SRTM_E_UNSUPPORTED;
+  const srtm::WorkLayout wl =
+      srtm::make_work_layout(sh->nx, sh->ny, sh->L, sh->N, esz, smoother, p.B != nullptr, p.tv);
   if (ws_bytes < wl.total) return SRTM_E_WORKSPACE;
   if (events && n_events < 2 * srtm_kernel_count(smoother ? 1 : 0)) return SRTM_E_SHAPE;
   return srtm::dispatch(*sh, p, smoother, static_cast<hipStream_t>(stream),
@@ -110,6 +112,16 @@ srtm_status srtm_workspace_size_inputs(const srtm_shape* shape, int32_t smoother
   return SRTM_OK;
 }
 
+srtm_status srtm_workspace_size_tv(const srtm_shape* shape, int32_t smoother, size_t* bytes) {
+  srtm_status s = check_shape(shape);
+  if (s != SRTM_OK) return s;
+  if (!bytes) return SRTM_E_NULL;
+  if (shape->nx > srtm::TV_NX_MAX) return SRTM_E_UNSUPPORTED;
+  const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
+  *bytes = srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, smoother != 0, false, true).total;
+  return SRTM_OK;
+}
+
 int32_t srtm_supported(int32_t nx, int32_t ny) { return srtm::pair_supported(nx, ny) ? 1 : 0; }
 
 srtm_status srtm_filter(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
@@ -149,6 +161,25 @@ srtm_status srtm_smooth_inputs(const srtm_shape* shape, const srtm_inputs* input
                mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
   const srtm_status s = with_inputs(inputs, p);
   if (s != SRTM_OK) return s;
+  return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_filter_tv(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                           const void* m0, const void* P0, const void* y, void* m_fast, void* P_fast, void* m_slow,
+                           void* P_slow, void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, nullptr, nullptr, nullptr, nullptr,
+               m_fast, P_fast, m_slow, P_slow, workspace, info};
+  p.tv = true;
+  return run_common(shape, p, false, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_smooth_tv(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                           const void* m0, const void* P0, const void* y, void* ms_fast, void* Ps_fast,
+                           void* ms_slow, void* Ps_slow, void* mf_fast, void* Pf_fast, void* mf_slow,
+                           void* Pf_slow, void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
+               mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
+  p.tv = true;
   return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
 }
 
@@ -234,7 +265,7 @@ static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t n
     srtm_status st = check_shape(&sh);
     if (st != SRTM_OK) return st;
     if (d[s].tile0 != tiles || d[s].smoother != 1) return SRTM_E_SHAPE;
-    if (d[s].B || d[s].u || d[s].nu || d[s].reserved) return SRTM_E_SHAPE;  // batches carry no inputs
+    if (d[s].B || d[s].u || d[s].nu || d[s].tv) return SRTM_E_SHAPE;  // batches: time-invariant, no inputs
     const int32_t* map = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) +
                                                           srtm::batch_tile_map_offset(nseq));
     const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;

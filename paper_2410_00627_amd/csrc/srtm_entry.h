@@ -26,7 +26,12 @@ struct Ptrs {
   const void* B = nullptr;
   const void* u = nullptr;
   int nu = 0;
+  bool tv = false;  // F, Q, H, R given per window ([N][...]); no inputs then
 };
+
+// Largest state size of the per-window (time-varying) path: its scans hold whole filter
+// elements of all 256 windows of a tile in LDS.
+constexpr int TV_NX_MAX = 4;
 
 // What follows the scans: fast-rate recovery modes 1 (filter), 2 (smoother), 3 (both), the
 // log-likelihood alone (REC_LL) or the log-likelihood and its gradient (REC_GRAD).

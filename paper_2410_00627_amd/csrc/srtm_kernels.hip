@@ -1006,11 +1006,13 @@ SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, in
 //   P^- = A P^f_{k,l} A^T + Q,  E = P^f_{k,1,l} A^T (P^-)^{-1},  g = m^f_{k,1} - E A m^f_{k,l},
 //   S = P^f_{k,1} - E A (P^f_{k,1,l})^T = P^f_{k,1} - E P^- E^T;   last window: (0, m^f_{N,1}, P^f_{N,1}).
 // Also returns P^-, (P^-)^{-1} and the predicted mean A m^f_{k,l}, which the smoother correction
-// reuses. With inputs, z1 = B u_{k,0} is added to m^f_{k,1} and bnext = B u_{k+1,0} to the prediction.
+// reuses. (A, Qm) is the model of the step into x_{k+1,1}. With inputs, z1 = B u_{k,0} is added to
+// m^f_{k,1} and bnext = B u_{k+1,0} to the prediction.
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, bool last,
                               const T (&mL)[NX], const T (&PL)[NX][NX], const T (&z1)[NX], const T (&bnext)[NX],
-                              SElem<T, NX>& el, T (&Pmi)[NX][NX], T (&mpred)[NX], T (&Pm)[NX][NX]) {
+                              const T (&A)[NX][NX], const T (&Qm)[NX][NX], SElem<T, NX>& el, T (&Pmi)[NX][NX],
+                              T (&mpred)[NX], T (&Pm)[NX][NX]) {
   T mf1[NX], Pf11[NX][NX], Pf1L[NX][NX];
   window_step<T, NX, NY, true>(M, w, 1, mf1, Pf11, Pf1L);
   if constexpr (INP) {
@@ -1033,9 +1035,6 @@ SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, 
     }
     return 0;
   }
-  T A[NX][NX], Qm[NX][NX];
-  load(A, M.cst + M.lay.A);
-  load(Qm, M.cst + M.lay.Q);
   sandwich(A, PL, Qm, Pm);
   if (!spd_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
   mv(A, mL, mpred);
@@ -1736,35 +1735,20 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
 }
 
 // ============================================================================ backward
-// K3s (smoother): per tile, the forward down-sweep of K3; then, from the exclusive and
-// inclusive filter states of window k, its smoother element (eq. parallel-ak-smoothing), an
-// in-tile reverse Kogge-Stone scan of those elements under eq. op-smoother, the tile's
-// aggregate a_first (x) ... (x) a_last, and per window the smoother correction of eq.
-// seq-smoothing-all written as terms linear in the smoothed state (m_in, P_in) that enters
-// the tile from the right (the first window after it). With B = (P^-)^{-1} A and the
-// in-tile exclusive suffix (E', g', S') = a_{k+1} (x) ... (x) a_{last of tile}:
-//   v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}) = Et m_in + gt,
-//   W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A = Et P_in Et^T + St,
-//   Et = B^T E',  gt = B^T (g' - A m^f_{k,l}),  St = B^T (S' - P^-) B;
-// all three are zero for the last window, whose smoothed blocks equal the filtered ones.
+// The smoother half of the fused forward/backward kernel for window k of tile `tile`, given the
+// window's exclusive and inclusive filter states and (An, Qn), the model of the step into
+// x_{k+1,1}: its smoother element (eq. parallel-ak-smoothing), the in-tile reverse Kogge-Stone
+// scan under eq. op-smoother, the tile aggregate and the per-window correction record (see
+// fwd_bwd_body). Returns numerical status bits.
 template <bool INP, typename T, int NX, int NY>
-SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
-                           const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ ftstate,
-                           T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
-                           T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info, int64_t tile) {
-  constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
-  extern __shared__ char smraw[];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
-  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+SRTM_DEV int smoother_part(const Model<T, NX, NY>& M, const Slots<T>& S, int L, int64_t k, int64_t N,
+                           const T (&yt)[NY], const T (&mprev)[NX], const T (&Pprev)[NX][NX], const T (&m)[NX],
+                           const T (&P)[NX][NX], const T (&An)[NX][NX], const T (&Qn)[NX][NX],
+                           T* __restrict__ btagg, T* __restrict__ sfx, int64_t tile) {
+  constexpr int NN = NX * NX, SE = 2 * NN + NX, SF = sfx_stride(NX);
   const int tid = threadIdx.x;
-  const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
-  T yt[NY], zL[NX];
-  window_meas<INP>(M, y, k, N, yt, zL);
-  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
-  if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
-
+  int flag = 0;
   SElem<T, NX> x;
   T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T (predicted mean), B^T P^- B
   {
@@ -1778,11 +1762,9 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
       if (k + 1 < N) input_drive(M.in, M.in.u + (k + 1) * L * M.in.nu, bnext);
     }
     T Pmi[NX][NX], mpred[NX], Pm[NX][NX];
-    const int f = smoother_element<INP>(M, L, w, k == N - 1, m, P, z1, bnext, x, Pmi, mpred, Pm);
+    const int f = smoother_element<INP>(M, L, w, k == N - 1, m, P, z1, bnext, An, Qn, x, Pmi, mpred, Pm);
     if (valid) flag |= f;
-    T A[NX][NX];
-    load(A, M.cst + M.lay.A);
-    mm(Pmi, A, B);
+    mm(Pmi, An, B);
     mtv(B, mpred, Bm);
     T PB[NX][NX];
     mm(Pm, B, PB);
@@ -1884,6 +1866,42 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 #pragma unroll
     for (int r = 0; r < SF; ++r) put_global(dst + r, rec[r]);
   }
+  return flag;
+}
+
+// K3s (smoother): per tile, the forward down-sweep of K3; then, from the exclusive and
+// inclusive filter states of window k, its smoother element (eq. parallel-ak-smoothing), an
+// in-tile reverse Kogge-Stone scan of those elements under eq. op-smoother, the tile's
+// aggregate a_first (x) ... (x) a_last, and per window the smoother correction of eq.
+// seq-smoothing-all written as terms linear in the smoothed state (m_in, P_in) that enters
+// the tile from the right (the first window after it). With B = (P^-)^{-1} A and the
+// in-tile exclusive suffix (E', g', S') = a_{k+1} (x) ... (x) a_{last of tile}:
+//   v = A^T (P^-)^{-1} (m^s_{k+1,1} - A m^f_{k,l}) = Et m_in + gt,
+//   W = A^T (P^-)^{-1} (P^s_{k+1,1} - P^-) (P^-)^{-1} A = Et P_in Et^T + St,
+//   Et = B^T E',  gt = B^T (g' - A m^f_{k,l}),  St = B^T (S' - P^-) B;
+// all three are zero for the last window, whose smoothed blocks equal the filtered ones.
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
+                           const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ ftstate,
+                           T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
+                           T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info, int64_t tile) {
+  constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
+  extern __shared__ char smraw[];
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+  const int tid = threadIdx.x;
+  const int64_t k = tile * TILE + tid;
+  const bool valid = k < N;
+  T yt[NY], zL[NX];
+  window_meas<INP>(M, y, k, N, yt, zL);
+  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
+  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
+  if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
+
+  T An[NX][NX], Qn[NX][NX];  // time-invariant: the step into x_{k+1,1} has the model's A and Q
+  load(An, M.cst + M.lay.A);
+  load(Qn, M.cst + M.lay.Q);
+  flag |= smoother_part<INP>(M, S, L, k, N, yt, mprev, Pprev, m, P, An, Qn, btagg, sfx, tile);
   if (flag && info) atomicOr(info, flag);
 }
 
@@ -1892,8 +1910,10 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
-template <typename T, int NX, int NY, int MODE, bool INP>
+// TV: per-window model; `cst` then holds one constants block of `bstride` scalars per window.
+template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
+                           int64_t bstride,
                            InputView<T> in,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                            const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast,
@@ -1904,10 +1924,11 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
   using Stg = OutStage<T, NX>;
   extern __shared__ char smraw[];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const int64_t w0 = tile * TILE + wv * 64;
+  const int64_t kb = (TV && k < N) ? k : 0;
+  const Model<T, NX, NY> M{TV ? cst + kb * bstride : cst, make_const_layout(NX, NY, L), in};
   const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
   const Stg fst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
   const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
@@ -2031,6 +2052,497 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
     wave_sync();
   }
   if (!fin && valid) flag |= SRTM_INFO_NONFINITE;
+  if (flag && info) atomicOr(info, flag);
+}
+
+// ============================================================================ per-window models
+// Time-varying model given per window: window k's F_k, Q_k drive its fast steps x_{k,1} ..
+// x_{k,l} (the step from x_{k-1,l} included) and H_k, R_k give y_k. What the time-invariant path
+// computes once per call (per-step tables, slow-rate constants, the element matrices) is computed
+// once per window, by one lane, into a per-window constants block of the time-invariant layout
+// (without level records) and an element record (F, D, J). The forward scan then combines
+// whole elements: the level tables of the time-invariant path do not exist here.
+
+// Per-window constants (float64 in registers, one lane): the block `blk` (layout `lay`) and the
+// element matrices `el` = F, D, J of the model (Fm, Qm, Hm, Rm), by the formulas of the constants
+// kernel: Q_ii = A Q_{i-1,i-1} A^T + Q, Q_il = Q_ii (A^{l-i})^T,
+// c_i = (1/l) [a_i + Q_ii (C Sig_{l-i})^T] with a_1 = 0, a_{i+1} = A (a_i + Q_ii C^T) and
+// Sig_s = sum_{u<=s} A^u, C_bar = (C/l)(Sig_l - I), R_x = (1/l) sum_i C c_i + R, K = c_l R_x^{-1},
+// F = A^l - K C_bar, D = Q_ll - K c_l^T, J = C_bar^T R_x^{-1} C_bar. A forward pass stores A^i,
+// Q_ii and a_i; a backward pass (s = l - i rising, A^s and Sig_s in registers) reads Q_ii and a_i
+// back in the block's precision and completes Q_il and c_i.
+template <typename T, int NX, int NY>
+SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
+                                 const T* __restrict__ Rm, int L, const ConstLayout& lay, T* __restrict__ blk,
+                                 T* __restrict__ el) {
+  int flag = 0;
+  double A[NX][NX], Q[NX][NX], C[NY][NX], R[NY][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      A[r][c] = (double)gld(Fm + r * NX + c);
+      Q[r][c] = (double)gld(Qm + r * NX + c);
+    }
+#pragma unroll
+  for (int r = 0; r < NY; ++r) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) C[r][c] = (double)gld(Hm + r * NX + c);
+#pragma unroll
+    for (int c = 0; c < NY; ++c) R[r][c] = (double)gld(Rm + r * NY + c);
+  }
+  auto pi = [&](int i) { return blk + lay.per_i + (i - 1) * lay.per_i_stride; };
+  // forward pass: A^i, Q_ii and a_i (stored in the c_i slot until the backward pass)
+  double Ai[NX][NX], Qi[NX][NX], a[NX][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      Ai[r][c] = (r == c) ? 1.0 : 0.0;
+      Qi[r][c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NY; ++c) a[r][c] = 0.0;
+  }
+#pragma unroll 1
+  for (int i = 1; i <= L; ++i) {
+    if (i > 1) {  // a_i = A (a_{i-1} + Q_{i-1,i-1} C^T)
+      double b[NX][NY];
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NY; ++c) {
+          double v = a[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v += Qi[r][q] * C[c][q];
+          b[r][c] = v;
+        }
+      mm(A, b, a);
+    }
+    double t[NX][NX], AQ[NX][NX];
+    mm(A, Ai, t);
+    mm(A, Qi, AQ);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) Ai[r][c] = t[r][c];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        double v = Q[r][c];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += AQ[r][q] * A[c][q];
+        Qi[r][c] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < r; ++c) Qi[r][c] = Qi[c][r];
+    T* d = pi(i);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        put_global(d + lay.o_Ai + r * NX + c, (T)Ai[r][c]);
+        put_global(d + lay.o_Qii + r * NX + c, (T)Qi[r][c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NY; ++c) put_global(d + lay.o_ci + r * NY + c, (T)a[r][c]);
+    }
+  }
+  // Ai = A^l, Qi = Q_ll.  Backward pass, s = l - i = 0 .. l-1: A^s, Sig_s, Q_il, c_i, R_x.
+  double As[NX][NX], Sig[NX][NX], cL[NX][NY], Rx[NY][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) As[r][c] = Sig[r][c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) Rx[r][c] = 0.0;
+  const double il = 1.0 / (double)L;
+  // Q_ii and a_i of the next step are loaded one iteration ahead of their use
+  T nQ[NX][NX], na[NX][NY];
+  gload(nQ, pi(L) + lay.o_Qii);
+  gload(na, pi(L) + lay.o_ci);
+#pragma unroll 1
+  for (int sp = 0; sp < L; ++sp) {
+    const int i = L - sp;
+    T* d = pi(i);
+    double Qii[NX][NX], ai[NX][NY];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) Qii[r][c] = (double)nQ[r][c];
+#pragma unroll
+      for (int c = 0; c < NY; ++c) ai[r][c] = (double)na[r][c];
+    }
+    if (i > 1) {
+      gload(nQ, pi(i - 1) + lay.o_Qii);
+      gload(na, pi(i - 1) + lay.o_ci);
+    }
+    if (sp > 0) {  // A^s = A A^{s-1}, Sig_s = Sig_{s-1} + A^s
+      double t[NX][NX];
+      mm(A, As, t);
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          As[r][c] = t[r][c];
+          Sig[r][c] += t[r][c];
+        }
+    }
+    double CS[NY][NX];
+    mm(C, Sig, CS);
+    double ci[NX][NY];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += Qii[r][q] * As[c][q];
+        put_global(d + lay.o_QiL + r * NX + c, (T)v);
+      }
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double v = ai[r][c];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += Qii[r][q] * CS[c][q];
+        ci[r][c] = v * il;
+        put_global(d + lay.o_ci + r * NY + c, (T)ci[r][c]);
+      }
+    }
+    if (sp == 0) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NY; ++c) cL[r][c] = ci[r][c];
+    }
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += C[r][q] * ci[q][c];
+        Rx[r][c] += v;
+      }
+  }
+  // Sig_l = Sig_{l-1} + A^l;  C_bar = (C/l)(Sig_l - I)
+  double Cb[NY][NX];
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) v += C[r][q] * (Sig[q][c] + Ai[q][c] - (q == c ? 1.0 : 0.0));
+      Cb[r][c] = v * il;
+    }
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) Rx[r][c] = Rx[r][c] * il + R[r][c];
+  symmetrize(Rx);
+  double Rxi[NY][NY];
+  if (!spd_inv(Rx, Rxi)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  double K[NX][NY], Heta[NX][NY], Fe[NX][NX], De[NX][NX], Je[NX][NX];
+  mm(cL, Rxi, K);
+  mm_tn(Cb, Rxi, Heta);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double f = Ai[r][c], dd = Qi[r][c];
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        f -= K[r][q] * Cb[q][c];
+        dd -= K[r][q] * cL[c][q];
+      }
+      Fe[r][c] = f;
+      De[r][c] = dd;
+    }
+  mm(Heta, Cb, Je);
+  symmetrize(De);
+  symmetrize(Je);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      put_global(blk + lay.A + r * NX + c, (T)A[r][c]);
+      put_global(blk + lay.Q + r * NX + c, (T)Q[r][c]);
+      put_global(el + r * NX + c, (T)Fe[r][c]);
+      put_global(el + NX * NX + r * NX + c, (T)De[r][c]);
+      put_global(el + 2 * NX * NX + r * NX + c, (T)Je[r][c]);
+    }
+#pragma unroll
+  for (int r = 0; r < NY; ++r) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c) put_global(blk + lay.Cbar + r * NX + c, (T)Cb[r][c]);
+#pragma unroll
+    for (int c = 0; c < NY; ++c) put_global(blk + lay.Rx + r * NY + c, (T)Rx[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) {
+      put_global(blk + lay.K + r * NY + c, (T)K[r][c]);
+      put_global(blk + lay.Heta + r * NY + c, (T)Heta[r][c]);
+    }
+  return flag;
+}
+
+// Window k's filter element: (F, D, J) from its element record, d = K y_k, eta = C_bar^T R_x^{-1} y_k
+// from its block; the identity element past the last window.
+template <typename T, int NX, int NY>
+SRTM_DEV void tv_element(const T* __restrict__ blk, const T* __restrict__ el, const ConstLayout& lay,
+                         const T* __restrict__ y, int64_t k, int64_t N, FElem<T, NX>& a) {
+  if (k >= N) {
+    elem_identity(a);
+    return;
+  }
+  constexpr int NN = NX * NX;
+  gload(a.F, el);
+  gload(a.D, el + NN);
+  gload(a.J, el + 2 * NN);
+  T yk[NY], K[NX][NY], He[NX][NY];
+  gloadv(yk, y + k * NY);
+  gload(K, blk + lay.K);
+  gload(He, blk + lay.Heta);
+  mv(K, yk, a.d);
+  mv(He, yk, a.e);
+}
+
+// Per tile: the window constants of every window, then the tile's aggregate a_first (x) ... (x)
+// a_last under eq. op-filter by an in-place tree in LDS (TILE whole elements).
+template <typename T, int NX, int NY>
+SRTM_DEV void tv_reduce_body(const T* __restrict__ Fa, const T* __restrict__ Qa, const T* __restrict__ Ha,
+                             const T* __restrict__ Ra, const T* __restrict__ y, int64_t N, int L, T* __restrict__ blks,
+                             T* __restrict__ els, T* __restrict__ tagg, int32_t* info, int64_t tile) {
+  constexpr int NN = NX * NX, NY2 = NY * NY, NXY = NX * NY, FA = 3 * NN + 2 * NX;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+  const ConstLayout lay = make_const_layout(NX, NY, L, 0);
+  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
+  const int tid = threadIdx.x;
+  const int64_t k = tile * TILE + tid;
+  int flag = 0;
+  if (k < N)
+    flag |= tv_window_constants<T, NX, NY>(Fa + k * NN, Qa + k * NN, Ha + k * NXY, Ra + k * NY2, L, lay,
+                                           blks + k * bs, els + k * es);
+  FElem<T, NX> a;
+  tv_element<T, NX, NY>(blks + (k < N ? k : 0) * bs, els + (k < N ? k : 0) * es, lay, y, k, N, a);
+  st_felem(S, tid, a);
+  __syncthreads();
+#pragma unroll 1
+  for (int p = 0; p < LOG_TILE; ++p) {
+    const int sp = 1 << p;
+    if (((tid + 1) & (2 * sp - 1)) == 0) {
+      FElem<T, NX> lft, rgt, o;
+      ld_felem(S, tid - sp, lft);
+      ld_felem(S, tid, rgt);
+      if (!elem_combine(lft, rgt, o)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      st_felem(S, tid, o);
+    }
+    __syncthreads();
+  }
+  if (tid == TILE - 1) {
+    FElem<T, NX> o;
+    ld_felem(S, tid, o);
+    T* dst = tagg + tile * FA;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      put_global(dst + NN + r, o.d[r]);
+      put_global(dst + 2 * NN + NX + r, o.e[r]);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        put_global(dst + r * NX + c, o.F[r][c]);
+        put_global(dst + NN + NX + r * NX + c, o.D[r][c]);
+        put_global(dst + 2 * NN + 2 * NX + r * NX + c, o.J[r][c]);
+      }
+    }
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+template <typename T, int NX>
+SRTM_DEV void ld_felem_global(const T* __restrict__ src, FElem<T, NX>& a) {
+  constexpr int NN = NX * NX;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    a.d[r] = gld(src + NN + r);
+    a.e[r] = gld(src + 2 * NN + NX + r);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      a.F[r][c] = gld(src + r * NX + c);
+      a.D[r][c] = gld(src + NN + NX + r * NX + c);
+      a.J[r][c] = gld(src + 2 * NN + 2 * NX + r * NX + c);
+    }
+  }
+}
+
+// One workgroup of KS threads: Kogge-Stone scan of the tile aggregates (whole elements). Thread
+// tau folds its chunk of 2^lchunk tiles; the prior is folded into thread 0, which makes it a
+// state; at step q threads [2^q, 2^{q+1}) combine the state of thread tau - 2^q with their run and
+// the others merge two runs (eq. op-filter). Each thread then walks its chunk from its exclusive
+// state, writing every tile's incoming state.
+template <typename T, int NX>
+SRTM_DEV void tv_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, int steps, const T* __restrict__ m0,
+                            const T* __restrict__ P0, T* __restrict__ tstate, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN, FA = 3 * NN + 2 * NX;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), KS};
+  const int tid = threadIdx.x;
+  const int64_t c = int64_t(1) << lchunk;
+  const int64_t t0 = tid * c;
+  int flag = 0;
+  FElem<T, NX> run;
+  elem_identity(run);
+  T m[NX], P[NX][NX];  // a state once the thread's run reaches back to the prior
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    m[r] = T(0);
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc) P[r][cc] = T(0);
+  }
+#pragma unroll 1
+  for (int64_t j = 0; j < c; ++j) {
+    const int64_t t = t0 + j;
+    if (t >= nt) break;
+    FElem<T, NX> b;
+    ld_felem_global(tagg + t * FA, b);
+    if (j == 0) {
+      run = b;
+    } else if (!elem_combine(run, b, run)) {
+      flag |= SRTM_INFO_COMBINE_SINGULAR;
+    }
+  }
+  if (tid == 0) {
+    gloadv(m, m0);
+    gload(P, P0);
+    symmetrize(P);
+    if (!state_combine(m, P, run.F, run.d, run.D, run.e, run.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  }
+#pragma unroll 1
+  for (int q = 0; q < steps; ++q) {
+    const int sp = 1 << q;
+    if (tid < sp) {
+      st_state<T, NX>(S, tid, m, P);
+    } else {
+      st_felem(S, tid, run);
+    }
+    __syncthreads();
+    if (tid >= sp && tid < 2 * sp) {
+      ld_state<T, NX>(S, tid - sp, m, P);
+      if (!state_combine(m, P, run.F, run.d, run.D, run.e, run.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    } else if (tid >= 2 * sp) {
+      FElem<T, NX> lft;
+      ld_felem(S, tid - sp, lft);
+      if (!elem_combine(lft, run, run)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    }
+    __syncthreads();
+  }
+  st_state<T, NX>(S, tid, m, P);  // every thread now holds the inclusive state through its chunk
+  __syncthreads();
+  if (t0 < nt) {
+    T X[NX], XP[NX][NX];
+    if (tid == 0) {
+      gloadv(X, m0);
+      gload(XP, P0);
+      symmetrize(XP);
+    } else {
+      ld_state<T, NX>(S, tid - 1, X, XP);
+    }
+#pragma unroll 1
+    for (int64_t t = t0; t < t0 + c && t < nt; ++t) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) put_global(tstate + t * ST + r, X[r]);
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int cc = 0; cc < NX; ++cc) put_global(tstate + t * ST + NX + r * NX + cc, XP[r][cc]);
+      if (t + 1 < t0 + c && t + 1 < nt) {
+        FElem<T, NX> b;
+        ld_felem_global(tagg + t * FA, b);
+        if (!state_combine(X, XP, b.F, b.d, b.D, b.e, b.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+      }
+    }
+  }
+  if (flag && info) atomicOr(info, flag);
+}
+
+// Per tile: an in-tile inclusive Kogge-Stone scan of the windows' elements, then each window's
+// exclusive and inclusive filter states from the tile's incoming state; the carry (and slow
+// filter outputs); with SMOOTH the smoother half of the fused kernel, with the next window's
+// F and Q as the model of the step into x_{k+1,1}.
+template <typename T, int NX, int NY, bool SMOOTH>
+SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, const T* __restrict__ y, int64_t N,
+                          int L, const T* __restrict__ blks, const T* __restrict__ els, const T* __restrict__ m0,
+                          const T* __restrict__ P0, const T* __restrict__ ftstate, T* __restrict__ carry,
+                          T* __restrict__ m_slow, T* __restrict__ P_slow, T* __restrict__ btagg, T* __restrict__ sfx,
+                          int32_t* info, int64_t tile) {
+  constexpr int NN = NX * NX, ST = NX + NN;
+  extern __shared__ char smraw[];
+  const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
+  const ConstLayout lay = make_const_layout(NX, NY, L, 0);
+  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
+  const int tid = threadIdx.x;
+  const int64_t k = tile * TILE + tid;
+  const bool valid = k < N;
+  const int64_t kc = valid ? k : 0;
+  int flag = 0;
+  FElem<T, NX> a, x;
+  tv_element<T, NX, NY>(blks + kc * bs, els + kc * es, lay, y, k, N, a);
+  x = a;
+#pragma unroll 1
+  for (int sp = 1; sp < TILE; sp *= 2) {  // x <- a_first (x) ... (x) a_k
+    st_felem(S, tid, x);
+    __syncthreads();
+    FElem<T, NX> lft;
+    if (tid >= sp) ld_felem(S, tid - sp, lft);
+    __syncthreads();
+    if (tid >= sp && !elem_combine(lft, x, x)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  }
+  st_felem(S, tid, x);
+  __syncthreads();
+  T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
+  {
+    gloadv(mprev, ftstate + tile * ST);
+    gload(Pprev, ftstate + tile * ST + NX);
+    symmetrize(Pprev);
+    if (tid > 0) {
+      FElem<T, NX> ex;
+      ld_felem(S, tid - 1, ex);
+      if (!state_combine(mprev, Pprev, ex.F, ex.d, ex.D, ex.e, ex.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+    }
+    if (k == 0) {  // the prior itself
+      gloadv(mprev, m0);
+      gload(Pprev, P0);
+      symmetrize(Pprev);
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      m[r] = mprev[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) P[r][c] = Pprev[r][c];
+    }
+    if (!state_combine(m, P, a.F, a.d, a.D, a.e, a.J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
+  }
+  if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
+  if constexpr (SMOOTH) {
+    __syncthreads();  // the slots switch from forward elements to smoother elements
+    const Model<T, NX, NY> M{blks + kc * bs, lay};
+    T yt[NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) yt[r] = valid ? gld(y + k * NY + r) : T(0);
+    T An[NX][NX], Qn[NX][NX];
+    const int64_t kn = (k + 1 < N) ? k + 1 : kc;  // the last window's element ignores them
+    gload(An, Fa + kn * NN);
+    gload(Qn, Qa + kn * NN);
+    flag |= smoother_part<false>(M, S, L, k, N, yt, mprev, Pprev, m, P, An, Qn, btagg, sfx, tile);
+  }
   if (flag && info) atomicOr(info, flag);
 }
 
@@ -2449,7 +2961,7 @@ template <typename T, int NX, int NY>
 struct Seq {  // one sequence's typed arrays and scan plan
   const T *F, *Q, *H, *R, *m0, *P0, *y;
   T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
-  T *cst, *ftagg, *ftst, *carry, *btagg, *btst, *sfx;
+  T *cst, *ftagg, *ftst, *carry, *btagg, *btst, *sfx, *tvblk, *tvel;
   double *hand, *stats;
   int64_t N, tile0;
   int L;
@@ -2481,7 +2993,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.tile0 = d.tile0;
   q.L = d.L;
   q.plan = make_scan_plan(d.N);
-  const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0, d.B != nullptr);
+  const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0, d.B != nullptr, d.tv != 0);
   char* base = as_global(b.ws) + d.ws_off;
   q.cst = reinterpret_cast<T*>(base + wl.consts);
   q.hand = reinterpret_cast<double*>(base + wl.chain);
@@ -2491,6 +3003,8 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.btagg = reinterpret_cast<T*>(base + wl.btile_agg);
   q.btst = reinterpret_cast<T*>(base + wl.btile_state);
   q.sfx = reinterpret_cast<T*>(base + wl.sfx);
+  q.tvblk = reinterpret_cast<T*>(base + wl.tvblk);
+  q.tvel = reinterpret_cast<T*>(base + wl.tvel);
   q.stats = reinterpret_cast<double*>(base + wl.stats);
   q.info = b.info ? b.info + s : nullptr;
   q.in = InputView<T>{as_global<T>(d.B), as_global<T>(d.u), q.H,
@@ -2547,14 +3061,37 @@ __global__ void __launch_bounds__(KS) k_bwd_tiles(Batch b) {
   bwd_tiles_body<T, NX, NY>(q.btagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.btst);
 }
 
+// Per-window (time-varying) models: per-window constants and tile aggregates; the tile-level
+// scan of whole elements; the fused per-tile forward (and smoother) pass.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE) k_tv_reduce(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  tv_reduce_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.y, q.N, q.L, q.tvblk, q.tvel, q.ftagg, q.info,
+                            (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(KS) k_tv_tiles(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  tv_tiles_body<T, NX>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.m0, q.P0, q.ftst, q.info);
+}
+
+template <typename T, int NX, int NY, bool SMOOTH>
+__global__ void __launch_bounds__(TILE) k_tv_fwd(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  tv_fwd_body<T, NX, NY, SMOOTH>(q.F, q.Q, q.y, q.N, q.L, q.tvblk, q.tvel, q.m0, q.P0, q.ftst, q.carry,
+                                 q.mf_slow, q.Pf_slow, q.btagg, q.sfx, q.info, (int64_t)blockIdx.x - q.tile0);
+}
+
 // MODE 1: filter outputs only; 2: smoother outputs; 3: both. Fast-rate outputs take all L
 // steps; with only the slow smoothed state requested, step 1 suffices.
-template <typename T, int NX, int NY, int MODE, bool INP>
+template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
   const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
   if (!fast && !q.ms_slow && !q.Ps_slow) return;
-  recover_body<T, NX, NY, MODE, INP>(q.y, q.N, q.L, fast ? q.L : 1, q.cst, q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
+  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst,
+                                         (int64_t)tv_block_size(NX, NY, q.L), q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
                                 q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
                                 (int64_t)blockIdx.x - q.tile0);
 }
@@ -2724,6 +3261,55 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   return SRTM_OK;
 }
 
+// Per-window (time-varying) model, one sequence: 6 launches for the smoother (k_tv_reduce,
+// k_tv_tiles, k_tv_fwd<1>, k_bwd_tiles, k_recover), 4 for the filter.
+template <typename T, int NX, int NY>
+srtm_status launch_tv(const Batch& b, const Launch& g, bool smoother, int rec_mode, hipStream_t st) {
+  if constexpr (NX > TV_NX_MAX) {
+    return SRTM_E_UNSUPPORTED;
+  } else {
+    constexpr int NN = NX * NX, FA = 3 * NN + 2 * NX;
+    const size_t lds_el = sizeof(T) * (size_t)TILE * FA;  // a tile of whole elements
+    if (!allow_lds((const void*)k_tv_reduce<T, NX, NY>, lds_el)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_tv_reduce<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds_el, st, b);
+    SRTM_CHECK_LAUNCH();
+    const size_t lds_ks = sizeof(T) * (size_t)KS * FA;
+    if (!allow_lds((const void*)k_tv_tiles<T, NX, NY>, lds_ks)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_tv_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ks, st, b);
+    SRTM_CHECK_LAUNCH();
+    const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES;
+    if (!smoother) {
+      if (!allow_lds((const void*)k_tv_fwd<T, NX, NY, false>, lds_el)) return SRTM_E_HIP;
+      hipLaunchKernelGGL((k_tv_fwd<T, NX, NY, false>), dim3(g.ntiles), dim3(TILE), lds_el, st, b);
+      SRTM_CHECK_LAUNCH();
+      if (rec_mode == 1) {
+        if (!allow_lds((const void*)k_recover<T, NX, NY, 1, false, true>, lds_rec)) return SRTM_E_HIP;
+        hipLaunchKernelGGL((k_recover<T, NX, NY, 1, false, true>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+        SRTM_CHECK_LAUNCH();
+      }
+      return SRTM_OK;
+    }
+    if (!allow_lds((const void*)k_tv_fwd<T, NX, NY, true>, lds_el)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_tv_fwd<T, NX, NY, true>), dim3(g.ntiles), dim3(TILE), lds_el, st, b);
+    SRTM_CHECK_LAUNCH();
+    const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
+    if (!allow_lds((const void*)k_bwd_tiles<T, NX, NY>, lds_bk)) return SRTM_E_HIP;
+    hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_bk, st, b);
+    SRTM_CHECK_LAUNCH();
+    if (rec_mode == 2 || rec_mode == 3) {  // filter and smoother outputs: two recovery passes
+      if (rec_mode == 3) {
+        if (!allow_lds((const void*)k_recover<T, NX, NY, 1, false, true>, lds_rec)) return SRTM_E_HIP;
+        hipLaunchKernelGGL((k_recover<T, NX, NY, 1, false, true>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+        SRTM_CHECK_LAUNCH();
+      }
+      if (!allow_lds((const void*)k_recover<T, NX, NY, 2, false, true>, lds_rec)) return SRTM_E_HIP;
+      hipLaunchKernelGGL((k_recover<T, NX, NY, 2, false, true>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+      SRTM_CHECK_LAUNCH();
+    }
+    return SRTM_OK;
+  }
+}
+
 // One sequence (srtm_filter / srtm_smooth).
 template <typename T, int NX, int NY>
 srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t st, Events ev, int lik_mode = 0,
@@ -2745,12 +3331,16 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   d.B = p.B;
   d.u = p.u;
   d.nu = p.B ? p.nu : 0;
-  d.reserved = 0;
+  d.tv = p.tv ? 1 : 0;
   const Launch g{1u, (unsigned)((sh.N + TILE - 1) / TILE), (int)sh.L};
   const bool want_f = p.mf_fast || p.Pf_fast;
   const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
   const int mode = lik_mode ? lik_mode : (smoother ? (want_f ? 3 : (want_s ? 2 : 0)) : (want_f ? 1 : 0));
   const LikOut<T> lo{static_cast<T*>(ll), static_cast<T*>(dF), static_cast<T*>(dQ), static_cast<T*>(dR)};
+  if (p.tv) {
+    if (lik_mode || ev.ev) return SRTM_E_UNSUPPORTED;  // no log-likelihood or profiling form
+    return launch_tv<T, NX, NY>(b, g, smoother, mode, st);
+  }
   if (p.B) return launch_all<T, NX, NY, true>(b, g, smoother, mode, st, ev, lo);
   return launch_all<T, NX, NY, false>(b, g, smoother, mode, st, ev, lo);
 }

@@ -79,8 +79,15 @@ inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, inp, total;
+  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel, total;
 };
+
+// Time-varying (per-window) models: scalars of one window's constants block (the layout of
+// make_const_layout without level records) and of its element record (F, D, J).
+inline __host__ __device__ int tv_block_size(int nx, int ny, int L) {
+  return make_const_layout(nx, ny, L, 0).total;
+}
+inline __host__ __device__ constexpr int tv_elem_size(int nx) { return 3 * nx * nx; }
 
 // Scalars (float64) of one tile's log-likelihood / gradient record.
 inline __host__ __device__ constexpr int stat_size(int nx, int ny) { return 1 + 4 * nx * nx + ny * ny; }
@@ -91,17 +98,20 @@ inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + n
 inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // `inputs`: the call has known inputs, whose per-window record (y_k - mu_k, z_{k,l}) [N][ny + nx]
-// the tile reductions write for the later kernels.
+// the tile reductions write for the later kernels. `tv`: the model is given per window; the
+// per-window constants blocks [N][tv_block_size] and element records [N][tv_elem_size] follow,
+// and the tile aggregates of the forward scan are whole elements.
 inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, int64_t N, size_t esz, bool smoother,
-                                                       bool inputs = false) {
+                                                       bool inputs = false, bool tv = false) {
   WorkLayout w;
   const ConstLayout c = make_const_layout(nx, ny, L, make_scan_plan(N).nlev);
   const int64_t nt = (N + TILE - 1) / TILE;
   const size_t nn = (size_t)nx * nx;
+  const size_t fagg = tv ? (size_t)(3 * nn + 2 * nx) : (size_t)(2 * nx);  // scalars per tile aggregate
   size_t o = 0;
   w.consts = o; o = align256(o + (size_t)c.total * esz);
   w.chain = o; o = align256(o + 3 * nn * sizeof(double));  // float64 F, D, J handed between launches
-  w.ftile_agg = o; o = align256(o + (size_t)nt * 2 * nx * esz);
+  w.ftile_agg = o; o = align256(o + (size_t)nt * fagg * esz);
   w.ftile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
   w.carry = o; o = align256(o + (size_t)N * (nx + nn) * esz);
   if (smoother) {
@@ -116,6 +126,12 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
     w.inp = o; o = align256(o + (size_t)N * (nx + ny) * esz);
   } else {
     w.inp = 0;
+  }
+  if (tv) {
+    w.tvblk = o; o = align256(o + (size_t)N * tv_block_size(nx, ny, L) * esz);
+    w.tvel = o; o = align256(o + (size_t)N * tv_elem_size(nx) * esz);
+  } else {
+    w.tvblk = w.tvel = 0;
   }
   w.total = o;
   return w;
@@ -133,7 +149,7 @@ struct SeqDesc {
   int32_t smoother;  // the block holds the smoother regions
   const void *B, *u;  // known inputs (null without)
   int32_t nu;
-  int32_t reserved;
+  int32_t tv;  // F, Q, H, R are given per window ([N][...])
 };
 
 // What every kernel receives: either one sequence (`table` null) or a device table of

@@ -59,12 +59,18 @@ def lib():
     L.srtm_workspace_size.restype = ctypes.c_int
     L.srtm_workspace_size_inputs.argtypes = L.srtm_workspace_size.argtypes
     L.srtm_workspace_size_inputs.restype = ctypes.c_int
+    L.srtm_workspace_size_tv.argtypes = L.srtm_workspace_size.argtypes
+    L.srtm_workspace_size_tv.restype = ctypes.c_int
     L.srtm_supported.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.srtm_supported.restype = ctypes.c_int32
     L.srtm_filter.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_filter.restype = ctypes.c_int
     L.srtm_smooth.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 16 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_smooth.restype = ctypes.c_int
+    L.srtm_filter_tv.argtypes = L.srtm_filter.argtypes
+    L.srtm_filter_tv.restype = ctypes.c_int
+    L.srtm_smooth_tv.argtypes = L.srtm_smooth.argtypes
+    L.srtm_smooth_tv.restype = ctypes.c_int
     L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
                                        [ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_int32])
     L.srtm_smooth_profiled.restype = ctypes.c_int
@@ -123,11 +129,13 @@ def shape_of(nx: int, ny: int, L: int, N: int, dtype: torch.dtype) -> Shape:
 
 
 def workspace_size(nx: int, ny: int, L: int, N: int, dtype: torch.dtype, smoother: bool,
-                   inputs: bool = False) -> int:
-    """Workspace bytes of srtm_filter (smoother False) or srtm_smooth, or of their *_inputs forms."""
+                   inputs: bool = False, tv: bool = False) -> int:
+    """Workspace bytes of srtm_filter (smoother False) or srtm_smooth, or of their *_inputs or
+    per-window (*_tv) forms."""
     out = ctypes.c_size_t(0)
     sh = shape_of(nx, ny, L, N, dtype)
-    fn = lib().srtm_workspace_size_inputs if inputs else lib().srtm_workspace_size
+    fn = (lib().srtm_workspace_size_tv if tv else
+          lib().srtm_workspace_size_inputs if inputs else lib().srtm_workspace_size)
     _check(fn(ctypes.byref(sh), int(smoother), ctypes.byref(out)), "srtm_workspace_size")
     return int(out.value)
 
@@ -147,9 +155,11 @@ def _prep(F, Q, H, R, L, m0, P0, y):
             raise SrtmError(f"{k} must be on a GPU (got {t.device}); there is no CPU path")
         if t.device != dev or t.dtype != dt:
             raise SrtmError(f"{k} must share device {dev} and dtype {dt}")
-    nx, ny = F.shape[0], H.shape[0]
+    tv = F.dim() == 3  # per-window (time-varying) model: F, Q, H, R are [N, ...]
+    nx, ny = F.shape[-1], H.shape[-2]
     N = y.shape[0]
-    exp = dict(F=(nx, nx), Q=(nx, nx), H=(ny, nx), R=(ny, ny), m0=(nx,), P0=(nx, nx), y=(N, ny))
+    w = (N,) if tv else ()
+    exp = dict(F=w + (nx, nx), Q=w + (nx, nx), H=w + (ny, nx), R=w + (ny, ny), m0=(nx,), P0=(nx, nx), y=(N, ny))
     for k, s in exp.items():
         if tuple(ts[k].shape) != s:
             raise SrtmError(f"{k} has shape {tuple(ts[k].shape)}, expected {s}")
@@ -190,9 +200,13 @@ def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
            check: bool = True, B=None, u=None) -> Dict[str, torch.Tensor]:
     """p(x_{k,i} | y_{1:k}) as m_fast [N,L,nx], P_fast [N,L,nx,nx]; p(x_{k,L} | y_{1:k}) as m_slow, P_slow.
 
-    B [nx, nu] and u [N, L, nu] add known inputs (u[k-1, i-1] drives x_{k,i})."""
+    B [nx, nu] and u [N, L, nu] add known inputs (u[k-1, i-1] drives x_{k,i}). F, Q, H, R given
+    per window ([N, ...]) select the time-varying form (srtm_filter_tv)."""
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
     inp = _prep_inputs(B, u, nx, L, N, y)
+    tv = F.dim() == 3
+    if tv and inp is not None:
+        raise SrtmError("a per-window model takes no inputs")
     dev, dt = y.device, y.dtype
     out = {}
     if fast:
@@ -201,7 +215,7 @@ def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     if slow:
         out["m_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
         out["P_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
-    nbytes = workspace_size(nx, ny, L, N, dt, False, inp is not None)
+    nbytes = workspace_size(nx, ny, L, N, dt, False, inp is not None, tv)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
     if info is None:
@@ -211,7 +225,9 @@ def filter(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     args = ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
             [_ptr(out.get(k)) for k in ("m_fast", "P_fast", "m_slow", "P_slow")] +
             [_ptr(workspace), workspace.numel(), _ptr(info), ctypes.c_void_p(stream)])
-    if inp is None:
+    if tv:
+        _check(lib().srtm_filter_tv(ctypes.byref(sh), *args), "srtm_filter_tv")
+    elif inp is None:
         _check(lib().srtm_filter(ctypes.byref(sh), *args), "srtm_filter")
     else:
         _check(lib().srtm_filter_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *args), "srtm_filter_inputs")
@@ -240,8 +256,11 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     """
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
     inp = _prep_inputs(B, u, nx, L, N, y)
-    if inp is not None and events is not None:
-        raise SrtmError("the profiling entry point takes no inputs")
+    tv = F.dim() == 3
+    if (inp is not None or tv) and events is not None:
+        raise SrtmError("the profiling entry point takes neither inputs nor a per-window model")
+    if tv and inp is not None:
+        raise SrtmError("a per-window model takes no inputs")
     dev, dt = y.device, y.dtype
     if out is None:
         out = {}
@@ -256,7 +275,7 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
             out["Pf_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
             out["mf_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
             out["Pf_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
-    nbytes = workspace_size(nx, ny, L, N, dt, True, inp is not None)
+    nbytes = workspace_size(nx, ny, L, N, dt, True, inp is not None, tv)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
     if info is None:
@@ -264,7 +283,9 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     sh = shape_of(nx, ny, L, N, dt)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     args = _smooth_args(ts, out, workspace, info)
-    if inp is not None:
+    if tv:
+        _check(lib().srtm_smooth_tv(ctypes.byref(sh), *args, stream), "srtm_smooth_tv")
+    elif inp is not None:
         code = lib().srtm_smooth_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *args, stream)
         _check(code, "srtm_smooth_inputs")
     elif events is None:
@@ -284,6 +305,8 @@ def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):
     inp = _prep_inputs(B, u, nx, L, N, y)
     if inp is not None and grad:
         raise SrtmError("the log-likelihood gradient takes no inputs")
+    if F.dim() == 3:
+        raise SrtmError("the log-likelihood entry points take a time-invariant model")
     dev, dt = y.device, y.dtype
     ll = torch.empty(1, device=dev, dtype=dt)
     dF = torch.empty((nx, nx), device=dev, dtype=dt) if grad else None

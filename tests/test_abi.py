@@ -296,3 +296,29 @@ def test_inputs_call_rejects_plain_workspace_size(L):
     plain = _ws(2, 1, 10, 5)[1]
     ok = srtm.InputsC(0x9000, 0xA000, 1, 0)
     assert _call_inputs(L.srtm_smooth_inputs, sh, ok, FAKE, plain, 8) == 6
+
+
+def test_time_varying_entry_points_validate(L):
+    """Per-window models: nx <= 4 only; a larger workspace (per-window constants) than the plain one."""
+    sh = srtm.Shape(4, 2, 20, 1, 1000)
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.srtm_workspace_size(ctypes.byref(sh), 1, ctypes.byref(a)) == 0
+    assert L.srtm_workspace_size_tv(ctypes.byref(sh), 1, ctypes.byref(b)) == 0
+    assert b.value > a.value + 1000 * 20 * 56 * 8
+    assert L.srtm_workspace_size_tv(ctypes.byref(srtm.Shape(6, 1, 20, 1, 1000)), 1, ctypes.byref(b)) == 4
+    small = srtm.Shape(2, 1, 10, 1, 5)
+    assert _call(L.srtm_smooth_tv, small, FAKE, _ws(2, 1, 10, 5)[1], 8) == 6   # plain size is too small
+    assert _call(L.srtm_filter_tv, small, FAKE, 16, 4) == 6
+    assert _call(L.srtm_smooth_tv, srtm.Shape(6, 1, 10, 1, 5), FAKE, 1 << 30, 8) == 4
+    ptrs = list(FAKE)
+    ptrs[0] = 0
+    assert _call(L.srtm_smooth_tv, small, ptrs, 1 << 30, 8) == 1
+
+
+def test_binding_declares_every_signature(L):
+    """The Python binding gives every C entry point its argument and result types (a missing
+    declaration would pass 64-bit sizes as C ints)."""
+    for n in _declared_functions():
+        fn = getattr(L, n)
+        assert fn.argtypes is not None, f"{n}: argtypes not set"
+        assert fn.restype is not None, f"{n}: restype not set"

@@ -1,0 +1,171 @@
+"""GPU parity for per-window (time-varying) models through srtm_filter_tv / srtm_smooth_tv,
+against the float64 CPU reference with the same per-window model.
+
+Tolerances as in test_gpu_parity: 1e-8 (float64), 1e-3 (float32, reference on rounded inputs).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_00627_amd import workloads as wl
+from conftest import assert_close_states
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-8, torch.float32: 1e-3}
+
+
+def _srtm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_00627_amd import srtm
+    srtm.lib()
+    return srtm
+
+
+def _r(a, dtype):
+    a = np.asarray(a, dtype=np.float64)
+    return a if dtype == torch.float64 else a.astype(np.float32).astype(np.float64)
+
+
+def _rounded(m, y, dtype):
+    return (wl.TVModel(_r(m.A, dtype), _r(m.Q, dtype), _r(m.C, dtype), _r(m.R, dtype), m.L, _r(m.m0, dtype),
+                       _r(m.P0, dtype), m.name), _r(y, dtype))
+
+
+def _gpu(srtm, m, y, dtype, *, filter_only=False):
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", dtype)
+    yt = torch.as_tensor(y, dtype=torch.float64).to("cuda", dtype)
+    if filter_only:
+        out = srtm.filter(F, Q, H, R, m.L, m0, P0, yt)
+    else:
+        out = srtm.smooth(F, Q, H, R, m.L, m0, P0, yt, with_filter=True)
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in out.items()}
+
+
+CASES = [
+    # nx, ny, L, N, seed, general -- several 256-window tiles with a ragged tail
+    (4, 2, 20, 300, 1, False),
+    (4, 2, 5, 845, 2, True),
+    (2, 1, 10, 600, 3, True),
+    (3, 2, 7, 300, 4, True),
+    (1, 1, 3, 513, 5, True),
+    (2, 2, 1, 700, 6, True),     # l = 1: a time-varying Kalman filter + RTS smoother
+    (4, 1, 4, 1100, 7, False),
+]
+
+
+# float32 on the drifting models of the workload family; float64 also on unrelated random
+# per-window models (full Q, R, non-orthogonal A), which are for structure and can be too poorly
+# conditioned for float32 covariances to hold 1e-3.
+CASES32 = [(4, 2, 20, 300, 1, False), (4, 1, 4, 1100, 7, False), (2, 1, 10, 600, 8, False), (3, 2, 7, 300, 9, False),
+           (2, 2, 1, 700, 10, False)]
+PARAMS = [(c, torch.float64) for c in CASES] + [(c, torch.float32) for c in CASES32]
+
+
+@pytest.mark.parametrize("case,dtype", PARAMS,
+                         ids=[f"{'f64' if d == torch.float64 else 'f32'}-nx{c[0]}ny{c[1]}L{c[2]}N{c[3]}"
+                              f"{'gen' if c[5] else 'drift'}" for c, d in PARAMS])
+def test_tv_smoother_parity(case, dtype):
+    nx, ny, L, N, seed, general = case
+    srtm = _srtm()
+    m = wl.time_varying_model(nx, ny, L, N, seed, general=general)
+    y = wl.simulate_tv(m, seed + 50)
+    print(f"[gpu] smooth_tv nx={nx} ny={ny} L={L} N={N} {dtype}", flush=True)
+    o = _gpu(srtm, m, y, dtype)
+    mr, yr = _rounded(m, y, dtype)
+    ref = oracle.srtm_smoother_tv(mr.A, mr.Q, mr.C, mr.R, L, mr.m0, mr.P0, yr, with_filter=True)
+    tol = TOL[dtype]
+    assert int(o["info"][0]) == 0
+    assert_close_states(o["ms_fast"], o["Ps_fast"], ref["ms_fast"], ref["Ps_fast"], tol, "smoothed fast")
+    assert_close_states(o["ms_slow"], o["Ps_slow"], ref["ms_slow"], ref["Ps_slow"], tol, "smoothed slow")
+    assert_close_states(o["mf_fast"], o["Pf_fast"], ref["m_fast"], ref["P_fast"], tol, "filtered fast")
+    assert_close_states(o["mf_slow"], o["Pf_slow"], ref["m_slow"], ref["P_slow"], tol, "filtered slow")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_tv_filter_entry_point(dtype):
+    srtm = _srtm()
+    m = wl.time_varying_model(3, 2, 6, 400, 21, general=dtype == torch.float64)
+    y = wl.simulate_tv(m, 22)
+    o = _gpu(srtm, m, y, dtype, filter_only=True)
+    mr, yr = _rounded(m, y, dtype)
+    ref = oracle.srtm_filter_tv(mr.A, mr.Q, mr.C, mr.R, m.L, mr.m0, mr.P0, yr)
+    assert_close_states(o["m_fast"], o["P_fast"], ref["m_fast"], ref["P_fast"], TOL[dtype], "filter fast")
+    assert_close_states(o["m_slow"], o["P_slow"], ref["m_slow"], ref["P_slow"], TOL[dtype], "filter slow")
+
+
+def test_tv_edge_lengths():
+    srtm = _srtm()
+    for N in (1, 2, 255, 256, 257):
+        m = wl.time_varying_model(3, 2, 4, N, 30 + N, general=True)
+        y = wl.simulate_tv(m, 31 + N)
+        print(f"[gpu] smooth_tv N={N}", flush=True)
+        o = _gpu(srtm, m, y, torch.float64)
+        ref = oracle.srtm_smoother_tv(m.A, m.Q, m.C, m.R, m.L, m.m0, m.P0, y, with_filter=True)
+        assert_close_states(o["ms_fast"], o["Ps_fast"], ref["ms_fast"], ref["Ps_fast"], 1e-8, f"N={N} smoothed")
+        assert_close_states(o["mf_fast"], o["Pf_fast"], ref["m_fast"], ref["P_fast"], 1e-8, f"N={N} filtered")
+
+
+def test_tv_equal_windows_match_time_invariant_path():
+    """A per-window model whose windows are all equal gives the time-invariant path's results."""
+    srtm = _srtm()
+    m = wl.random_general_model(4, 2, 8, 41)
+    y = wl.simulate(m, 700, 42)
+    N = y.shape[0]
+    rep = lambda X: np.repeat(np.asarray(X)[None], N, axis=0)  # noqa: E731
+    tvm = wl.TVModel(rep(m.A), rep(m.Q), rep(m.C), rep(m.R), m.L, m.m0, m.P0)
+    a = _gpu(srtm, m, y, torch.float64)
+    b = _gpu(srtm, tvm, y, torch.float64)
+    for mk, pk in (("ms_fast", "Ps_fast"), ("mf_fast", "Pf_fast"), ("ms_slow", "Ps_slow"), ("mf_slow", "Pf_slow")):
+        assert_close_states(b[mk], b[pk], a[mk], a[pk], 1e-10, f"{mk} per-window vs time-invariant")
+
+
+def test_tv_refuses_larger_states():
+    srtm = _srtm()
+    m = wl.time_varying_model(6, 1, 4, 20, 51, general=True)
+    y = wl.simulate_tv(m, 52)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", torch.float64)
+    with pytest.raises(srtm.SrtmError):
+        srtm.smooth(F, Q, H, R, m.L, m0, P0, torch.as_tensor(y, device="cuda"))
+
+
+def test_tv_full_size_local_checks():
+    """nx=4, ny=2, L=20, N=2^17 drifting model: at sampled windows one IMKF step of the reference
+    from the GPU's slow carry of window k-1 reproduces the GPU's carry and fast filter of window
+    k, and one smoother step from the GPU's smoothed slow state of window k+1 reproduces the
+    GPU's smoothed window k; the last 16 windows match the reference smoother started from the
+    GPU's carry."""
+    srtm = _srtm()
+    N = wl.HEADLINE_N
+    m = wl.time_varying_model(4, 2, 20, N, 2027)
+    y = wl.simulate_tv(m, 2028)
+    print("[gpu] smooth_tv headline size", flush=True)
+    o = _gpu(srtm, m, y, torch.float64)
+    assert int(o["info"][0]) == 0
+    nx, L = m.nx, m.L
+    rng = np.random.default_rng(3)
+    for k in sorted(set(rng.integers(1, N - 1, 20).tolist()) | {1, 255, 256, N // 2, N - 2}):
+        mp, Pp = o["mf_slow"][k - 1], o["Pf_slow"][k - 1]
+        sl = slice(k, k + 1)
+        one = oracle.srtm_filter_tv(m.A[sl], m.Q[sl], m.C[sl], m.R[sl], L, mp, Pp, y[sl])
+        assert_close_states(o["mf_slow"][sl], o["Pf_slow"][sl], one["m_slow"], one["P_slow"], 1e-8, f"carry {k}")
+        assert_close_states(o["mf_fast"][sl], o["Pf_fast"][sl], one["m_fast"], one["P_fast"], 1e-8, f"fast filter {k}")
+        bm = oracle.batch_model(m.A[k], m.Q[k], m.C[k], L)
+        M_f, P_f = oracle.fast_filter_window(bm, m.R[k], mp, Pp, y[k])
+        Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), m.A[k + 1]])
+        mpr = Ahat @ M_f
+        Ppr = Ahat @ P_f @ Ahat.T + m.Q[k + 1]
+        G = np.linalg.solve(Ppr.T, (P_f @ Ahat.T).T).T
+        M_s = M_f + G @ (o["ms_slow"][k + 1] - mpr)
+        P_s = P_f + G @ (o["Ps_slow"][k + 1] - Ppr) @ G.T
+        msk = M_s.reshape(L, nx)
+        Psk = np.stack([P_s[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] for i in range(L)])
+        assert_close_states(o["ms_fast"][k], o["Ps_fast"][k], msk, Psk, 1e-7, f"smoother step {k}")
+    n = 16
+    s0 = N - n
+    tail = oracle.srtm_smoother_tv(m.A[s0:], m.Q[s0:], m.C[s0:], m.R[s0:], L, o["mf_slow"][s0 - 1],
+                                   o["Pf_slow"][s0 - 1], y[s0:])
+    assert_close_states(o["ms_fast"][s0:], o["Ps_fast"][s0:], tail["ms_fast"], tail["Ps_fast"], 1e-8, "tail")
