@@ -448,14 +448,53 @@ struct InputView {
   int nu;
 };
 
-template <typename T, int NX, int NY>
+// A call's constants block. SOA: one window's block of a per-window model, stored window-minor
+// (scalar j of the window at cst[j * cs + lane], cst the base of its tile's columns), so that
+// consecutive lanes read consecutive addresses.
+template <typename T, int NX, int NY, bool SOA = false>
 struct Model {
   const T* __restrict__ cst;
   ConstLayout lay;
   InputView<T> in{};
+  int64_t cs = 1;
   SRTM_DEV const T* per_i(int i) const { return cst + lay.per_i + (i - 1) * lay.per_i_stride; }
+  SRTM_DEV int per_i_off(int i) const { return lay.per_i + (i - 1) * lay.per_i_stride; }
   SRTM_DEV const T* level(int p) const { return cst + lay.lev + p * lay.lev_stride; }
+  int lane = 0;  // SOA: the window's column within the block of columns at `cst`
+  template <int R, int C>
+  SRTM_DEV void get(T (&a)[R][C], int off) const {
+    if constexpr (SOA) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[r][c] = at(off + r * C + c);
+    } else {
+      load(a, cst + off);
+    }
+  }
+  // SOA: the row base cst + off * cs is the same for every lane of a workgroup (it stays in
+  // scalar registers); each lane adds its column.
+  SRTM_DEV T at(int off) const {
+    if constexpr (SOA)
+      return gld(cst + (int64_t)off * cs + lane);
+    else
+      return cst[off];
+  }
 };
+
+// Per-window blocks and element records are stored tile by tile, window-minor within a tile:
+// scalar j of window k at base[(k / TILE) * width * TILE + j * TILE + k % TILE] for records of
+// `width` scalars, so that the lanes of a wave read and write consecutive addresses and one
+// tile's records stay within width * TILE scalars. Returns window k's column (stride TILE).
+template <typename T>
+SRTM_DEV T* tv_column(T* base, int64_t k, int width) {
+  return base + (k / TILE) * (int64_t)width * TILE + (k % TILE);
+}
+// The block of columns of window k's tile (tv_column minus the column).
+template <typename T>
+SRTM_DEV T* tv_tile_base(T* base, int64_t k, int width) {
+  return base + (k / TILE) * (int64_t)width * TILE;
+}
 
 template <typename T, int N>
 SRTM_DEV T symget(const T (&P)[N][N], int r, int c) { return r <= c ? P[r][c] : P[c][r]; }
@@ -750,12 +789,12 @@ struct Window {
   T Y2[NY][NX];    // S^{-1} U_l^T
 };
 
-template <typename T, int NX, int NY>
-SRTM_DEV bool window_setup(const Model<T, NX, NY>& M, int L, const T (&m)[NX], const T (&P)[NX][NX],
+template <typename T, int NX, int NY, bool SOA>
+SRTM_DEV bool window_setup(const Model<T, NX, NY, SOA>& M, int L, const T (&m)[NX], const T (&P)[NX][NX],
                            const T (&yk)[NY], Window<T, NX, NY>& w) {
   T Cb[NY][NX], Rx[NY][NY];
-  load(Cb, M.cst + M.lay.Cbar);
-  load(Rx, M.cst + M.lay.Rx);
+  M.get(Cb, M.lay.Cbar);
+  M.get(Rx, M.lay.Rx);
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
@@ -787,8 +826,8 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY>& M, int L, const T (&m)[NX], c
   }
   // U_l = A^l V + c_l, Y2 = S^{-1} U_l^T, Y1 = P A^{lT} - V Y2
   T AL[NX][NX], cL[NX][NY];
-  load(AL, M.per_i(L) + M.lay.o_Ai);
-  load(cL, M.per_i(L) + M.lay.o_ci);
+  M.get(AL, M.per_i_off(L) + M.lay.o_Ai);
+  M.get(cL, M.per_i_off(L) + M.lay.o_ci);
   T UL[NX][NY];
   mm(AL, w.V, UL);
 #pragma unroll
@@ -811,13 +850,13 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY>& M, int L, const T (&m)[NX], c
 }
 
 // Filter blocks of fast step i: mean, P^f_{i,i} and (optionally) P^f_{i,l}.
-template <typename T, int NX, int NY, bool CROSS>
-SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w, int i, T (&mf)[NX],
+template <typename T, int NX, int NY, bool CROSS, bool SOA>
+SRTM_DEV void window_step(const Model<T, NX, NY, SOA>& M, const Window<T, NX, NY>& w, int i, T (&mf)[NX],
                           T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
-  const T* pi = M.per_i(i);
+  const int po = M.per_i_off(i);
   T Ai[NX][NX], ci[NX][NY];
-  load(Ai, pi + M.lay.o_Ai);
-  load(ci, pi + M.lay.o_ci);
+  M.get(Ai, po + M.lay.o_Ai);
+  M.get(ci, po + M.lay.o_ci);
   // mean
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -857,7 +896,7 @@ SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w,
     }
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T s = pi[M.lay.o_Qii + r * NX + c];
+      T s = M.at(po + M.lay.o_Qii + r * NX + c);
 #pragma unroll
       for (int k = 0; k < NX; ++k) s = my_fma(AP[k], Ai[c][k], s);
 #pragma unroll
@@ -872,7 +911,7 @@ SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w,
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
-        T s = pi[M.lay.o_QiL + r * NX + c];
+        T s = M.at(po + M.lay.o_QiL + r * NX + c);
 #pragma unroll
         for (int k = 0; k < NX; ++k) s = my_fma(Ai[r][k], w.Y1[k][c], s);
 #pragma unroll
@@ -1008,8 +1047,8 @@ SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, in
 // Also returns P^-, (P^-)^{-1} and the predicted mean A m^f_{k,l}, which the smoother correction
 // reuses. (A, Qm) is the model of the step into x_{k+1,1}. With inputs, z1 = B u_{k,0} is added to
 // m^f_{k,1} and bnext = B u_{k+1,0} to the prediction.
-template <bool INP, typename T, int NX, int NY>
-SRTM_DEV int smoother_element(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, bool last,
+template <bool INP, typename T, int NX, int NY, bool SOA>
+SRTM_DEV int smoother_element(const Model<T, NX, NY, SOA>& M, int L, const Window<T, NX, NY>& w, bool last,
                               const T (&mL)[NX], const T (&PL)[NX][NX], const T (&z1)[NX], const T (&bnext)[NX],
                               const T (&A)[NX][NX], const T (&Qm)[NX][NX], SElem<T, NX>& el, T (&Pmi)[NX][NX],
                               T (&mpred)[NX], T (&Pm)[NX][NX]) {
@@ -1740,8 +1779,8 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
 // x_{k+1,1}: its smoother element (eq. parallel-ak-smoothing), the in-tile reverse Kogge-Stone
 // scan under eq. op-smoother, the tile aggregate and the per-window correction record (see
 // fwd_bwd_body). Returns numerical status bits.
-template <bool INP, typename T, int NX, int NY>
-SRTM_DEV int smoother_part(const Model<T, NX, NY>& M, const Slots<T>& S, int L, int64_t k, int64_t N,
+template <bool INP, typename T, int NX, int NY, bool SOA>
+SRTM_DEV int smoother_part(const Model<T, NX, NY, SOA>& M, const Slots<T>& S, int L, int64_t k, int64_t N,
                            const T (&yt)[NY], const T (&mprev)[NX], const T (&Pprev)[NX][NX], const T (&m)[NX],
                            const T (&P)[NX][NX], const T (&An)[NX][NX], const T (&Qn)[NX][NX],
                            T* __restrict__ btagg, T* __restrict__ sfx, int64_t tile) {
@@ -1910,10 +1949,9 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
-// TV: per-window model; `cst` then holds one constants block of `bstride` scalars per window.
+// TV: per-window model; `cst` then holds the per-window constants blocks (stored by tv_column).
 template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
-                           int64_t bstride,
                            InputView<T> in,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                            const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast,
@@ -1927,8 +1965,8 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const int64_t w0 = tile * TILE + wv * 64;
-  const int64_t kb = (TV && k < N) ? k : 0;
-  const Model<T, NX, NY> M{TV ? cst + kb * bstride : cst, make_const_layout(NX, NY, L), in};
+  const Model<T, NX, NY, TV> M{TV ? tv_tile_base(cst, k, tv_block_size(NX, NY, L)) : cst,
+                               make_const_layout(NX, NY, L), in, TV ? TILE : 1, TV ? (int)(k % TILE) : 0};
   const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
   const Stg fst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
   const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
@@ -2070,12 +2108,17 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
 // Sig_s = sum_{u<=s} A^u, C_bar = (C/l)(Sig_l - I), R_x = (1/l) sum_i C c_i + R, K = c_l R_x^{-1},
 // F = A^l - K C_bar, D = Q_ll - K c_l^T, J = C_bar^T R_x^{-1} C_bar. A forward pass stores A^i,
 // Q_ii and a_i; a backward pass (s = l - i rising, A^s and Sig_s in registers) reads Q_ii and a_i
-// back in the block's precision and completes Q_il and c_i.
+// back in the block's precision and completes Q_il and c_i. `blk` and `el` are the window's
+// columns (tv_column): scalar j at blk[j * cs] and el[j * cs].
 template <typename T, int NX, int NY>
 SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
                                  const T* __restrict__ Rm, int L, const ConstLayout& lay, T* __restrict__ blk,
-                                 T* __restrict__ el) {
+                                 T* __restrict__ el, int64_t cs) {
   int flag = 0;
+  // scalar j of the window's block / element record (column stride cs)
+  auto W = [&](int j, double v) { put_global(blk + (int64_t)j * cs, (T)v); };
+  auto Rd = [&](int j) { return (double)gld(blk + (int64_t)j * cs); };
+  auto WE = [&](int j, double v) { put_global(el + (int64_t)j * cs, (T)v); };
   double A[NX][NX], Q[NX][NX], C[NY][NX], R[NY][NY];
 #pragma unroll
   for (int r = 0; r < NX; ++r)
@@ -2091,7 +2134,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
 #pragma unroll
     for (int c = 0; c < NY; ++c) R[r][c] = (double)gld(Rm + r * NY + c);
   }
-  auto pi = [&](int i) { return blk + lay.per_i + (i - 1) * lay.per_i_stride; };
+  auto pi = [&](int i) { return lay.per_i + (i - 1) * lay.per_i_stride; };
   // forward pass: A^i, Q_ii and a_i (stored in the c_i slot until the backward pass)
   double Ai[NX][NX], Qi[NX][NX], a[NX][NY];
 #pragma unroll
@@ -2139,16 +2182,16 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = 0; c < r; ++c) Qi[r][c] = Qi[c][r];
-    T* d = pi(i);
+    const int d = pi(i);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
-        put_global(d + lay.o_Ai + r * NX + c, (T)Ai[r][c]);
-        put_global(d + lay.o_Qii + r * NX + c, (T)Qi[r][c]);
+        W(d + lay.o_Ai + r * NX + c, Ai[r][c]);
+        W(d + lay.o_Qii + r * NX + c, Qi[r][c]);
       }
 #pragma unroll
-      for (int c = 0; c < NY; ++c) put_global(d + lay.o_ci + r * NY + c, (T)a[r][c]);
+      for (int c = 0; c < NY; ++c) W(d + lay.o_ci + r * NY + c, a[r][c]);
     }
   }
   // Ai = A^l, Qi = Q_ll.  Backward pass, s = l - i = 0 .. l-1: A^s, Sig_s, Q_il, c_i, R_x.
@@ -2163,25 +2206,30 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
     for (int c = 0; c < NY; ++c) Rx[r][c] = 0.0;
   const double il = 1.0 / (double)L;
   // Q_ii and a_i of the next step are loaded one iteration ahead of their use
-  T nQ[NX][NX], na[NX][NY];
-  gload(nQ, pi(L) + lay.o_Qii);
-  gload(na, pi(L) + lay.o_ci);
+  double nQ[NX][NX], na[NX][NY];
+  auto fetch = [&](int i) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) nQ[r][c] = Rd(pi(i) + lay.o_Qii + r * NX + c);
+#pragma unroll
+      for (int c = 0; c < NY; ++c) na[r][c] = Rd(pi(i) + lay.o_ci + r * NY + c);
+    }
+  };
+  fetch(L);
 #pragma unroll 1
   for (int sp = 0; sp < L; ++sp) {
     const int i = L - sp;
-    T* d = pi(i);
+    const int d = pi(i);
     double Qii[NX][NX], ai[NX][NY];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) Qii[r][c] = (double)nQ[r][c];
+      for (int c = 0; c < NX; ++c) Qii[r][c] = nQ[r][c];
 #pragma unroll
-      for (int c = 0; c < NY; ++c) ai[r][c] = (double)na[r][c];
+      for (int c = 0; c < NY; ++c) ai[r][c] = na[r][c];
     }
-    if (i > 1) {
-      gload(nQ, pi(i - 1) + lay.o_Qii);
-      gload(na, pi(i - 1) + lay.o_ci);
-    }
+    if (i > 1) fetch(i - 1);
     if (sp > 0) {  // A^s = A A^{s-1}, Sig_s = Sig_{s-1} + A^s
       double t[NX][NX];
       mm(A, As, t);
@@ -2203,7 +2251,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NX; ++q) v += Qii[r][q] * As[c][q];
-        put_global(d + lay.o_QiL + r * NX + c, (T)v);
+        W(d + lay.o_QiL + r * NX + c, v);
       }
 #pragma unroll
       for (int c = 0; c < NY; ++c) {
@@ -2211,7 +2259,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
 #pragma unroll
         for (int q = 0; q < NX; ++q) v += Qii[r][q] * CS[c][q];
         ci[r][c] = v * il;
-        put_global(d + lay.o_ci + r * NY + c, (T)ci[r][c]);
+        W(d + lay.o_ci + r * NY + c, ci[r][c]);
       }
     }
     if (sp == 0) {
@@ -2271,31 +2319,32 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      put_global(blk + lay.A + r * NX + c, (T)A[r][c]);
-      put_global(blk + lay.Q + r * NX + c, (T)Q[r][c]);
-      put_global(el + r * NX + c, (T)Fe[r][c]);
-      put_global(el + NX * NX + r * NX + c, (T)De[r][c]);
-      put_global(el + 2 * NX * NX + r * NX + c, (T)Je[r][c]);
+      W(lay.A + r * NX + c, A[r][c]);
+      W(lay.Q + r * NX + c, Q[r][c]);
+      WE(r * NX + c, Fe[r][c]);
+      WE(NX * NX + r * NX + c, De[r][c]);
+      WE(2 * NX * NX + r * NX + c, Je[r][c]);
     }
 #pragma unroll
   for (int r = 0; r < NY; ++r) {
 #pragma unroll
-    for (int c = 0; c < NX; ++c) put_global(blk + lay.Cbar + r * NX + c, (T)Cb[r][c]);
+    for (int c = 0; c < NX; ++c) W(lay.Cbar + r * NX + c, Cb[r][c]);
 #pragma unroll
-    for (int c = 0; c < NY; ++c) put_global(blk + lay.Rx + r * NY + c, (T)Rx[r][c]);
+    for (int c = 0; c < NY; ++c) W(lay.Rx + r * NY + c, Rx[r][c]);
   }
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NY; ++c) {
-      put_global(blk + lay.K + r * NY + c, (T)K[r][c]);
-      put_global(blk + lay.Heta + r * NY + c, (T)Heta[r][c]);
+      W(lay.K + r * NY + c, K[r][c]);
+      W(lay.Heta + r * NY + c, Heta[r][c]);
     }
   return flag;
 }
 
 // Window k's filter element: (F, D, J) from its element record, d = K y_k, eta = C_bar^T R_x^{-1} y_k
-// from its block; the identity element past the last window.
+// from its block (both stored by tile_column, `blk` and `el` pointing at window k's column); the
+// identity element past the last window.
 template <typename T, int NX, int NY>
 SRTM_DEV void tv_element(const T* __restrict__ blk, const T* __restrict__ el, const ConstLayout& lay,
                          const T* __restrict__ y, int64_t k, int64_t N, FElem<T, NX>& a) {
@@ -2304,13 +2353,15 @@ SRTM_DEV void tv_element(const T* __restrict__ blk, const T* __restrict__ el, co
     return;
   }
   constexpr int NN = NX * NX;
-  gload(a.F, el);
-  gload(a.D, el + NN);
-  gload(a.J, el + 2 * NN);
+  const Model<T, NX, NY, true> E{el, lay, InputView<T>{}, TILE, 0};  // the element record, window-minor
+  const Model<T, NX, NY, true> M{blk, lay, InputView<T>{}, TILE, 0};
+  E.get(a.F, 0);
+  E.get(a.D, NN);
+  E.get(a.J, 2 * NN);
   T yk[NY], K[NX][NY], He[NX][NY];
   gloadv(yk, y + k * NY);
-  gload(K, blk + lay.K);
-  gload(He, blk + lay.Heta);
+  M.get(K, lay.K);
+  M.get(He, lay.Heta);
   mv(K, yk, a.d);
   mv(He, yk, a.e);
 }
@@ -2331,9 +2382,9 @@ SRTM_DEV void tv_reduce_body(const T* __restrict__ Fa, const T* __restrict__ Qa,
   int flag = 0;
   if (k < N)
     flag |= tv_window_constants<T, NX, NY>(Fa + k * NN, Qa + k * NN, Ha + k * NXY, Ra + k * NY2, L, lay,
-                                           blks + k * bs, els + k * es);
+                                           tv_column(blks, k, bs), tv_column(els, k, es), TILE);
   FElem<T, NX> a;
-  tv_element<T, NX, NY>(blks + (k < N ? k : 0) * bs, els + (k < N ? k : 0) * es, lay, y, k, N, a);
+  tv_element<T, NX, NY>(tv_column(blks, k, bs), tv_column(els, k, es), lay, y, k, N, a);
   st_felem(S, tid, a);
   __syncthreads();
 #pragma unroll 1
@@ -2487,14 +2538,14 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
   const ConstLayout lay = make_const_layout(NX, NY, L, 0);
-  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
   const int64_t kc = valid ? k : 0;
   int flag = 0;
+  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
   FElem<T, NX> a, x;
-  tv_element<T, NX, NY>(blks + kc * bs, els + kc * es, lay, y, k, N, a);
+  tv_element<T, NX, NY>(tv_column(blks, k, bs), tv_column(els, k, es), lay, y, k, N, a);
   x = a;
 #pragma unroll 1
   for (int sp = 1; sp < TILE; sp *= 2) {  // x <- a_first (x) ... (x) a_k
@@ -2533,7 +2584,7 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if constexpr (SMOOTH) {
     __syncthreads();  // the slots switch from forward elements to smoother elements
-    const Model<T, NX, NY> M{blks + kc * bs, lay};
+    const Model<T, NX, NY, true> M{tv_tile_base(blks, k, bs), lay, InputView<T>{}, TILE, (int)(k % TILE)};
     T yt[NY];
 #pragma unroll
     for (int r = 0; r < NY; ++r) yt[r] = valid ? gld(y + k * NY + r) : T(0);
@@ -3090,8 +3141,7 @@ __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
   const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
   if (!fast && !q.ms_slow && !q.Ps_slow) return;
-  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst,
-                                         (int64_t)tv_block_size(NX, NY, q.L), q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
+  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst, q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
                                 q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
                                 (int64_t)blockIdx.x - q.tile0);
 }

@@ -127,9 +127,9 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
   } else {
     w.inp = 0;
   }
-  if (tv) {
-    w.tvblk = o; o = align256(o + (size_t)N * tv_block_size(nx, ny, L) * esz);
-    w.tvel = o; o = align256(o + (size_t)N * tv_elem_size(nx) * esz);
+  if (tv) {  // stored tile by tile (whole tiles)
+    w.tvblk = o; o = align256(o + (size_t)nt * TILE * tv_block_size(nx, ny, L) * esz);
+    w.tvel = o; o = align256(o + (size_t)nt * TILE * tv_elem_size(nx) * esz);
   } else {
     w.tvblk = w.tvel = 0;
   }
