@@ -216,3 +216,42 @@ def test_longest_windows(nx, ny, L, N, dtype):
     m = wl.random_stable_model(nx, ny, L, 70 + nx)
     y = wl.simulate(m, N, 71 + nx)
     check_smoother(m, y, dtype, f"nx{nx} ny{ny} L{L} N{N}")
+
+
+def test_largest_sequence():
+    """N = 2^26 windows (the build's maximum; l = 1, nx = ny = 1, float64): the chunked tile
+    scans at their deepest (1024 tiles per Kogge-Stone lane). Checked: the first 2000 windows'
+    filter against the sequential IMKF from the prior; at sampled windows one IMKF step from the
+    GPU's carry of the previous window and one smoother step from the GPU's smoothed state of
+    the next; the last 16 windows against the smoother started from the GPU's carry."""
+    srtm = _need_gpu()
+    N = 1 << 26
+    m = wl.random_stable_model(1, 1, 1, 91)
+    y = wl.simulate(m, N, 92)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", torch.float64)
+    yt = torch.as_tensor(y, device="cuda")
+    out = {"ms_fast": torch.empty(N, 1, 1, device="cuda", dtype=torch.float64)}
+    out["Ps_fast"] = torch.empty(N, 1, 1, 1, device="cuda", dtype=torch.float64)
+    out["mf_slow"] = torch.empty(N, 1, device="cuda", dtype=torch.float64)
+    out["Pf_slow"] = torch.empty(N, 1, 1, device="cuda", dtype=torch.float64)
+    print(f"[gpu] largest sequence N={N}", flush=True)
+    o = srtm.smooth(F, Q, H, R, 1, m0, P0, yt, out=out)
+    torch.cuda.synchronize()
+    assert int(o["info"][0]) == 0
+    ms, Ps = o["ms_fast"][:, 0].cpu().numpy(), o["Ps_fast"][:, 0].cpu().numpy()
+    mf, Pf = o["mf_slow"].cpu().numpy(), o["Pf_slow"].cpu().numpy()
+    head_m, head_P, _ = oracle.imkf(m.A, m.Q, m.C, m.R, 1, m.m0, m.P0, y[:2000])
+    assert_close_states(mf[:2000], Pf[:2000], head_m, head_P, 1e-8, "filter head")
+    rng = np.random.default_rng(93)
+    for k in sorted(set(rng.integers(1, N - 1, 40).tolist()) | {1 << 18, (1 << 26) - 2}):
+        one_m, one_P, _ = oracle.imkf(m.A, m.Q, m.C, m.R, 1, mf[k - 1], Pf[k - 1], y[k:k + 1])
+        assert_close_states(mf[k:k + 1], Pf[k:k + 1], one_m, one_P, 1e-8, f"filter step {k}")
+        # RTS step (l = 1): G = P A^T (A P A^T + Q)^{-1}
+        Pp = m.A @ Pf[k] @ m.A.T + m.Q
+        G = Pf[k] @ m.A.T @ np.linalg.inv(Pp)
+        m_s = mf[k] + G @ (ms[k + 1] - m.A @ mf[k])
+        P_s = Pf[k] + G @ (Ps[k + 1] - Pp) @ G.T
+        assert_close_states(ms[k:k + 1], Ps[k:k + 1], m_s[None], P_s[None], 1e-8, f"smoother step {k}")
+    n = 16
+    tail = oracle.srtm_smoother(m.A, m.Q, m.C, m.R, 1, mf[N - n - 1], Pf[N - n - 1], y[N - n:])
+    assert_close_states(ms[N - n:], Ps[N - n:], tail["ms_fast"][:, 0], tail["Ps_fast"][:, 0], 1e-8, "tail")
