@@ -24,6 +24,8 @@
 //    cross-covariances): P^f_{k,i,i}, P^f_{k,i,l} and means, from per-step constants
 //    A^i, Q_ii, Q_il, c_i, instead of the dense (l nx)^2 window covariance.
 
+#include <type_traits>
+
 #include "srtm_device.h"
 #include "srtm_entry.h"
 #include "srtm_layout.h"
@@ -448,38 +450,20 @@ struct InputView {
   int nu;
 };
 
-// A call's constants block. SOA: one window's block of a per-window model, stored window-minor
-// (scalar j of the window at cst[j * cs + lane], cst the base of its tile's columns), so that
-// consecutive lanes read consecutive addresses.
-template <typename T, int NX, int NY, bool SOA = false>
+// A call's constants block (time-invariant model).
+template <typename T, int NX, int NY>
 struct Model {
   const T* __restrict__ cst;
   ConstLayout lay;
   InputView<T> in{};
-  int64_t cs = 1;
   SRTM_DEV const T* per_i(int i) const { return cst + lay.per_i + (i - 1) * lay.per_i_stride; }
   SRTM_DEV int per_i_off(int i) const { return lay.per_i + (i - 1) * lay.per_i_stride; }
   SRTM_DEV const T* level(int p) const { return cst + lay.lev + p * lay.lev_stride; }
-  int lane = 0;  // SOA: the window's column within the block of columns at `cst`
+  SRTM_DEV int AL_off(int L) const { return per_i_off(L) + lay.o_Ai; }  // A^l
+  SRTM_DEV int cL_off(int L) const { return per_i_off(L) + lay.o_ci; }  // c_l
   template <int R, int C>
-  SRTM_DEV void get(T (&a)[R][C], int off) const {
-    if constexpr (SOA) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < C; ++c) a[r][c] = at(off + r * C + c);
-    } else {
-      load(a, cst + off);
-    }
-  }
-  // SOA: the row base cst + off * cs is the same for every lane of a workgroup (it stays in
-  // scalar registers); each lane adds its column.
-  SRTM_DEV T at(int off) const {
-    if constexpr (SOA)
-      return gld(cst + (int64_t)off * cs + lane);
-    else
-      return cst[off];
-  }
+  SRTM_DEV void get(T (&a)[R][C], int off) const { load(a, cst + off); }
+  SRTM_DEV T at(int off) const { return cst[off]; }
 };
 
 // Per-window blocks and element records are stored tile by tile, window-minor within a tile:
@@ -495,6 +479,30 @@ template <typename T>
 SRTM_DEV T* tv_tile_base(T* base, int64_t k, int width) {
   return base + (k / TILE) * (int64_t)width * TILE;
 }
+
+// One window of a per-window model: its constants block (TvLayout, one column of its tile's
+// block of columns at `blk`: the row base blk + off * TILE is the same for every lane of a
+// workgroup and each lane adds its column) and its own A, Q and C (row-major, the caller's arrays).
+template <typename T, int NX, int NY>
+struct TvModel {
+  const T* __restrict__ blk;
+  TvLayout lay;
+  int lane;
+  const T* __restrict__ A;
+  const T* __restrict__ Q;
+  const T* __restrict__ C;
+  SRTM_DEV int AL_off(int) const { return lay.AL; }
+  SRTM_DEV int cL_off(int) const { return lay.cL; }
+  SRTM_DEV int step_off(int i) const { return lay.step + (i - 1) * lay.step_stride; }
+  template <int R, int CC>
+  SRTM_DEV void get(T (&a)[R][CC], int off) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) a[r][c] = at(off + r * CC + c);
+  }
+  SRTM_DEV T at(int off) const { return gld(blk + (int64_t)off * TILE + lane); }
+};
 
 template <typename T, int N>
 SRTM_DEV T symget(const T (&P)[N][N], int r, int c) { return r <= c ? P[r][c] : P[c][r]; }
@@ -780,6 +788,7 @@ SRTM_DEV void ld_selem(const Slots<T>& S, int s, SElem<T, NX>& a) {
 //   P^f_{k,i,l} = A^i P A^{lT} + Q_il - U_i S^{-1} U_l^T          (eq. update-fast, blockwise).
 template <typename T, int NX, int NY>
 struct Window {
+  T m[NX];         // prior mean (of x_{k,0})
   T mp[NX];        // m' = m + V S^{-1} e      ->  m^f_i = A^i m' + c_i Se
   T Se[NY];        // S^{-1} e
   T P[NX][NX];     // prior covariance (symmetric)
@@ -789,8 +798,9 @@ struct Window {
   T Y2[NY][NX];    // S^{-1} U_l^T
 };
 
-template <typename T, int NX, int NY, bool SOA>
-SRTM_DEV bool window_setup(const Model<T, NX, NY, SOA>& M, int L, const T (&m)[NX], const T (&P)[NX][NX],
+// MV: Model (one constants block) or TvModel (the window's own block).
+template <typename T, int NX, int NY, class MV>
+SRTM_DEV bool window_setup(const MV& M, int L, const T (&m)[NX], const T (&P)[NX][NX],
                            const T (&yk)[NY], Window<T, NX, NY>& w) {
   T Cb[NY][NX], Rx[NY][NY];
   M.get(Cb, M.lay.Cbar);
@@ -819,6 +829,7 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY, SOA>& M, int L, const T (&m)[N
   mv(w.Si, e, w.Se);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
+    w.m[r] = m[r];
     T s = m[r];
 #pragma unroll
     for (int k = 0; k < NY; ++k) s = my_fma(w.V[r][k], w.Se[k], s);
@@ -826,8 +837,8 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY, SOA>& M, int L, const T (&m)[N
   }
   // U_l = A^l V + c_l, Y2 = S^{-1} U_l^T, Y1 = P A^{lT} - V Y2
   T AL[NX][NX], cL[NX][NY];
-  M.get(AL, M.per_i_off(L) + M.lay.o_Ai);
-  M.get(cL, M.per_i_off(L) + M.lay.o_ci);
+  M.get(AL, M.AL_off(L));
+  M.get(cL, M.cL_off(L));
   T UL[NX][NY];
   mm(AL, w.V, UL);
 #pragma unroll
@@ -849,14 +860,11 @@ SRTM_DEV bool window_setup(const Model<T, NX, NY, SOA>& M, int L, const T (&m)[N
   return ok;
 }
 
-// Filter blocks of fast step i: mean, P^f_{i,i} and (optionally) P^f_{i,l}.
-template <typename T, int NX, int NY, bool CROSS, bool SOA>
-SRTM_DEV void window_step(const Model<T, NX, NY, SOA>& M, const Window<T, NX, NY>& w, int i, T (&mf)[NX],
-                          T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
-  const int po = M.per_i_off(i);
-  T Ai[NX][NX], ci[NX][NY];
-  M.get(Ai, po + M.lay.o_Ai);
-  M.get(ci, po + M.lay.o_ci);
+// Filter blocks of fast step i: mean, P^f_{i,i} and (optionally) P^f_{i,l}, from the step's
+// A^i and c_i and entries (r, c) of Q_ii and Q_il given by qii(r, c) and qil(r, c).
+template <bool CROSS, typename T, int NX, int NY, class QII, class QIL>
+SRTM_DEV void step_blocks(const Window<T, NX, NY>& w, const T (&Ai)[NX][NX], const T (&ci)[NX][NY], QII qii,
+                          QIL qil, T (&mf)[NX], T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
   // mean
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -896,7 +904,7 @@ SRTM_DEV void window_step(const Model<T, NX, NY, SOA>& M, const Window<T, NX, NY
     }
 #pragma unroll
     for (int c = r; c < NX; ++c) {
-      T s = M.at(po + M.lay.o_Qii + r * NX + c);
+      T s = qii(r, c);
 #pragma unroll
       for (int k = 0; k < NX; ++k) s = my_fma(AP[k], Ai[c][k], s);
 #pragma unroll
@@ -911,7 +919,7 @@ SRTM_DEV void window_step(const Model<T, NX, NY, SOA>& M, const Window<T, NX, NY
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = 0; c < NX; ++c) {
-        T s = M.at(po + M.lay.o_QiL + r * NX + c);
+        T s = qil(r, c);
 #pragma unroll
         for (int k = 0; k < NX; ++k) s = my_fma(Ai[r][k], w.Y1[k][c], s);
 #pragma unroll
@@ -919,6 +927,158 @@ SRTM_DEV void window_step(const Model<T, NX, NY, SOA>& M, const Window<T, NX, NY
         PiL[r][c] = s;
       }
   }
+}
+
+// Time-invariant model: the step's tables from the constants block (wave-uniform loads).
+template <typename T, int NX, int NY, bool CROSS>
+SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w, int i, T (&mf)[NX],
+                          T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
+  const int po = M.per_i_off(i);
+  T Ai[NX][NX], ci[NX][NY];
+  M.get(Ai, po + M.lay.o_Ai);
+  M.get(ci, po + M.lay.o_ci);
+  step_blocks<CROSS>(
+      w, Ai, ci, [&](int r, int c) { return M.at(po + M.lay.o_Qii + r * NX + c); },
+      [&](int r, int c) { return M.at(po + M.lay.o_QiL + r * NX + c); }, mf, Pii, PiL);
+}
+
+// Per-window model: the fast steps of window k in order, in the prior-inclusive form. With the
+// window's prior (m, P) of x_{k,0} and Sig_i = Cov(x_{k,i} | y_{1:k-1}) = A^i P A^{iT} + Q_ii,
+//   Sig_i = A Sig_{i-1} A^T + Q (Sig_0 = P),  mu_i = A mu_{i-1} (mu_0 = m),
+//   al_i = A (al_{i-1} + Sig_{i-1} C^T) (al_1 = 0),
+//   U_i = Cov(x_{k,i}, y_k | y_{1:k-1}) = (1/l) [al_i + Sig_i (C Sig_{l-i})^T],
+//   m^f_{k,i} = mu_i + U_i S^{-1} e,  P^f_{k,i,i} = Sig_i - U_i S^{-1} U_i^T,
+//   P^f_{k,i,l} = Sig_i (A^{l-i})^T - U_i S^{-1} U_l^T
+// (the same blocks as step_blocks: A^i P A^{lT} + Q_il = Sig_i (A^{l-i})^T), from the window's own
+// A, Q and C and the backward factors A^{l-i} and C Sig_{l-i} of its block.
+template <typename T, int NX, int NY>
+struct TvSteps {
+  T Sg[NX][NX], al[NX][NY], mu[NX];  // Sg: upper triangle only
+  int i = 0;  // the last step formed
+  template <bool CROSS>
+  SRTM_DEV void next(const TvModel<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, T (&mf)[NX], T (&Pii)[NX][NX],
+                     T (&PiL)[NX][NX]) {
+    const int so = M.step_off(i + 1);
+    T CS[NY][NX], As[NX][NX], A[NX][NX], C[NY][NX];
+    M.get(CS, so + M.lay.o_CS);
+    if (CROSS) M.get(As, so + M.lay.o_As);
+    gload(A, M.A);
+    gload(C, M.C);
+    if (i == 0) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        mu[r] = w.m[r];
+#pragma unroll
+        for (int c = r; c < NX; ++c) Sg[r][c] = w.P[r][c];
+#pragma unroll
+        for (int c = 0; c < NY; ++c) al[r][c] = T(0);
+      }
+    } else {
+      T b[NX][NY];
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NY; ++c) {
+          T v = al[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v = my_fma(symget(Sg, r, q), C[c][q], v);
+          b[r][c] = v;
+        }
+      mm(A, b, al);
+    }
+    {  // Sig_i = A Sig_{i-1} A^T + Q, mu_i = A mu_{i-1}
+      T AS[NX][NX], nm[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = T(0);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(A[r][q], mu[q], t);
+        nm[r] = t;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T v = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v = my_fma(A[r][q], symget(Sg, q, c), v);
+          AS[r][c] = v;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        mu[r] = nm[r];
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T v = gld(M.Q + r * NX + c);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v = my_fma(AS[r][q], A[c][q], v);
+          Sg[r][c] = v;
+        }
+      }
+    }
+    ++i;
+    // U = (1/l) (al + Sig C Sig_{l-i}^T),  US = U S^{-1}
+    const T il = T(1) / T(L);
+    T U[NX][NY], US[NX][NY];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        T v = al[r][c];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v = my_fma(symget(Sg, r, q), CS[c][q], v);
+        U[r][c] = v * il;
+      }
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        T v = T(0);
+#pragma unroll
+        for (int q = 0; q < NY; ++q) v = my_fma(U[r][q], symget(w.Si, q, c), v);
+        US[r][c] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      T v = mu[r];
+#pragma unroll
+      for (int q = 0; q < NY; ++q) v = my_fma(U[r][q], w.Se[q], v);
+      mf[r] = v;
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T t = Sg[r][c];
+#pragma unroll
+        for (int q = 0; q < NY; ++q) t = my_fma(-US[r][q], U[c][q], t);
+        Pii[r][c] = t;
+        Pii[c][r] = t;
+      }
+    }
+    if (CROSS) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T v = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v = my_fma(symget(Sg, r, q), As[c][q], v);
+#pragma unroll
+          for (int q = 0; q < NY; ++q) v = my_fma(-U[r][q], w.Y2[q][c], v);
+          PiL[r][c] = v;
+        }
+    }
+  }
+};
+
+// Blocks of fast step 1 (the smoother element's): from the constants block, or from the
+// window's own model.
+template <typename T, int NX, int NY>
+SRTM_DEV void first_step(const Model<T, NX, NY>& M, int, const Window<T, NX, NY>& w, T (&mf)[NX], T (&Pii)[NX][NX],
+                         T (&PiL)[NX][NX]) {
+  window_step<T, NX, NY, true>(M, w, 1, mf, Pii, PiL);
+}
+template <typename T, int NX, int NY>
+SRTM_DEV void first_step(const TvModel<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, T (&mf)[NX],
+                         T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
+  TvSteps<T, NX, NY> st;
+  st.template next<true>(M, L, w, mf, Pii, PiL);
 }
 
 template <typename T, int NX, int NY>
@@ -1047,13 +1207,13 @@ SRTM_DEV void window_meas(const Model<T, NX, NY>& M, const T* __restrict__ y, in
 // Also returns P^-, (P^-)^{-1} and the predicted mean A m^f_{k,l}, which the smoother correction
 // reuses. (A, Qm) is the model of the step into x_{k+1,1}. With inputs, z1 = B u_{k,0} is added to
 // m^f_{k,1} and bnext = B u_{k+1,0} to the prediction.
-template <bool INP, typename T, int NX, int NY, bool SOA>
-SRTM_DEV int smoother_element(const Model<T, NX, NY, SOA>& M, int L, const Window<T, NX, NY>& w, bool last,
+template <bool INP, typename T, int NX, int NY, class MV>
+SRTM_DEV int smoother_element(const MV& M, int L, const Window<T, NX, NY>& w, bool last,
                               const T (&mL)[NX], const T (&PL)[NX][NX], const T (&z1)[NX], const T (&bnext)[NX],
                               const T (&A)[NX][NX], const T (&Qm)[NX][NX], SElem<T, NX>& el, T (&Pmi)[NX][NX],
                               T (&mpred)[NX], T (&Pm)[NX][NX]) {
   T mf1[NX], Pf11[NX][NX], Pf1L[NX][NX];
-  window_step<T, NX, NY, true>(M, w, 1, mf1, Pf11, Pf1L);
+  first_step(M, L, w, mf1, Pf11, Pf1L);
   if constexpr (INP) {
 #pragma unroll
     for (int r = 0; r < NX; ++r) mf1[r] += z1[r];
@@ -1779,8 +1939,8 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
 // x_{k+1,1}: its smoother element (eq. parallel-ak-smoothing), the in-tile reverse Kogge-Stone
 // scan under eq. op-smoother, the tile aggregate and the per-window correction record (see
 // fwd_bwd_body). Returns numerical status bits.
-template <bool INP, typename T, int NX, int NY, bool SOA>
-SRTM_DEV int smoother_part(const Model<T, NX, NY, SOA>& M, const Slots<T>& S, int L, int64_t k, int64_t N,
+template <bool INP, typename T, int NX, int NY, class MV>
+SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int64_t N,
                            const T (&yt)[NY], const T (&mprev)[NX], const T (&Pprev)[NX][NX], const T (&m)[NX],
                            const T (&P)[NX][NX], const T (&An)[NX][NX], const T (&Qn)[NX][NX],
                            T* __restrict__ btagg, T* __restrict__ sfx, int64_t tile) {
@@ -1950,9 +2110,25 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
 // TV: per-window model; `cst` then holds the per-window constants blocks (stored by tv_column).
+// The model view of window k: the call's constants block, or (TV) the window's own block
+// (per-window models: `cst` holds the blocks, Fa and Qa the per-window F and Q; kc is k clamped
+// to a window of the sequence).
+template <bool TV, typename T, int NX, int NY>
+SRTM_DEV auto recover_model(const T* __restrict__ cst, int L, const InputView<T>& in, const T* __restrict__ Fa,
+                            const T* __restrict__ Qa, int64_t k, int64_t kc) {
+  if constexpr (TV) {
+    return TvModel<T, NX, NY>{tv_tile_base(cst, k, tv_block_size(NX, NY, L)), make_tv_layout(NX, NY, L),
+                              (int)(k % TILE), Fa + kc * NX * NX, Qa + kc * NX * NX, in.H + kc * NX * NY};
+  } else {
+    return Model<T, NX, NY>{cst, make_const_layout(NX, NY, L), in};
+  }
+}
+
+struct NoSteps {};
+
 template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
-                           InputView<T> in,
+                           InputView<T> in, const T* __restrict__ Fa, const T* __restrict__ Qa,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                            const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ mf_fast,
                            T* __restrict__ Pf_fast, T* __restrict__ ms_fast, T* __restrict__ Ps_fast,
@@ -1965,13 +2141,12 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const int64_t w0 = tile * TILE + wv * 64;
-  const Model<T, NX, NY, TV> M{TV ? tv_tile_base(cst, k, tv_block_size(NX, NY, L)) : cst,
-                               make_const_layout(NX, NY, L), in, TV ? TILE : 1, TV ? (int)(k % TILE) : 0};
   const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
   const Stg fst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
   const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
   const bool valid = k < N;
   const int64_t kc = valid ? k : 0;   // clamped index for loads of padding lanes
+  const auto M = recover_model<TV, T, NX, NY>(cst, L, in, Fa, Qa, k, kc);
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
   if constexpr (INP) {
@@ -1986,10 +2161,10 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   T z[NX], un[NU_MAX];  // input response z_{k,i} and the next step's inputs (inputs only)
 #pragma unroll
   for (int r = 0; r < NX; ++r) z[r] = T(0);
-  const T* uk = INP ? M.in.u + kc * L * M.in.nu : nullptr;
+  const T* uk = INP ? in.u + kc * L * in.nu : nullptr;
   if constexpr (INP) {
 #pragma unroll
-    for (int j = 0; j < NU_MAX; ++j) un[j] = (j < M.in.nu) ? gld(uk + j) : T(0);
+    for (int j = 0; j < NU_MAX; ++j) un[j] = (j < in.nu) ? gld(uk + j) : T(0);
   }
   T v[NX], W[NX][NX];
   if (SMOOTH) {  // v = Et m_in + gt,  W = Et P_in Et^T + St
@@ -2020,10 +2195,14 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
       }
   }
   bool fin = true;
+  std::conditional_t<TV, TvSteps<T, NX, NY>, NoSteps> steps;
 #pragma unroll 1
   for (int i = 1; i <= ilim; ++i) {
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
-    window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
+    if constexpr (TV)
+      steps.template next<SMOOTH>(M, L, w, mf, Pii, PiL);
+    else
+      window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
     if constexpr (INP) {  // z_i = A z_{i-1} + B u_{k,i-1}, the loads of step i+1 issued first
       T uc[NU_MAX];
 #pragma unroll
@@ -2096,28 +2275,28 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
 // ============================================================================ per-window models
 // Time-varying model given per window: window k's F_k, Q_k drive its fast steps x_{k,1} ..
 // x_{k,l} (the step from x_{k-1,l} included) and H_k, R_k give y_k. What the time-invariant path
-// computes once per call (per-step tables, slow-rate constants, the element matrices) is computed
-// once per window, by one lane, into a per-window constants block of the time-invariant layout
-// (without level records) and an element record (F, D, J). The forward scan then combines
-// whole elements: the level tables of the time-invariant path do not exist here.
+// computes once per call (slow-rate constants, the element matrices) is computed once per window,
+// by one lane, into a per-window constants block (TvLayout: window-level constants and the
+// backward factors of the fast steps; the forward quantities are recomputed where they are
+// used, see TvSteps) and an element record (F, D, J). The forward scan then combines whole
+// elements: the level tables of the time-invariant path do not exist here.
 
-// Per-window constants (float64 in registers, one lane): the block `blk` (layout `lay`) and the
-// element matrices `el` = F, D, J of the model (Fm, Qm, Hm, Rm), by the formulas of the constants
-// kernel: Q_ii = A Q_{i-1,i-1} A^T + Q, Q_il = Q_ii (A^{l-i})^T,
-// c_i = (1/l) [a_i + Q_ii (C Sig_{l-i})^T] with a_1 = 0, a_{i+1} = A (a_i + Q_ii C^T) and
-// Sig_s = sum_{u<=s} A^u, C_bar = (C/l)(Sig_l - I), R_x = (1/l) sum_i C c_i + R, K = c_l R_x^{-1},
-// F = A^l - K C_bar, D = Q_ll - K c_l^T, J = C_bar^T R_x^{-1} C_bar. A forward pass stores A^i,
-// Q_ii and a_i; a backward pass (s = l - i rising, A^s and Sig_s in registers) reads Q_ii and a_i
-// back in the block's precision and completes Q_il and c_i. `blk` and `el` are the window's
-// columns (tv_column): scalar j at blk[j * cs] and el[j * cs].
+// Per-window constants (float64 in registers, one lane, one pass over the window's fast steps):
+// the block `blk` (TvLayout `lay`) and the element matrices `el` = F, D, J of the model
+// (Fm, Qm, Hm, Rm). With s_i = x_{k,1} + ... + x_{k,i} and the noise covariances (x_{k,0} = 0)
+// P_xx = Q_ii, P_xs = Cov(x_{k,i}, s_i), P_ss = Cov(s_i), one fast step x <- A x + w gives
+//   P_xx' = A P_xx A^T + Q,  P_xs' = A P_xs + P_xx',  P_ss' = P_ss + A P_xs + (A P_xs)^T + P_xx',
+// and after l steps Q_ll = P_xx, c_l = (1/l) P_xs C^T, R_x = (1/l^2) C P_ss C^T + R (eq. h-k-l-2 and
+// eq. y-k-l-2: the noise parts of Cov(x_{k,l}, y_k) and Cov(y_k)); C_bar = (C/l)(Sig_l - I),
+// K = c_l R_x^{-1}, F = A^l - K C_bar, D = Q_ll - K c_l^T, J = C_bar^T R_x^{-1} C_bar. At step j the
+// pass also stores A^j and C Sig_j as the backward factors of fast step i = l - j.
+// `blk` and `el` are the window's columns (tv_column): scalar j at blk[j * cs] and el[j * cs].
 template <typename T, int NX, int NY>
 SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
-                                 const T* __restrict__ Rm, int L, const ConstLayout& lay, T* __restrict__ blk,
+                                 const T* __restrict__ Rm, int L, const TvLayout& lay, T* __restrict__ blk,
                                  T* __restrict__ el, int64_t cs) {
   int flag = 0;
-  // scalar j of the window's block / element record (column stride cs)
   auto W = [&](int j, double v) { put_global(blk + (int64_t)j * cs, (T)v); };
-  auto Rd = [&](int j) { return (double)gld(blk + (int64_t)j * cs); };
   auto WE = [&](int j, double v) { put_global(el + (int64_t)j * cs, (T)v); };
   double A[NX][NX], Q[NX][NX], C[NY][NX], R[NY][NY];
 #pragma unroll
@@ -2125,7 +2304,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       A[r][c] = (double)gld(Fm + r * NX + c);
-      Q[r][c] = (double)gld(Qm + r * NX + c);
+      Q[r][c] = (double)gld(Qm + (c >= r ? r * NX + c : c * NX + r));  // the upper triangle
     }
 #pragma unroll
   for (int r = 0; r < NY; ++r) {
@@ -2134,165 +2313,100 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
 #pragma unroll
     for (int c = 0; c < NY; ++c) R[r][c] = (double)gld(Rm + r * NY + c);
   }
-  auto pi = [&](int i) { return lay.per_i + (i - 1) * lay.per_i_stride; };
-  // forward pass: A^i, Q_ii and a_i (stored in the c_i slot until the backward pass)
-  double Ai[NX][NX], Qi[NX][NX], a[NX][NY];
+  double Aj[NX][NX], Sig[NX][NX], Pxx[NX][NX], Pxs[NX][NX], Pss[NX][NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) {
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      Ai[r][c] = (r == c) ? 1.0 : 0.0;
-      Qi[r][c] = 0.0;
+      Aj[r][c] = Sig[r][c] = (r == c) ? 1.0 : 0.0;
+      Pxx[r][c] = Pxs[r][c] = Pss[r][c] = 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < NY; ++c) a[r][c] = 0.0;
-  }
 #pragma unroll 1
-  for (int i = 1; i <= L; ++i) {
-    if (i > 1) {  // a_i = A (a_{i-1} + Q_{i-1,i-1} C^T)
-      double b[NX][NY];
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = 0; c < NY; ++c) {
-          double v = a[r][c];
-#pragma unroll
-          for (int q = 0; q < NX; ++q) v += Qi[r][q] * C[c][q];
-          b[r][c] = v;
-        }
-      mm(A, b, a);
-    }
-    double t[NX][NX], AQ[NX][NX];
-    mm(A, Ai, t);
-    mm(A, Qi, AQ);
+  for (int j = 0; j < L; ++j) {
+    // backward factors of fast step i = l - j: A^j and C Sig_j
+    const int so = lay.step + (L - j - 1) * lay.step_stride;
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) Ai[r][c] = t[r][c];
+      for (int c = 0; c < NX; ++c) W(so + lay.o_As + r * NX + c, Aj[r][c]);
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += C[r][q] * Sig[q][c];
+        W(so + lay.o_CS + r * NX + c, v);
+      }
+    // one fast step of the noise covariances
+    double t[NX][NX], AP[NX][NX];
+    mm(A, Pxs, t);  // A P_xs
+    mm(A, Pxx, AP);
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = r; c < NX; ++c) {
         double v = Q[r][c];
 #pragma unroll
-        for (int q = 0; q < NX; ++q) v += AQ[r][q] * A[c][q];
-        Qi[r][c] = v;
+        for (int q = 0; q < NX; ++q) v += AP[r][q] * A[c][q];
+        Pxx[r][c] = v;
+        Pxx[c][r] = v;
       }
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < r; ++c) Qi[r][c] = Qi[c][r];
-    const int d = pi(i);
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        W(d + lay.o_Ai + r * NX + c, Ai[r][c]);
-        W(d + lay.o_Qii + r * NX + c, Qi[r][c]);
+      for (int c = r; c < NX; ++c) {
+        const double v = Pss[r][c] + t[r][c] + t[c][r] + Pxx[r][c];
+        Pss[r][c] = v;
+        Pss[c][r] = v;
       }
 #pragma unroll
-      for (int c = 0; c < NY; ++c) W(d + lay.o_ci + r * NY + c, a[r][c]);
-    }
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) Pxs[r][c] = t[r][c] + Pxx[r][c];
+    mm(A, Aj, t);  // A^{j+1}, Sig_{j+1}
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        Aj[r][c] = t[r][c];
+        Sig[r][c] += t[r][c];
+      }
   }
-  // Ai = A^l, Qi = Q_ll.  Backward pass, s = l - i = 0 .. l-1: A^s, Sig_s, Q_il, c_i, R_x.
-  double As[NX][NX], Sig[NX][NX], cL[NX][NY], Rx[NY][NY];
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = 0; c < NX; ++c) As[r][c] = Sig[r][c] = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-  for (int r = 0; r < NY; ++r)
-#pragma unroll
-    for (int c = 0; c < NY; ++c) Rx[r][c] = 0.0;
+  // Aj = A^l, Sig = Sig_l, Pxx = Q_ll, Pxs = Cov(x_{k,l}, s_l), Pss = Cov(s_l)
   const double il = 1.0 / (double)L;
-  // Q_ii and a_i of the next step are loaded one iteration ahead of their use
-  double nQ[NX][NX], na[NX][NY];
-  auto fetch = [&](int i) {
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int c = 0; c < NX; ++c) nQ[r][c] = Rd(pi(i) + lay.o_Qii + r * NX + c);
-#pragma unroll
-      for (int c = 0; c < NY; ++c) na[r][c] = Rd(pi(i) + lay.o_ci + r * NY + c);
-    }
-  };
-  fetch(L);
-#pragma unroll 1
-  for (int sp = 0; sp < L; ++sp) {
-    const int i = L - sp;
-    const int d = pi(i);
-    double Qii[NX][NX], ai[NX][NY];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int c = 0; c < NX; ++c) Qii[r][c] = nQ[r][c];
-#pragma unroll
-      for (int c = 0; c < NY; ++c) ai[r][c] = na[r][c];
-    }
-    if (i > 1) fetch(i - 1);
-    if (sp > 0) {  // A^s = A A^{s-1}, Sig_s = Sig_{s-1} + A^s
-      double t[NX][NX];
-      mm(A, As, t);
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = 0; c < NX; ++c) {
-          As[r][c] = t[r][c];
-          Sig[r][c] += t[r][c];
-        }
-    }
-    double CS[NY][NX];
-    mm(C, Sig, CS);
-    double ci[NX][NY];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) v += Qii[r][q] * As[c][q];
-        W(d + lay.o_QiL + r * NX + c, v);
-      }
-#pragma unroll
-      for (int c = 0; c < NY; ++c) {
-        double v = ai[r][c];
-#pragma unroll
-        for (int q = 0; q < NX; ++q) v += Qii[r][q] * CS[c][q];
-        ci[r][c] = v * il;
-        W(d + lay.o_ci + r * NY + c, ci[r][c]);
-      }
-    }
-    if (sp == 0) {
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = 0; c < NY; ++c) cL[r][c] = ci[r][c];
-    }
-#pragma unroll
-    for (int r = 0; r < NY; ++r)
-#pragma unroll
-      for (int c = 0; c < NY; ++c) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) v += C[r][q] * ci[q][c];
-        Rx[r][c] += v;
-      }
-  }
-  // Sig_l = Sig_{l-1} + A^l;  C_bar = (C/l)(Sig_l - I)
-  double Cb[NY][NX];
+  double Cb[NY][NX], cL[NX][NY], Rx[NY][NY];
 #pragma unroll
   for (int r = 0; r < NY; ++r)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
       double v = 0.0;
 #pragma unroll
-      for (int q = 0; q < NX; ++q) v += C[r][q] * (Sig[q][c] + Ai[q][c] - (q == c ? 1.0 : 0.0));
+      for (int q = 0; q < NX; ++q) v += C[r][q] * (Sig[q][c] - (q == c ? 1.0 : 0.0));
       Cb[r][c] = v * il;
     }
 #pragma unroll
-  for (int r = 0; r < NY; ++r)
+  for (int r = 0; r < NX; ++r)
 #pragma unroll
-    for (int c = 0; c < NY; ++c) Rx[r][c] = Rx[r][c] * il + R[r][c];
+    for (int c = 0; c < NY; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) v += Pxs[r][q] * C[c][q];
+      cL[r][c] = v * il;
+    }
+  {
+    double CP[NY][NX];
+    mm(C, Pss, CP);
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) v += CP[r][q] * C[c][q];
+        Rx[r][c] = v * il * il + R[r][c];
+      }
+  }
   symmetrize(Rx);
   double Rxi[NY][NY];
   if (!spd_inv(Rx, Rxi)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
@@ -2303,7 +2417,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      double f = Ai[r][c], dd = Qi[r][c];
+      double f = Aj[r][c], dd = Pxx[r][c];
 #pragma unroll
       for (int q = 0; q < NY; ++q) {
         f -= K[r][q] * Cb[q][c];
@@ -2319,8 +2433,7 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
-      W(lay.A + r * NX + c, A[r][c]);
-      W(lay.Q + r * NX + c, Q[r][c]);
+      W(lay.AL + r * NX + c, Aj[r][c]);
       WE(r * NX + c, Fe[r][c]);
       WE(NX * NX + r * NX + c, De[r][c]);
       WE(2 * NX * NX + r * NX + c, Je[r][c]);
@@ -2336,32 +2449,40 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int c = 0; c < NY; ++c) {
+      W(lay.cL + r * NY + c, cL[r][c]);
       W(lay.K + r * NY + c, K[r][c]);
       W(lay.Heta + r * NY + c, Heta[r][c]);
     }
   return flag;
 }
 
+// R x C scalars of a window's column (tv_column) from scalar `off` on.
+template <typename T, int R, int C>
+SRTM_DEV void col_get(T (&a)[R][C], const T* __restrict__ col, int off) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[r][c] = gld(col + (int64_t)(off + r * C + c) * TILE);
+}
+
 // Window k's filter element: (F, D, J) from its element record, d = K y_k, eta = C_bar^T R_x^{-1} y_k
-// from its block (both stored by tile_column, `blk` and `el` pointing at window k's column); the
-// identity element past the last window.
+// from its block (`blk` and `el` are window k's columns, tv_column); the identity element past
+// the last window.
 template <typename T, int NX, int NY>
-SRTM_DEV void tv_element(const T* __restrict__ blk, const T* __restrict__ el, const ConstLayout& lay,
+SRTM_DEV void tv_element(const T* __restrict__ blk, const T* __restrict__ el, const TvLayout& lay,
                          const T* __restrict__ y, int64_t k, int64_t N, FElem<T, NX>& a) {
   if (k >= N) {
     elem_identity(a);
     return;
   }
   constexpr int NN = NX * NX;
-  const Model<T, NX, NY, true> E{el, lay, InputView<T>{}, TILE, 0};  // the element record, window-minor
-  const Model<T, NX, NY, true> M{blk, lay, InputView<T>{}, TILE, 0};
-  E.get(a.F, 0);
-  E.get(a.D, NN);
-  E.get(a.J, 2 * NN);
+  col_get(a.F, el, 0);
+  col_get(a.D, el, NN);
+  col_get(a.J, el, 2 * NN);
   T yk[NY], K[NX][NY], He[NX][NY];
   gloadv(yk, y + k * NY);
-  M.get(K, lay.K);
-  M.get(He, lay.Heta);
+  col_get(K, blk, lay.K);
+  col_get(He, blk, lay.Heta);
   mv(K, yk, a.d);
   mv(He, yk, a.e);
 }
@@ -2375,8 +2496,8 @@ SRTM_DEV void tv_reduce_body(const T* __restrict__ Fa, const T* __restrict__ Qa,
   constexpr int NN = NX * NX, NY2 = NY * NY, NXY = NX * NY, FA = 3 * NN + 2 * NX;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
-  const ConstLayout lay = make_const_layout(NX, NY, L, 0);
-  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
+  const TvLayout lay = make_tv_layout(NX, NY, L);
+  const int bs = lay.total, es = tv_elem_size(NX);
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
   int flag = 0;
@@ -2529,7 +2650,8 @@ SRTM_DEV void tv_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk, 
 // filter outputs); with SMOOTH the smoother half of the fused kernel, with the next window's
 // F and Q as the model of the step into x_{k+1,1}.
 template <typename T, int NX, int NY, bool SMOOTH>
-SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, const T* __restrict__ y, int64_t N,
+SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, const T* __restrict__ Ha,
+                          const T* __restrict__ y, int64_t N,
                           int L, const T* __restrict__ blks, const T* __restrict__ els, const T* __restrict__ m0,
                           const T* __restrict__ P0, const T* __restrict__ ftstate, T* __restrict__ carry,
                           T* __restrict__ m_slow, T* __restrict__ P_slow, T* __restrict__ btagg, T* __restrict__ sfx,
@@ -2537,13 +2659,13 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
   constexpr int NN = NX * NX, ST = NX + NN;
   extern __shared__ char smraw[];
   const Slots<T> S{reinterpret_cast<T*>(smraw), TILE};
-  const ConstLayout lay = make_const_layout(NX, NY, L, 0);
+  const TvLayout lay = make_tv_layout(NX, NY, L);
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
   const int64_t kc = valid ? k : 0;
   int flag = 0;
-  const int bs = tv_block_size(NX, NY, L), es = tv_elem_size(NX);
+  const int bs = lay.total, es = tv_elem_size(NX);
   FElem<T, NX> a, x;
   tv_element<T, NX, NY>(tv_column(blks, k, bs), tv_column(els, k, es), lay, y, k, N, a);
   x = a;
@@ -2584,7 +2706,8 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if constexpr (SMOOTH) {
     __syncthreads();  // the slots switch from forward elements to smoother elements
-    const Model<T, NX, NY, true> M{tv_tile_base(blks, k, bs), lay, InputView<T>{}, TILE, (int)(k % TILE)};
+    const TvModel<T, NX, NY> M{tv_tile_base(blks, k, bs), lay, (int)(k % TILE), Fa + kc * NN, Qa + kc * NN,
+                               Ha + kc * NX * NY};
     T yt[NY];
 #pragma unroll
     for (int r = 0; r < NY; ++r) yt[r] = valid ? gld(y + k * NY + r) : T(0);
@@ -3130,7 +3253,7 @@ __global__ void __launch_bounds__(KS) k_tv_tiles(Batch b) {
 template <typename T, int NX, int NY, bool SMOOTH>
 __global__ void __launch_bounds__(TILE) k_tv_fwd(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  tv_fwd_body<T, NX, NY, SMOOTH>(q.F, q.Q, q.y, q.N, q.L, q.tvblk, q.tvel, q.m0, q.P0, q.ftst, q.carry,
+  tv_fwd_body<T, NX, NY, SMOOTH>(q.F, q.Q, q.H, q.y, q.N, q.L, q.tvblk, q.tvel, q.m0, q.P0, q.ftst, q.carry,
                                  q.mf_slow, q.Pf_slow, q.btagg, q.sfx, q.info, (int64_t)blockIdx.x - q.tile0);
 }
 
@@ -3141,7 +3264,8 @@ __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
   const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
   if (!fast && !q.ms_slow && !q.Ps_slow) return;
-  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst, q.in, q.m0, q.P0, q.carry, q.sfx, q.btst,
+  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst, q.in, q.F, q.Q, q.m0, q.P0,
+                                         q.carry, q.sfx, q.btst,
                                 q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
                                 (int64_t)blockIdx.x - q.tile0);
 }

@@ -82,11 +82,36 @@ struct WorkLayout {
   size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel, total;
 };
 
-// Time-varying (per-window) models: scalars of one window's constants block (the layout of
-// make_const_layout without level records) and of its element record (F, D, J).
-inline __host__ __device__ int tv_block_size(int nx, int ny, int L) {
-  return make_const_layout(nx, ny, L, 0).total;
+// Time-varying (per-window) models: offsets (in scalars) into one window's constants block.
+// Window-level: C_bar, R_x, K, Heta = C_bar^T R_x^{-1}, A^l and c_l. Per fast step i = 1..l: A^{l-i}
+// and C Sig_{l-i} with Sig_s = sum_{u<=s} A^u, the two factors of Q_il = Q_ii (A^{l-i})^T and
+// c_i = (1/l) [a_i + Q_ii (C Sig_{l-i})^T] that run backwards in i. The recovery forms A^i, Q_ii
+// and a_i by forward recursions from the window's own A, Q and C.
+struct TvLayout {
+  int Cbar, Rx, K, Heta, AL, cL;
+  int step, step_stride, o_As, o_CS;
+  int total;
+};
+
+inline __host__ __device__ TvLayout make_tv_layout(int nx, int ny, int L) {
+  TvLayout t;
+  const int nn = nx * nx, nxy = nx * ny;
+  int o = 0;
+  t.Cbar = o; o += nxy;
+  t.Rx = o; o += ny * ny;
+  t.K = o; o += nxy;
+  t.Heta = o; o += nxy;
+  t.AL = o; o += nn;
+  t.cL = o; o += nxy;
+  t.o_As = 0; t.o_CS = nn;
+  t.step_stride = nn + nxy;
+  t.step = o; o += L * t.step_stride;
+  t.total = o;
+  return t;
 }
+
+// Scalars of one window's constants block and of its element record (F, D, J).
+inline __host__ __device__ int tv_block_size(int nx, int ny, int L) { return make_tv_layout(nx, ny, L).total; }
 inline __host__ __device__ constexpr int tv_elem_size(int nx) { return 3 * nx * nx; }
 
 // Scalars (float64) of one tile's log-likelihood / gradient record.
