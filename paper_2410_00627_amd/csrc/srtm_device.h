@@ -34,6 +34,12 @@ SRTM_DEV T gld(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Loads from LDS through a local-address-space pointer (p must point into LDS).
+template <typename T>
+SRTM_DEV T sld(const T* p) {
+  return *(const __attribute__((address_space(3))) T*)p;
+}
+
 template <typename T, int R, int C>
 SRTM_DEV void gload(T (&a)[R][C], const T* __restrict__ p) {
 #pragma unroll

@@ -482,8 +482,10 @@ SRTM_DEV T* tv_tile_base(T* base, int64_t k, int width) {
 
 // One window of a per-window model: its constants block (TvLayout, one column of its tile's
 // block of columns at `blk`: the row base blk + off * TILE is the same for every lane of a
-// workgroup and each lane adds its column) and its own A, Q and C (row-major, the caller's arrays).
-template <typename T, int NX, int NY>
+// workgroup and each lane adds its column) and its own A, Q and C, entry j at A[j * ms]: the
+// caller's row-major arrays (LDSM false, ms = 1) or a window-minor copy in LDS (LDSM, ms the
+// copy's column count).
+template <typename T, int NX, int NY, bool LDSM = false>
 struct TvModel {
   const T* __restrict__ blk;
   TvLayout lay;
@@ -491,9 +493,11 @@ struct TvModel {
   const T* __restrict__ A;
   const T* __restrict__ Q;
   const T* __restrict__ C;
+  int ms = 1;
+  SRTM_DEV T mdl(const T* p, int j) const { return LDSM ? sld(p + j * ms) : gld(p + j * ms); }
   SRTM_DEV int AL_off(int) const { return lay.AL; }
   SRTM_DEV int cL_off(int) const { return lay.cL; }
-  SRTM_DEV int step_off(int i) const { return lay.step + (i - 1) * lay.step_stride; }
+  SRTM_DEV int slot_off(int q) const { return lay.slot + q * lay.slot_stride; }
   template <int R, int CC>
   SRTM_DEV void get(T (&a)[R][CC], int off) const {
 #pragma unroll
@@ -950,20 +954,53 @@ SRTM_DEV void window_step(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w,
 //   m^f_{k,i} = mu_i + U_i S^{-1} e,  P^f_{k,i,i} = Sig_i - U_i S^{-1} U_i^T,
 //   P^f_{k,i,l} = Sig_i (A^{l-i})^T - U_i S^{-1} U_l^T
 // (the same blocks as step_blocks: A^i P A^{lT} + Q_il = Sig_i (A^{l-i})^T), from the window's own
-// A, Q and C and the backward factors A^{l-i} and C Sig_{l-i} of its block.
+// A, Q and C and the backward factors A^s and C Sig_s (s = l - i) of its block, stored for even s
+// (TvLayout): a step with odd s forms them from the slot it shares with step i + 1.
 template <typename T, int NX, int NY>
 struct TvSteps {
   T Sg[NX][NX], al[NX][NY], mu[NX];  // Sg: upper triangle only
+  T fCS[NY][NX], fAs[NX][NX];        // the factors of the slot in use: C Sig_{2q}, A^{2q}
   int i = 0;  // the last step formed
-  template <bool CROSS>
-  SRTM_DEV void next(const TvModel<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, T (&mf)[NX], T (&Pii)[NX][NX],
-                     T (&PiL)[NX][NX]) {
-    const int so = M.step_off(i + 1);
+  template <bool CROSS, bool LDSM>
+  SRTM_DEV void next(const TvModel<T, NX, NY, LDSM>& M, int L, const Window<T, NX, NY>& w, T (&mf)[NX],
+                     T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
+    const int s = L - (i + 1);
+    if (i == 0 || (s & 1)) {  // the first step, or the first of the two steps of slot s / 2
+      const int so = M.slot_off(s >> 1);
+      M.get(fCS, so + M.lay.o_CS);
+      M.get(fAs, so + M.lay.o_As);
+    }
     T CS[NY][NX], As[NX][NX], A[NX][NX], C[NY][NX];
-    M.get(CS, so + M.lay.o_CS);
-    if (CROSS) M.get(As, so + M.lay.o_As);
-    gload(A, M.A);
-    gload(C, M.C);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) A[r][c] = M.mdl(M.A, r * NX + c);
+    }
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+#pragma unroll
+      for (int c = 0; c < NX; ++c) C[r][c] = M.mdl(M.C, r * NX + c);
+    }
+    if (s & 1) {  // A^s = A A^{s-1},  C Sig_s = C Sig_{s-1} + C A^s
+      mm(A, fAs, As);
+#pragma unroll
+      for (int r = 0; r < NY; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T v = fCS[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) v = my_fma(C[r][q], As[q][c], v);
+          CS[r][c] = v;
+        }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+#pragma unroll
+        for (int c = 0; c < NX; ++c) As[r][c] = fAs[r][c];
+#pragma unroll
+        for (int c = 0; c < NY; ++c) CS[c][r] = fCS[c][r];
+      }
+    }
     if (i == 0) {
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
@@ -1007,7 +1044,7 @@ struct TvSteps {
         mu[r] = nm[r];
 #pragma unroll
         for (int c = r; c < NX; ++c) {
-          T v = gld(M.Q + r * NX + c);
+          T v = M.mdl(M.Q, r * NX + c);
 #pragma unroll
           for (int q = 0; q < NX; ++q) v = my_fma(AS[r][q], A[c][q], v);
           Sg[r][c] = v;
@@ -1078,7 +1115,7 @@ template <typename T, int NX, int NY>
 SRTM_DEV void first_step(const TvModel<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, T (&mf)[NX],
                          T (&Pii)[NX][NX], T (&PiL)[NX][NX]) {
   TvSteps<T, NX, NY> st;
-  st.template next<true>(M, L, w, mf, Pii, PiL);
+  st.template next<true, false>(M, L, w, mf, Pii, PiL);
 }
 
 template <typename T, int NX, int NY>
@@ -2110,15 +2147,38 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
 // terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
 // `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
 // TV: per-window model; `cst` then holds the per-window constants blocks (stored by tv_column).
-// The model view of window k: the call's constants block, or (TV) the window's own block
-// (per-window models: `cst` holds the blocks, Fa and Qa the per-window F and Q; kc is k clamped
-// to a window of the sequence).
+// Per-window models in the recovery: the tile's A, Q and C (the caller's per-window F, Q, H)
+// copied to LDS window-minor, entry j of window w at mdl[(j * TV_MS) + w] (j < nx^2: A, then Q,
+// then C), with a padded column count so that the row-major reads of the copy spread over the
+// banks. Windows past the end of the sequence get zeros.
+constexpr int TV_MS = TILE + 1;
+template <typename T, int NX, int NY>
+constexpr size_t tv_model_lds_bytes() { return sizeof(T) * (size_t)(2 * NX * NX + NY * NX) * TV_MS; }
+
+template <typename T, int NX, int NY>
+SRTM_DEV void tv_model_to_lds(const T* __restrict__ Fa, const T* __restrict__ Qa, const T* __restrict__ Ha,
+                              int64_t t0, int nw, T* mdl) {
+  constexpr int NN = NX * NX, NXY = NX * NY;
+  for (int q = threadIdx.x; q < TILE * NN; q += TILE) {
+    const int w = q / NN, j = q % NN;
+    mdl[j * TV_MS + w] = (w < nw) ? gld(Fa + t0 * NN + q) : T(0);
+    mdl[(NN + j) * TV_MS + w] = (w < nw) ? gld(Qa + t0 * NN + q) : T(0);
+  }
+  for (int q = threadIdx.x; q < TILE * NXY; q += TILE) {
+    const int w = q / NXY, j = q % NXY;
+    mdl[(2 * NN + j) * TV_MS + w] = (w < nw) ? gld(Ha + t0 * NXY + q) : T(0);
+  }
+}
+
+// The model view of window k: the call's constants block, or (TV) the window's own block with
+// its A, Q and C from the tile's LDS copy `mdl` (per-window models: `cst` holds the blocks).
 template <bool TV, typename T, int NX, int NY>
-SRTM_DEV auto recover_model(const T* __restrict__ cst, int L, const InputView<T>& in, const T* __restrict__ Fa,
-                            const T* __restrict__ Qa, int64_t k, int64_t kc) {
+SRTM_DEV auto recover_model(const T* __restrict__ cst, int L, const InputView<T>& in, const T* mdl, int64_t k) {
   if constexpr (TV) {
-    return TvModel<T, NX, NY>{tv_tile_base(cst, k, tv_block_size(NX, NY, L)), make_tv_layout(NX, NY, L),
-                              (int)(k % TILE), Fa + kc * NX * NX, Qa + kc * NX * NX, in.H + kc * NX * NY};
+    constexpr int NN = NX * NX;
+    const int w = (int)(k % TILE);
+    return TvModel<T, NX, NY, true>{tv_tile_base(cst, k, tv_block_size(NX, NY, L)), make_tv_layout(NX, NY, L), w,
+                                    mdl + w, mdl + NN * TV_MS + w, mdl + 2 * NN * TV_MS + w, TV_MS};
   } else {
     return Model<T, NX, NY>{cst, make_const_layout(NX, NY, L), in};
   }
@@ -2146,7 +2206,13 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   const Stg sst(smraw + (size_t)wv * Stg::BYTES * (FILT && SMOOTH ? 2 : 1) + (FILT && SMOOTH ? Stg::BYTES : 0));
   const bool valid = k < N;
   const int64_t kc = valid ? k : 0;   // clamped index for loads of padding lanes
-  const auto M = recover_model<TV, T, NX, NY>(cst, L, in, Fa, Qa, k, kc);
+  T* mdl = reinterpret_cast<T*>(smraw + (size_t)4 * Stg::BYTES * (FILT && SMOOTH ? 2 : 1));
+  if constexpr (TV) {
+    const int64_t t0 = tile * TILE;
+    tv_model_to_lds<T, NX, NY>(Fa, Qa, in.H, t0, (int)((N - t0) < TILE ? (N - t0) : TILE), mdl);
+    __syncthreads();
+  }
+  const auto M = recover_model<TV, T, NX, NY>(cst, L, in, mdl, k);
   T m[NX], P[NX][NX], yk[NY];
   load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
   if constexpr (INP) {
@@ -2200,7 +2266,7 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   for (int i = 1; i <= ilim; ++i) {
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
     if constexpr (TV)
-      steps.template next<SMOOTH>(M, L, w, mf, Pii, PiL);
+      steps.template next<SMOOTH, true>(M, L, w, mf, Pii, PiL);
     else
       window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
     if constexpr (INP) {  // z_i = A z_{i-1} + B u_{k,i-1}, the loads of step i+1 issued first
@@ -2289,7 +2355,7 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
 // and after l steps Q_ll = P_xx, c_l = (1/l) P_xs C^T, R_x = (1/l^2) C P_ss C^T + R (eq. h-k-l-2 and
 // eq. y-k-l-2: the noise parts of Cov(x_{k,l}, y_k) and Cov(y_k)); C_bar = (C/l)(Sig_l - I),
 // K = c_l R_x^{-1}, F = A^l - K C_bar, D = Q_ll - K c_l^T, J = C_bar^T R_x^{-1} C_bar. At step j the
-// pass also stores A^j and C Sig_j as the backward factors of fast step i = l - j.
+// pass also stores A^j and C Sig_j for even j, the backward factors of fast step i = l - j.
 // `blk` and `el` are the window's columns (tv_column): scalar j at blk[j * cs] and el[j * cs].
 template <typename T, int NX, int NY>
 SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
@@ -2323,21 +2389,22 @@ SRTM_DEV int tv_window_constants(const T* __restrict__ Fm, const T* __restrict__
     }
 #pragma unroll 1
   for (int j = 0; j < L; ++j) {
-    // backward factors of fast step i = l - j: A^j and C Sig_j
-    const int so = lay.step + (L - j - 1) * lay.step_stride;
+    if ((j & 1) == 0) {  // backward factors A^j and C Sig_j (fast step i = l - j), slot j / 2
+      const int so = lay.slot + (j >> 1) * lay.slot_stride;
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
+      for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) W(so + lay.o_As + r * NX + c, Aj[r][c]);
+        for (int c = 0; c < NX; ++c) W(so + lay.o_As + r * NX + c, Aj[r][c]);
 #pragma unroll
-    for (int r = 0; r < NY; ++r)
+      for (int r = 0; r < NY; ++r)
 #pragma unroll
-      for (int c = 0; c < NX; ++c) {
-        double v = 0.0;
+        for (int c = 0; c < NX; ++c) {
+          double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < NX; ++q) v += C[r][q] * Sig[q][c];
-        W(so + lay.o_CS + r * NX + c, v);
-      }
+          for (int q = 0; q < NX; ++q) v += C[r][q] * Sig[q][c];
+          W(so + lay.o_CS + r * NX + c, v);
+        }
+    }
     // one fast step of the noise covariances
     double t[NX][NX], AP[NX][NX];
     mm(A, Pxs, t);  // A P_xs
@@ -3451,7 +3518,7 @@ srtm_status launch_tv(const Batch& b, const Launch& g, bool smoother, int rec_mo
     if (!allow_lds((const void*)k_tv_tiles<T, NX, NY>, lds_ks)) return SRTM_E_HIP;
     hipLaunchKernelGGL((k_tv_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ks, st, b);
     SRTM_CHECK_LAUNCH();
-    const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES;
+    const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES + tv_model_lds_bytes<T, NX, NY>();
     if (!smoother) {
       if (!allow_lds((const void*)k_tv_fwd<T, NX, NY, false>, lds_el)) return SRTM_E_HIP;
       hipLaunchKernelGGL((k_tv_fwd<T, NX, NY, false>), dim3(g.ntiles), dim3(TILE), lds_el, st, b);

@@ -83,13 +83,15 @@ struct WorkLayout {
 };
 
 // Time-varying (per-window) models: offsets (in scalars) into one window's constants block.
-// Window-level: C_bar, R_x, K, Heta = C_bar^T R_x^{-1}, A^l and c_l. Per fast step i = 1..l: A^{l-i}
-// and C Sig_{l-i} with Sig_s = sum_{u<=s} A^u, the two factors of Q_il = Q_ii (A^{l-i})^T and
-// c_i = (1/l) [a_i + Q_ii (C Sig_{l-i})^T] that run backwards in i. The recovery forms A^i, Q_ii
-// and a_i by forward recursions from the window's own A, Q and C.
+// Window-level: C_bar, R_x, K, Heta = C_bar^T R_x^{-1}, A^l and c_l. Then the backward factors of
+// the fast steps, A^s and C Sig_s with s = l - i and Sig_s = sum_{u<=s} A^u (Q_il = Q_ii (A^s)^T,
+// c_i = (1/l) [a_i + Q_ii (C Sig_s)^T] run backwards in i), for even s only: slot q = 0 ..
+// ceil(l/2)-1 holds A^{2q} and C Sig_{2q}; the odd s = 2q+1 follows as A A^{2q} and
+// C Sig_{2q} + C A^{2q+1}. The recovery forms A^i, Q_ii and a_i by forward recursions from the
+// window's own A, Q and C.
 struct TvLayout {
   int Cbar, Rx, K, Heta, AL, cL;
-  int step, step_stride, o_As, o_CS;
+  int slot, slot_stride, o_As, o_CS;
   int total;
 };
 
@@ -104,8 +106,8 @@ inline __host__ __device__ TvLayout make_tv_layout(int nx, int ny, int L) {
   t.AL = o; o += nn;
   t.cL = o; o += nxy;
   t.o_As = 0; t.o_CS = nn;
-  t.step_stride = nn + nxy;
-  t.step = o; o += L * t.step_stride;
+  t.slot_stride = nn + nxy;
+  t.slot = o; o += ((L + 1) / 2) * t.slot_stride;
   t.total = o;
   return t;
 }

@@ -300,12 +300,13 @@ def test_inputs_call_rejects_plain_workspace_size(L):
 
 def test_time_varying_entry_points_validate(L):
     """Per-window models: nx <= 4 only; a larger workspace than the plain one: per window the
-    element (3 nx^2) and per fast step the two backward factors A^{l-i}, C Sig_{l-i} (nx^2 + ny nx)."""
+    element (3 nx^2) and, for every other fast step, the two backward factors A^s, C Sig_s
+    (nx^2 + ny nx)."""
     sh = srtm.Shape(4, 2, 20, 1, 1000)
     a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
     assert L.srtm_workspace_size(ctypes.byref(sh), 1, ctypes.byref(a)) == 0
     assert L.srtm_workspace_size_tv(ctypes.byref(sh), 1, ctypes.byref(b)) == 0
-    assert b.value > a.value + 1000 * (3 * 16 + 20 * (16 + 8)) * 8
+    assert b.value > a.value + 1000 * (3 * 16 + 10 * (16 + 8)) * 8
     assert L.srtm_workspace_size_tv(ctypes.byref(srtm.Shape(6, 1, 20, 1, 1000)), 1, ctypes.byref(b)) == 4
     small = srtm.Shape(2, 1, 10, 1, 5)
     assert _call(L.srtm_smooth_tv, small, FAKE, _ws(2, 1, 10, 5)[1], 8) == 6   # plain size is too small
