@@ -18,11 +18,14 @@
 //    generic element of window 1; this equals the paper's a_1 = (0, m^f_{1,l}, P^f_{1,l}).
 //  * A prefix that contains the prior has F = 0, so every exclusive prefix is a "state"
 //    (m, P) and the down-sweeps combine states with aligned segments.
-//  * The suffix scan runs as a prefix scan over reversed window order with the operands
-//    of eq. op-smoother swapped.
+//  * The suffix scan is a Kogge-Stone scan towards lower window indices inside a tile and,
+//    at tile level, a Kogge-Stone scan over the tiles counted from the end; a suffix that
+//    reaches the last window has E = 0 and is the smoothed state itself.
 //  * Within a window only the blocks the outputs need are formed (Remark
 //    cross-covariances): P^f_{k,i,i}, P^f_{k,i,l} and means, from per-step constants
 //    A^i, Q_ii, Q_il, c_i, instead of the dense (l nx)^2 window covariance.
+//  * Models given per window (time varying) share nothing between elements: their kernels
+//    (k_tv_*) build each window's constants and element in one lane and scan whole elements.
 
 #include <type_traits>
 
@@ -2141,12 +2144,6 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
   if (flag && info) atomicOr(info, flag);
 }
 
-// K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
-// MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
-// (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
-// terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
-// `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
-// TV: per-window model; `cst` then holds the per-window constants blocks (stored by tv_column).
 // Per-window models in the recovery: the tile's A, Q and C (the caller's per-window F, Q, H)
 // copied to LDS window-minor, entry j of window w at mdl[(j * TV_MS) + w] (j < nx^2: A, then Q,
 // then C), with a padded column count so that the row-major reads of the copy spread over the
@@ -2186,6 +2183,13 @@ SRTM_DEV auto recover_model(const T* __restrict__ cst, int L, const InputView<T>
 
 struct NoSteps {};
 
+// K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
+// MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
+// (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
+// terms linear in the smoothed state entering the tile; a workgroup covers exactly one tile.
+// `ilim` is L when fast-rate outputs are requested and 1 when only the slow smoothed state is.
+// TV: per-window model; `cst` then holds the per-window constants blocks (stored by tv_column)
+// and Fa, Qa (with in.H) the per-window F, Q and H.
 template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, const T* __restrict__ cst,
                            InputView<T> in, const T* __restrict__ Fa, const T* __restrict__ Qa,
@@ -2196,6 +2200,8 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX);
   static_assert(TILE == 256, "one recovery workgroup per tile");
   constexpr bool FILT = (MODE & 1) != 0, SMOOTH = (MODE & 2) != 0;
+  static_assert(!(TV && FILT && SMOOTH), "per-window models: filter and smoother outputs in two passes "
+                                         "(the LDS copy of the model follows one staging buffer per wave)");
   using Stg = OutStage<T, NX>;
   extern __shared__ char smraw[];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
