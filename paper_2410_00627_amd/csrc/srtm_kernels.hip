@@ -1376,10 +1376,11 @@ SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T (&yt)[NY], const T 
   }
 }
 
-// K1: per-tile aggregate of the vector parts (d, eta) of the filter elements.
+// K1: per-tile aggregate of the vector parts (d, eta) of the filter elements; the whole up-sweep
+// tree (2 nx rows of TILE slots) goes to `utree` for the per-tile forward pass.
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L,
-                              InputView<T> in, T* __restrict__ tagg, int64_t tile) {
+                              InputView<T> in, T* __restrict__ tagg, T* __restrict__ utree, int64_t tile) {
   __shared__ T smem[2 * NX * TILE];
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{smem, TILE};
@@ -1411,6 +1412,9 @@ SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __res
   }
   __syncthreads();
   fwd_upsweep(M, S, tid);
+  T* ut = utree + tile * (2 * NX * TILE);
+#pragma unroll
+  for (int r = 0; r < 2 * NX; ++r) put_global(ut + r * TILE + tid, S.at(r, tid));
   if (tid == TILE - 1) {
 #pragma unroll
     for (int r = 0; r < 2 * NX; ++r) tagg[tile * 2 * NX + r] = S.at(r, TILE - 1);
@@ -1856,23 +1860,20 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
 // Per tile, down-sweep from the tile's exclusive state to every window: lane k ends with
 // the exclusive state (m^f_{k-1,l}, P^f_{k-1,l}) in (mprev, Pprev) and the inclusive one
 // (m^f_{k,l}, P^f_{k,l}) in (m, P). S needs TILE * max(2 nx, nx + nx^2) scalars.
-// (yt, zL): window k's measurement and input response (window_meas).
+// (yt, zL): window k's measurement and input response (window_meas); `tree`: the tile's
+// up-sweep tree as the tile reduction left it (2 nx rows of TILE slots).
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T (&yt)[NY], const T (&zL)[NX],
                              int64_t k, const T* __restrict__ m0, const T* __restrict__ P0,
-                             const T* __restrict__ tile_state, T (&mprev)[NX], T (&Pprev)[NX][NX], T (&m)[NX],
-                             T (&P)[NX][NX]) {
+                             const T* __restrict__ tile_state, const T* __restrict__ tree, T (&mprev)[NX],
+                             T (&Pprev)[NX][NX], T (&m)[NX], T (&P)[NX][NX]) {
   const int tid = threadIdx.x;
   int flag = 0;
-  T d[NX], e[NX];
-  fwd_element<INP>(M, yt, zL, d, e);
 #pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    S.at(r, tid) = d[r];
-    S.at(NX + r, tid) = e[r];
-  }
+  for (int r = 0; r < 2 * NX; ++r) S.at(r, tid) = gld(tree + r * TILE + tid);
+  T d[NX], e[NX];  // the window's own element, for the inclusive state
+  fwd_element<INP>(M, yt, zL, d, e);
   __syncthreads();
-  fwd_upsweep(M, S, tid);
   // down-sweep with states; slot TILE-1 <- the tile's exclusive state
   if (tid == TILE - 1) {
     T mt[NX], Pt[NX][NX];
@@ -1958,7 +1959,7 @@ SRTM_DEV int store_carry(int64_t k, const T (&m)[NX], const T (&P)[NX][NX], T* _
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
                              const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ tstate,
-                             T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info,
+                             const T* __restrict__ utree, T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow, int32_t* info,
                              int64_t tile) {
   constexpr int ST = NX + NX * NX;
   extern __shared__ char smraw[];
@@ -1968,7 +1969,8 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
   T yt[NY], zL[NX];
   window_meas<INP>(M, y, k, N, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, tstate + tile * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, tstate + tile * ST, utree + tile * (2 * NX * TILE), mprev,
+                                  Pprev, m, P);
   if (k < N) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
   if (flag && info) atomicOr(info, flag);
 }
@@ -2122,7 +2124,7 @@ SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
                            const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ ftstate,
-                           T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
+                           const T* __restrict__ utree, T* __restrict__ carry, T* __restrict__ m_slow, T* __restrict__ P_slow,
                            T* __restrict__ btagg, T* __restrict__ sfx, int32_t* info, int64_t tile) {
   constexpr int NN = NX * NX, ST = NX + NN, SE = 2 * NN + NX, SF = sfx_stride(NX);
   extern __shared__ char smraw[];
@@ -2134,7 +2136,8 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
   T yt[NY], zL[NX];
   window_meas<INP>(M, y, k, N, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, mprev, Pprev, m, P);
+  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, utree + tile * (2 * NX * TILE),
+                                  mprev, Pprev, m, P);
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
 
   T An[NX][NX], Qn[NX][NX];  // time-invariant: the step into x_{k+1,1} has the model's A and Q
@@ -3208,7 +3211,7 @@ template <typename T, int NX, int NY>
 struct Seq {  // one sequence's typed arrays and scan plan
   const T *F, *Q, *H, *R, *m0, *P0, *y;
   T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
-  T *cst, *ftagg, *ftst, *carry, *btagg, *btst, *sfx, *tvblk, *tvel;
+  T *cst, *ftagg, *ftst, *utree, *carry, *btagg, *btst, *sfx, *tvblk, *tvel;
   double *hand, *stats;
   int64_t N, tile0;
   int L;
@@ -3246,6 +3249,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.hand = reinterpret_cast<double*>(base + wl.chain);
   q.ftagg = reinterpret_cast<T*>(base + wl.ftile_agg);
   q.ftst = reinterpret_cast<T*>(base + wl.ftile_state);
+  q.utree = reinterpret_cast<T*>(base + wl.utree);
   q.carry = reinterpret_cast<T*>(base + wl.carry);
   q.btagg = reinterpret_cast<T*>(base + wl.btile_agg);
   q.btst = reinterpret_cast<T*>(base + wl.btile_state);
@@ -3278,7 +3282,7 @@ __global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b, int nseq) {
   }
   const int64_t t = (int64_t)blockIdx.x - nseq;
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, b.tile_seq ? b.tile_seq[t] : 0);
-  fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, t - q.tile0);
+  fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, q.utree, t - q.tile0);
 }
 
 template <typename T, int NX, int NY>
@@ -3291,14 +3295,14 @@ __global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
 template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_final(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_final_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.info,
+  fwd_final_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.utree, q.carry, q.mf_slow, q.Pf_slow, q.info,
                             (int64_t)blockIdx.x - q.tile0);
 }
 
 template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_bwd(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_bwd_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
+  fwd_bwd_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.utree, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
                           q.info, (int64_t)blockIdx.x - q.tile0);
 }
 

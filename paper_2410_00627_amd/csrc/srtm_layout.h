@@ -79,7 +79,8 @@ inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, chain, ftile_agg, ftile_state, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel, total;
+  size_t consts, chain, ftile_agg, ftile_state, utree, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel,
+      total;
 };
 
 // Time-varying (per-window) models: offsets (in scalars) into one window's constants block.
@@ -124,6 +125,8 @@ inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + n
 
 inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// `utree` (time-invariant models): the tile reductions' up-sweep trees, per tile 2 nx rows of TILE
+// scalars, which the per-tile forward pass reloads instead of repeating the up-sweep.
 // `inputs`: the call has known inputs, whose per-window record (y_k - mu_k, z_{k,l}) [N][ny + nx]
 // the tile reductions write for the later kernels. `tv`: the model is given per window; the
 // per-window constants blocks [N][tv_block_size] and element records [N][tv_elem_size] follow,
@@ -140,6 +143,11 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
   w.chain = o; o = align256(o + 3 * nn * sizeof(double));  // float64 F, D, J handed between launches
   w.ftile_agg = o; o = align256(o + (size_t)nt * fagg * esz);
   w.ftile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);
+  if (!tv) {
+    w.utree = o; o = align256(o + (size_t)nt * TILE * 2 * nx * esz);
+  } else {
+    w.utree = 0;
+  }
   w.carry = o; o = align256(o + (size_t)N * (nx + nn) * esz);
   if (smoother) {
     w.btile_agg = o; o = align256(o + (size_t)nt * (2 * nn + nx) * esz);
