@@ -128,11 +128,12 @@ def test_filter_entry_point_matches_smoother_filter_outputs():
     assert_close_states(f["m_slow"], f["P_slow"], ref["m_slow"], ref["P_slow"], 1e-8, "srtm_filter slow")
 
 
-def test_bitwise_deterministic():
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_bitwise_deterministic(dtype):
     m = wl.random_stable_model(4, 2, 20, 41)
     y = wl.simulate(m, 1000, 42)
-    a = run_gpu(m, y, torch.float64)
-    b = run_gpu(m, y, torch.float64)
+    a = run_gpu(m, y, dtype)
+    b = run_gpu(m, y, dtype)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
 

@@ -123,6 +123,18 @@ def test_tv_equal_windows_match_time_invariant_path():
         assert_close_states(b[mk], b[pk], a[mk], a[pk], 1e-10, f"{mk} per-window vs time-invariant")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_tv_bitwise_deterministic(dtype):
+    """Two calls on the same inputs give bitwise equal outputs (no atomics or races in the values)."""
+    srtm = _srtm()
+    m = wl.time_varying_model(4, 2, 7, 700, 61)
+    y = wl.simulate_tv(m, 62)
+    a = _gpu(srtm, m, y, dtype)
+    b = _gpu(srtm, m, y, dtype)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_tv_refuses_larger_states():
     srtm = _srtm()
     m = wl.time_varying_model(6, 1, 4, 20, 51, general=True)
