@@ -208,6 +208,32 @@ def test_headline_full_size(dtype):
     print(f"[gpu] headline {dtype}: tail max err mean {em.max():.2e} cov {eP.max():.2e}", flush=True)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_filter_entry_point_full_size(dtype):
+    """srtm_filter on the long-sequence shape (nx=4, ny=2, L=20, N=2^17): slow filter at every
+    window against the sequential IMKF, fast filter at sampled windows against the dense window
+    filter started from the IMKF carry of the previous window."""
+    m = wl.headline_model()
+    N = wl.HEADLINE_N
+    y = wl.simulate(m, N, seed=2031)
+    out = run_gpu(m, y, dtype, filter_only=True)
+    assert int(out["info"][0]) == 0
+    mr, yr = _rounded(m, y, dtype)
+    tol = TOL[dtype]
+    ms, Ps, _ = oracle.imkf(*_args(mr), yr)
+    assert_close_states(out["m_slow"], out["P_slow"], ms, Ps, tol, "srtm_filter slow, all windows")
+    bm = oracle.batch_model(mr.A, mr.Q, mr.C, mr.L)
+    rng = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([[0, 1, 255, 256, 257, N // 2, N - 1], rng.integers(1, N, 24)]))
+    nx, L = m.nx, m.L
+    for k in sample:
+        mp, Pp = (mr.m0, mr.P0) if k == 0 else (ms[k - 1], Ps[k - 1])
+        M_f, P_f = oracle.fast_filter_window(bm, mr.R, mp, Pp, yr[k])
+        mf = M_f.reshape(L, nx)
+        Pf = np.stack([P_f[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] for i in range(L)])
+        assert_close_states(out["m_fast"][k], out["P_fast"][k], mf, Pf, tol, f"srtm_filter fast window {k}")
+
+
 @pytest.mark.parametrize("nx,ny,L,N", [(4, 2, 128, 12), (6, 1, 128, 10), (1, 1, 128, 300)],
                          ids=["nx4ny2L128", "nx6ny1L128", "nx1ny1L128N300"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
