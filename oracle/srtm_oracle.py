@@ -168,7 +168,7 @@ def srtm_filter(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     return dict(m_fast=m_fast, P_fast=P_fast, m_slow=m_slow, P_slow=P_slow, loglik=ll)
 
 
-def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None):
+def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None, lag1=False):
     """Fast- and slow-rate smoothing marginals by the proposed sequential smoother.
 
     eq. smoothing-dynamic / eq. seq-smoothing-all (Sec. III-C): for k = N-1..1,
@@ -185,6 +185,12 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
 
     Returns dict with ms_fast/Ps_fast [N, L, ...] = p(x_{k,i} | y_{1:N}) and
     ms_slow/Ps_slow [N, ...] = p(x_{k,1} | y_{1:N}) (the smoother's slow state).
+
+    lag1: also Cs_fast [N, L, nx, nx], the lag-one smoothed cross-covariances
+    Cov(x_{k,i}, x_{k,i-1} | y_{1:N}) with x_{k,0} = x_{k-1,l} and x_{1,0} = x_0 (Remark
+    cross-covariances): inside a window the off-diagonal blocks of the smoothed window
+    covariance; across a boundary the smoother's cross term Cov(window k, x_{k+1,1}) = G_k P^s_{k+1,1},
+    and for x_0 the same with the one-step gain P0 A^T (A P0 A^T + Q)^{-1}.
     """
     tv = np.ndim(A) == 3
     nx, N = np.shape(A)[-1], y.shape[0]
@@ -193,6 +199,7 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
     Ahat = np.hstack([np.zeros((nx, (L - 1) * nx)), A]) if not tv else None
     ms_fast = np.zeros((N, L, nx))
     Ps_fast = np.zeros((N, L, nx, nx))
+    Cs_fast = np.zeros((N, L, nx, nx)) if lag1 else None
     out = {}
     if with_filter:
         out["m_fast"] = np.zeros((N, L, nx))
@@ -215,8 +222,19 @@ def srtm_smoother(A, Q, C, R, L, m0, P0, y, *, with_filter=False, B=None, u=None
             G = np.linalg.solve(P_pred.T, (P_f @ Ahat.T).T).T
             M_s = M_f + G @ (ms1 - m_pred)
             P_s = _sym(P_f + G @ (Ps1 - P_pred) @ G.T)
+            if lag1:  # x_{k+1,1} with x_{k,l}: the last block row of G P^s_{k+1,1}, transposed
+                Cs_fast[k + 1, 0] = (G @ Ps1)[(L - 1) * nx:, :].T
         ms_fast[k], Ps_fast[k] = _blocks(M_s, P_s, nx, L)
+        if lag1:
+            for i in range(1, L):
+                Cs_fast[k, i] = P_s[i * nx:(i + 1) * nx, (i - 1) * nx:i * nx]
         ms1, Ps1 = ms_fast[k, 0].copy(), Ps_fast[k, 0].copy()
+    if lag1:  # x_{1,1} with the prior state x_0
+        A1, Q1 = (A[0], Q[0]) if tv else (A, Q)
+        P_one = A1 @ P0 @ A1.T + Q1
+        G0 = np.linalg.solve(P_one.T, (P0 @ A1.T).T).T
+        Cs_fast[0, 0] = (G0 @ Ps_fast[0, 0]).T
+        out["Cs_fast"] = Cs_fast
     out.update(ms_fast=ms_fast, Ps_fast=Ps_fast, ms_slow=ms_fast[:, 0].copy(),
                Ps_slow=Ps_fast[:, 0].copy(), m_slow=m_slow, P_slow=P_slow, loglik=ll)
     return out

@@ -68,6 +68,7 @@ def posteriors(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     """Exact filter and smoother marginals of every fast state x_{k,i}.
 
     Returns dict: m_fast/P_fast = p(x_{k,i} | y_{1:k}), ms_fast/Ps_fast = p(x_{k,i} | y_{1:N}),
+    Cs_fast = Cov(x_{k,i}, x_{k,i-1} | y_{1:N}) (x_{k,0} = x_{k-1,L}, x_{1,0} = x_0),
     and loglik = log N(Y; Psi mu_Z, Psi S_Z Psi^T + I (x) R).
     """
     nx, ny = np.shape(A)[-1], np.shape(C)[-2]
@@ -84,15 +85,17 @@ def posteriors(A, Q, C, R, L, m0, P0, y, B=None, u=None):
     mu, S = _condition(muZ, SZ, Psi, SY, y, np.arange(N * ny))
     ms_fast = np.zeros((N, L, nx))
     Ps_fast = np.zeros((N, L, nx, nx))
+    Cs_fast = np.zeros((N, L, nx, nx))   # Cov(x_t, x_{t-1} | y_{1:N}), t = (k-1) L + i
     for k in range(N):
         for i in range(L):
             t = k * L + i + 1
             ms_fast[k, i] = mu[t * nx:(t + 1) * nx]
             Ps_fast[k, i] = S[t * nx:(t + 1) * nx, t * nx:(t + 1) * nx]
+            Cs_fast[k, i] = S[t * nx:(t + 1) * nx, (t - 1) * nx:t * nx]
     r = y.reshape(-1) - Psi @ muZ
     _, logdet = np.linalg.slogdet(SY)
     ll = -0.5 * (r @ np.linalg.solve(SY, r) + logdet + len(r) * np.log(2 * np.pi))
-    return dict(m_fast=m_fast, P_fast=P_fast, ms_fast=ms_fast, Ps_fast=Ps_fast, loglik=ll)
+    return dict(m_fast=m_fast, P_fast=P_fast, ms_fast=ms_fast, Ps_fast=Ps_fast, Cs_fast=Cs_fast, loglik=ll)
 
 
 def one_window_moments(A, Q, C, R, L):
