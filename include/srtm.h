@@ -114,6 +114,25 @@ srtm_status srtm_smooth(const srtm_shape* shape,
                         void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
                         void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
+/* Smoothing with the lag-one cross-covariances of consecutive fast states (Remark
+ * cross-covariances; the second moments that EM updates and the gradient of the
+ * log-likelihood need), same inputs as srtm_filter:
+ *      Cs_fast [N][L][nx][nx] : Cov(x_{k,i}, x_{k,i-1} | y_{1:N}), i = 1..L, with x_{k,0} = x_{k-1,L}
+ *                               (the last fast state of window k-1) and x_{1,0} = x_0 ~ N(m0, P0);
+ *                               required (SRTM_E_NULL when NULL), 16-byte aligned.
+ *      ms_fast, Ps_fast, ms_slow, Ps_slow      : as srtm_smooth, each may be NULL.
+ *  Inside a window Cov(x_{k,i}, x_{k,i-1} | y_{1:k}) = F P^f_{k,i-1} + (F c_{i-1} - c_i) S_k^{-1} U_{k,i-1}^T
+ *  (c_i, U_{k,i}: the noise and total cross-covariances of x_{k,i} with y_k) plus the smoother's
+ *  correction through x_{k,L}; across a boundary it is P^s_{k,1} G^T with the one-step gain
+ *  G = P F^T (F P F^T + Q)^{-1} of the filter state (m, P) of x_{k-1,L} (eq. seq-smoothing-all).
+ *  Time-invariant model without inputs. Workspace: srtm_workspace_size(shape, 1) bytes. Numerical
+ *  status bits as srtm_smooth (4 also when F P F^T + Q is singular). */
+srtm_status srtm_smooth_lag1(const srtm_shape* shape,
+                             const void* F, const void* Q, const void* H, const void* R,
+                             const void* m0, const void* P0, const void* y,
+                             void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow, void* Cs_fast,
+                             void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
 /* Profiling variant of srtm_smooth: identical work, and additionally records
  * events[2j] before and events[2j+1] after the j-th kernel it enqueues, j = 0 ..
  * srtm_kernel_count(1) - 1. `events` holds caller-created hipEvent_t handles and

@@ -61,7 +61,7 @@ srtm_status run_common(const srtm_shape* sh, const srtm::Ptrs& p, bool smoother,
   if (s != SRTM_OK) return s;
   if (!p.F || !p.Q || !p.H || !p.R || !p.m0 || !p.P0 || !p.y || !p.ws) return SRTM_E_NULL;
   const void* all[] = {p.F, p.Q, p.H, p.R, p.m0, p.P0, p.y, p.ms_fast, p.Ps_fast, p.ms_slow,
-                       p.Ps_slow, p.mf_fast, p.Pf_fast, p.mf_slow, p.Pf_slow};
+                       p.Ps_slow, p.mf_fast, p.Pf_fast, p.mf_slow, p.Pf_slow, p.Cs_fast};
   for (const void* q : all)
     if (!aligned(q, 16)) return SRTM_E_ALIGN;
   if (!aligned(p.ws, 256) || !aligned(p.info, 4)) return SRTM_E_ALIGN;
@@ -138,6 +138,17 @@ srtm_status srtm_smooth(const srtm_shape* shape, const void* F, const void* Q, c
                         void* Pf_slow, void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
   const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
                      mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
+  return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_smooth_lag1(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
+                             const void* m0, const void* P0, const void* y, void* ms_fast, void* Ps_fast,
+                             void* ms_slow, void* Ps_slow, void* Cs_fast, void* workspace, size_t workspace_bytes,
+                             int32_t* info, void* stream) {
+  if (!Cs_fast) return SRTM_E_NULL;
+  srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
+               nullptr, nullptr, nullptr, nullptr, workspace, info};
+  p.Cs_fast = Cs_fast;
   return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
 }
 
@@ -265,7 +276,8 @@ static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t n
     srtm_status st = check_shape(&sh);
     if (st != SRTM_OK) return st;
     if (d[s].tile0 != tiles || d[s].smoother != 1) return SRTM_E_SHAPE;
-    if (d[s].B || d[s].u || d[s].nu || d[s].tv) return SRTM_E_SHAPE;  // batches: time-invariant, no inputs
+    if (d[s].B || d[s].u || d[s].nu || d[s].tv || d[s].Cs_fast)  // batches: time-invariant, no inputs
+      return SRTM_E_SHAPE;
     const int32_t* map = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) +
                                                           srtm::batch_tile_map_offset(nseq));
     const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;

@@ -27,6 +27,7 @@ struct Ptrs {
   const void* u = nullptr;
   int nu = 0;
   bool tv = false;  // F, Q, H, R given per window ([N][...]); no inputs then
+  void* Cs_fast = nullptr;  // lag-one smoothed cross-covariances [N][L][nx][nx] (srtm_smooth_lag1)
 };
 
 // Largest state size of the per-window (time-varying) path: its scans hold whole filter

@@ -2796,6 +2796,194 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
   if (flag && info) atomicOr(info, flag);
 }
 
+// ============================================================================ lag-one cross-covariances
+// U_i = A^i V + c_i, the cross-covariance of x_{k,i} with y_k given y_{1:k-1}.
+template <typename T, int NX, int NY>
+SRTM_DEV void window_U(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w, int i, T (&Ui)[NX][NY]) {
+  const T* pi = M.per_i(i);
+  T Ai[NX][NX], ci[NX][NY];
+  load(Ai, pi + M.lay.o_Ai);
+  load(ci, pi + M.lay.o_ci);
+  mm(Ai, w.V, Ui);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) Ui[r][c] += ci[r][c];
+}
+
+// Across the window boundary, x_{k-1,l} (x_0 for the first window) given x_{k,1}, with (m, P) the
+// filter state of x_{k-1,l}: the one-step smoother gain G = P A^T (P^-)^{-1}, P^- = A P A^T + Q,
+// E[x_{k-1,l} | y_{1:N}] = m + G (m^s_{k,1} - A m) and Cov(x_{k,1}, x_{k-1,l} | y_{1:N}) = P^s_{k,1} G^T
+// (eq. seq-smoothing-all for one step). Returns false when P^- is singular.
+template <typename T, int NX>
+SRTM_DEV bool lag1_boundary(const T (&A)[NX][NX], const T (&Qq)[NX][NX], const T (&m)[NX], const T (&P)[NX][NX],
+                            const T (&ms)[NX], const T (&Ps)[NX][NX], T (&G)[NX][NX], T (&Pm)[NX][NX], T (&mb)[NX],
+                            T (&C)[NX][NX]) {
+  T Pmi[NX][NX], PA[NX][NX];
+  sandwich(A, P, Qq, Pm);
+  const bool ok = spd_inv(Pm, Pmi);
+  mm_nt(P, A, PA);
+  mm(PA, Pmi, G);
+  T Am[NX], dm[NX];
+  mv(A, m, Am);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) dm[r] = ms[r] - Am[r];
+  mv(G, dm, mb);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) mb[r] += m[r];
+  mm_nt(Ps, G, C);
+  return ok;
+}
+
+// Inside window k, fast step i >= 2: Cov(x_{k,i}, x_{k,i-1} | y_{1:k}) = A P^f_{i-1,i-1}
+// + (A c_{i-1} - c_i) S^{-1} U_{i-1}^T (x_{k,i} = A x_{k,i-1} + w, conditioned on y_k), plus the smoothing
+// term P^f_{i,l} W P^f_{i-1,l}^T (PLW = P^f_{i,l} W): Cov(x_{k,i}, x_{k,i-1} | y_{1:N}).
+template <typename T, int NX, int NY>
+SRTM_DEV void lag1_within(const Model<T, NX, NY>& M, const Window<T, NX, NY>& w, int i, const T (&A)[NX][NX],
+                          const T (&Pprev)[NX][NX], const T (&Uprev)[NX][NY], const T (&PLW)[NX][NX],
+                          const T (&PLprev)[NX][NX], T (&C)[NX][NX]) {
+  T Dc[NX][NY], SU[NY][NX];
+  {
+    T cp[NX][NY], ci[NX][NY];
+    load(cp, M.per_i(i - 1) + M.lay.o_ci);
+    load(ci, M.per_i(i) + M.lay.o_ci);
+    mm(A, cp, Dc);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) Dc[r][c] -= ci[r][c];
+  }
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      T t = T(0);
+#pragma unroll
+      for (int q = 0; q < NY; ++q) t = my_fma(symget(w.Si, r, q), Uprev[c][q], t);
+      SU[r][c] = t;
+    }
+  mm(A, Pprev, C);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      T t = C[r][c];
+#pragma unroll
+      for (int q = 0; q < NY; ++q) t = my_fma(Dc[r][q], SU[q][c], t);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) t = my_fma(PLW[r][q], PLprev[c][q], t);
+      C[r][c] = t;
+    }
+}
+
+// K8 (optional output): per tile, the lag-one smoothed cross-covariances of every fast step of
+// its windows, Cs_fast[k][i-1] = Cov(x_{k,i}, x_{k,i-1} | y_{1:N}) with x_{k,0} = x_{k-1,l} and the prior
+// state x_0 for the first window (Remark cross-covariances), from the same window quantities,
+// carry and smoother correction (v, W) as the recovery; records staged and written as K7's.
+template <typename T, int NX, int NY>
+SRTM_DEV void lag1_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                        const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+                        const T* __restrict__ sfx, const T* __restrict__ tin, T* __restrict__ Cs_fast,
+                        int32_t* info, int64_t tile) {
+  constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX);
+  static_assert(TILE == 256, "one workgroup per tile");
+  using Stg = OutStage<T, NX>;
+  extern __shared__ char smraw[];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t k = tile * TILE + tid;
+  const int64_t w0 = tile * TILE + wv * 64;
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  const int nvalid = (int)((N - w0) < 64 ? ((N - w0) > 0 ? (N - w0) : 0) : 64);
+  const Stg stg(smraw + (size_t)wv * Stg::BYTES);
+  const bool valid = k < N;
+  const int64_t kc = valid ? k : 0;
+  T m[NX], P[NX][NX], yk[NY];
+  load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
+  gloadv(yk, y + kc * NY);
+  Window<T, NX, NY> w;
+  int flag = 0;
+  if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  T v[NX], W[NX][NX];  // v = Et m_in + gt,  W = Et P_in Et^T + St
+  {
+    const T* src = sfx + kc * SF;
+    const T* ti = tin + tile * ST;
+    T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
+    gload(Et, src);
+    gloadv(mi, ti);
+    gload(Pi, ti + NX);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      T t = gld(src + NN + r);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
+      v[r] = t;
+    }
+    mm(Et, Pi, EP);
+    int o = NN + NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T t = gld(src + o++);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
+        W[r][c] = t;
+        W[c][r] = t;
+      }
+  }
+  T A[NX][NX];
+  load(A, M.cst + M.lay.A);
+  T Pprev[NX][NX], PLprev[NX][NX], Uprev[NX][NY];
+  const T zero[NX] = {};
+  bool fin = true;
+#pragma unroll 1
+  for (int i = 1; i <= L; ++i) {
+    T mf[NX], Pii[NX][NX], PiL[NX][NX], PLW[NX][NX], C[NX][NX];
+    window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
+    mm(PiL, W, PLW);
+    if (i == 1) {  // across the window boundary, from the smoothed block of x_{k,1}
+      T ms[NX], Ps[NX][NX], Qq[NX][NX], G[NX][NX], Pm[NX][NX], mb[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = mf[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(PiL[r][q], v[q], t);
+        ms[r] = t;
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T u = Pii[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) u = my_fma(PLW[r][q], PiL[c][q], u);
+          Ps[r][c] = u;
+          Ps[c][r] = u;
+        }
+      }
+      load(Qq, M.cst + M.lay.Q);
+      if (!lag1_boundary(A, Qq, m, P, ms, Ps, G, Pm, mb, C) && valid) flag |= SRTM_INFO_PRED_SINGULAR;
+    } else {
+      lag1_within(M, w, i, A, Pprev, Uprev, PLW, PLprev, C);
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) fin = fin && isfinite(C[r][c]);
+    window_U(M, w, i, Uprev);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        Pprev[r][c] = Pii[r][c];
+        PLprev[r][c] = PiL[r][c];
+      }
+    stg.put(lane, i, zero, C);
+    wave_sync();
+    stg.flush(lane, nvalid, nullptr, Cs_fast, w0, L, i, L);
+    wave_sync();
+  }
+  if (!fin && valid) flag |= SRTM_INFO_NONFINITE;
+  if (flag && info) atomicOr(info, flag);
+}
+
 // ============================================================================ log-likelihood and gradient
 // Marginal log-likelihood log p(y_{1:N}) = sum_k log N(y_k; C_bar m^f_{k-1,l}, S_k) (the IMKF
 // prediction of y_k, eq. m-h-k-l), and its gradient with respect to F, Q and R by Fisher's
@@ -2947,37 +3135,12 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
       for (int r = 0; r < NX; ++r)
 #pragma unroll
         for (int c = 0; c < NX; ++c) S11[r][c] += my_fma(ms[r], ms[c], Ps[r][c]);
-      // U_i = A^i V + c_i (the cross-covariance of x_{k,i} with y_k given y_{1:k-1})
-      const T* pi = M.per_i(i);
       T Ui[NX][NY];
-      {
-        T Ai[NX][NX], ci[NX][NY];
-        load(Ai, pi + M.lay.o_Ai);
-        load(ci, pi + M.lay.o_ci);
-        mm(Ai, w.V, Ui);
-#pragma unroll
-        for (int r = 0; r < NX; ++r)
-#pragma unroll
-          for (int c = 0; c < NY; ++c) Ui[r][c] += ci[r][c];
-      }
-      if (i == 1) {
-        // across the window boundary: x_{k-1,l} (or x_0) given x_{k,1} has the one-step smoother
-        // gain G = P A^T (A P A^T + Q)^{-1}, with (m, P) the filter state of x_{k-1,l}
-        T Qq[NX][NX], Pm[NX][NX], Pmi[NX][NX], PA[NX][NX], G[NX][NX];
+      window_U(M, w, i, Ui);
+      if (i == 1) {  // across the window boundary
+        T Qq[NX][NX], Pm[NX][NX], G[NX][NX], mb[NX], PsG[NX][NX];
         load(Qq, M.cst + M.lay.Q);
-        sandwich(A, P, Qq, Pm);
-        if (!spd_inv(Pm, Pmi) && valid) flag |= SRTM_INFO_PRED_SINGULAR;
-        mm_nt(P, A, PA);
-        mm(PA, Pmi, G);
-        T Am[NX], dm[NX], mb[NX];
-        mv(A, m, Am);
-#pragma unroll
-        for (int r = 0; r < NX; ++r) dm[r] = ms[r] - Am[r];
-        mv(G, dm, mb);
-#pragma unroll
-        for (int r = 0; r < NX; ++r) mb[r] += m[r];   // E[x_{k-1,l} | y_{1:N}]
-        T PsG[NX][NX];
-        mm_nt(Ps, G, PsG);
+        if (!lag1_boundary(A, Qq, m, P, ms, Ps, G, Pm, mb, PsG) && valid) flag |= SRTM_INFO_PRED_SINGULAR;
 #pragma unroll
         for (int r = 0; r < NX; ++r)
 #pragma unroll
@@ -2999,41 +3162,13 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
               part[SL::X0 + r * NX + c] = (double)t;
             }
         }
-      } else {
-        // within the window: Cov(x_{k,i}, x_{k,i-1} | y_{1:k}) = A P^f_{i-1,i-1} + (A c_{i-1} - c_i) S^{-1} U_{i-1}^T,
-        // plus the smoothing term P^f_{i,l} W P^f_{i-1,l}^T
-        T Dc[NX][NY], SU[NY][NX], C[NX][NX];
-        {
-          T cp[NX][NY], ci[NX][NY];
-          load(cp, M.per_i(i - 1) + M.lay.o_ci);
-          load(ci, pi + M.lay.o_ci);
-          mm(A, cp, Dc);
-#pragma unroll
-          for (int r = 0; r < NX; ++r)
-#pragma unroll
-            for (int c = 0; c < NY; ++c) Dc[r][c] -= ci[r][c];
-        }
-#pragma unroll
-        for (int r = 0; r < NY; ++r)
-#pragma unroll
-          for (int c = 0; c < NX; ++c) {
-            T t = T(0);
-#pragma unroll
-            for (int q = 0; q < NY; ++q) t = my_fma(symget(w.Si, r, q), Uprev[c][q], t);
-            SU[r][c] = t;
-          }
-        mm(A, Pprev, C);
+      } else {  // within the window
+        T C[NX][NX];
+        lag1_within(M, w, i, A, Pprev, Uprev, PLW, PLprev, C);
 #pragma unroll
         for (int r = 0; r < NX; ++r)
 #pragma unroll
-          for (int c = 0; c < NX; ++c) {
-            T t = C[r][c];
-#pragma unroll
-            for (int q = 0; q < NY; ++q) t = my_fma(Dc[r][q], SU[q][c], t);
-#pragma unroll
-            for (int q = 0; q < NX; ++q) t = my_fma(PLW[r][q], PLprev[c][q], t);
-            S10[r][c] += my_fma(ms[r], msprev[c], t);
-          }
+          for (int c = 0; c < NX; ++c) S10[r][c] += my_fma(ms[r], msprev[c], C[r][c]);
       }
       if (valid && k == N - 1 && i == L) {  // E[x_T x_T^T]
 #pragma unroll
@@ -3210,7 +3345,7 @@ SRTM_DEV void stats_final_body(int64_t N, int L, int64_t nt, const T* __restrict
 template <typename T, int NX, int NY>
 struct Seq {  // one sequence's typed arrays and scan plan
   const T *F, *Q, *H, *R, *m0, *P0, *y;
-  T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow;
+  T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow, *Cs_fast;
   T *cst, *ftagg, *ftst, *utree, *carry, *btagg, *btst, *sfx, *tvblk, *tvel;
   double *hand, *stats;
   int64_t N, tile0;
@@ -3239,6 +3374,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   q.Pf_fast = as_global<T>(d.Pf_fast);
   q.mf_slow = as_global<T>(d.mf_slow);
   q.Pf_slow = as_global<T>(d.Pf_slow);
+  q.Cs_fast = as_global<T>(d.Cs_fast);
   q.N = d.N;
   q.tile0 = d.tile0;
   q.L = d.L;
@@ -3345,6 +3481,14 @@ __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
                                          q.carry, q.sfx, q.btst,
                                 q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
                                 (int64_t)blockIdx.x - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(TILE) k_lag1(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
+  if (!q.Cs_fast) return;
+  lag1_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.carry, q.sfx, q.btst, q.Cs_fast, q.info,
+                       (int64_t)blockIdx.x - q.tile0);
 }
 
 template <typename T, int NX, int NY, bool GRAD, bool INP>
@@ -3583,6 +3727,7 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   d.u = p.u;
   d.nu = p.B ? p.nu : 0;
   d.tv = p.tv ? 1 : 0;
+  d.Cs_fast = p.Cs_fast;
   const Launch g{1u, (unsigned)((sh.N + TILE - 1) / TILE), (int)sh.L};
   const bool want_f = p.mf_fast || p.Pf_fast;
   const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
@@ -3593,7 +3738,16 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
     return launch_tv<T, NX, NY>(b, g, smoother, mode, st);
   }
   if (p.B) return launch_all<T, NX, NY, true>(b, g, smoother, mode, st, ev, lo);
-  return launch_all<T, NX, NY, false>(b, g, smoother, mode, st, ev, lo);
+  if (!p.Cs_fast) return launch_all<T, NX, NY, false>(b, g, smoother, mode, st, ev, lo);
+  // lag-one cross-covariances: the smoother's launches, then one more pass over the tiles
+  if (!smoother || lik_mode || ev.ev) return SRTM_E_UNSUPPORTED;
+  const srtm_status s = launch_all<T, NX, NY, false>(b, g, smoother, mode, st, ev, lo);
+  if (s != SRTM_OK) return s;
+  const size_t lds = (size_t)4 * OutStage<T, NX>::BYTES;
+  if (!allow_lds((const void*)k_lag1<T, NX, NY>, lds)) return SRTM_E_HIP;
+  hipLaunchKernelGGL((k_lag1<T, NX, NY>), dim3(g.ntiles), dim3(TILE), lds, st, b);
+  SRTM_CHECK_LAUNCH();
+  return SRTM_OK;
 }
 
 // Many sequences (srtm_smooth_batch): `table` holds nseq descriptors followed by the sequence

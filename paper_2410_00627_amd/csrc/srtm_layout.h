@@ -185,6 +185,7 @@ struct SeqDesc {
   const void *B, *u;  // known inputs (null without)
   int32_t nu;
   int32_t tv;  // F, Q, H, R are given per window ([N][...])
+  void* Cs_fast;  // lag-one smoothed cross-covariances [N][L][nx][nx] (single calls only; null otherwise)
 };
 
 // What every kernel receives: either one sequence (`table` null) or a device table of

@@ -71,6 +71,8 @@ def lib():
     L.srtm_filter_tv.restype = ctypes.c_int
     L.srtm_smooth_tv.argtypes = L.srtm_smooth.argtypes
     L.srtm_smooth_tv.restype = ctypes.c_int
+    L.srtm_smooth_lag1.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 13 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth_lag1.restype = ctypes.c_int
     L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
                                        [ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_int32])
     L.srtm_smooth_profiled.restype = ctypes.c_int
@@ -247,12 +249,14 @@ def _smooth_args(ts, out, workspace, info):
 def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = True, with_filter: bool = False,
            workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
            out: Optional[Dict[str, torch.Tensor]] = None, check: bool = True,
-           events=None, B=None, u=None) -> Dict[str, torch.Tensor]:
+           events=None, B=None, u=None, lag1: bool = False) -> Dict[str, torch.Tensor]:
     """p(x_{k,i} | y_{1:N}) as ms_fast [N,L,nx], Ps_fast [N,L,nx,nx]; p(x_{k,1} | y_{1:N}) as ms_slow, Ps_slow.
 
     with_filter also returns the filter outputs (mf_fast, Pf_fast, mf_slow, Pf_slow). `out` may
     supply preallocated output tensors; `events` (a ctypes array of hipEvent_t) selects the
     profiling entry point. B [nx, nu] and u [N, L, nu] add known inputs (u[k-1, i-1] drives x_{k,i}).
+    lag1 also returns Cs_fast [N,L,nx,nx] = Cov(x_{k,i}, x_{k,i-1} | y_{1:N}) (x_{k,0} = x_{k-1,L},
+    x_{1,0} = x_0) through srtm_smooth_lag1 (time-invariant model, no inputs or filter outputs).
     """
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
     inp = _prep_inputs(B, u, nx, L, N, y)
@@ -261,6 +265,8 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
         raise SrtmError("the profiling entry point takes neither inputs nor a per-window model")
     if tv and inp is not None:
         raise SrtmError("a per-window model takes no inputs")
+    if lag1 and (tv or inp is not None or events is not None or with_filter):
+        raise SrtmError("lag-one cross-covariances: time-invariant model, no inputs, filter outputs or events")
     dev, dt = y.device, y.dtype
     if out is None:
         out = {}
@@ -275,6 +281,8 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
             out["Pf_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
             out["mf_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
             out["Pf_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+        if lag1:
+            out["Cs_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
     nbytes = workspace_size(nx, ny, L, N, dt, True, inp is not None, tv)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
@@ -283,7 +291,12 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
     sh = shape_of(nx, ny, L, N, dt)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     args = _smooth_args(ts, out, workspace, info)
-    if tv:
+    if lag1:
+        lag_args = ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
+                    [_ptr(out.get(k)) for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow", "Cs_fast")] +
+                    [_ptr(workspace), workspace.numel(), _ptr(info)])
+        _check(lib().srtm_smooth_lag1(ctypes.byref(sh), *lag_args, stream), "srtm_smooth_lag1")
+    elif tv:
         _check(lib().srtm_smooth_tv(ctypes.byref(sh), *args, stream), "srtm_smooth_tv")
     elif inp is not None:
         code = lib().srtm_smooth_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *args, stream)

@@ -324,3 +324,24 @@ def test_binding_declares_every_signature(L):
         fn = getattr(L, n)
         assert fn.argtypes is not None, f"{n}: argtypes not set"
         assert fn.restype is not None, f"{n}: restype not set"
+
+
+def test_lag1_entry_point_validates(L):
+    """srtm_smooth_lag1: the cross-covariance array is required and aligned; the other checks are
+    srtm_smooth's (unsupported pair, small workspace). No kernel is launched on these paths."""
+    _no_gpu()
+    sh = srtm.Shape(2, 1, 10, 1, 5)
+    _, need = _ws(2, 1, 10, 5)
+
+    def call(shape, cs, ws_bytes, nulled=None):
+        P = [ctypes.c_void_p(p) for p in FAKE]
+        if nulled is not None:
+            P[nulled] = None
+        return L.srtm_smooth_lag1(ctypes.byref(shape), *P[:7], None, None, None, None,
+                                  None if cs is None else ctypes.c_void_p(cs), P[7], ws_bytes, None, None)
+
+    assert call(sh, None, need) == 1                      # Cs_fast is required
+    assert call(sh, 0x9008, need) == 5                    # misaligned Cs_fast
+    assert call(sh, 0x9000, need, nulled=0) == 1          # null model array
+    assert call(sh, 0x9000, need - 256) == 6              # workspace too small
+    assert call(srtm.Shape(5, 1, 10, 1, 5), 0x9000, need) == 4   # pair not compiled
