@@ -281,6 +281,61 @@ def run_inputs(args):
     print(json.dumps(line))
 
 
+def run_lag1(args):
+    """The long-sequence workload (nx=4, ny=2, L=20, N=2^17) with the lag-one smoothed
+    cross-covariances Cov(x_t, x_{t-1} | y_{1:N}) as an extra output (srtm_smooth_lag1), against
+    the same smoother call without them."""
+    import torch
+    from paper_2410_00627_amd import srtm, workloads as wl
+    dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m = wl.headline_model()
+    N = args.N or wl.HEADLINE_N
+    y = wl.simulate(m, N, seed=2024)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, dev, dt)
+    yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dt)
+    nx, L = m.nx, m.L
+    out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+           "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+           "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+           "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt),
+           "Cs_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt)}
+    ws = torch.empty(srtm.workspace_size(nx, m.ny, L, N, dt, True), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+
+    def timed(lag1):
+        for _ in range(args.warmup):
+            srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, lag1=lag1)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, lag1=lag1)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / args.steps
+
+    t_plain = timed(False)
+    t_lag = timed(True)
+    if int(info.item()) != 0:
+        raise RuntimeError(f"numerical failure: info={int(info.item())}")
+    esz = 8 if dt == torch.float64 else 4
+    fast_states = N * L
+    line = {"metric": "fast-rate smoothed states/sec (filter+smoother) with lag-one cross-covariances",
+            "value": round(fast_states / t_lag), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_lag * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+            "config": {"workload": "one sequence, nx=4, ny=2, L=20, N=2^17, A=0.99*Haar, Q=0.01I, C Gaussian, "
+                                   "R=0.05I; outputs ms/Ps fast and slow plus Cs_fast",
+                       "N": N, "L": L, "fast_states": fast_states,
+                       "cross_covariance_bytes_per_call": int(N * L * nx * nx * esz)},
+            "without_cross_covariances_ms_per_step": round(t_plain * 1e3, 4),
+            "cost_of_cross_covariances": round(t_lag / t_plain, 3)}
+    print(json.dumps(line))
+
+
 def run_gradient(args):
     """Log-likelihood and gradient w.r.t. F, Q, R for 64 sequences (nx=4, ny=1, L=10, N=2^14,
     A=0.99*Haar, Q=0.01I, C Gaussian, R=0.1), batched against one call per sequence."""
@@ -380,7 +435,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs", "tv"],
+    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs", "tv", "lag1"],
                     default="headline",
                     help="headline: one long sequence (default); batched: 256 uneven sequences; "
                          "serving: Poisson arrivals with continuous batching")
@@ -407,6 +462,8 @@ def main():
         return run_serving(args)
     if args.workload == "inputs":
         return run_inputs(args)
+    if args.workload == "lag1":
+        return run_lag1(args)
     if args.workload == "tv":
         return run_tv(args)
     if args.workload == "gradient":
