@@ -279,6 +279,22 @@ def test_smooth_batch_rejects_descriptors_with_inputs(L):
                                None, None) == 2
 
 
+def test_smooth_batch_rejects_descriptors_with_cross_covariances(L):
+    """Batch descriptors carry no lag-one cross-covariance output (single calls only)."""
+    _no_gpu()
+    arr = _seqs([(300, 5)])
+    _, tsz, wsz, nt, _ = _plan(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    # after B, u (8 bytes each) and nu, tv (4 each): the cross-covariance output pointer
+    off_cs = 15 * 8 + 3 * 8 + 2 * 4 + 2 * 8 + 2 * 4
+    assert bytes(buf[off_cs:off_cs + 8]) == bytes(8)
+    ctypes.c_uint64.from_buffer(buf, off_cs).value = 0x9000
+    host = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.srtm_smooth_batch(4, 2, 1, 1, host, ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x8000000), wsz,
+                               None, None) == 2
+
+
 def test_workspace_size_with_inputs(L):
     """The *_inputs entry points need one more per-window record of nx + ny scalars."""
     for dtype, esz in ((1, 8), (0, 4)):
