@@ -55,7 +55,9 @@ typedef enum {
   SRTM_E_UNSUPPORTED = 4, /* (nx, ny) pair not compiled, or L / N above the limits      */
   SRTM_E_ALIGN = 5,       /* an array is not 16-byte aligned (workspace: 256 bytes)     */
   SRTM_E_WORKSPACE = 6,   /* workspace_bytes smaller than srtm_workspace_size()         */
-  SRTM_E_HIP = 7          /* a HIP runtime call (kernel launch, event record) failed    */
+  SRTM_E_HIP = 7,         /* a HIP runtime call (kernel launch, event record) failed    */
+  SRTM_E_SCRATCH = 8      /* srtm_smooth_noalloc: the problem needs more workspace than
+                             the library's fixed scratch (SRTM_NOALLOC_SCRATCH_BYTES)     */
 } srtm_status;
 
 /* Device-side numerical status bits (OR-ed into *info). */
@@ -144,6 +146,31 @@ srtm_status srtm_smooth_profiled(const srtm_shape* shape,
                                  void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
                                  void* workspace, size_t workspace_bytes, int32_t* info,
                                  void* stream, void* const* events, int32_t n_events);
+
+/* ------------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, and harnesses that forbid hipMalloc. srtm_smooth_noalloc is srtm_smooth
+ * (same kernels, same outputs, bitwise) with its workspace taken from a scratch array the
+ * library holds in device memory, SRTM_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the
+ * call runs on keeps until the process ends. The call itself allocates nothing and makes
+ * no hipMalloc / hipFree.
+ *  - Device: the scratch of the CURRENT device (hipGetDevice) is used; `stream` must belong
+ *    to that device. Its address is looked up once per device, on the first call there.
+ *  - Limit: problems whose workspace, srtm_workspace_size(shape, 1), exceeds
+ *    SRTM_NOALLOC_SCRATCH_BYTES return SRTM_E_SCRATCH before anything is enqueued (for
+ *    nx = 4, ny = 2, L = 20 in float64 that is about 2^17 windows).
+ *  - Sharing: every call on one GPU uses that GPU's one array, which keeps whatever the last
+ *    call left there (nothing in it has to start at zero). Calls that overlap on one GPU
+ *    (other streams, other host threads) RACE on the array: serialise them.
+ *  - Arguments, outputs, errors and info bits as srtm_smooth; SRTM_E_HIP if the scratch
+ *    address cannot be obtained. */
+#define SRTM_NOALLOC_SCRATCH_BYTES (64u << 20)
+srtm_status srtm_smooth_noalloc(const srtm_shape* shape,
+                                const void* F, const void* Q, const void* H, const void* R,
+                                const void* m0, const void* P0, const void* y,
+                                void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                                void* mf_fast, void* Pf_fast, void* mf_slow, void* Pf_slow,
+                                int32_t* info, void* stream);
 
 /* ------------------------------------------------------------------ known inputs
  * The model of eq. original-linear-SSM with its input term:

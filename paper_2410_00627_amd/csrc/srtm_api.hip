@@ -5,9 +5,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "srtm_entry.h"
 #include "srtm_layout.h"
+
+// Workspace of srtm_smooth_noalloc: one array per GPU, resident until the process ends. Host
+// code never passes `scratch` itself to a kernel (on the host it only names the symbol); it
+// uses the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SRTM_NOALLOC_SCRATCH_BYTES];
 
 namespace srtm {
 bool pair_supported(int nx, int ny) {
@@ -86,6 +92,25 @@ srtm_status with_inputs(const srtm_inputs* in, srtm::Ptrs& p) {
   return SRTM_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per device (with that
+// device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+srtm_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SRTM_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return SRTM_E_HIP;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return SRTM_OK;
+}
+
 const char* const kFilterKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles", "k_fwd_final", "k_recover"};
 const char* const kSmoothKernels[] = {"k_constants", "k_fwd_reduce", "k_fwd_tiles",
                                       "k_fwd_bwd",   "k_bwd_tiles",  "k_recover"};
@@ -139,6 +164,24 @@ srtm_status srtm_smooth(const srtm_shape* shape, const void* F, const void* Q, c
   const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
                      mf_fast, Pf_fast, mf_slow, Pf_slow, workspace, info};
   return run_common(shape, p, true, workspace_bytes, stream, nullptr, 0);
+}
+
+srtm_status srtm_smooth_noalloc(const srtm_shape* shape, const void* F, const void* Q, const void* H,
+                                const void* R, const void* m0, const void* P0, const void* y, void* ms_fast,
+                                void* Ps_fast, void* ms_slow, void* Ps_slow, void* mf_fast, void* Pf_fast,
+                                void* mf_slow, void* Pf_slow, int32_t* info, void* stream) {
+  srtm_status s = check_shape(shape);
+  if (s != SRTM_OK) return s;
+  if (!F || !Q || !H || !R || !m0 || !P0 || !y) return SRTM_E_NULL;
+  const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
+  if (srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, true).total > SRTM_NOALLOC_SCRATCH_BYTES)
+    return SRTM_E_SCRATCH;
+  void* ws = nullptr;
+  s = scratch_address(&ws);
+  if (s != SRTM_OK) return s;
+  const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
+                     mf_fast, Pf_fast, mf_slow, Pf_slow, ws, info};
+  return run_common(shape, p, true, SRTM_NOALLOC_SCRATCH_BYTES, stream, nullptr, 0);
 }
 
 srtm_status srtm_smooth_lag1(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
@@ -375,6 +418,7 @@ const char* srtm_status_string(int32_t status) {
     case SRTM_E_ALIGN: return "array not 16-byte aligned (workspace: 256 bytes)";
     case SRTM_E_WORKSPACE: return "workspace smaller than srtm_workspace_size()";
     case SRTM_E_HIP: return "HIP runtime error while enqueueing work";
+    case SRTM_E_SCRATCH: return "srtm_smooth_noalloc: workspace larger than SRTM_NOALLOC_SCRATCH_BYTES";
     default: return "unknown status";
   }
 }

@@ -73,6 +73,8 @@ def lib():
     L.srtm_smooth_tv.restype = ctypes.c_int
     L.srtm_smooth_lag1.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 13 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_smooth_lag1.restype = ctypes.c_int
+    L.srtm_smooth_noalloc.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 17
+    L.srtm_smooth_noalloc.restype = ctypes.c_int
     L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
                                        [ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_int32])
     L.srtm_smooth_profiled.restype = ctypes.c_int
@@ -311,6 +313,26 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
         _raise_info(info, "srtm_smooth")
     out["info"] = info
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def smooth_noalloc(F, Q, H, R, L: int, m0, P0, y, out: Dict[str, torch.Tensor], info: torch.Tensor) -> int:
+    """srtm_smooth_noalloc: the smoother with the library's fixed per-GPU scratch as workspace.
+
+    `out` holds the caller's preallocated outputs (keys of `smooth`, each optional) and `info`
+    a zeroed device int32. Nothing is allocated here or in the library. Returns the status
+    code (0 = ok; SRTM_E_SCRATCH = 8 when the problem needs more than NOALLOC_SCRATCH_BYTES)
+    without raising, so callers can test the limit."""
+    ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    sh = shape_of(nx, ny, L, N, y.dtype)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(y.device).cuda_stream)
+    args = ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
+            [_ptr(out.get(k)) for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow",
+                                        "mf_fast", "Pf_fast", "mf_slow", "Pf_slow")] +
+            [_ptr(info), stream])
+    return int(lib().srtm_smooth_noalloc(ctypes.byref(sh), *args))
 
 
 def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):

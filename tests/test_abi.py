@@ -40,7 +40,7 @@ def test_version_and_kernel_names(L):
     assert srtm.kernel_names(False)[0] == "k_constants"
     assert len(srtm.kernel_names(True)) == L.srtm_kernel_count(1)
     assert L.srtm_kernel_name(1, 99) is None
-    for c in range(8):
+    for c in range(9):
         assert isinstance(srtm.status_string(c), str)
 
 
@@ -172,6 +172,19 @@ def test_profiled_requires_events(L):
     P = [ctypes.c_void_p(p) for p in FAKE]
     assert L.srtm_smooth_profiled(ctypes.byref(sh), *P[:7], *([None] * 8), P[7], 1 << 30, None, None,
                                   None, 0) == 1
+
+
+def test_noalloc_validates_before_touching_the_device(L):
+    """srtm_smooth_noalloc: shape and null checks, and the scratch limit, all on the host."""
+    P = [ctypes.c_void_p(p) for p in FAKE]
+    sh = srtm.Shape(4, 2, 20, 1, 5)
+    assert L.srtm_smooth_noalloc(ctypes.byref(sh), None, *P[1:7], *([None] * 8), None, None) == 1
+    assert L.srtm_smooth_noalloc(ctypes.byref(srtm.Shape(4, 2, 0, 1, 5)), *P[:7], *([None] * 8), None, None) == 2
+    big = srtm.Shape(4, 2, 20, 1, 1 << 18)   # workspace above SRTM_NOALLOC_SCRATCH_BYTES
+    code, need = _ws(4, 2, 20, 1 << 18)
+    assert code == 0 and need > srtm.NOALLOC_SCRATCH_BYTES
+    assert L.srtm_smooth_noalloc(ctypes.byref(big), *P[:7], *([None] * 8), None, None) == 8
+    assert "SCRATCH" in srtm.status_string(8).upper()
 
 
 def test_python_binding_refuses_cpu_tensors():
