@@ -81,6 +81,7 @@ class Request:
     done: Optional[float] = None
     outputs: Dict[str, torch.Tensor] = field(default_factory=dict)
     info: int = 0
+    batch: int = -1            # index of the launch that carried the request
 
 
 class _Flight:
@@ -222,6 +223,8 @@ class Server:
                 b.launch(s.cuda_stream)
                 ev = torch.cuda.Event()
                 ev.record(s)
+            for r in take:
+                r.batch = self.batches_launched
             self.free_streams.pop()
             self.waiting = self.waiting[len(take):]
             self.flights.append(_Flight(take, ranges, s, ev, b))

@@ -88,26 +88,27 @@ def test_lag1_edge_lengths():
         assert lag1_error(o["Cs_fast"], ref["Cs_fast"], ref["Ps_fast"]) < 1e-8, f"N={N}"
 
 
-def test_lag1_full_size_tail():
-    """The long-sequence shape (nx=4, ny=2, L=20, N=2^17): the last 24 windows against the reference
-    smoother started from the IMKF carry (its prior step then is the boundary step into window
-    N-24), and the smoothed blocks of the same call."""
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_lag1_full_size(dtype):
+    """The long-sequence shape (nx=4, ny=2, L=20, N=2^17, 512 tiles): every window's lag-one
+    cross-covariances and smoothed blocks against the reference smoother over the whole sequence
+    (float32: reference on the rounded inputs), and the smoothed blocks equal to srtm_smooth's."""
+    from threadpoolctl import threadpool_limits
     srtm = _srtm()
     m = wl.headline_model()
     N = wl.HEADLINE_N
     y = wl.simulate(m, N, seed=2032)
-    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", torch.float64)
-    yt = torch.as_tensor(y, device="cuda")
-    print("[gpu] smooth_lag1 headline size", flush=True)
-    o = srtm.smooth(F, Q, H, R, m.L, m0, P0, yt, lag1=True)
-    torch.cuda.synchronize()
+    o, plain = _run(srtm, m, y, dtype)
     assert int(o["info"][0]) == 0
-    Cs, ms, Ps = (o[k].cpu().numpy() for k in ("Cs_fast", "ms_fast", "Ps_fast"))
-    mf, Pf, _ = oracle.imkf(m.A, m.Q, m.C, m.R, m.L, m.m0, m.P0, y)
-    n = 24
-    tail = oracle.srtm_smoother(m.A, m.Q, m.C, m.R, m.L, mf[N - n - 1], Pf[N - n - 1], y[N - n:], lag1=True)
-    assert lag1_error(Cs[N - n:], tail["Cs_fast"], tail["Ps_fast"]) < 1e-8
-    assert_close_states(ms[N - n:], Ps[N - n:], tail["ms_fast"], tail["Ps_fast"], 1e-8, "smoothed tail")
+    mr, yr = _rounded(m, y, dtype)
+    with threadpool_limits(limits=1):
+        ref = oracle.srtm_smoother(mr.A, mr.Q, mr.C, mr.R, m.L, mr.m0, mr.P0, yr, lag1=True)
+    err = lag1_error(o["Cs_fast"], ref["Cs_fast"], ref["Ps_fast"])
+    print(f"[gpu] lag1 full size {dtype}: max err {err:.2e}", flush=True)
+    assert err < TOL[dtype]
+    assert_close_states(o["ms_fast"], o["Ps_fast"], ref["ms_fast"], ref["Ps_fast"], TOL[dtype], "smoothed, all windows")
+    for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+        assert np.array_equal(o[k], plain[k]), k
 
 
 def test_lag1_refuses_inputs_and_filter_outputs():
