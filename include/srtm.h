@@ -253,9 +253,11 @@ srtm_status srtm_loglik(const srtm_shape* shape,
  * dR [ny][ny]: symmetric-matrix gradients G, i.e. a small symmetric change E of Q changes
  * ll by tr(G E)).
  * Computed by Fisher's identity: the expected gradient of the complete-data log-density
- * under the smoothing distribution, whose second moments (including lag-one cross terms
- * between consecutive fast states) come from the same forward and reverse scans as
- * srtm_smooth, recomputed per window rather than stored. Workspace:
+ * under the smoothing distribution, written with the process noise w = x_t - F x_{t-1} and the
+ * measurement residual r_k = y_k - (H/L) sum_i x_{k,i}: dF = Q^{-1} sum E[w x_{t-1}^T],
+ * dQ = Q^{-1} sum (E[w w^T] - Q) Q^{-1} / 2, dR = R^{-1} sum (E[r r^T] - R) R^{-1} / 2. Each summand
+ * is formed per fast step in that centred form, in float64 for both element types, from the same
+ * forward and reverse scans as srtm_smooth (recomputed per window rather than stored). Workspace:
  * srtm_workspace_size(shape, 1) bytes. All outputs are device arrays of the shape's dtype. */
 srtm_status srtm_loglik_grad(const srtm_shape* shape,
                              const void* F, const void* Q, const void* H, const void* R,

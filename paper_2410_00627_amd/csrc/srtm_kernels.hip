@@ -238,7 +238,7 @@ SRTM_DEV void chain_tail_body(T* __restrict__ cst, const double* __restrict__ ha
 template <typename T, int NX, int NY>
 SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm, const T* __restrict__ Hm,
                              const T* __restrict__ Rm, int L, int nlev, T* __restrict__ cst,
-                             double* __restrict__ hand, int32_t* info) {
+                             double* __restrict__ cst64, double* __restrict__ hand, int32_t* info) {
   constexpr int NN = NX * NX, NXY = NX * NY;
   constexpr int W2S = (NN > 2 * NXY ? NN : 2 * NXY);
   extern __shared__ double sm[];
@@ -349,23 +349,28 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
   }
   __syncthreads();
 
-  // Per-step tables to the constants block: A^i, Q_ii, Q_il = Q_ii (A^{l-i})^T, c_i.
+  // Per-step tables to the constants block: A^i, Q_ii, Q_il = Q_ii (A^{l-i})^T, c_i. Every entry of
+  // the model part (below the level tables) also goes, unrounded, to the float64 copy.
+  auto put = [&](int off, double v) {
+    cst[off] = (T)v;
+    cst64[off] = v;
+  };
   for (int e = tid; e < L * NN; e += nthr) {
     const int i = 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
-    T* dst = cst + lay.per_i + (i - 1) * lay.per_i_stride;
-    dst[lay.o_Ai + rc] = (T)Apow[i * NN + rc];
-    dst[lay.o_Qii + rc] = (T)Qii[i * NN + rc];
+    const int base = lay.per_i + (i - 1) * lay.per_i_stride;
+    put(base + lay.o_Ai + rc, Apow[i * NN + rc]);
+    put(base + lay.o_Qii + rc, Qii[i * NN + rc]);
     double acc = 0.0;
     for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * Apow[(L - i) * NN + c * NX + k];
-    dst[lay.o_QiL + rc] = (T)acc;
+    put(base + lay.o_QiL + rc, acc);
   }
   for (int e = tid; e < L * NXY; e += nthr) {
     const int i = 1 + e / NXY, rc = e % NXY;
-    cst[lay.per_i + (i - 1) * lay.per_i_stride + lay.o_ci + rc] = (T)ci[i * NXY + rc];
+    put(lay.per_i + (i - 1) * lay.per_i_stride + lay.o_ci + rc, ci[i * NXY + rc]);
   }
   for (int e = tid; e < NN; e += nthr) {
-    cst[lay.A + e] = (T)sA[e];
-    cst[lay.Q + e] = (T)sQ[e];
+    put(lay.A + e, sA[e]);
+    put(lay.Q + e, sQ[e]);
   }
 
   // C_bar = (C/l)(Sig_l - I) and R_x = (1/l) sum_i C c_i + R, into LDS (W2 is free again)
@@ -420,13 +425,13 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
     symmetrize(D);
     symmetrize(J);
     for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NX; ++c) cst[lay.Cbar + r * NX + c] = (T)Cbar[r][c];
+      for (int c = 0; c < NX; ++c) put(lay.Cbar + r * NX + c, Cbar[r][c]);
     for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NY; ++c) cst[lay.Rx + r * NY + c] = (T)Rx[r][c];
+      for (int c = 0; c < NY; ++c) put(lay.Rx + r * NY + c, Rx[r][c]);
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NY; ++c) {
-        cst[lay.K + r * NY + c] = (T)K[r][c];
-        cst[lay.Heta + r * NY + c] = (T)Heta[r][c];
+        put(lay.K + r * NY + c, K[r][c]);
+        put(lay.Heta + r * NY + c, Heta[r][c]);
       }
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) {
@@ -2988,23 +2993,38 @@ SRTM_DEV void lag1_body(const T* __restrict__ y, int64_t N, int L, const T* __re
 // Marginal log-likelihood log p(y_{1:N}) = sum_k log N(y_k; C_bar m^f_{k-1,l}, S_k) (the IMKF
 // prediction of y_k, eq. m-h-k-l), and its gradient with respect to F, Q and R by Fisher's
 // identity: the gradient of log p(y | theta) is the expectation, under the smoothing
-// distribution p(x_{0:Nl} | y_{1:N}), of the gradient of the complete-data log-density
+// distribution, of the gradient of the complete-data log-density
 //   log p(x_0) + sum_t log N(x_t; F x_{t-1}, Q) + sum_k log N(y_k; (H/l) sum_i x_{k,i}, R).
-// With T = N l transitions and the smoothed sums S11 = sum_{t>=1} E[x_t x_t^T],
-// S10 = sum_{t>=1} E[x_t x_{t-1}^T], S00 = E[x_0 x_0^T] + S11 - E[x_T x_T^T] and
-// SY = sum_k E[(y_k - H xbar_k)(y_k - H xbar_k)^T]:
-//   dll/dF = Q^{-1} (S10 - F S00),
-//   dll/dQ = 1/2 Q^{-1} (S11 - F S10^T - S10 F^T + F S00 F^T - T Q) Q^{-1},
-//   dll/dR = 1/2 R^{-1} (SY - N R) R^{-1}
-// (symmetric-matrix gradients for Q and R: dll = tr(G dQ) for symmetric dQ).
+// Written with the process noise w_t = x_t - F x_{t-1} and the measurement residual
+// r_k = y_k - H xbar_k (xbar_k the window average):
+//   dll/dF = Q^{-1} sum_t E[w_t x_{t-1}^T],
+//   dll/dQ = 1/2 Q^{-1} sum_t (E[w_t w_t^T] - Q) Q^{-1},   dll/dR = 1/2 R^{-1} sum_k (E[r_k r_k^T] - R) R^{-1}
+// (expectations under p(. | y_{1:N}); symmetric-matrix gradients for Q and R: dll = tr(G dQ)).
+// The summands are formed per fast step directly in their centred form, from quantities that
+// scale with Q and R, never as differences of second moments of the states: near the data's
+// own parameters the sums nearly vanish, and differences of state moments would carry the
+// rounding of the states into the gradient multiplied by the number of steps.
 //
-// Per-tile record (float64): ll, S11, S10, SY summed over the tile's windows, and in the
-// records of the first and last tiles E[x_0 x_0^T] and E[x_T x_T^T].
+// Per window k, with the window prior (m, P) of x_{k,0} = x_{k-1,l}, S, e and U_i as in
+// eq. update-fast, the noise w_i = x_{k,i} - F x_{k,i-1} of fast step i has
+//   Cov(w_i, y_k | y_{1:k-1}) = b_i = c_i - F c_{i-1}   (c_0 = 0),
+//   Cov(w_i, x_{k,l} | y_{1:k}) = K_i = Q (F^{l-i})^T - b_i S^{-1} U_l^T,
+// and the future measurements reach the window only through x_{k,l} (the smoother correction
+// v_k, W_k of eq. seq-smoothing-all), so under p(. | y_{1:N}):
+//   E[w_i] = mu_i = b_i S^{-1} e + K_i v,   E[w_i w_i^T] - Q = -b_i S^{-1} b_i^T + K_i W K_i^T + mu_i mu_i^T,
+//   E[w_i x_{k,i-1}^T] = -b_i S^{-1} U_{i-1}^T + K_i W P^f_{k,i-1,l}^T + mu_i m^s_{k,i-1}^T
+// with U_0 = P C_bar^T, P^f_{k,0,l} = P F^{lT} - U_0 S^{-1} U_l^T and m^s_{k,i-1} = m^f_{k,i-1} + P^f_{k,i-1,l} v.
+// The measurement residual: E[r_k] = R S^{-1} e - Z v and E[r_k r_k^T] - R = E[r_k] E[r_k]^T - R S^{-1} R
+// + Z W Z^T with Z = R S^{-1} U_l^T.
+// These statistics are computed in float64 for both element types, from the float64 copy of the
+// model constants and the stored carry and smoother correction.
+//
+// Per-tile record (float64): ll, then (gradient) the tile sums of E[w w^T] - Q, E[w x^T] and
+// E[r r^T] - R.
 template <int NX, int NY>
 struct StatLayout {
   static constexpr int NN = NX * NX;
-  static constexpr int LL = 0, S11 = 1, S10 = 1 + NN, SY = 1 + 2 * NN, X0 = 1 + 2 * NN + NY * NY,
-                       XT = X0 + NN, SIZE = XT + NN;
+  static constexpr int LL = 0, SW = 1, SWX = 1 + NN, SY = 1 + 2 * NN, SIZE = SY + NY * NY;
 };
 
 template <typename T, int N>
@@ -3023,211 +3043,283 @@ SRTM_DEV double wave_sum(double v) {
   return v;
 }
 
+template <typename T, int R, int C>
+SRTM_DEV void gload_f64(double (&a)[R][C], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[r][c] = (double)gld(p + r * C + c);
+}
+template <typename T, int R>
+SRTM_DEV void gloadv_f64(double (&a)[R], const T* __restrict__ p) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = (double)gld(p + r);
+}
+
+// Gradient statistics of window k (float64), added to Sw, Swx, Sy; the window's log-likelihood
+// term in *ll. (m, P): its prior; yk: its measurement; sfx, tin: its smoother-correction record
+// and its tile's incoming smoothed state (element type T).
+template <typename T, int NX, int NY>
+SRTM_DEV bool grad_window(const Model<double, NX, NY>& M, int L, const double (&m)[NX], const double (&P)[NX][NX],
+                          const double (&yk)[NY], const double (&R)[NY][NY], const T* __restrict__ src,
+                          const T* __restrict__ ti, double& ll, double (&Sw)[NX][NX], double (&Swx)[NX][NX],
+                          double (&Sy)[NY][NY]) {
+  constexpr int NN = NX * NX;
+  Window<double, NX, NY> w;
+  const bool ok = window_setup(M, L, m, P, yk, w);
+  double e[NY];
+  {
+    double Cb[NY][NX];
+    M.get(Cb, M.lay.Cbar);
+    double quad = 0.0;
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+      double t = yk[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) t = fma(-Cb[r][c], m[c], t);
+      e[r] = t;
+      quad += t * w.Se[r];
+    }
+    ll = -0.5 * (quad - log(det_small(w.Si)) + NY * 1.8378770664093453);  // log(2 pi)
+  }
+  // v = Et m_in + gt, W = Et P_in Et^T + St
+  double v[NX], W[NX][NX];
+  {
+    double Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
+    gload_f64(Et, src);
+    gloadv_f64(mi, ti);
+    gload_f64(Pi, ti + NX);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double t = (double)gld(src + NN + r);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) t = fma(Et[r][q], mi[q], t);
+      v[r] = t;
+    }
+    mm(Et, Pi, EP);
+    int o = NN + NX;
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        double t = (double)gld(src + o++);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = fma(EP[r][q], Et[c][q], t);
+        W[r][c] = t;
+        W[c][r] = t;
+      }
+  }
+  double A[NX][NX], Qm[NX][NX];
+  M.get(A, M.lay.A);
+  M.get(Qm, M.lay.Q);
+  // step i-1 quantities: U_{i-1}, P^f_{k,i-1,l}, m^f_{k,i-1}, c_{i-1}
+  double Up[NX][NY], PLp[NX][NX], mfp[NX], cp[NX][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    mfp[r] = w.mp[r];
+#pragma unroll
+    for (int c = 0; c < NY; ++c) {
+      Up[r][c] = w.V[r][c];
+      cp[r][c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) PLp[r][c] = w.Y1[r][c];
+  }
+#pragma unroll 1
+  for (int i = 1; i <= L; ++i) {
+    double ci[NX][NY], b[NX][NY], Kq[NX][NX];
+    M.get(ci, M.per_i_off(i) + M.lay.o_ci);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double t = ci[r][c];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = fma(-A[r][q], cp[q][c], t);
+        b[r][c] = t;
+      }
+    // K_i = Q (A^{l-i})^T - b_i Y2 (Y2 = S^{-1} U_l^T)
+    if (i < L) {
+      double As[NX][NX];
+      M.get(As, M.per_i_off(L - i) + M.lay.o_Ai);
+      mm_nt(Qm, As, Kq);
+    } else {
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NX; ++c) Kq[r][c] = Qm[r][c];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        double t = Kq[r][c];
+#pragma unroll
+        for (int q = 0; q < NY; ++q) t = fma(-b[r][q], w.Y2[q][c], t);
+        Kq[r][c] = t;
+      }
+    double bS[NX][NY], mu[NX], KW[NX][NX], msp[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NY; ++q) t = fma(b[r][q], symget(w.Si, q, c), t);
+        bS[r][c] = t;
+      }
+    mm(Kq, W, KW);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double t = 0.0, s2 = mfp[r];
+#pragma unroll
+      for (int q = 0; q < NY; ++q) t = fma(b[r][q], w.Se[q], t);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        t = fma(Kq[r][q], v[q], t);
+        s2 = fma(PLp[r][q], v[q], s2);
+      }
+      mu[r] = t;
+      msp[r] = s2;
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        double sw = mu[r] * mu[c], sx = mu[r] * msp[c];
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+          sw = fma(-bS[r][q], b[c][q], sw);
+          sx = fma(-bS[r][q], Up[c][q], sx);
+        }
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+          sw = fma(KW[r][q], Kq[c][q], sw);
+          sx = fma(KW[r][q], PLp[c][q], sx);
+        }
+        Sw[r][c] += sw;
+        Swx[r][c] += sx;
+      }
+    // step i's own blocks for the next step
+    if (i < L) {
+      double Pii[NX][NX];
+      window_step<double, NX, NY, true>(M, w, i, mfp, Pii, PLp);
+      window_U(M, w, i, Up);
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = 0; c < NY; ++c) cp[r][c] = ci[r][c];
+    }
+  }
+  // measurement residual: E[r] = R S^{-1} e - Z v, E[r r^T] - R = E[r]E[r]^T - R S^{-1} R + Z W Z^T
+  {
+    double RSi[NY][NY], Z[NY][NX], d[NY], ZW[NY][NX], Si[NY][NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) Si[r][c] = symget(w.Si, r, c);
+    mm(R, Si, RSi);
+    mm(R, w.Y2, Z);
+    mm(Z, W, ZW);
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < NY; ++q) t = fma(RSi[r][q], e[q], t);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) t = fma(-Z[r][q], v[q], t);
+      d[r] = t;
+    }
+#pragma unroll
+    for (int r = 0; r < NY; ++r)
+#pragma unroll
+      for (int c = 0; c < NY; ++c) {
+        double t = d[r] * d[c];
+#pragma unroll
+        for (int q = 0; q < NY; ++q) t = fma(-RSi[r][q], R[q][c], t);
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = fma(ZW[r][q], Z[c][q], t);
+        Sy[r][c] += t;
+      }
+  }
+  return ok;
+}
+
 template <typename T, int NX, int NY, bool GRAD, bool INP>
-SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst, InputView<T> in,
-                         const T* __restrict__ Rm, const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
+SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                         const double* __restrict__ cst64, InputView<T> in, const T* __restrict__ Rm,
+                         const T* __restrict__ m0, const T* __restrict__ P0, const T* __restrict__ carry,
                          const T* __restrict__ sfx, const T* __restrict__ tin, double* __restrict__ parts,
-                         int32_t* info, int64_t tile, int64_t nt) {
+                         int32_t* info, int64_t tile) {
   using SL = StatLayout<NX, NY>;
-  constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX), NR = SL::X0;  // reduced components
-  __shared__ double red[TILE / 64][NR];
-  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
+  constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX), NC = SL::SIZE;
+  static_assert(!(GRAD && INP), "the gradient is built without inputs");
+  __shared__ double red[TILE / 64][NC];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
   const bool valid = k < N;
   const int64_t kc = valid ? k : 0;
   double* part = parts + tile * SL::SIZE;
-  T m[NX], P[NX][NX], yk[NY];
-  load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
-  static_assert(!(GRAD && INP), "the gradient is built without inputs");
-  if constexpr (INP) {
-    T zL[NX];
-    window_meas<true>(M, y, kc, N, yk, zL);
-  } else {
-    gloadv(yk, y + kc * NY);
-  }
-  Window<T, NX, NY> w;
   int flag = 0;
-  if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
-  T e[NY];
-  double ll;
-  {
+  double ll = 0.0;
+  double Sw[NX][NX], Swx[NX][NX], Sy[NY][NY];
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = 0; c < NX; ++c) Sw[r][c] = Swx[r][c] = 0.0;
+#pragma unroll
+  for (int r = 0; r < NY; ++r)
+#pragma unroll
+    for (int c = 0; c < NY; ++c) Sy[r][c] = 0.0;
+  if constexpr (GRAD) {
+    const Model<double, NX, NY> M{cst64, make_const_layout(NX, NY, L)};
+    double m[NX], P[NX][NX], yk[NY], R[NY][NY];
+    if (kc == 0) {
+      gloadv_f64(m, m0);
+      gload_f64(P, P0);
+    } else {
+      gloadv_f64(m, carry + (kc - 1) * ST);
+      gload_f64(P, carry + (kc - 1) * ST + NX);
+    }
+    gloadv_f64(yk, y + kc * NY);
+    gload_f64(R, Rm);
+    if (!grad_window<T, NX, NY>(M, L, m, P, yk, R, sfx + kc * SF, tin + tile * ST, ll, Sw, Swx, Sy) && valid)
+      flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  } else {
+    const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
+    T m[NX], P[NX][NX], yk[NY];
+    load_prior<T, NX, NY>(carry, m0, P0, kc, m, P);
+    if constexpr (INP) {
+      T zL[NX];
+      window_meas<true>(M, y, kc, N, yk, zL);
+    } else {
+      gloadv(yk, y + kc * NY);
+    }
+    Window<T, NX, NY> w;
+    if (!window_setup(M, L, m, P, yk, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
     T Cb[NY][NX];
     load(Cb, M.cst + M.lay.Cbar);
     double quad = 0.0;
 #pragma unroll
     for (int r = 0; r < NY; ++r) {
-      T s = yk[r];
+      T t = yk[r];
 #pragma unroll
-      for (int c = 0; c < NX; ++c) s = my_fma(-Cb[r][c], m[c], s);
-      e[r] = s;
-      quad += (double)s * (double)w.Se[r];
+      for (int c = 0; c < NX; ++c) t = my_fma(-Cb[r][c], m[c], t);
+      quad += (double)t * (double)w.Se[r];
     }
-    const double logdetS = -log((double)det_small(w.Si));
-    ll = -0.5 * (quad + logdetS + NY * 1.8378770664093453);  // log(2 pi)
+    ll = -0.5 * (quad - log((double)det_small(w.Si)) + NY * 1.8378770664093453);  // log(2 pi)
   }
-  T S11[NX][NX], S10[NX][NX], SY[NY][NY];
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int c = 0; c < NX; ++c) S11[r][c] = S10[r][c] = T(0);
-#pragma unroll
-  for (int r = 0; r < NY; ++r)
-#pragma unroll
-    for (int c = 0; c < NY; ++c) SY[r][c] = T(0);
-  if constexpr (GRAD) {
-    // (v, W) of the smoother correction, from the window's record and its tile's incoming state
-    T v[NX], W[NX][NX];
-    {
-      const T* src = sfx + kc * SF;
-      const T* ti = tin + tile * ST;
-      T Et[NX][NX], mi[NX], Pi[NX][NX], EP[NX][NX];
-      gload(Et, src);
-      gloadv(mi, ti);
-      gload(Pi, ti + NX);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        T t = gld(src + NN + r);
-#pragma unroll
-        for (int q = 0; q < NX; ++q) t = my_fma(Et[r][q], mi[q], t);
-        v[r] = t;
-      }
-      mm(Et, Pi, EP);
-      int o = NN + NX;
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = r; c < NX; ++c) {
-          T t = gld(src + o++);
-#pragma unroll
-          for (int q = 0; q < NX; ++q) t = my_fma(EP[r][q], Et[c][q], t);
-          W[r][c] = t;
-          W[c][r] = t;
-        }
-    }
-    T A[NX][NX];
-    load(A, M.cst + M.lay.A);
-    T Pprev[NX][NX], PLprev[NX][NX], Uprev[NX][NY], msprev[NX];
-#pragma unroll 1
-    for (int i = 1; i <= L; ++i) {
-      T mf[NX], Pii[NX][NX], PiL[NX][NX];
-      window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
-      T ms[NX], Ps[NX][NX], PLW[NX][NX];
-      mm(PiL, W, PLW);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        T s = mf[r];
-#pragma unroll
-        for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
-        ms[r] = s;
-      }
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = r; c < NX; ++c) {
-          T t = Pii[r][c];
-#pragma unroll
-          for (int q = 0; q < NX; ++q) t = my_fma(PLW[r][q], PiL[c][q], t);
-          Ps[r][c] = t;
-          Ps[c][r] = t;
-        }
-#pragma unroll
-      for (int r = 0; r < NX; ++r)
-#pragma unroll
-        for (int c = 0; c < NX; ++c) S11[r][c] += my_fma(ms[r], ms[c], Ps[r][c]);
-      T Ui[NX][NY];
-      window_U(M, w, i, Ui);
-      if (i == 1) {  // across the window boundary
-        T Qq[NX][NX], Pm[NX][NX], G[NX][NX], mb[NX], PsG[NX][NX];
-        load(Qq, M.cst + M.lay.Q);
-        if (!lag1_boundary(A, Qq, m, P, ms, Ps, G, Pm, mb, PsG) && valid) flag |= SRTM_INFO_PRED_SINGULAR;
-#pragma unroll
-        for (int r = 0; r < NX; ++r)
-#pragma unroll
-          for (int c = 0; c < NX; ++c) S10[r][c] += my_fma(ms[r], mb[c], PsG[r][c]);
-        if (valid && k == 0) {  // E[x_0 x_0^T] = P0 + G (P^s_{1,1} - P^-) G^T + mb mb^T
-          T D[NX][NX], GD[NX][NX];
-#pragma unroll
-          for (int r = 0; r < NX; ++r)
-#pragma unroll
-            for (int c = 0; c < NX; ++c) D[r][c] = Ps[r][c] - Pm[r][c];
-          mm(G, D, GD);
-#pragma unroll
-          for (int r = 0; r < NX; ++r)
-#pragma unroll
-            for (int c = 0; c < NX; ++c) {
-              T t = my_fma(mb[r], mb[c], P[r][c]);
-#pragma unroll
-              for (int q = 0; q < NX; ++q) t = my_fma(GD[r][q], G[c][q], t);
-              part[SL::X0 + r * NX + c] = (double)t;
-            }
-        }
-      } else {  // within the window
-        T C[NX][NX];
-        lag1_within(M, w, i, A, Pprev, Uprev, PLW, PLprev, C);
-#pragma unroll
-        for (int r = 0; r < NX; ++r)
-#pragma unroll
-          for (int c = 0; c < NX; ++c) S10[r][c] += my_fma(ms[r], msprev[c], C[r][c]);
-      }
-      if (valid && k == N - 1 && i == L) {  // E[x_T x_T^T]
-#pragma unroll
-        for (int r = 0; r < NX; ++r)
-#pragma unroll
-          for (int c = 0; c < NX; ++c) part[SL::XT + r * NX + c] = (double)my_fma(ms[r], ms[c], Ps[r][c]);
-      }
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        msprev[r] = ms[r];
-#pragma unroll
-        for (int c = 0; c < NX; ++c) {
-          Pprev[r][c] = Pii[r][c];
-          PLprev[r][c] = PiL[r][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NY; ++c) Uprev[r][c] = Ui[r][c];
-      }
-    }
-    // measurement statistic: y_k - H xbar = R S^{-1} e - Z v, Cov = R - R S^{-1} R + Z W Z^T, Z = R S^{-1} U_l^T
-    {
-      T R[NY][NY], RSi[NY][NY], Z[NY][NX], d[NY], ZW[NY][NX];
-      gload(R, Rm);
-      mm(R, w.Si, RSi);
-      mm(R, w.Y2, Z);
-      mm(Z, W, ZW);
-#pragma unroll
-      for (int r = 0; r < NY; ++r) {
-        T s = T(0);
-#pragma unroll
-        for (int q = 0; q < NY; ++q) s = my_fma(RSi[r][q], e[q], s);
-#pragma unroll
-        for (int q = 0; q < NX; ++q) s = my_fma(-Z[r][q], v[q], s);
-        d[r] = s;
-      }
-#pragma unroll
-      for (int r = 0; r < NY; ++r)
-#pragma unroll
-        for (int c = 0; c < NY; ++c) {
-          T t = my_fma(d[r], d[c], R[r][c]);
-#pragma unroll
-          for (int q = 0; q < NY; ++q) t = my_fma(-RSi[r][q], R[q][c], t);
-#pragma unroll
-          for (int q = 0; q < NX; ++q) t = my_fma(ZW[r][q], Z[c][q], t);
-          SY[r][c] = t;
-        }
-    }
-  }
-  // tile sums of the reduced components (fixed order: butterfly per wave, then waves 0..3)
+  // tile sums (fixed order: butterfly per wave, then waves 0..3)
   auto comp = [&](int c) -> double {
     if (!valid) return 0.0;
     if (c == SL::LL) return ll;
-    if (c < SL::S10) return (double)S11[(c - SL::S11) / NX][(c - SL::S11) % NX];
-    if (c < SL::SY) return (double)S10[(c - SL::S10) / NX][(c - SL::S10) % NX];
-    return (double)SY[(c - SL::SY) / NY][(c - SL::SY) % NY];
+    if (c < SL::SWX) return Sw[(c - SL::SW) / NX][(c - SL::SW) % NX];
+    if (c < SL::SY) return Swx[(c - SL::SWX) / NX][(c - SL::SWX) % NX];
+    return Sy[(c - SL::SY) / NY][(c - SL::SY) % NY];
   };
-  const int ncomp = GRAD ? NR : 1;
+  const int ncomp = GRAD ? NC : 1;
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
+  for (int c = 0; c < NC; ++c) {
     if (c >= ncomp) break;
     const double s = wave_sum(comp(c));
     if (lane == 0) red[wv][c] = s;
@@ -3238,17 +3330,17 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
     for (int q = 1; q < TILE / 64; ++q) s += red[q][c];
     part[c] = s;
   }
-  (void)nt;
   if (flag && info) atomicOr(info, flag);
 }
 
-// One workgroup per sequence: sums the tile records in a fixed order and forms the outputs.
+// One workgroup per sequence: sums the tile records in a fixed order and forms the outputs
+// dF = Q^{-1} Swx, dQ = 1/2 Q^{-1} Sw Q^{-1}, dR = 1/2 R^{-1} Sy R^{-1}.
 template <typename T, int NX, int NY, bool GRAD>
-SRTM_DEV void stats_final_body(int64_t N, int L, int64_t nt, const T* __restrict__ Fm, const T* __restrict__ Qm,
-                               const T* __restrict__ Rm, const double* __restrict__ parts, T* __restrict__ ll_out,
-                               T* __restrict__ dF, T* __restrict__ dQ, T* __restrict__ dR, int32_t* info) {
+SRTM_DEV void stats_final_body(int64_t nt, const T* __restrict__ Qm, const T* __restrict__ Rm,
+                               const double* __restrict__ parts, T* __restrict__ ll_out, T* __restrict__ dF,
+                               T* __restrict__ dQ, T* __restrict__ dR, int32_t* info) {
   using SL = StatLayout<NX, NY>;
-  constexpr int NN = NX * NX, NR = SL::X0, G = 16;
+  constexpr int NR = SL::SIZE, G = 16;
   __shared__ double red[256][G];
   __shared__ double tot[NR];
   const int tid = threadIdx.x;
@@ -3279,64 +3371,42 @@ SRTM_DEV void stats_final_body(int64_t N, int L, int64_t nt, const T* __restrict
   if (tid != 0) return;
   if (ll_out) ll_out[0] = (T)tot[SL::LL];
   if constexpr (GRAD) {
-    double F[NX][NX], Q[NX][NX], R[NY][NY], Qi[NX][NX], Ri[NY][NY];
-    double S11[NX][NX], S10[NX][NX], S00[NX][NX], SY[NY][NY];
-    const double* first = parts;
-    const double* last = parts + (nt - 1) * SL::SIZE;
+    double Q[NX][NX], R[NY][NY], Qi[NX][NX], Ri[NY][NY], Sw[NX][NX], Swx[NX][NX], Sy[NY][NY];
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) {
-        F[r][c] = (double)Fm[r * NX + c];
         Q[r][c] = (double)Qm[r * NX + c];
-        S11[r][c] = tot[SL::S11 + r * NX + c];
-        S10[r][c] = tot[SL::S10 + r * NX + c];
-        S00[r][c] = first[SL::X0 + r * NX + c] + S11[r][c] - last[SL::XT + r * NX + c];
+        Sw[r][c] = tot[SL::SW + r * NX + c];
+        Swx[r][c] = tot[SL::SWX + r * NX + c];
       }
     for (int r = 0; r < NY; ++r)
       for (int c = 0; c < NY; ++c) {
         R[r][c] = (double)Rm[r * NY + c];
-        SY[r][c] = tot[SL::SY + r * NY + c];
+        Sy[r][c] = tot[SL::SY + r * NY + c];
       }
     symmetrize(Q);
     symmetrize(R);
+    symmetrize(Sw);
+    symmetrize(Sy);
     int flag = 0;
     if (!spd_inv(Q, Qi)) flag |= SRTM_INFO_PRED_SINGULAR;
     if (!spd_inv(R, Ri)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
-    const double Tn = (double)N * (double)L;
-    // dF = Q^{-1} (S10 - F S00)
-    double FS00[NX][NX], B[NX][NX], Sig[NX][NX], FS10t[NX][NX], tmp[NX][NX];
-    mm(F, S00, FS00);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) B[r][c] = S10[r][c] - FS00[r][c];
-    mm(Qi, B, tmp);
+    double tmp[NX][NX], G2[NX][NX];
+    mm(Qi, Swx, tmp);
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) dF[r * NX + c] = (T)tmp[r][c];
-    // Sig = S11 - F S10^T - S10 F^T + F S00 F^T - T Q
-    mm_nt(F, S10, FS10t);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) {
-        double t = S11[r][c] - FS10t[r][c] - FS10t[c][r] - Tn * Q[r][c];
-        for (int q = 0; q < NX; ++q) t += FS00[r][q] * F[c][q];
-        Sig[r][c] = t;
-      }
-    symmetrize(Sig);
-    double QS[NX][NX], G2[NX][NX];
-    mm(Qi, Sig, QS);
-    mm(QS, Qi, G2);
+    mm(Qi, Sw, tmp);
+    mm(tmp, Qi, G2);
     symmetrize(G2);
     for (int r = 0; r < NX; ++r)
       for (int c = 0; c < NX; ++c) dQ[r * NX + c] = (T)(0.5 * G2[r][c]);
-    double SR[NY][NY], RS[NY][NY], GR[NY][NY];
-    for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NY; ++c) SR[r][c] = SY[r][c] - (double)N * R[r][c];
-    symmetrize(SR);
-    mm(Ri, SR, RS);
+    double RS[NY][NY], GR[NY][NY];
+    mm(Ri, Sy, RS);
     mm(RS, Ri, GR);
     symmetrize(GR);
     for (int r = 0; r < NY; ++r)
       for (int c = 0; c < NY; ++c) dR[r * NY + c] = (T)(0.5 * GR[r][c]);
     if (flag && info) atomicOr(info, flag);
   }
-  (void)NN;
 }
 
 // ============================================================================ kernels
@@ -3347,7 +3417,7 @@ struct Seq {  // one sequence's typed arrays and scan plan
   const T *F, *Q, *H, *R, *m0, *P0, *y;
   T *ms_fast, *Ps_fast, *ms_slow, *Ps_slow, *mf_fast, *Pf_fast, *mf_slow, *Pf_slow, *Cs_fast;
   T *cst, *ftagg, *ftst, *utree, *carry, *btagg, *btst, *sfx, *tvblk, *tvel;
-  double *hand, *stats;
+  double *cst64, *hand, *stats;
   int64_t N, tile0;
   int L;
   ScanPlan plan;
@@ -3382,6 +3452,7 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   const WorkLayout wl = make_work_layout(NX, NY, d.L, d.N, sizeof(T), d.smoother != 0, d.B != nullptr, d.tv != 0);
   char* base = as_global(b.ws) + d.ws_off;
   q.cst = reinterpret_cast<T*>(base + wl.consts);
+  q.cst64 = reinterpret_cast<double*>(base + wl.consts64);
   q.hand = reinterpret_cast<double*>(base + wl.chain);
   q.ftagg = reinterpret_cast<T*>(base + wl.ftile_agg);
   q.ftst = reinterpret_cast<T*>(base + wl.ftile_state);
@@ -3404,7 +3475,7 @@ SRTM_DEV int tile_sequence(const Batch& b) { return b.tile_seq ? b.tile_seq[bloc
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(256) k_constants(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.hand, q.info);
+  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.cst64, q.hand, q.info);
 }
 
 // Workgroups 0 .. nseq-1 continue the level chains of the sequences; the others reduce tile
@@ -3494,8 +3565,8 @@ __global__ void __launch_bounds__(TILE) k_lag1(Batch b) {
 template <typename T, int NX, int NY, bool GRAD, bool INP>
 __global__ void __launch_bounds__(TILE) k_stats(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  stats_body<T, NX, NY, GRAD, INP>(q.y, q.N, q.L, q.cst, q.in, q.R, q.m0, q.P0, q.carry, q.sfx, q.btst, q.stats, q.info,
-                              (int64_t)blockIdx.x - q.tile0, q.plan.nt);
+  stats_body<T, NX, NY, GRAD, INP>(q.y, q.N, q.L, q.cst, q.cst64, q.in, q.R, q.m0, q.P0, q.carry, q.sfx, q.btst,
+                                   q.stats, q.info, (int64_t)blockIdx.x - q.tile0);
 }
 
 // Outputs: the given arrays (one sequence), or else, per sequence of a batch, its four output
@@ -3504,7 +3575,7 @@ template <typename T, int NX, int NY, bool GRAD>
 __global__ void __launch_bounds__(256) k_stats_final(Batch b, T* ll, T* dF, T* dQ, T* dR) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
   const bool own = ll == nullptr;
-  stats_final_body<T, NX, NY, GRAD>(q.N, q.L, q.plan.nt, q.F, q.Q, q.R, q.stats, own ? q.ms_fast : ll,
+  stats_final_body<T, NX, NY, GRAD>(q.plan.nt, q.Q, q.R, q.stats, own ? q.ms_fast : ll,
                                     own ? q.Ps_fast : dF, own ? q.ms_slow : dQ, own ? q.Ps_slow : dR, q.info);
 }
 

@@ -79,7 +79,7 @@ inline __host__ __device__ size_t constants_lds_bytes(int nx, int ny, int L) {
 
 // Workspace regions, byte offsets (256-byte aligned).
 struct WorkLayout {
-  size_t consts, chain, ftile_agg, ftile_state, utree, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel,
+  size_t consts, consts64, chain, ftile_agg, ftile_state, utree, carry, btile_agg, btile_state, sfx, stats, inp, tvblk, tvel,
       total;
 };
 
@@ -118,7 +118,7 @@ inline __host__ __device__ int tv_block_size(int nx, int ny, int L) { return mak
 inline __host__ __device__ constexpr int tv_elem_size(int nx) { return 3 * nx * nx; }
 
 // Scalars (float64) of one tile's log-likelihood / gradient record.
-inline __host__ __device__ constexpr int stat_size(int nx, int ny) { return 1 + 4 * nx * nx + ny * ny; }
+inline __host__ __device__ constexpr int stat_size(int nx, int ny) { return 1 + 2 * nx * nx + ny * ny; }
 
 // Per-window smoother-correction record: Et (nx^2), gt (nx), St (upper triangle).
 inline __host__ __device__ constexpr int sfx_stride(int nx) { return nx * nx + nx + nx * (nx + 1) / 2; }
@@ -140,6 +140,7 @@ inline __host__ __device__ WorkLayout make_work_layout(int nx, int ny, int L, in
   const size_t fagg = tv ? (size_t)(3 * nn + 2 * nx) : (size_t)(2 * nx);  // scalars per tile aggregate
   size_t o = 0;
   w.consts = o; o = align256(o + (size_t)c.total * esz);
+  w.consts64 = o; o = align256(o + (size_t)c.lev * sizeof(double));  // float64 copy of the model part
   w.chain = o; o = align256(o + 3 * nn * sizeof(double));  // float64 F, D, J handed between launches
   w.ftile_agg = o; o = align256(o + (size_t)nt * fagg * esz);
   w.ftile_state = o; o = align256(o + (size_t)nt * (nx + nn) * esz);

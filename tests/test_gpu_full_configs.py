@@ -6,10 +6,9 @@ bench.py times, on outputs the float64 CPU reference can compute one by one.
   captured in a HIP graph), and the float64 check run on the same rounded inputs: every window
   of every sequence against the reference smoother (1e-3 and 1e-8).
 * Gradient: 64 sequences of N = 2^14 windows (nx = 4, ny = 1, L = 10), float32, batched; the
-  log-likelihood of two sequences against the IMKF; for one sequence the float64 gradient against
-  central finite differences of the float64 reference (1e-6) and the float32 gradient against the
-  float64 one within the float32 conditioning bound of a gradient that is a small difference of
-  large sums (near the data's own parameters it nearly vanishes).
+  log-likelihood of two sequences against the IMKF; for one sequence the float32 gradient (from
+  the batch) and the float64 one against central finite differences of the float64 reference on
+  the rounded inputs (h = 1e-6), relative to the largest entry: 1e-3 (float32), 1e-6 (float64).
 """
 import numpy as np
 import pytest
@@ -105,27 +104,17 @@ def test_gradient_workload_full_size():
         print(f"[gpu] sequence {j}: ll {got:.6f} reference {ref_ll:.6f}", flush=True)
         assert abs(got - ref_ll) <= 2e-5 * max(1.0, abs(ref_ll))
         if j == 0:
-            # float64 path on the same (rounded) inputs against the reference's central differences
+            # float64 and float32 paths (same rounded inputs) against the reference's central differences
             t64 = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()  # noqa: E731
             ll64, dF64, dQ64, dR64 = srtm.loglik_grad(t64(r["A"]), t64(r["Q"]), t64(r["C"]), t64(r["R"]), 10,
                                                       t64(r["m0"]), t64(r["P0"]), t64(r["y"]))
             gA, gQ, gR = oracle.loglik_grad_fd(r["A"], r["Q"], r["C"], r["R"], 10, r["m0"], r["P0"], r["y"])
             o = b.outputs[j]
-            T, Nw = 10 << 14, 1 << 14
-            eps = float(np.finfo(np.float32).eps)
-            ex = 1.0  # bound on the entries of E[x x^T] of this stable model (stationary variance 0.5)
-            iq = np.linalg.norm(np.linalg.inv(r["Q"]), 2)
-            ir = np.linalg.norm(np.linalg.inv(r["R"]), 2)
-            # float32 conditioning: the gradients are differences of sums of T second moments, each
-            # carried with relative error ~eps, scaled by Q^{-1} (F), Q^{-1}..Q^{-1} (Q), R^{-1}..R^{-1} (R)
-            bound32 = {"F": iq * T * eps * ex, "Q": 0.5 * iq * iq * T * eps * ex, "R": 0.5 * ir * ir * Nw * eps * ex}
             for name, g32, g64, want in (("F", o["dF"], dF64, gA), ("Q", o["dQ"], dQ64, gQ), ("R", o["dR"], dR64, gR)):
-                g32 = g32.double().cpu().numpy()
-                g64 = g64.cpu().numpy()
                 scale = max(1.0, np.max(np.abs(want)))
-                e64 = np.max(np.abs(g64 - want)) / scale
-                e32 = np.max(np.abs(g32 - g64))
-                print(f"[gpu]   d/d{name}: float64 vs differences {e64:.2e} (scale {scale:.3g}); "
-                      f"float32 vs float64 {e32:.3g} (bound {bound32[name]:.3g})", flush=True)
+                e64 = np.max(np.abs(g64.cpu().numpy() - want)) / scale
+                e32 = np.max(np.abs(g32.double().cpu().numpy() - want)) / scale
+                print(f"[gpu]   d/d{name}: max rel err vs differences: float64 {e64:.2e}, float32 {e32:.2e} "
+                      f"(scale {scale:.3g})", flush=True)
                 assert e64 <= 1e-6, f"d/d{name} float64: {e64:.3e}"
-                assert e32 <= bound32[name], f"d/d{name} float32: {e32:.3e} > {bound32[name]:.3e}"
+                assert e32 <= 1e-3, f"d/d{name} float32: {e32:.3e}"

@@ -51,7 +51,7 @@ def test_loglik_and_gradient_against_finite_differences(nx, ny, L, N, seed, dtyp
     assert abs(float(ll) - ref_ll) <= tol_ll * max(1.0, abs(ref_ll))
     assert abs(float(ll_only) - ref_ll) <= tol_ll * max(1.0, abs(ref_ll))
     gA, gQ, gR = oracle.loglik_grad_fd(r["A"], r["Q"], r["C"], r["R"], L, r["m0"], r["P0"], r["y"])
-    tol = 1e-6 if dtype == torch.float64 else 2e-3
+    tol = 1e-6 if dtype == torch.float64 else 1e-3
     for name, got, want in (("F", dF, gA), ("Q", dQ, gQ), ("R", dR, gR)):
         got = got.double().cpu().numpy()
         scale = max(1.0, np.max(np.abs(want)))
