@@ -6,10 +6,13 @@ simulated from the model with a fixed seed. One step = one srtm_smooth call (fil
 scan, smoother scan, fast-rate recovery) producing smoothed fast- and slow-rate means
 and covariances, inputs already resident in HBM.
 
-Prints one JSON line. `roofline` is computed for the kernel with the largest measured
-time from HIP events recorded around every kernel on the launch stream; `cpu_baseline`
-times the float64 CPU reference (single BLAS thread) on a bounded prefix of the same
-workload.
+Prints one JSON line. `roofline` is the kernel with the largest measured time (HIP events
+recorded around every kernel on the launch stream): the call's algorithmic bytes (184.8 B per
+fast state in float64, 92.4 B in float32: y read, slow-filter carry written and read once,
+smoothed outputs written) over that kernel's average duration. `roofline_whole_path` is the same
+bytes over the whole call, the path's own fraction of HBM peak. The line also carries the other
+precision's figures, a short serving leg (Poisson arrivals at 2000/s, float32) with its p50/p99
+latency, and `cpu_baseline`, the float64 CPU oracle on the same workload with its host.
 """
 from __future__ import annotations
 
@@ -28,20 +31,14 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(nx, ny, L, N, esz):
-    """Bytes the method must move per call, by kernel and in total.
-
-    Whole path: read y; write and read the slow-filter carry (m, P) once; write smoothed
-    slow (m, P) and fast (m, P) outputs. Per kernel: the arrays it must read and write
-    (the carry is read once; both window neighbours come from the same array).
-    """
+    """Bytes one srtm_smooth call (smoothed fast and slow outputs, no filter outputs) must move:
+    read y; write and read the slow-filter carry (m, P) once (the forward and reverse scans are
+    sequentially dependent); write the smoothed slow (m, P) and fast (m, P) outputs: per window
+    ny + 2 st + st + L st scalars with st = nx + nx^2, i.e. 184.8 B (float64) and 92.4 B (float32)
+    per fast state at nx=4, ny=2, L=20. Workspace beyond the carry
+    (scan trees, tile records, the smoother-correction record) is overhead, not counted."""
     st = nx + nx * nx
-    sf = nx * nx + nx + nx * (nx + 1) // 2   # per-window smoother-correction record
-    total = N * (ny + 2 * st + st + L * st) * esz
-    return dict(total=total,
-                k_recover=N * (ny + st + sf + st + L * st) * esz,  # reads y, carry, record; writes outputs
-                k_fwd_bwd=N * (ny + st + sf) * esz,                # reads y; writes the carry and the record
-                k_fwd_final=N * (ny + st) * esz,                   # reads y; writes the carry
-                k_fwd_reduce=N * ny * esz)
+    return N * (ny + 2 * st + st + L * st) * esz
 
 
 def profiled_traffic(kernel, dtype):
@@ -62,7 +59,24 @@ def profiled_traffic(kernel, dtype):
     return None
 
 
-def cpu_baseline(model, y, n_windows, max_seconds=30.0):
+def host_record():
+    """The host the CPU baseline ran on: usable cores and the CPU model string."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return {"nproc": ncpu, "cpu_model": model}
+
+
+def cpu_baseline(model, y, n_windows):
     import numpy as np  # noqa: F401
     from threadpoolctl import threadpool_limits
     import oracle
@@ -72,8 +86,10 @@ def cpu_baseline(model, y, n_windows, max_seconds=30.0):
         oracle.srtm_smoother(model.A, model.Q, model.C, model.R, model.L, model.m0, model.P0, y[:n])
         dt = time.perf_counter() - t0
     return dict(value=n * model.L / dt, unit="fast-rate smoothed states/s", cores=1, kind="oracle",
-                sample=f"first {n} of {y.shape[0]} windows of the same workload (float64 sequential smoother "
-                       f"with dense windows, one BLAS thread), {dt:.2f} s")
+                sample=f"first {n} of {y.shape[0]} windows of the same workload: the oracle as it stands (float64 "
+                       f"sequential IMKF + dense (L nx)^2 window filter + smoother, numpy, one BLAS thread), "
+                       f"{dt:.2f} s; not the reduced per-window form",
+                host=host_record())
 
 
 def run_batched(args):
@@ -386,34 +402,44 @@ def run_gradient(args):
         "speedup_vs_single_calls": round(t_s / t_b, 2)}))
 
 
-def run_serving(args):
-    """Requests arriving as a Poisson process (nx=4, ny=2, L=10, N = round(10^U(2,5)) windows,
-    the headline model's construction), served with continuous batching under an HBM budget;
-    reports p50/p99 latency (arrival to observed completion) beside throughput."""
+def serve_poisson(rate, seconds, dtype, hbm_budget_gb=32.0, streams=4, seed=4040):
+    """Requests arriving as a Poisson process at `rate` per second for `seconds` (nx=4, ny=2, L=10,
+    N = round(10^U(2,5)) windows, the long-sequence model's construction), served with continuous
+    batching under an HBM budget. Returns the server's statistics: p50/p99 latency (arrival to
+    observed completion) and throughput."""
     import numpy as np
     import torch
     from paper_2410_00627_amd import serving, workloads as wl
-    dt = torch.float64 if (args.dtype or "f32") == "f64" else torch.float32
     torch.cuda.set_device(0)
     model = wl.random_stable_model(4, 2, 10, 2024, rho=0.99, q=0.01, r=0.05)
-    rng = np.random.default_rng(4040)
+    rng = np.random.default_rng(seed)
     pools = [wl.simulate(model, 100000, 4100 + j) for j in range(4)]
     reqs, t = [], 0.0
-    n = int(args.rate * args.serve_seconds)
+    n = int(rate * seconds)
     for j in range(n):
-        t += rng.exponential(1.0 / args.rate)
+        t += rng.exponential(1.0 / rate)
         N = int(round(10.0 ** rng.uniform(2.0, 5.0)))
         pool = pools[j % len(pools)]
         off = int(rng.integers(0, pool.shape[0] - N + 1))
         reqs.append(serving.Request(rid=j, arrival=t, F=model.A, Q=model.Q, H=model.C, R=model.R, L=10,
                                     m0=model.m0, P0=model.P0, y=pool[off:off + N]))
-    srv = serving.Server(4, 2, dt, hbm_budget=int(args.hbm_budget_gb * (1 << 30)), streams=args.streams,
+    srv = serving.Server(4, 2, dtype, hbm_budget=int(hbm_budget_gb * (1 << 30)), streams=streams,
                          max_batch=64, keep_outputs=False)
     # warm-up: a few requests through the same server (kernels loaded, allocator primed)
     serving.serve(srv, [serving.Request(rid=-1 - k, arrival=0.0, F=model.A, Q=model.Q, H=model.C, R=model.R,
                                         L=10, m0=model.m0, P0=model.P0, y=pools[0][:1000]) for k in range(4)])
     srv.batches_launched = 0
     st = serving.serve(srv, reqs)
+    st["offered_fast_states_per_s"] = st["fast_states"] / seconds
+    return st
+
+
+def run_serving(args):
+    """The serving workload alone: Poisson arrivals (default 2000/s for 60 s), continuous batching,
+    p50/p99 latency beside throughput."""
+    import torch
+    dt = torch.float64 if (args.dtype or "f32") == "f64" else torch.float32
+    st = serve_poisson(args.rate, args.serve_seconds, dt, args.hbm_budget_gb, args.streams)
     line = {"metric": "fast-rate smoothed states/sec served; p50/p99 latency",
             "value": round(st["fast_states_per_s"]), "unit": "fast-rate smoothed states/s", "n_gpus": 1,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -425,7 +451,7 @@ def run_serving(args):
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
             "max_ms": round(st["max_ms"], 3), "batches": st["batches"],
             "requests_per_batch": round(st["requests"] / max(st["batches"], 1), 2),
-            "offered_fast_states_per_s": round(st["fast_states"] / args.serve_seconds),
+            "offered_fast_states_per_s": round(st["offered_fast_states_per_s"]),
             "failed_requests": len(st["failed"])}
     print(json.dumps(line))
 
@@ -449,6 +475,10 @@ def main():
     ap.add_argument("--cpu-windows", type=int, default=None, help="windows timed on the CPU (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-events", action="store_true")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="headline: skip the second precision (float32 beside the default float64)")
+    ap.add_argument("--serving-seconds", type=float, default=3.0,
+                    help="headline: length of the serving leg whose p50/p99 join the line (0 = none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -469,19 +499,78 @@ def main():
     if args.workload == "gradient":
         return run_gradient(args)
     args.dtype = args.dtype or "f64"
-
-    import numpy as np
     import torch
-    from paper_2410_00627_amd import srtm, workloads as wl
-    from paper_2410_00627_amd.hip_events import EventArray
+    from paper_2410_00627_amd import workloads as wl
 
-    dtype = torch.float64 if args.dtype == "f64" else torch.float32
-    esz = 8 if dtype == torch.float64 else 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     model = wl.headline_model()
     N = args.N or wl.HEADLINE_N
     y = wl.simulate(model, N, seed=2024)
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, device=dev, dtype=torch.uint8).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] copy calibration: 3 x 256 MiB device copies", file=sys.stderr, flush=True)
+
+    main_dt = torch.float64 if args.dtype == "f64" else torch.float32
+    head = measure_headline(model, y, main_dt, args)
+    fast_states = N * model.L
+    res = {
+        "metric": "fast-rate smoothed states/sec (filter+smoother)",
+        "value": round(fast_states / (head["ms_per_step"] * 1e-3), 1),
+        "unit": "fast-rate smoothed states/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "one long SRTM sequence, nx=4 ny=2 L=20 N=%d (%d fast states), A=0.99*Haar, "
+                               "Q=0.01I, C Gaussian, R=0.05I" % (N, fast_states),
+                   "nx": model.nx, "ny": model.ny, "L": model.L, "N": N, "fast_states": fast_states},
+    }
+    res.update({k: v for k, v in head.items() if k != "ms_per_step"})
+    if not args.no_other_precision:
+        other = torch.float32 if main_dt == torch.float64 else torch.float64
+        o = measure_headline(model, y, other, args)
+        res["f32" if other == torch.float32 else "f64"] = {
+            "ms_per_step": round(o["ms_per_step"], 5),
+            "value": round(fast_states / (o["ms_per_step"] * 1e-3), 1),
+            "hbm_frac_whole_path": o["hbm_frac_whole_path"],
+            "roofline": o["roofline"], "per_kernel_ms": o["per_kernel_ms"]}
+    if args.serving_seconds > 0:
+        print(f"[bench] serving leg: {args.rate:g} req/s for {args.serving_seconds:g} s ...", file=sys.stderr,
+              flush=True)
+        st = serve_poisson(args.rate, args.serving_seconds, torch.float32)
+        res["serving"] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                          "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                          "requests": st["requests"], "failed": len(st["failed"]), "batches": st["batches"],
+                          "fast_states_per_s": round(st["fast_states_per_s"]),
+                          "offered_fast_states_per_s": round(st["offered_fast_states_per_s"]),
+                          "dtype": "f32",
+                          "workload": f"Poisson arrivals at {args.rate:g}/s for {args.serving_seconds:g} s, nx=4 "
+                                      "ny=2 L=10, N=round(10^U(2,5)), continuous batching, 32 GB budget, 4 streams"}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(model, y, args.cpu_windows or N)
+    print(json.dumps(res), flush=True)
+
+
+def measure_headline(model, y, dtype, args):
+    """Times srtm_smooth on the long sequence (inputs resident in HBM): args.steps calls between two
+    events after args.warmup untimed calls, then the same number of calls with HIP events recorded
+    around every kernel on the launch stream (per-kernel durations)."""
+    import ctypes
+    import torch
+    from paper_2410_00627_amd import srtm
+    from paper_2410_00627_amd.hip_events import EventArray
+
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    esz = 8 if dtype == torch.float64 else 4
+    tag = "f64" if dtype == torch.float64 else "f32"
+    N = y.shape[0]
     F, Q, H, R, m0, P0 = srtm.model_tensors(model, dev, dtype)
     yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dtype)
     nx, ny, L = model.nx, model.ny, model.L
@@ -492,15 +581,6 @@ def main():
     ws = torch.empty(srtm.workspace_size(nx, ny, L, N, dtype, True), device=dev, dtype=torch.uint8)
     info = torch.zeros(1, device=dev, dtype=torch.int32)
 
-    if args.copy_calibration:
-        src = torch.empty(256 << 20, device=dev, dtype=torch.uint8).fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print("[bench] copy calibration: 3 x 256 MiB device copies", file=sys.stderr, flush=True)
-
     def step(events=None):
         srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info, check=False, events=events)
 
@@ -509,9 +589,7 @@ def main():
     torch.cuda.synchronize()
     if int(info.item()) != 0:
         raise RuntimeError(f"numerical failure during warmup: info={int(info.item())}")
-    print(f"[bench] warmup done: N={N} dtype={args.dtype}", file=sys.stderr, flush=True)
-
-    # timed region: plain calls
+    print(f"[bench] warmup done: N={N} dtype={tag}", file=sys.stderr, flush=True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -523,11 +601,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_per_step = t0.elapsed_time(t1) / args.steps
-    fast_states = N * L
-    value = fast_states / (ms_per_step * 1e-3)
-    print(f"[bench] timed: {ms_per_step * 1e3:.1f} us/step ({wall:.3f} s wall)", file=sys.stderr, flush=True)
+    print(f"[bench] timed {tag}: {ms_per_step * 1e3:.1f} us/step ({wall:.3f} s wall)", file=sys.stderr, flush=True)
 
-    # per-kernel durations from events on the launch stream (separate region, same work)
     names = srtm.kernel_names(True)
     per_kernel = {n: 0.0 for n in names}
     prof_ms = None
@@ -547,38 +622,26 @@ def main():
     if int(info.item()) != 0:
         raise RuntimeError(f"numerical failure: info={int(info.item())}")
 
-    ab = algorithmic_bytes(nx, ny, L, N, esz)
+    alg = algorithmic_bytes(nx, ny, L, N, esz)
     dom = max(per_kernel, key=per_kernel.get) if not args.no_profile_events else "k_recover"
     dom_ms = per_kernel.get(dom, 0.0)
-    dom_bytes = ab.get(dom, None)
     roof = None
-    if dom_ms > 0 and dom_bytes:
-        ach = dom_bytes / (dom_ms * 1e-3) / 1e9
+    if dom_ms > 0:
+        ach = alg / (dom_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(dom, args.dtype),
-                "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 5)}
-    whole_gbs = ab["total"] / (ms_per_step * 1e-3) / 1e9
-    res = {
-        "metric": "fast-rate smoothed states/sec (filter+smoother)",
-        "value": round(value, 1),
-        "unit": "fast-rate smoothed states/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": "one long SRTM sequence, nx=4 ny=2 L=20 N=%d (%d fast states), A=0.99*Haar, "
-                               "Q=0.01I, C Gaussian, R=0.05I" % (N, fast_states),
-                   "nx": nx, "ny": ny, "L": L, "N": N, "fast_states": fast_states},
-        "hbm_frac_whole_path": round(whole_gbs / HBM_PEAK_GBS, 4),
-        "whole_path_algorithmic_GBps": round(whole_gbs, 1),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(dom, tag),
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(dom_ms, 5)}
+    whole = alg / (ms_per_step * 1e-3) / 1e9
+    return {
+        "ms_per_step": ms_per_step,
+        "roofline": roof,
+        "roofline_whole_path": {"bound": "hbm", "achieved": round(whole, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(whole / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_call": alg,
+                                "avg_call_ms": round(ms_per_step, 5)},
+        "hbm_frac_whole_path": round(whole / HBM_PEAK_GBS, 4),
         "per_kernel_ms": {k: round(v, 5) for k, v in per_kernel.items()},
         "profiled_ms_per_step": None if prof_ms is None else round(prof_ms, 5),
-        "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(model, y, args.cpu_windows or N)
-    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":
