@@ -456,12 +456,99 @@ def run_serving(args):
     print(json.dumps(line))
 
 
+def time_calls(fn, reps, warmup=2):
+    """Mean milliseconds per call of fn() over `reps` calls between two events, after `warmup`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def sequential_gpu(model, y, dtype, reps=1):
+    """The paper's sequential comparison method on the same GPU (srtm_smooth_sequential: IMKF
+    forwards and the sequential smoother backwards on one lane, no scan): ms per call."""
+    import torch
+    from paper_2410_00627_amd import srtm
+    dev = torch.device("cuda:0")
+    F, Q, H, R, m0, P0 = srtm.model_tensors(model, dev, dtype)
+    yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dtype)
+    N, nx, L = y.shape[0], model.nx, model.L
+    out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dtype),
+           "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dtype),
+           "ms_slow": torch.empty((N, nx), device=dev, dtype=dtype),
+           "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dtype)}
+    ws = torch.empty(srtm.workspace_size(nx, model.ny, L, N, dtype, True), device=dev, dtype=torch.uint8)
+    info = torch.zeros(1, device=dev, dtype=torch.int32)
+    ms = time_calls(lambda: srtm.smooth_sequential(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info,
+                                                   check=False), reps, warmup=1)
+    if int(info.item()) != 0:
+        raise RuntimeError(f"sequential comparator: numerical failure info={int(info.item())}")
+    return ms
+
+
+def run_fig1(args):
+    """The paper's comparison design (Sec. V, Fig. 1): parallel vs sequential filter+smoother runtime
+    as the number of windows grows, window length 16, on the same GPU. The paper's CSTR model is not
+    available; a stable random model of the long-sequence construction (nx=4, ny=2, A=0.99*Haar,
+    Q=0.01I, C Gaussian, R=0.05I) stands in for it. N log-spaced from 16 to 6000 windows."""
+    import numpy as np
+    import torch
+    from paper_2410_00627_amd import srtm, workloads as wl
+    dt = torch.float64 if (args.dtype or "f64") == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = 16
+    model = wl.random_stable_model(4, 2, L, 2024, rho=0.99, q=0.01, r=0.05)
+    Ns = [int(n) for n in np.unique(np.round(np.logspace(np.log10(16), np.log10(6000), 12)))]
+    ypool = wl.simulate(model, max(Ns), 2034)
+    rows = []
+    for N in Ns:
+        y = ypool[:N]
+        F, Q, H, R, m0, P0 = srtm.model_tensors(model, dev, dt)
+        yt = torch.as_tensor(y, dtype=torch.float64).to(dev, dt)
+        nx = model.nx
+        out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+               "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+               "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+               "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
+        ws = torch.empty(srtm.workspace_size(nx, 2, L, N, dt, True), device=dev, dtype=torch.uint8)
+        info = torch.zeros(1, device=dev, dtype=torch.int32)
+        t_par = time_calls(lambda: srtm.smooth(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws, info=info,
+                                               check=False), args.steps)
+        t_seq = time_calls(lambda: srtm.smooth_sequential(F, Q, H, R, L, m0, P0, yt, out=out, workspace=ws,
+                                                          info=info, check=False), max(3, args.steps // 10))
+        if int(info.item()) != 0:
+            raise RuntimeError(f"numerical failure at N={N}")
+        rows.append({"N": N, "parallel_ms": round(t_par, 4), "sequential_ms": round(t_seq, 4),
+                     "speedup": round(t_seq / t_par, 2)})
+        print(f"[bench] fig1 N={N}: parallel {t_par * 1e3:.1f} us, sequential {t_seq * 1e3:.1f} us",
+              file=sys.stderr, flush=True)
+    big = rows[-1]
+    print(json.dumps({
+        "metric": "filter+smoother runtime, parallel scan vs sequential, window length 16",
+        "value": big["speedup"], "unit": "x (sequential / parallel at the largest N)", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64" if dt == torch.float64 else "f32", "data": "synthetic",
+        "config": {"workload": "one sequence per point, nx=4 ny=2 L=16, A=0.99*Haar, Q=0.01I, C Gaussian, R=0.05I "
+                               "(stand-in for the paper's CSTR model); N log-spaced 16..6000 windows",
+                   "L": L, "N": Ns},
+        "points": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs", "tv", "lag1"],
+    ap.add_argument("--workload", choices=["headline", "batched", "serving", "gradient", "inputs", "tv", "lag1",
+                                           "fig1"],
                     default="headline",
                     help="headline: one long sequence (default); batched: 256 uneven sequences; "
                          "serving: Poisson arrivals with continuous batching")
@@ -475,6 +562,7 @@ def main():
     ap.add_argument("--cpu-windows", type=int, default=None, help="windows timed on the CPU (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-events", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true", help="headline: skip the sequential GPU comparator")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="headline: skip the second precision (float32 beside the default float64)")
     ap.add_argument("--serving-seconds", type=float, default=3.0,
@@ -498,6 +586,8 @@ def main():
         return run_tv(args)
     if args.workload == "gradient":
         return run_gradient(args)
+    if args.workload == "fig1":
+        return run_fig1(args)
     args.dtype = args.dtype or "f64"
     import torch
     from paper_2410_00627_amd import workloads as wl
@@ -540,6 +630,12 @@ def main():
             "value": round(fast_states / (o["ms_per_step"] * 1e-3), 1),
             "hbm_frac_whole_path": o["hbm_frac_whole_path"],
             "roofline": o["roofline"], "per_kernel_ms": o["per_kernel_ms"]}
+    if not args.no_sequential:
+        print("[bench] sequential comparator ...", file=sys.stderr, flush=True)
+        t_seq = sequential_gpu(model, y, main_dt)
+        res["sequential_gpu"] = {"ms_per_call": round(t_seq, 3), "value": round(fast_states / (t_seq * 1e-3), 1),
+                                 "speedup_of_parallel": round(t_seq / head["ms_per_step"], 1),
+                                 "kind": "the paper's sequential IMKF + smoother on one GPU lane (same outputs)"}
     if args.serving_seconds > 0:
         print(f"[bench] serving leg: {args.rate:g} req/s for {args.serving_seconds:g} s ...", file=sys.stderr,
               flush=True)

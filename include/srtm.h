@@ -135,6 +135,18 @@ srtm_status srtm_smooth_lag1(const srtm_shape* shape,
                              void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow, void* Cs_fast,
                              void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
+/* The paper's sequential comparison method (Sec. V: sequential IMKF and IMS) on the same GPU:
+ * one lane walks the windows forwards with the IMKF (eq. prediction, eq. m-h-k-l) and backwards
+ * with the sequential SRTM smoother (eq. seq-smoothing-all, eq. seq-smoothing-1), writing the same
+ * smoothed outputs as srtm_smooth (each may be NULL) with no associative scan. For measurement
+ * against the parallel path; work and depth are O(N). Workspace: srtm_workspace_size(shape, 1)
+ * bytes. Errors and info bits as srtm_smooth. */
+srtm_status srtm_smooth_sequential(const srtm_shape* shape,
+                                   const void* F, const void* Q, const void* H, const void* R,
+                                   const void* m0, const void* P0, const void* y,
+                                   void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
+                                   void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
 /* Profiling variant of srtm_smooth: identical work, and additionally records
  * events[2j] before and events[2j+1] after the j-th kernel it enqueues, j = 0 ..
  * srtm_kernel_count(1) - 1. `events` holds caller-created hipEvent_t handles and

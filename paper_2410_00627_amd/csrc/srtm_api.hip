@@ -184,6 +184,25 @@ srtm_status srtm_smooth_noalloc(const srtm_shape* shape, const void* F, const vo
   return run_common(shape, p, true, SRTM_NOALLOC_SCRATCH_BYTES, stream, nullptr, 0);
 }
 
+srtm_status srtm_smooth_sequential(const srtm_shape* shape, const void* F, const void* Q, const void* H,
+                                   const void* R, const void* m0, const void* P0, const void* y, void* ms_fast,
+                                   void* Ps_fast, void* ms_slow, void* Ps_slow, void* workspace,
+                                   size_t workspace_bytes, int32_t* info, void* stream) {
+  srtm_status s = check_shape(shape);
+  if (s != SRTM_OK) return s;
+  if (!F || !Q || !H || !R || !m0 || !P0 || !y || !workspace) return SRTM_E_NULL;
+  const void* all[] = {F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow};
+  for (const void* q : all)
+    if (!aligned(q, 16)) return SRTM_E_ALIGN;
+  if (!aligned(workspace, 256) || !aligned(info, 4)) return SRTM_E_ALIGN;
+  const size_t esz = shape->dtype == SRTM_F64 ? 8 : 4;
+  if (workspace_bytes < srtm::make_work_layout(shape->nx, shape->ny, shape->L, shape->N, esz, true).total)
+    return SRTM_E_WORKSPACE;
+  const srtm::Ptrs p{F, Q, H, R, m0, P0, y, ms_fast, Ps_fast, ms_slow, Ps_slow,
+                     nullptr, nullptr, nullptr, nullptr, workspace, info};
+  return srtm::dispatch(*shape, p, true, static_cast<hipStream_t>(stream), nullptr, 0, srtm::REC_SEQ);
+}
+
 srtm_status srtm_smooth_lag1(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,
                              const void* m0, const void* P0, const void* y, void* ms_fast, void* Ps_fast,
                              void* ms_slow, void* Ps_slow, void* Cs_fast, void* workspace, size_t workspace_bytes,

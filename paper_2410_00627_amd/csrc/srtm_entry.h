@@ -35,8 +35,9 @@ struct Ptrs {
 constexpr int TV_NX_MAX = 4;
 
 // What follows the scans: fast-rate recovery modes 1 (filter), 2 (smoother), 3 (both), the
-// log-likelihood alone (REC_LL) or the log-likelihood and its gradient (REC_GRAD).
-constexpr int REC_LL = 4, REC_GRAD = 5;
+// log-likelihood alone (REC_LL) or the log-likelihood and its gradient (REC_GRAD). REC_SEQ
+// selects the sequential comparator instead of the scans (srtm_smooth_sequential).
+constexpr int REC_LL = 4, REC_GRAD = 5, REC_SEQ = 6;
 
 // Largest input size of the kernels with known inputs.
 constexpr int NU_MAX = SRTM_MAX_NU;

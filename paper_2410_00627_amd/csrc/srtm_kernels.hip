@@ -2352,6 +2352,160 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
   if (flag && info) atomicOr(info, flag);
 }
 
+// ============================================================================ sequential comparator
+// The sequential route of Sec. III on the GPU, one lane per sequence and no scan: the IMKF walks
+// the windows forwards (eq. prediction and eq. m-h-k-l, written as block l of the window filter
+// of eq. update-fast) and stores the slow-rate carry (m^f_{k,l}, P^f_{k,l}); the sequential SRTM
+// smoother then walks them backwards (eq. smoothing-dynamic, eq. seq-smoothing-all): with the
+// smoothed state (m^s_{k+1,1}, P^s_{k+1,1}) of the window after, P^- = A P^f_{k,l} A^T + Q and
+// B = (P^-)^{-1} A, the correction v = B^T (m^s_{k+1,1} - A m^f_{k,l}), W = B^T (P^s_{k+1,1} - P^-) B
+// gives every fast step's smoothed blocks m^s_{k,i} = m^f_{k,i} + P^f_{k,i,l} v and
+// P^s_{k,i} = P^f_{k,i,i} + P^f_{k,i,l} W P^f_{k,i,l}^T, and block i = 1 is the state the window before
+// needs (eq. seq-smoothing-1). The per-window arithmetic is the parallel path's; only the order
+// of evaluation differs (a recursion instead of the two scans). This is the paper's sequential
+// comparison method (Sec. V), run on the same GPU.
+template <typename T, int NX, int NY>
+SRTM_DEV void seq_body(const T* __restrict__ y, int64_t N, int L, const T* __restrict__ cst,
+                       const T* __restrict__ m0, const T* __restrict__ P0, T* __restrict__ carry,
+                       T* __restrict__ ms_fast, T* __restrict__ Ps_fast, T* __restrict__ ms_slow,
+                       T* __restrict__ Ps_slow, int32_t* info) {
+  constexpr int NN = NX * NX, ST = NX + NN;
+  const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L)};
+  int flag = 0;
+  bool fin = true;
+  T m[NX], P[NX][NX];
+  gloadv(m, m0);
+  gload(P, P0);
+  symmetrize(P);
+#pragma unroll 1
+  for (int64_t k = 0; k < N; ++k) {  // forward: the IMKF
+    T yk[NY];
+    gloadv(yk, y + k * NY);
+    Window<T, NX, NY> w;
+    if (!window_setup(M, L, m, P, yk, w)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    T PiL[NX][NX];
+    window_step<T, NX, NY, false>(M, w, L, m, P, PiL);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) put_global(carry + k * ST + r, m[r]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) put_global(carry + k * ST + NX + r * NX + c, P[r][c]);
+  }
+  T A[NX][NX], Qm[NX][NX];
+  load(A, M.cst + M.lay.A);
+  load(Qm, M.cst + M.lay.Q);
+  T ms1[NX], Ps1[NX][NX];
+#pragma unroll 1
+  for (int64_t k = N - 1; k >= 0; --k) {  // backward: the sequential smoother
+    T yk[NY];
+    gloadv(yk, y + k * NY);
+    if (k == 0) {
+      gloadv(m, m0);
+      gload(P, P0);
+      symmetrize(P);
+    } else {
+      gloadv(m, carry + (k - 1) * ST);
+      gload(P, carry + (k - 1) * ST + NX);
+    }
+    Window<T, NX, NY> w;
+    if (!window_setup(M, L, m, P, yk, w)) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    T v[NX], W[NX][NX];
+    if (k == N - 1) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        v[r] = T(0);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) W[r][c] = T(0);
+      }
+    } else {
+      T mL[NX], PL[NX][NX], Pm[NX][NX], Pmi[NX][NX], B[NX][NX], d[NX], D[NX][NX], DB[NX][NX];
+      gloadv(mL, carry + k * ST);
+      gload(PL, carry + k * ST + NX);
+      sandwich(A, PL, Qm, Pm);
+      if (!spd_inv(Pm, Pmi)) flag |= SRTM_INFO_PRED_SINGULAR;
+      mm(Pmi, A, B);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T t = ms1[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) t = my_fma(-A[r][q], mL[q], t);
+        d[r] = t;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) D[r][c] = Ps1[r][c] - Pm[r][c];
+      }
+      mtv(B, d, v);
+      mm(D, B, DB);
+#pragma unroll
+      for (int r = 0; r < NX; ++r)
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(B[q][r], DB[q][c], t);
+          W[r][c] = t;
+          W[c][r] = t;
+        }
+    }
+#pragma unroll 1
+    for (int i = 1; i <= L; ++i) {
+      T mf[NX], Pii[NX][NX], PiL[NX][NX], ms[NX], Ps[NX][NX];
+      window_step<T, NX, NY, true>(M, w, i, mf, Pii, PiL);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        T s = mf[r];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) s = my_fma(PiL[r][q], v[q], s);
+        ms[r] = s;
+        T TW[NX];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          T t = T(0);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(PiL[r][q], W[q][c], t);
+          TW[c] = t;
+        }
+#pragma unroll
+        for (int c = r; c < NX; ++c) {
+          T t = Pii[r][c];
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = my_fma(TW[q], PiL[c][q], t);
+          Ps[r][c] = t;
+          Ps[c][r] = t;
+        }
+      }
+      fin = fin && finite_state(ms, Ps);
+      const int64_t o = k * L + (i - 1);
+      if (ms_fast) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) put_global(ms_fast + o * NX + r, ms[r]);
+      }
+      if (Ps_fast) {
+#pragma unroll
+        for (int r = 0; r < NN; ++r) put_global(Ps_fast + o * NN + r, Ps[r / NX][r % NX]);
+      }
+      if (i == 1) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          ms1[r] = ms[r];
+#pragma unroll
+          for (int c = 0; c < NX; ++c) Ps1[r][c] = Ps[r][c];
+        }
+        if (ms_slow) {
+#pragma unroll
+          for (int r = 0; r < NX; ++r) put_global(ms_slow + k * NX + r, ms[r]);
+        }
+        if (Ps_slow) {
+#pragma unroll
+          for (int r = 0; r < NN; ++r) put_global(Ps_slow + k * NN + r, Ps[r / NX][r % NX]);
+        }
+      }
+    }
+  }
+  if (!fin) flag |= SRTM_INFO_NONFINITE;
+  if (flag && info) atomicOr(info, flag);
+}
+
 // ============================================================================ per-window models
 // Time-varying model given per window: window k's F_k, Q_k drive its fast steps x_{k,1} ..
 // x_{k,l} (the step from x_{k-1,l} included) and H_k, R_k give y_k. What the time-invariant path
@@ -3554,6 +3708,22 @@ __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
                                 (int64_t)blockIdx.x - q.tile0);
 }
 
+// The constants block without the scan levels (the sequential comparator needs no scan), and the
+// sequential comparator itself: one lane per sequence.
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(256) k_constants_seq(Batch b) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+  constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, 0, q.cst, q.cst64, q.hand, q.info);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(64) k_seq(Batch b, int nseq) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= nseq) return;
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, s);
+  seq_body<T, NX, NY>(q.y, q.N, q.L, q.cst, q.m0, q.P0, q.carry, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info);
+}
+
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(TILE) k_lag1(Batch b) {
   const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
@@ -3727,6 +3897,18 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   return SRTM_OK;
 }
 
+// The sequential comparator (REC_SEQ): the constants, then one lane per sequence.
+template <typename T, int NX, int NY>
+srtm_status launch_seq(const Batch& b, const Launch& g, hipStream_t st) {
+  const size_t lds0 = constants_lds_bytes(NX, NY, g.max_L);
+  if (!allow_lds((const void*)k_constants_seq<T, NX, NY>, lds0)) return SRTM_E_HIP;
+  hipLaunchKernelGGL((k_constants_seq<T, NX, NY>), dim3(g.nseq), dim3(256), lds0, st, b);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_seq<T, NX, NY>), dim3((g.nseq + 63) / 64), dim3(64), 0, st, b, (int)g.nseq);
+  SRTM_CHECK_LAUNCH();
+  return SRTM_OK;
+}
+
 // Per-window (time-varying) model, one sequence: 6 launches for the smoother (k_tv_reduce,
 // k_tv_tiles, k_tv_fwd<1>, k_bwd_tiles, k_recover), 4 for the filter.
 template <typename T, int NX, int NY>
@@ -3804,6 +3986,10 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
   const int mode = lik_mode ? lik_mode : (smoother ? (want_f ? 3 : (want_s ? 2 : 0)) : (want_f ? 1 : 0));
   const LikOut<T> lo{static_cast<T*>(ll), static_cast<T*>(dF), static_cast<T*>(dQ), static_cast<T*>(dR)};
+  if (lik_mode == REC_SEQ) {
+    if (p.tv || p.B || p.Cs_fast || ev.ev || !smoother) return SRTM_E_UNSUPPORTED;
+    return launch_seq<T, NX, NY>(b, g, st);
+  }
   if (p.tv) {
     if (lik_mode || ev.ev) return SRTM_E_UNSUPPORTED;  // no log-likelihood or profiling form
     return launch_tv<T, NX, NY>(b, g, smoother, mode, st);

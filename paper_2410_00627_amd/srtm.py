@@ -73,6 +73,8 @@ def lib():
     L.srtm_smooth_tv.restype = ctypes.c_int
     L.srtm_smooth_lag1.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 13 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_smooth_lag1.restype = ctypes.c_int
+    L.srtm_smooth_sequential.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth_sequential.restype = ctypes.c_int
     L.srtm_smooth_noalloc.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 17
     L.srtm_smooth_noalloc.restype = ctypes.c_int
     L.srtm_smooth_profiled.argtypes = ([ctypes.POINTER(Shape)] + [_vp] * 16 +
@@ -311,6 +313,35 @@ def smooth(F, Q, H, R, L: int, m0, P0, y, *, fast: bool = True, slow: bool = Tru
         _check(code, "srtm_smooth_profiled")
     if check:
         _raise_info(info, "srtm_smooth")
+    out["info"] = info
+    return out
+
+
+def smooth_sequential(F, Q, H, R, L: int, m0, P0, y, *, out: Optional[Dict[str, torch.Tensor]] = None,
+                      workspace: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
+                      check: bool = True) -> Dict[str, torch.Tensor]:
+    """srtm_smooth_sequential: the same smoothed outputs as `smooth` by the sequential IMKF and
+    smoother on one GPU lane (the paper's sequential comparison method; no scan)."""
+    ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+    dev, dt = y.device, y.dtype
+    if out is None:
+        out = {"ms_fast": torch.empty((N, L, nx), device=dev, dtype=dt),
+               "Ps_fast": torch.empty((N, L, nx, nx), device=dev, dtype=dt),
+               "ms_slow": torch.empty((N, nx), device=dev, dtype=dt),
+               "Ps_slow": torch.empty((N, nx, nx), device=dev, dtype=dt)}
+    nbytes = workspace_size(nx, ny, L, N, dt, True)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, device=dev, dtype=torch.uint8)
+    if info is None:
+        info = torch.zeros(1, device=dev, dtype=torch.int32)
+    sh = shape_of(nx, ny, L, N, dt)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    args = ([_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")] +
+            [_ptr(out.get(k)) for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow")] +
+            [_ptr(workspace), workspace.numel(), _ptr(info), stream])
+    _check(lib().srtm_smooth_sequential(ctypes.byref(sh), *args), "srtm_smooth_sequential")
+    if check:
+        _raise_info(info, "srtm_smooth_sequential")
     out["info"] = info
     return out
 

@@ -187,6 +187,15 @@ def test_noalloc_validates_before_touching_the_device(L):
     assert "SCRATCH" in srtm.status_string(8).upper()
 
 
+def test_sequential_validates(L):
+    P = [ctypes.c_void_p(p) for p in FAKE]
+    sh = srtm.Shape(4, 2, 20, 1, 50)
+    assert L.srtm_smooth_sequential(ctypes.byref(sh), *P[:7], *([None] * 4), None, 1 << 30, None, None) == 1
+    assert L.srtm_smooth_sequential(ctypes.byref(sh), *P[:7], *([None] * 4), P[7], 16, None, None) == 6
+    assert L.srtm_smooth_sequential(ctypes.byref(srtm.Shape(5, 2, 20, 1, 50)), *P[:7], *([None] * 4), P[7],
+                                    1 << 30, None, None) == 4
+
+
 def test_python_binding_refuses_cpu_tensors():
     import torch
     from paper_2410_00627_amd import workloads as wl
