@@ -137,59 +137,46 @@ SRTM_DEV int level_chain(double* chain, T* __restrict__ cst, const ConstLayout& 
       }
     }
     wave_sync();
-    for (int q = e; q < 3 * NN; q += 64) {  // W F (and G3 = (W F)^T), G1 = F W, sym(W D)
+    // The three products of each phase are formed by three groups of lanes with the same
+    // instructions (operands chosen by pointer and stride, no divergent branches):
+    //   WF = W F, G1 = F W, XD = sym(W D);
+    for (int q = e; q < 3 * NN; q += 64) {
       const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
-      double acc = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += sW[er * NX + k] * F[k * NX + ec];
-        sWF[o] = acc;
-        rec[5 * NN + ec * NX + er] = acc;
-      } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sW[k * NX + ec];
-        rec[3 * NN + o] = acc;
-      } else {
-        double acc2 = 0.0;
-        for (int k = 0; k < NX; ++k) {
-          acc += sW[er * NX + k] * D[k * NX + ec];
-          acc2 += sW[ec * NX + k] * D[k * NX + er];
-        }
-        sXD[o] = 0.5 * (acc + acc2);
+      const double* X = part == 1 ? F : sW;
+      const double* Y = part == 0 ? F : (part == 1 ? sW : D);
+      double t1 = 0.0, t2 = 0.0;
+      for (int k = 0; k < NX; ++k) {
+        t1 += X[er * NX + k] * Y[k * NX + ec];
+        t2 += X[ec * NX + k] * Y[k * NX + er];
       }
+      double* dst = part == 0 ? sWF + o : (part == 1 ? rec + 3 * NN + o : sXD + o);
+      *dst = part == 2 ? 0.5 * (t1 + t2) : t1;
     }
     wave_sync();
-    for (int q = e; q < 3 * NN; q += 64) {  // G2 = F (W D), G4 = (W F)^T J, next F = F (W F)
+    //   G2 = F XD, G4 = (WF)^T J, next F = F WF; and G3 = (WF)^T;
+    for (int q = e; q < 3 * NN; q += 64) {
       const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
+      const double* X = part == 1 ? sWF : F;
+      const int xr = part == 1 ? 1 : NX, xk = part == 1 ? NX : 1;
+      const double* Y = part == 0 ? sXD : (part == 1 ? J : sWF);
       double acc = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sXD[k * NX + ec];
-        rec[4 * NN + o] = acc;
-      } else if (part == 1) {
-        for (int k = 0; k < NX; ++k) acc += sWF[k * NX + er] * J[k * NX + ec];
-        rec[6 * NN + o] = acc;
-      } else {
-        for (int k = 0; k < NX; ++k) acc += F[er * NX + k] * sWF[k * NX + ec];
-        nrec[o] = acc;
-      }
+      for (int k = 0; k < NX; ++k) acc += X[er * xr + k * xk] * Y[k * NX + ec];
+      double* dst = part == 0 ? rec + 4 * NN + o : (part == 1 ? rec + 6 * NN + o : nrec + o);
+      *dst = acc;
+      if (part == 0) rec[5 * NN + ec * NX + er] = sWF[o];
     }
     wave_sync();
-    for (int q = e; q < 2 * NN; q += 64) {  // next D = sym(G2 F^T) + D, next J = sym(G4 F) + J
+    //   next D = sym(G2 F^T) + D, next J = sym(G4 F) + J.
+    for (int q = e; q < 2 * NN; q += 64) {
       const int part = q / NN, o = q % NN, er = o / NX, ec = o % NX;
-      const double* G2 = rec + 4 * NN;
-      const double* G4 = rec + 6 * NN;
-      double acc = 0.0, acc2 = 0.0;
-      if (part == 0) {
-        for (int k = 0; k < NX; ++k) {
-          acc += G2[er * NX + k] * F[ec * NX + k];
-          acc2 += G2[ec * NX + k] * F[er * NX + k];
-        }
-        nrec[NN + o] = 0.5 * (acc + acc2) + D[o];
-      } else {
-        for (int k = 0; k < NX; ++k) {
-          acc += G4[er * NX + k] * F[k * NX + ec];
-          acc2 += G4[ec * NX + k] * F[k * NX + er];
-        }
-        nrec[2 * NN + o] = 0.5 * (acc + acc2) + J[o];
+      const double* X = rec + (part == 0 ? 4 : 6) * NN;
+      const int yk = part == 0 ? 1 : NX, yc = part == 0 ? NX : 1;
+      double t1 = 0.0, t2 = 0.0;
+      for (int k = 0; k < NX; ++k) {
+        t1 += X[er * NX + k] * F[k * yk + ec * yc];
+        t2 += X[ec * NX + k] * F[k * yk + er * yc];
       }
+      nrec[(1 + part) * NN + o] = 0.5 * (t1 + t2) + rec[(1 + part) * NN + o];
     }
     T* dst = cst + lay.lev + p * lay.lev_stride;  // the level record, as laid out in LDS
     for (int q = e; q < 7 * NN; q += 64) dst[q] = (T)rec[q];
@@ -1311,13 +1298,14 @@ SRTM_DEV int smoother_element(const MV& M, int L, const Window<T, NX, NY>& w, bo
 // ============================================================================ forward
 // Vector part of eq. op-filter for two runs of 2^p elements (level-p coefficients).
 template <typename T, int NX>
-SRTM_DEV void level_vec_combine(const T* __restrict__ lev, const ConstLayout& lay, const T (&di)[NX],
-                                const T (&ei)[NX], T (&dj)[NX], T (&ej)[NX]) {
+SRTM_DEV void level_vec_combine_g(const T* __restrict__ G, const T (&di)[NX], const T (&ei)[NX], T (&dj)[NX],
+                                  T (&ej)[NX]) {
+  constexpr int NN = NX * NX;
   T G1[NX][NX], G2[NX][NX], G3[NX][NX], G4[NX][NX];
-  load(G1, lev + lay.o_G1);
-  load(G2, lev + lay.o_G2);
-  load(G3, lev + lay.o_G3);
-  load(G4, lev + lay.o_G4);
+  load(G1, G);
+  load(G2, G + NN);
+  load(G3, G + 2 * NN);
+  load(G4, G + 3 * NN);
   T nd[NX], ne[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -1339,9 +1327,19 @@ SRTM_DEV void level_vec_combine(const T* __restrict__ lev, const ConstLayout& la
   }
 }
 
-// In-place up-sweep over the vector parts of the tile's elements (slots 0..TILE-1).
-template <typename T, int NX, int NY>
-SRTM_DEV void fwd_upsweep(const Model<T, NX, NY>& M, const Slots<T>& S, int tid) {
+// Vector part of eq. op-filter for two runs of 2^p elements (level-p coefficients G1..G4, which
+// follow each other in a level record).
+template <typename T, int NX>
+SRTM_DEV void level_vec_combine(const T* __restrict__ lev, const ConstLayout& lay, const T (&di)[NX],
+                                const T (&ei)[NX], T (&dj)[NX], T (&ej)[NX]) {
+  level_vec_combine_g<T, NX>(lev + lay.o_G1, di, ei, dj, ej);
+}
+
+// In-place up-sweep over the vector parts of the tile's elements (slots 0..TILE-1); `G` holds the
+// coefficient blocks G1..G4 of levels 0..LOG_TILE-1, 4 nx^2 scalars per level.
+template <typename T, int NX>
+SRTM_DEV void fwd_upsweep(const T* __restrict__ G, const Slots<T>& S, int tid) {
+  constexpr int NN = NX * NX;
 #pragma unroll 1
   for (int p = 0; p < LOG_TILE; ++p) {
     const int s = 1 << p;
@@ -1354,7 +1352,7 @@ SRTM_DEV void fwd_upsweep(const Model<T, NX, NY>& M, const Slots<T>& S, int tid)
         dj[r] = S.at(r, tid);
         ej[r] = S.at(NX + r, tid);
       }
-      level_vec_combine(M.level(p), M.lay, di, ei, dj, ej);
+      level_vec_combine_g<T, NX>(G + p * 4 * NN, di, ei, dj, ej);
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         S.at(r, tid) = dj[r];
@@ -1386,11 +1384,16 @@ SRTM_DEV void fwd_element(const Model<T, NX, NY>& M, const T (&yt)[NY], const T 
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L,
                               InputView<T> in, T* __restrict__ tagg, T* __restrict__ utree, int64_t tile) {
+  constexpr int NN = NX * NX;
   __shared__ T smem[2 * NX * TILE];
+  __shared__ T sG[LOG_TILE * 4 * NN];  // G1..G4 of levels 0..LOG_TILE-1
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{smem, TILE};
   const int tid = threadIdx.x;
   const int64_t k = tile * TILE + tid;
+  // The level coefficients were written by an earlier launch, possibly on another die: one load
+  // each, all in flight together, instead of a dependent round trip per level.
+  for (int q = tid; q < LOG_TILE * 4 * NN; q += TILE) sG[q] = gld(M.level(q / (4 * NN)) + M.lay.o_G1 + q % (4 * NN));
   T yt[NY], zL[NX], d[NX], e[NX];
   if constexpr (INP) {  // one pass over the window's inputs; later kernels read the record
     if (k < N) {
@@ -1416,7 +1419,7 @@ SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __res
     S.at(NX + r, tid) = e[r];
   }
   __syncthreads();
-  fwd_upsweep(M, S, tid);
+  fwd_upsweep<T, NX>(sG, S, tid);
   T* ut = utree + tile * (2 * NX * TILE);
 #pragma unroll
   for (int r = 0; r < 2 * NX; ++r) put_global(ut + r * TILE + tid, S.at(r, tid));
@@ -1862,11 +1865,15 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
   return ok;
 }
 
-// Per tile, down-sweep from the tile's exclusive state to every window: lane k ends with
-// the exclusive state (m^f_{k-1,l}, P^f_{k-1,l}) in (mprev, Pprev) and the inclusive one
-// (m^f_{k,l}, P^f_{k,l}) in (m, P). S needs TILE * max(2 nx, nx + nx^2) scalars.
-// (yt, zL): window k's measurement and input response (window_meas); `tree`: the tile's
-// up-sweep tree as the tile reduction left it (2 nx rows of TILE slots).
+// Per tile, every window's exclusive state (m^f_{k-1,l}, P^f_{k-1,l}) in (mprev, Pprev) and inclusive
+// state (m^f_{k,l}, P^f_{k,l}) in (m, P). Window j of the tile is preceded inside the tile by the
+// aligned runs of 2^p windows for the set bits p of j, and the tile's up-sweep tree holds the vector
+// part of each such run [a, a + 2^p) in slot a + 2^p - 1 (no higher level of the in-place tree writes
+// there); their matrix parts are the level records. So each lane folds, highest bit first, the
+// tile's incoming state with those runs (eq. op-filter with the left operand a state) and then with
+// its own element: the same combines as a tree down-sweep, with no exchange between lanes.
+// S needs TILE * 2 nx scalars; (yt, zL): window k's measurement and input response (window_meas);
+// `tree`: the tile's up-sweep tree as the tile reduction left it (2 nx rows of TILE slots).
 template <bool INP, typename T, int NX, int NY>
 SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T (&yt)[NY], const T (&zL)[NX],
                              int64_t k, const T* __restrict__ m0, const T* __restrict__ P0,
@@ -1878,48 +1885,34 @@ SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const
   for (int r = 0; r < 2 * NX; ++r) S.at(r, tid) = gld(tree + r * TILE + tid);
   T d[NX], e[NX];  // the window's own element, for the inclusive state
   fwd_element<INP>(M, yt, zL, d, e);
-  __syncthreads();
-  // down-sweep with states; slot TILE-1 <- the tile's exclusive state
-  if (tid == TILE - 1) {
-    T mt[NX], Pt[NX][NX];
-    gloadv(mt, tile_state);
-    gload(Pt, tile_state + NX);
-    st_state<T, NX>(S, tid, mt, Pt);
+  if (k == 0) {  // the prior itself
+    gloadv(mprev, m0);
+    gload(Pprev, P0);
+  } else {
+    gloadv(mprev, tile_state);
+    gload(Pprev, tile_state + NX);
   }
+  symmetrize(Pprev);
   __syncthreads();
-#pragma unroll 1
+#pragma unroll
   for (int p = LOG_TILE - 1; p >= 0; --p) {
-    const int s = 1 << p;
-    const bool act = ((tid + 1) & (2 * s - 1)) == 0;
-    T dl[NX], el[NX], ma[NX], Pa[NX][NX];
-    if (act) {
+    if ((tid >> p) & 1) {
+      const int node = ((tid >> (p + 1)) << (p + 1)) + (1 << p) - 1;
+      T dl[NX], el[NX];
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
-        dl[r] = S.at(r, tid - s);
-        el[r] = S.at(NX + r, tid - s);
+        dl[r] = S.at(r, node);
+        el[r] = S.at(NX + r, node);
       }
-      ld_state<T, NX>(S, tid, ma, Pa);
-    }
-    __syncthreads();
-    if (act) {
-      st_state<T, NX>(S, tid - s, ma, Pa);
       const T* lv = M.level(p);
       T F[NX][NX], D[NX][NX], J[NX][NX];
       load(F, lv + M.lay.o_F);
       load(D, lv + M.lay.o_D);
       load(J, lv + M.lay.o_J);
-      if (!state_combine(ma, Pa, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
-      st_state<T, NX>(S, tid, ma, Pa);
+      if (!state_combine(mprev, Pprev, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
     }
-    __syncthreads();
   }
   // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
-  ld_state<T, NX>(S, tid, mprev, Pprev);
-  if (k == 0) {  // the prior itself, not a rounded copy through the tree
-    gloadv(mprev, m0);
-    gload(Pprev, P0);
-    symmetrize(Pprev);
-  }
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     m[r] = mprev[r];
