@@ -182,6 +182,8 @@ def run_batched(args):
                        "sequences": len(problems), "fast_states": int(fast_states),
                        "windows": int(sum(pr[7].shape[0] for pr in problems))},
             "tuned": runner.describe(), "candidates": log,
+            "single_launch_set": min((e for e in log if e.get("mixed") and e["segments"] == 1),
+                                     key=lambda e: e["seconds"], default=None),
             "plain_per_sequence": {"ms_per_pass": round(t_plain * 1e3, 4),
                                    "value": round(fast_states / t_plain), "bitwise_equal_to_batched": same},
             "speedup_vs_plain": round(t_plain / t_batch, 2), "fp64_check": check64}

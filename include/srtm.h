@@ -322,6 +322,57 @@ srtm_status srtm_loglik_grad_batch(int32_t nx, int32_t ny, int32_t dtype, int32_
                                    const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
                                    void* stream);
 
+/* ------------------------------------------------------------------ mixed batches
+ * One sequence of a mixed batch: as srtm_seq, plus its own (nx, ny) (any supported pair),
+ * optionally its known inputs (B [nx][nu], u [N][L][nu] as in srtm_inputs; NULL and nu = 0
+ * without) or a per-window model (per_window = 1: F, Q, H, R laid out as in srtm_smooth_tv;
+ * nx <= 4; no inputs then). Every pointer is a DEVICE pointer of the batch's dtype, 16-byte
+ * aligned; any output may be NULL. Each sequence is the problem of Sec. III (with the input
+ * term of srtm_inputs, or the per-window model of srtm_smooth_tv). */
+typedef struct {
+  int32_t nx, ny;
+  int32_t L;
+  int32_t per_window; /* 0 or 1 */
+  int64_t N;
+  const void *F, *Q, *H, *R, *m0, *P0, *y;
+  const void *B, *u;
+  int32_t nu;
+  int32_t reserved; /* must be 0 */
+  void *ms_fast, *Ps_fast, *ms_slow, *Ps_slow;
+} srtm_seq_ex;
+
+/* srtm_batch_plan for a mixed batch: validates every sequence (as srtm_smooth, srtm_smooth_inputs
+ * or srtm_smooth_tv would), then returns the table and workspace sizes, the tile count and the
+ * largest window length, and writes the table when `table` is large enough (same contract as
+ * srtm_batch_plan; each descriptor also records its sequence's nx, ny and kind). */
+srtm_status srtm_batch_plan_ex(int32_t dtype, const srtm_seq_ex* seqs, int32_t nseq, void* table,
+                               size_t table_bytes, size_t* table_size, size_t* workspace_size, int64_t* ntiles,
+                               int32_t* max_L);
+
+/* Smooths every sequence of a mixed batch with ONE set of six kernel launches, whatever the mix
+ * of (nx, ny) pairs and kinds: each workgroup dispatches on its own sequence's descriptor and
+ * runs the same arithmetic on the same tiles as srtm_smooth (srtm_smooth_inputs, srtm_smooth_tv)
+ * on that sequence alone. The launches size their registers and LDS for the largest pair
+ * present, so a batch of one pair can be faster through srtm_smooth_batch. Arguments, checks
+ * and info words as in srtm_smooth_batch (`table_host` and `table_dev` from srtm_batch_plan_ex).
+ * Enqueues kernels only (capturable in a HIP graph). */
+srtm_status srtm_smooth_batch_ex(int32_t dtype, int32_t nseq, const void* table_host, const void* table_dev,
+                                 void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
+/* ------------------------------------------------------------------ HIP graphs
+ * Thin wrappers over HIP stream capture so that a caller holding only streams can record a
+ * sequence of calls (for instance srtm_smooth_batch_ex on several streams joined by events)
+ * once and replay it. srtm_graph_begin starts capturing `stream` (relaxed mode; the legacy
+ * default stream, NULL, cannot be captured: SRTM_E_NULL). srtm_graph_end ends the capture and
+ * instantiates it into *exec (an opaque handle owned by the caller). srtm_graph_launch enqueues
+ * one replay on `stream`; srtm_graph_destroy frees the handle. Captured calls must not allocate
+ * or synchronise; every srtm_* launch entry point qualifies. Errors: SRTM_E_HIP with the HIP
+ * error left for hipGetLastError. */
+srtm_status srtm_graph_begin(void* stream);
+srtm_status srtm_graph_end(void* stream, void** exec);
+srtm_status srtm_graph_launch(void* exec, void* stream);
+srtm_status srtm_graph_destroy(void* exec);
+
 /* Number of kernels one srtm_filter (smoother = 0) or srtm_smooth (smoother = 1) call
  * enqueues, and the name of kernel j of that sequence (static string, or NULL). */
 int32_t srtm_kernel_count(int32_t smoother);

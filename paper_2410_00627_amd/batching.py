@@ -1,11 +1,13 @@
 """Running many independent SRTM smoothing problems on one GPU.
 
-A `BatchRunner` groups the problems by state/measurement size (one batched library call per
-group and segment: kernels over sequences run one workgroup per sequence, kernels over tiles
-one workgroup per tile of any sequence), optionally splits each group into `segments`
-sub-batches of similar work, runs the sub-batches on one stream or on a stream each, and can
-capture the whole launch sequence in a HIP graph. `autotune` times candidate configurations
-on the actual problems and keeps the fastest. All arithmetic is in libsrtm's kernels.
+A `BatchRunner` either puts every problem into one mixed batch (`mixed=True`: one set of six
+launches whatever the mix of state/measurement sizes, inputs and per-window models; each
+workgroup dispatches on its sequence) or groups the problems by (nx, ny) with one batched call
+per group (kernels compiled for that pair alone). Either way it can split the work into
+`segments` sub-batches of similar size, run the sub-batches on one stream or a stream each, and
+record the whole launch sequence once as a HIP graph (through the library's graph entry points)
+to replay it. `autotune` times the candidate configurations on the actual problems and keeps
+the fastest. All arithmetic is in libsrtm's kernels.
 """
 from __future__ import annotations
 
@@ -30,34 +32,55 @@ def _balanced_split(idx: List[int], weights: List[float], parts: int) -> List[Li
     return [sorted(b) for b in bins if b]
 
 
+def _sizes(pr) -> Tuple[int, int]:
+    """(nx, ny) of a problem tuple (F [.., nx, nx], Q, H [.., ny, nx], ...)."""
+    return int(pr[0].shape[-1]), int(pr[2].shape[-2])
+
+
+def _plain(pr) -> bool:
+    """Time-invariant model without inputs (what the per-pair batch entry point takes)."""
+    return len(pr) == 8 and pr[0].dim() == 2
+
+
 class BatchRunner:
-    """problems: tuples (F, Q, H, R, L, m0, P0, y) of device tensors (one dtype and device)."""
+    """problems: tuples (F, Q, H, R, L, m0, P0, y), or (F, Q, H, R, L, m0, P0, y, B, u) with known
+    inputs, of device tensors (one dtype and device); F, Q, H, R of shape [N, ...] give a
+    per-window model."""
 
     def __init__(self, problems: Sequence[tuple], *, fast: bool = True, slow: bool = True, segments: int = 1,
-                 multi_stream: bool = False, graph: bool = False, outputs: Optional[List[Dict]] = None):
+                 multi_stream: bool = False, graph: bool = False, mixed: bool = False,
+                 outputs: Optional[List[Dict]] = None):
         self.problems = list(problems)
         self.fast, self.slow = fast, slow
         self.segments, self.multi_stream, self.use_graph = int(segments), bool(multi_stream), bool(graph)
+        self.mixed = bool(mixed)
         if not self.problems:
             raise srtm.SrtmError("no problems")
         self.device = self.problems[0][7].device
         groups: Dict[Tuple[int, int], List[int]] = {}
         for j, pr in enumerate(self.problems):
-            groups.setdefault((pr[0].shape[0], pr[2].shape[0]), []).append(j)
-        work = [float(pr[7].shape[0] * pr[4] * (pr[0].shape[0] + pr[0].shape[0] ** 2)) for pr in self.problems]
+            groups.setdefault((0, 0) if self.mixed else _sizes(pr), []).append(j)
+        work = []
+        for pr in self.problems:
+            nx = _sizes(pr)[0]
+            work.append(float(pr[7].shape[0] * pr[4] * (nx + nx * nx)))
         self.outputs: List[Dict] = outputs if outputs is not None else [None] * len(self.problems)
-        self.batches: List[srtm.Batch] = []
+        self.batches: List = []
         self.members: List[List[int]] = []
         for key in sorted(groups):
             for part in _balanced_split(groups[key], work, self.segments):
                 outs = None if outputs is None else [outputs[j] for j in part]
-                b = srtm.Batch([self.problems[j] for j in part], fast=fast, slow=slow, outputs=outs)
+                probs = [self.problems[j] for j in part]
+                if not self.mixed and all(_plain(pr) for pr in probs):
+                    b = srtm.Batch(probs, fast=fast, slow=slow, outputs=outs)
+                else:
+                    b = srtm.BatchEx(probs, fast=fast, slow=slow, outputs=outs)
                 self.batches.append(b)
                 self.members.append(part)
                 for j, o in zip(part, b.outputs):
                     self.outputs[j] = o
         self.streams = [torch.cuda.Stream(self.device) for _ in self.batches] if self.multi_stream else []
-        self.graph: Optional[torch.cuda.CUDAGraph] = None
+        self.graph: Optional[srtm.Graph] = None
 
     def _enqueue(self):
         if not self.multi_stream:
@@ -78,13 +101,11 @@ class BatchRunner:
             main.wait_event(e)
 
     def capture(self):
-        """Capture the launch sequence once (warmed up eagerly first) in a HIP graph."""
+        """Record the launch sequence once (warmed up eagerly first) as a HIP graph."""
         self._enqueue()
         torch.cuda.synchronize(self.device)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self._enqueue()
-        torch.cuda.synchronize(self.device)
+        g = srtm.Graph(self.device)
+        g.record(self._enqueue)
         self.graph = g
 
     def run(self):
@@ -105,8 +126,9 @@ class BatchRunner:
             b.check()
 
     def describe(self) -> dict:
-        return dict(segments=self.segments, multi_stream=self.multi_stream, graph=self.use_graph,
-                    launches=len(self.batches))
+        """The configuration; `calls` batched library calls, `launches` kernel launches per pass."""
+        return dict(segments=self.segments, multi_stream=self.multi_stream, graph=self.use_graph, mixed=self.mixed,
+                    calls=len(self.batches), launches=6 * len(self.batches))
 
 
 def time_runner(r: BatchRunner, reps: int = 5, warmup: int = 2) -> float:
@@ -130,31 +152,36 @@ _CACHE: Dict[tuple, dict] = {}
 
 
 def signature(problems) -> tuple:
-    nxs = tuple(sorted({pr[0].shape[0] for pr in problems}))
+    pairs = tuple(sorted({_sizes(pr) for pr in problems}))
+    kinds = tuple(sorted({(len(pr), pr[0].dim()) for pr in problems}))
     fast = sum(pr[7].shape[0] * pr[4] for pr in problems)
-    return (len(problems), nxs, int(fast).bit_length(), str(problems[0][7].dtype))
+    return (len(problems), pairs, kinds, int(fast).bit_length(), str(problems[0][7].dtype))
 
 
 def autotune(problems, *, fast: bool = True, slow: bool = True, segments=(1, 2, 4), reps: int = 5,
              log: Optional[list] = None) -> BatchRunner:
-    """Times every (segments, multi_stream, graph) candidate on these problems, all writing the
-    same output tensors, and returns the fastest runner. Results are cached per workload
-    signature (count, state sizes, magnitude of the work, dtype) for the process."""
+    """Times every (mixed, segments, multi_stream, graph) candidate on these problems, all writing
+    the same output tensors, and returns the fastest runner. Results are cached per workload
+    signature (count, sizes, kinds, magnitude of the work, dtype) for the process."""
     sig = signature(problems)
     outputs = None
     if sig in _CACHE:
         cfg = _CACHE[sig]
         return BatchRunner(problems, fast=fast, slow=slow, **cfg)
+    groups = len({_sizes(pr) for pr in problems})
     best, best_t = None, float("inf")
-    for seg, ms, gr in itertools.product(segments, (False, True), (False, True)):
-        if seg == 1 and ms and len({pr[0].shape[0] for pr in problems}) == 1:
-            continue  # one launch group: a stream per group changes nothing
-        r = BatchRunner(problems, fast=fast, slow=slow, segments=seg, multi_stream=ms, graph=gr, outputs=outputs)
+    for mx, seg, ms, gr in itertools.product((True, False), segments, (False, True), (False, True)):
+        if mx and groups == 1:
+            continue  # one (nx, ny) group: its own kernels (register and LDS use sized for it) cover it
+        if seg == 1 and ms and (mx or groups == 1):
+            continue  # a single call: a stream per call changes nothing
+        r = BatchRunner(problems, fast=fast, slow=slow, segments=seg, multi_stream=ms, graph=gr, mixed=mx,
+                        outputs=outputs)
         outputs = r.outputs
         t = time_runner(r, reps=reps)
         if log is not None:
             log.append(dict(r.describe(), seconds=t))
         if t < best_t:
             best, best_t = r, t
-    _CACHE[sig] = dict(segments=best.segments, multi_stream=best.multi_stream, graph=best.use_graph)
+    _CACHE[sig] = dict(segments=best.segments, multi_stream=best.multi_stream, graph=best.use_graph, mixed=best.mixed)
     return best

@@ -22,10 +22,13 @@ def pairs():
 
 
 def units():
-    """(source, extra flags, object name): the host ABI code, and the kernels once per pair."""
+    """(source, extra flags, object name): the host ABI code, the kernels once per pair, and the
+    mixed-pair batch kernels once per element type."""
     out = [("srtm_api.hip", [], "srtm_api.o")]
     for a, b in pairs():
         out.append(("srtm_kernels.hip", [f"-DSRTM_NX={a}", f"-DSRTM_NY={b}"], f"srtm_kernels_{a}_{b}.o"))
+    for t in ("double", "float"):  # the mixed-pair batch kernels, once per element type
+        out.append(("srtm_kernels.hip", [f"-DSRTM_MIXED_T={t}"], f"srtm_kernels_mixed_{t}.o"))
     return out
 
 FLAGS = [

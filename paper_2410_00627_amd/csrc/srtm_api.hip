@@ -312,6 +312,8 @@ srtm_status srtm_batch_plan(int32_t nx, int32_t ny, int32_t dtype, const srtm_se
     e.ws_off = off;
     e.L = q.L;
     e.smoother = 1;
+    e.nx = nx;
+    e.ny = ny;
     d[s] = e;
     const int64_t nt = (q.N + srtm::TILE - 1) / srtm::TILE;
     for (int64_t t = 0; t < nt; ++t) map[t0 + t] = s;
@@ -368,6 +370,152 @@ srtm_status srtm_loglik_grad_batch(int32_t nx, int32_t ny, int32_t dtype, int32_
                                    const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
                                    void* stream) {
   return batch_common(nx, ny, dtype, nseq, table_host, table_dev, workspace, workspace_bytes, info, stream, true);
+}
+
+// Validates one mixed-batch sequence; its workspace block size goes to *ws.
+static srtm_status check_seq_ex(int32_t dtype, const srtm_seq_ex& q, size_t* ws) {
+  const srtm_shape sh{q.nx, q.ny, q.L, (srtm_dtype)dtype, q.N};
+  srtm_status st = check_shape(&sh);
+  if (st != SRTM_OK) return st;
+  if (q.reserved != 0 || (q.per_window != 0 && q.per_window != 1)) return SRTM_E_SHAPE;
+  if (!q.F || !q.Q || !q.H || !q.R || !q.m0 || !q.P0 || !q.y) return SRTM_E_NULL;
+  const bool inputs = q.B || q.u || q.nu;
+  if (inputs) {
+    if (!q.B || !q.u) return SRTM_E_NULL;
+    if (q.nu < 1 || q.nu > SRTM_MAX_NU) return SRTM_E_SHAPE;
+  }
+  if (q.per_window) {
+    if (q.nx > srtm::TV_NX_MAX) return SRTM_E_UNSUPPORTED;
+    if (inputs) return SRTM_E_SHAPE;  // per-window models take no inputs
+  }
+  const void* all[] = {q.F, q.Q, q.H, q.R, q.m0, q.P0, q.y, q.B, q.u, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow};
+  for (const void* p : all)
+    if (!aligned(p, 16)) return SRTM_E_ALIGN;
+  const size_t esz = dtype == SRTM_F64 ? 8 : 4;
+  *ws = srtm::align256(srtm::make_work_layout(q.nx, q.ny, q.L, q.N, esz, true, inputs, q.per_window != 0).total);
+  return SRTM_OK;
+}
+
+srtm_status srtm_batch_plan_ex(int32_t dtype, const srtm_seq_ex* seqs, int32_t nseq, void* table, size_t table_bytes,
+                               size_t* table_size, size_t* workspace_size, int64_t* ntiles, int32_t* max_L) {
+  if (!seqs || !table_size || !workspace_size || !ntiles || !max_L) return SRTM_E_NULL;
+  if (dtype != SRTM_F32 && dtype != SRTM_F64) return SRTM_E_DTYPE;
+  if (nseq < 1) return SRTM_E_SHAPE;
+  int64_t tiles = 0;
+  size_t ws = 0;
+  int32_t lmax = 1;
+  for (int32_t s = 0; s < nseq; ++s) {
+    size_t w = 0;
+    const srtm_status st = check_seq_ex(dtype, seqs[s], &w);
+    if (st != SRTM_OK) return st;
+    tiles += (seqs[s].N + srtm::TILE - 1) / srtm::TILE;
+    ws += w;
+    if (seqs[s].L > lmax) lmax = seqs[s].L;
+  }
+  if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
+  const size_t map_off = srtm::batch_tile_map_offset(nseq);
+  const size_t need = map_off + (size_t)tiles * sizeof(int32_t);
+  *table_size = need;
+  *workspace_size = ws;
+  *ntiles = tiles;
+  *max_L = lmax;
+  if (!table || table_bytes < need) return SRTM_OK;
+  srtm::SeqDesc* d = static_cast<srtm::SeqDesc*>(table);
+  int32_t* map = reinterpret_cast<int32_t*>(static_cast<char*>(table) + map_off);
+  int64_t t0 = 0;
+  size_t off = 0;
+  for (int32_t s = 0; s < nseq; ++s) {
+    const srtm_seq_ex& q = seqs[s];
+    srtm::SeqDesc e{};
+    e.F = q.F; e.Q = q.Q; e.H = q.H; e.R = q.R; e.m0 = q.m0; e.P0 = q.P0; e.y = q.y;
+    e.ms_fast = q.ms_fast; e.Ps_fast = q.Ps_fast; e.ms_slow = q.ms_slow; e.Ps_slow = q.Ps_slow;
+    e.N = q.N;
+    e.tile0 = t0;
+    e.ws_off = off;
+    e.L = q.L;
+    e.smoother = 1;
+    e.B = q.B;
+    e.u = q.u;
+    e.nu = q.B ? q.nu : 0;
+    e.tv = q.per_window;
+    e.nx = q.nx;
+    e.ny = q.ny;
+    d[s] = e;
+    const int64_t nt = (q.N + srtm::TILE - 1) / srtm::TILE;
+    for (int64_t t = 0; t < nt; ++t) map[t0 + t] = s;
+    t0 += nt;
+    size_t w = 0;
+    check_seq_ex(dtype, q, &w);
+    off += w;
+  }
+  return SRTM_OK;
+}
+
+srtm_status srtm_smooth_batch_ex(int32_t dtype, int32_t nseq, const void* table_host, const void* table_dev,
+                                 void* workspace, size_t workspace_bytes, int32_t* info, void* stream) {
+  if (!table_host || !table_dev || !workspace) return SRTM_E_NULL;
+  if (dtype != SRTM_F32 && dtype != SRTM_F64) return SRTM_E_DTYPE;
+  if (nseq < 1) return SRTM_E_SHAPE;
+  if (!aligned(table_dev, 16) || !aligned(workspace, 256) || !aligned(info, 4)) return SRTM_E_ALIGN;
+  const size_t esz = dtype == SRTM_F64 ? 8 : 4;
+  const srtm::SeqDesc* d = static_cast<const srtm::SeqDesc*>(table_host);
+  const int32_t* map =
+      reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) + srtm::batch_tile_map_offset(nseq));
+  int64_t tiles = 0;
+  int32_t lmax = 1;
+  for (int32_t s = 0; s < nseq; ++s) {
+    const srtm_shape sh{d[s].nx, d[s].ny, d[s].L, (srtm_dtype)dtype, d[s].N};
+    srtm_status st = check_shape(&sh);
+    if (st != SRTM_OK) return st;
+    if (d[s].tile0 != tiles || d[s].smoother != 1 || d[s].Cs_fast) return SRTM_E_SHAPE;
+    const bool inputs = d[s].B != nullptr;
+    if (inputs != (d[s].u != nullptr) || (inputs ? (d[s].nu < 1 || d[s].nu > SRTM_MAX_NU) : d[s].nu != 0))
+      return SRTM_E_SHAPE;
+    if (d[s].tv != 0 && (d[s].tv != 1 || inputs || d[s].nx > srtm::TV_NX_MAX)) return SRTM_E_SHAPE;
+    const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;
+    for (int64_t t = 0; t < nt; ++t)
+      if (map[tiles + t] != s) return SRTM_E_SHAPE;
+    const size_t end =
+        d[s].ws_off + srtm::make_work_layout(d[s].nx, d[s].ny, d[s].L, d[s].N, esz, true, inputs, d[s].tv != 0).total;
+    if (d[s].ws_off % 256 != 0 || end > workspace_bytes) return SRTM_E_WORKSPACE;
+    tiles += nt;
+    if (d[s].L > lmax) lmax = d[s].L;
+  }
+  if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == SRTM_F64 ? srtm::run_mixed_double(d, table_dev, nseq, tiles, lmax, workspace, info, st)
+                           : srtm::run_mixed_float(d, table_dev, nseq, tiles, lmax, workspace, info, st);
+}
+
+srtm_status srtm_graph_begin(void* stream) {
+  if (!stream) return SRTM_E_NULL;
+  return hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeRelaxed) == hipSuccess
+             ? SRTM_OK
+             : SRTM_E_HIP;
+}
+
+srtm_status srtm_graph_end(void* stream, void** exec) {
+  if (!stream || !exec) return SRTM_E_NULL;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || !g) return SRTM_E_HIP;
+  hipGraphExec_t e = nullptr;
+  const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (r != hipSuccess || !e) return SRTM_E_HIP;
+  *exec = e;
+  return SRTM_OK;
+}
+
+srtm_status srtm_graph_launch(void* exec, void* stream) {
+  if (!exec) return SRTM_E_NULL;
+  return hipGraphLaunch(static_cast<hipGraphExec_t>(exec), static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SRTM_OK
+             : SRTM_E_HIP;
+}
+
+srtm_status srtm_graph_destroy(void* exec) {
+  if (!exec) return SRTM_E_NULL;
+  return hipGraphExecDestroy(static_cast<hipGraphExec_t>(exec)) == hipSuccess ? SRTM_OK : SRTM_E_HIP;
 }
 
 static srtm_status lik_common(const srtm_shape* shape, const void* F, const void* Q, const void* H, const void* R,

@@ -1,6 +1,7 @@
 // Host-side interface between the C-ABI code (srtm_api.hip) and the kernel translation units.
 // srtm_kernels.hip is compiled once per supported (nx, ny) pair (-DSRTM_NX, -DSRTM_NY); each
-// object defines that pair's run_pair_<nx>_<ny> and run_batch_pair_<nx>_<ny>.
+// object defines that pair's run_pair_<nx>_<ny> and run_batch_pair_<nx>_<ny>. It is compiled
+// once more per element type (-DSRTM_MIXED_T=float / double) for the mixed-pair batches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,5 +51,13 @@ constexpr int NU_MAX = SRTM_MAX_NU;
                                        void* ws, int32_t* info, hipStream_t st, bool grad);
 SRTM_PAIRS(SRTM_PAIR_DECL)
 #undef SRTM_PAIR_DECL
+
+struct SeqDesc;
+// Mixed-pair batches (srtm_smooth_batch_ex): one object per element type. `host` is the host
+// copy of the validated table, `table_dev` its device copy.
+srtm_status run_mixed_double(const SeqDesc* host, const void* table_dev, int nseq, int64_t ntiles, int max_L,
+                             void* ws, int32_t* info, hipStream_t st);
+srtm_status run_mixed_float(const SeqDesc* host, const void* table_dev, int nseq, int64_t ntiles, int max_L,
+                            void* ws, int32_t* info, hipStream_t st);
 
 }  // namespace srtm

@@ -197,13 +197,23 @@ SRTM_DEV int level_chain(double* chain, T* __restrict__ cst, const ConstLayout& 
 constexpr int CHAIN_SPLIT = LOG_TILE + 2;
 static_assert(CHAIN_SPLIT >= LOG_TILE, "the tile reductions read levels below LOG_TILE");
 
+// Dynamic LDS of the tile-reduction launch: the larger of a tile reduction's slots and level
+// coefficients and a level chain's float64 scratch.
+template <typename T, int NX>
+constexpr size_t fwd_reduce_lds_bytes() {
+  constexpr size_t red = sizeof(T) * (size_t)(2 * NX * TILE + LOG_TILE * 4 * NX * NX);
+  constexpr size_t chn = sizeof(double) * (size_t)(19 * NX * NX);
+  return red > chn ? red : chn;
+}
+
 // The rest of the level chain (levels CHAIN_SPLIT .. nlev-1), continued from the handed-over
 // Theta(2^CHAIN_SPLIT). The wave runs at raised priority: it shares its SIMD with reductions.
 template <typename T, int NX, int NY>
 SRTM_DEV void chain_tail_body(T* __restrict__ cst, const double* __restrict__ hand, int L, int nlev,
                               int32_t* info) {
   constexpr int NN = NX * NX;
-  __shared__ double chain[19 * NN];
+  extern __shared__ char smraw[];
+  double* chain = reinterpret_cast<double*>(smraw);  // 19 nx^2 (fwd_reduce_lds_bytes)
   const int tid = threadIdx.x;
   if (tid >= 64 || nlev <= CHAIN_SPLIT) return;
   __builtin_amdgcn_s_setprio(3);
@@ -1385,8 +1395,9 @@ template <bool INP, typename T, int NX, int NY>
 SRTM_DEV void fwd_reduce_body(const T* __restrict__ y, int64_t N, const T* __restrict__ cst, int L,
                               InputView<T> in, T* __restrict__ tagg, T* __restrict__ utree, int64_t tile) {
   constexpr int NN = NX * NX;
-  __shared__ T smem[2 * NX * TILE];
-  __shared__ T sG[LOG_TILE * 4 * NN];  // G1..G4 of levels 0..LOG_TILE-1
+  extern __shared__ char smraw[];
+  T* smem = reinterpret_cast<T*>(smraw);  // 2 nx TILE slots, then
+  T* sG = smem + 2 * NX * TILE;           // G1..G4 of levels 0..LOG_TILE-1 (fwd_reduce_lds_bytes)
   const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
   const Slots<T> S{smem, TILE};
   const int tid = threadIdx.x;
@@ -3617,33 +3628,95 @@ SRTM_DEV Seq<T, NX, NY> seq_view(const Batch& b, int s) {
   return q;
 }
 
-SRTM_DEV int tile_sequence(const Batch& b) { return b.tile_seq ? b.tile_seq[blockIdx.x] : 0; }
+SRTM_DEV int tile_sequence(const Batch& b, int64_t bid) { return b.tile_seq ? b.tile_seq[bid] : 0; }
+SRTM_DEV int tile_sequence(const Batch& b) { return tile_sequence(b, blockIdx.x); }
 
+// Stage bodies of the smoothing launches, for workgroup `bid` of the launch; the kernels below
+// wrap them for one (nx, ny) pair, the mixed-pair kernels dispatch to them per workgroup.
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(256) k_constants(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+SRTM_DEV void kb_constants(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, (int)bid);
   constants_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.L, q.plan.nlev, q.cst, q.cst64, q.hand, q.info);
 }
 
 // Workgroups 0 .. nseq-1 continue the level chains of the sequences; the others reduce tile
-// blockIdx.x - nseq of the call.
+// bid - nseq of the call.
 template <typename T, int NX, int NY, bool INP>
-__global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b, int nseq) {
-  if ((int)blockIdx.x < nseq) {
-    const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+SRTM_DEV void kb_fwd_reduce(const Batch& b, int64_t bid, int nseq) {
+  if (bid < nseq) {
+    const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, (int)bid);
     chain_tail_body<T, NX, NY>(q.cst, q.hand, q.L, q.plan.nlev, q.info);
     return;
   }
-  const int64_t t = (int64_t)blockIdx.x - nseq;
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, b.tile_seq ? b.tile_seq[t] : 0);
+  const int64_t t = bid - nseq;
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b, t));
   fwd_reduce_body<INP, T, NX, NY>(q.y, q.N, q.cst, q.L, q.in, q.ftagg, q.utree, t - q.tile0);
 }
 
 template <typename T, int NX, int NY>
-__global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
+SRTM_DEV void kb_fwd_tiles(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, (int)bid);
   fwd_tiles_body<T, NX, NY>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.plan.nlev, q.cst, q.L, q.m0, q.P0,
                             q.ftst, q.info);
+}
+
+template <typename T, int NX, int NY, bool INP>
+SRTM_DEV void kb_fwd_bwd(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b, bid));
+  fwd_bwd_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.utree, q.carry, q.mf_slow, q.Pf_slow,
+                               q.btagg, q.sfx, q.info, bid - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+SRTM_DEV void kb_bwd_tiles(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, (int)bid);
+  bwd_tiles_body<T, NX, NY>(q.btagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.btst);
+}
+
+template <typename T, int NX, int NY>
+SRTM_DEV void kb_tv_reduce(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b, bid));
+  tv_reduce_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.y, q.N, q.L, q.tvblk, q.tvel, q.ftagg, q.info, bid - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+SRTM_DEV void kb_tv_tiles(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, (int)bid);
+  tv_tiles_body<T, NX>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.m0, q.P0, q.ftst, q.info);
+}
+
+template <typename T, int NX, int NY, bool SMOOTH>
+SRTM_DEV void kb_tv_fwd(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b, bid));
+  tv_fwd_body<T, NX, NY, SMOOTH>(q.F, q.Q, q.H, q.y, q.N, q.L, q.tvblk, q.tvel, q.m0, q.P0, q.ftst, q.carry,
+                                 q.mf_slow, q.Pf_slow, q.btagg, q.sfx, q.info, bid - q.tile0);
+}
+
+// MODE 1: filter outputs only; 2: smoother outputs; 3: both. Fast-rate outputs take all L
+// steps; with only the slow smoothed state requested, step 1 suffices.
+template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
+SRTM_DEV void kb_recover(const Batch& b, int64_t bid) {
+  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b, bid));
+  const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
+  if (!fast && !q.ms_slow && !q.Ps_slow) return;
+  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst, q.in, q.F, q.Q, q.m0,
+                                         q.P0, q.carry, q.sfx, q.btst, q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast,
+                                         q.ms_slow, q.Ps_slow, q.info, bid - q.tile0);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(256) k_constants(Batch b) {
+  kb_constants<T, NX, NY>(b, blockIdx.x);
+}
+
+template <typename T, int NX, int NY, bool INP>
+__global__ void __launch_bounds__(TILE) k_fwd_reduce(Batch b, int nseq) {
+  kb_fwd_reduce<T, NX, NY, INP>(b, blockIdx.x, nseq);
+}
+
+template <typename T, int NX, int NY>
+__global__ void __launch_bounds__(KS) k_fwd_tiles(Batch b) {
+  kb_fwd_tiles<T, NX, NY>(b, blockIdx.x);
 }
 
 template <typename T, int NX, int NY, bool INP>
@@ -3655,50 +3728,34 @@ __global__ void __launch_bounds__(TILE) k_fwd_final(Batch b) {
 
 template <typename T, int NX, int NY, bool INP>
 __global__ void __launch_bounds__(TILE) k_fwd_bwd(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  fwd_bwd_body<INP, T, NX, NY>(q.y, q.N, q.L, q.cst, q.in, q.m0, q.P0, q.ftst, q.utree, q.carry, q.mf_slow, q.Pf_slow, q.btagg, q.sfx,
-                          q.info, (int64_t)blockIdx.x - q.tile0);
+  kb_fwd_bwd<T, NX, NY, INP>(b, blockIdx.x);
 }
 
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(KS) k_bwd_tiles(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  bwd_tiles_body<T, NX, NY>(q.btagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.btst);
+  kb_bwd_tiles<T, NX, NY>(b, blockIdx.x);
 }
 
 // Per-window (time-varying) models: per-window constants and tile aggregates; the tile-level
 // scan of whole elements; the fused per-tile forward (and smoother) pass.
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(TILE) k_tv_reduce(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  tv_reduce_body<T, NX, NY>(q.F, q.Q, q.H, q.R, q.y, q.N, q.L, q.tvblk, q.tvel, q.ftagg, q.info,
-                            (int64_t)blockIdx.x - q.tile0);
+  kb_tv_reduce<T, NX, NY>(b, blockIdx.x);
 }
 
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(KS) k_tv_tiles(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, blockIdx.x);
-  tv_tiles_body<T, NX>(q.ftagg, q.plan.nt, q.plan.lchunk, q.plan.steps, q.m0, q.P0, q.ftst, q.info);
+  kb_tv_tiles<T, NX, NY>(b, blockIdx.x);
 }
 
 template <typename T, int NX, int NY, bool SMOOTH>
 __global__ void __launch_bounds__(TILE) k_tv_fwd(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  tv_fwd_body<T, NX, NY, SMOOTH>(q.F, q.Q, q.H, q.y, q.N, q.L, q.tvblk, q.tvel, q.m0, q.P0, q.ftst, q.carry,
-                                 q.mf_slow, q.Pf_slow, q.btagg, q.sfx, q.info, (int64_t)blockIdx.x - q.tile0);
+  kb_tv_fwd<T, NX, NY, SMOOTH>(b, blockIdx.x);
 }
 
-// MODE 1: filter outputs only; 2: smoother outputs; 3: both. Fast-rate outputs take all L
-// steps; with only the slow smoothed state requested, step 1 suffices.
 template <typename T, int NX, int NY, int MODE, bool INP, bool TV = false>
 __global__ void __launch_bounds__(TILE) k_recover(Batch b) {
-  const Seq<T, NX, NY> q = seq_view<T, NX, NY>(b, tile_sequence(b));
-  const bool fast = (MODE & 1) || q.ms_fast || q.Ps_fast;
-  if (!fast && !q.ms_slow && !q.Ps_slow) return;
-  recover_body<T, NX, NY, MODE, INP, TV>(q.y, q.N, q.L, fast ? q.L : 1, TV ? q.tvblk : q.cst, q.in, q.F, q.Q, q.m0, q.P0,
-                                         q.carry, q.sfx, q.btst,
-                                q.mf_fast, q.Pf_fast, q.ms_fast, q.Ps_fast, q.ms_slow, q.Ps_slow, q.info,
-                                (int64_t)blockIdx.x - q.tile0);
+  kb_recover<T, NX, NY, MODE, INP, TV>(b, blockIdx.x);
 }
 
 // The constants block without the scan levels (the sequential comparator needs no scan), and the
@@ -3806,7 +3863,8 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   SRTM_EV(ev.post(st));
 
   SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles + g.nseq), dim3(TILE), 0, st, b, (int)g.nseq);
+  constexpr size_t lds_red = fwd_reduce_lds_bytes<T, NX>();
+  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles + g.nseq), dim3(TILE), lds_red, st, b, (int)g.nseq);
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
@@ -3974,6 +4032,8 @@ srtm_status run(const srtm_shape& sh, const Ptrs& p, bool smoother, hipStream_t 
   d.nu = p.B ? p.nu : 0;
   d.tv = p.tv ? 1 : 0;
   d.Cs_fast = p.Cs_fast;
+  d.nx = NX;
+  d.ny = NY;
   const Launch g{1u, (unsigned)((sh.N + TILE - 1) / TILE), (int)sh.L};
   const bool want_f = p.mf_fast || p.Pf_fast;
   const bool want_s = p.ms_fast || p.Ps_fast || p.ms_slow || p.Ps_slow;
@@ -4016,9 +4076,185 @@ srtm_status run_batch(const void* table, int nseq, int64_t ntiles, int max_L, vo
 
 }  // namespace srtm
 
+#if defined(SRTM_MIXED_T)
+// ---------------------------------------------------------------- mixed-pair launches
+// One set of six launches for a batch whose sequences differ in (nx, ny) and kind (time-invariant
+// model, with known inputs, or per-window model): every workgroup reads its sequence's descriptor
+// and runs that pair's and kind's stage body. Each sequence gets exactly the per-pair kernels'
+// arithmetic on the same tiles. This object is compiled once per element type (SRTM_MIXED_T).
+namespace srtm {
+
+template <typename T>
+__global__ void __launch_bounds__(256) km_constants(Batch b) {
+  const SeqDesc& d = b.table[blockIdx.x];
+  if (d.tv) return;  // per-window models build their constants per tile in the next stage
+#define SRTM_MX(a, c)                          \
+  if (d.nx == a && d.ny == c) {                \
+    kb_constants<T, a, c>(b, blockIdx.x);      \
+    return;                                    \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+// Workgroups 0 .. nseq-1: level chains (time-invariant models); the rest: tile reductions.
+template <typename T>
+__global__ void __launch_bounds__(TILE) km_reduce(Batch b, int nseq) {
+  const int64_t bid = blockIdx.x;
+  const SeqDesc& d = b.table[bid < nseq ? (int)bid : tile_sequence(b, bid - nseq)];
+#define SRTM_MX(a, c)                                                    \
+  if (d.nx == a && d.ny == c) {                                          \
+    if (d.tv) {                                                          \
+      if constexpr (a <= TV_NX_MAX) {                                    \
+        if (bid >= nseq) kb_tv_reduce<T, a, c>(b, bid - nseq);           \
+      }                                                                  \
+    } else if (d.B) {                                                    \
+      kb_fwd_reduce<T, a, c, true>(b, bid, nseq);                        \
+    } else {                                                             \
+      kb_fwd_reduce<T, a, c, false>(b, bid, nseq);                       \
+    }                                                                    \
+    return;                                                              \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KS) km_fwd_tiles(Batch b) {
+  const SeqDesc& d = b.table[blockIdx.x];
+#define SRTM_MX(a, c)                                      \
+  if (d.nx == a && d.ny == c) {                            \
+    if (d.tv) {                                            \
+      if constexpr (a <= TV_NX_MAX) kb_tv_tiles<T, a, c>(b, blockIdx.x); \
+    } else {                                               \
+      kb_fwd_tiles<T, a, c>(b, blockIdx.x);                \
+    }                                                      \
+    return;                                                \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TILE) km_fwd_bwd(Batch b) {
+  const SeqDesc& d = b.table[tile_sequence(b)];
+#define SRTM_MX(a, c)                                                    \
+  if (d.nx == a && d.ny == c) {                                          \
+    if (d.tv) {                                                          \
+      if constexpr (a <= TV_NX_MAX) kb_tv_fwd<T, a, c, true>(b, blockIdx.x); \
+    } else if (d.B) {                                                    \
+      kb_fwd_bwd<T, a, c, true>(b, blockIdx.x);                          \
+    } else {                                                             \
+      kb_fwd_bwd<T, a, c, false>(b, blockIdx.x);                         \
+    }                                                                    \
+    return;                                                              \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KS) km_bwd_tiles(Batch b) {
+  const SeqDesc& d = b.table[blockIdx.x];
+#define SRTM_MX(a, c)                          \
+  if (d.nx == a && d.ny == c) {                \
+    kb_bwd_tiles<T, a, c>(b, blockIdx.x);      \
+    return;                                    \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TILE) km_recover(Batch b) {
+  const SeqDesc& d = b.table[tile_sequence(b)];
+#define SRTM_MX(a, c)                                                           \
+  if (d.nx == a && d.ny == c) {                                                 \
+    if (d.tv) {                                                                 \
+      if constexpr (a <= TV_NX_MAX) kb_recover<T, a, c, 2, false, true>(b, blockIdx.x); \
+    } else if (d.B) {                                                           \
+      kb_recover<T, a, c, 2, true>(b, blockIdx.x);                              \
+    } else {                                                                    \
+      kb_recover<T, a, c, 2, false>(b, blockIdx.x);                             \
+    }                                                                           \
+    return;                                                                     \
+  }
+  SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+}
+
+// Dynamic LDS of the six stages for one sequence of pair (NX, NY): the launch takes the largest
+// over the batch's sequences.
+template <typename T, int NX, int NY>
+void stage_lds(bool tv, int max_L, int nlev_max, size_t (&o)[6]) {
+  constexpr int NN = NX * NX;
+  auto up = [&](int j, size_t v) { o[j] = v > o[j] ? v : o[j]; };
+  if (!tv) {
+    up(0, constants_lds_bytes(NX, NY, max_L));
+    up(1, fwd_reduce_lds_bytes<T, NX>());
+    up(2, sizeof(T) * ((size_t)KS * (NX + NN) + (size_t)(nlev_max - LOG_TILE) * make_const_layout(NX, NY, 1).lev_stride));
+    up(3, sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN));
+    up(5, (size_t)4 * OutStage<T, NX>::BYTES);
+  } else {
+    if constexpr (NX <= TV_NX_MAX) {
+      constexpr int FA = 3 * NN + 2 * NX;
+      up(1, sizeof(T) * (size_t)TILE * FA);
+      up(2, sizeof(T) * (size_t)KS * FA);
+      up(3, sizeof(T) * (size_t)TILE * FA);
+      up(5, (size_t)4 * OutStage<T, NX>::BYTES + tv_model_lds_bytes<T, NX, NY>());
+    }
+  }
+  up(4, sizeof(T) * (size_t)KS * (2 * NN + NX));
+}
+
+template <typename T>
+srtm_status run_mixed(const SeqDesc* host, const void* table_dev, int nseq, int64_t ntiles, int max_L, void* ws,
+                      int32_t* info, hipStream_t st) {
+  Batch b{};
+  b.table = static_cast<const SeqDesc*>(table_dev);
+  b.tile_seq = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + batch_tile_map_offset(nseq));
+  b.ws = static_cast<char*>(ws);
+  b.info = info;
+  const int nlev_max = make_scan_plan(ntiles * TILE).nlev;
+  size_t lds[6] = {0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < nseq; ++s) {
+#define SRTM_MX(a, c) \
+  if (host[s].nx == a && host[s].ny == c) stage_lds<T, a, c>(host[s].tv != 0, max_L, nlev_max, lds);
+    SRTM_PAIRS(SRTM_MX)
+#undef SRTM_MX
+  }
+  const void* fn[6] = {(const void*)km_constants<T>, (const void*)km_reduce<T>, (const void*)km_fwd_tiles<T>,
+                       (const void*)km_fwd_bwd<T>, (const void*)km_bwd_tiles<T>, (const void*)km_recover<T>};
+  for (int j = 0; j < 6; ++j)
+    if (!allow_lds(fn[j], lds[j])) return SRTM_E_HIP;
+  const unsigned ns = (unsigned)nseq, nt = (unsigned)ntiles;
+  hipLaunchKernelGGL((km_constants<T>), dim3(ns), dim3(256), lds[0], st, b);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((km_reduce<T>), dim3(nt + ns), dim3(TILE), lds[1], st, b, nseq);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((km_fwd_tiles<T>), dim3(ns), dim3(KS), lds[2], st, b);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((km_fwd_bwd<T>), dim3(nt), dim3(TILE), lds[3], st, b);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((km_bwd_tiles<T>), dim3(ns), dim3(KS), lds[4], st, b);
+  SRTM_CHECK_LAUNCH();
+  hipLaunchKernelGGL((km_recover<T>), dim3(nt), dim3(TILE), lds[5], st, b);
+  SRTM_CHECK_LAUNCH();
+  return SRTM_OK;
+}
+
+#define SRTM_MIXED_NAME2(t) run_mixed_##t
+#define SRTM_MIXED_NAME(t) SRTM_MIXED_NAME2(t)
+srtm_status SRTM_MIXED_NAME(SRTM_MIXED_T)(const SeqDesc* host, const void* table_dev, int nseq, int64_t ntiles,
+                                          int max_L, void* ws, int32_t* info, hipStream_t st) {
+  return run_mixed<SRTM_MIXED_T>(host, table_dev, nseq, ntiles, max_L, ws, info, st);
+}
+
+}  // namespace srtm
+#else
 // ---------------------------------------------------------------- this object's (nx, ny) pair
 #if !defined(SRTM_NX) || !defined(SRTM_NY)
-#error "srtm_kernels.hip is compiled once per (nx, ny) pair: define SRTM_NX and SRTM_NY"
+#error "srtm_kernels.hip is compiled once per (nx, ny) pair (SRTM_NX, SRTM_NY) or per element type (SRTM_MIXED_T)"
 #endif
 #define SRTM_NAME2(p, a, b) p##a##_##b
 #define SRTM_NAME(p, a, b) SRTM_NAME2(p, a, b)
@@ -4039,3 +4275,4 @@ srtm_status SRTM_NAME(run_batch_pair_, SRTM_NX, SRTM_NY)(int dtype, const void* 
   return run_batch<float, SRTM_NX, SRTM_NY>(table, nseq, ntiles, max_L, ws, info, st, grad);
 }
 }  // namespace srtm
+#endif  // SRTM_MIXED_T

@@ -187,6 +187,7 @@ struct SeqDesc {
   int32_t nu;
   int32_t tv;  // F, Q, H, R are given per window ([N][...])
   void* Cs_fast;  // lag-one smoothed cross-covariances [N][L][nx][nx] (single calls only; null otherwise)
+  int32_t nx, ny;  // the sequence's sizes (the mixed-pair kernels dispatch on them)
 };
 
 // What every kernel receives: either one sequence (`table` null) or a device table of

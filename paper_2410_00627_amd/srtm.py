@@ -37,6 +37,15 @@ class SeqC(ctypes.Structure):
                 [("N", ctypes.c_int64), ("L", ctypes.c_int32), ("reserved", ctypes.c_int32)])
 
 
+class SeqExC(ctypes.Structure):
+    """srtm_seq_ex: one sequence of a mixed batch (its own nx, ny; optional inputs or per-window model)."""
+    _fields_ = ([("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("L", ctypes.c_int32), ("per_window", ctypes.c_int32),
+                 ("N", ctypes.c_int64)] +
+                [(n, ctypes.c_void_p) for n in ("F", "Q", "H", "R", "m0", "P0", "y", "B", "u")] +
+                [("nu", ctypes.c_int32), ("reserved", ctypes.c_int32)] +
+                [(n, ctypes.c_void_p) for n in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow")])
+
+
 class InputsC(ctypes.Structure):
     """srtm_inputs: known inputs B [nx][nu] and u [N][L][nu] (device pointers)."""
     _fields_ = [("B", ctypes.c_void_p), ("u", ctypes.c_void_p), ("nu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -90,6 +99,20 @@ def lib():
     L.srtm_smooth_batch.restype = ctypes.c_int
     L.srtm_loglik_grad_batch.argtypes = L.srtm_smooth_batch.argtypes
     L.srtm_loglik_grad_batch.restype = ctypes.c_int
+    L.srtm_batch_plan_ex.argtypes = [ctypes.c_int32, ctypes.POINTER(SeqExC), ctypes.c_int32, _vp, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    L.srtm_batch_plan_ex.restype = ctypes.c_int
+    L.srtm_smooth_batch_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+    L.srtm_smooth_batch_ex.restype = ctypes.c_int
+    L.srtm_graph_begin.argtypes = [_vp]
+    L.srtm_graph_begin.restype = ctypes.c_int
+    L.srtm_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
+    L.srtm_graph_end.restype = ctypes.c_int
+    L.srtm_graph_launch.argtypes = [_vp, _vp]
+    L.srtm_graph_launch.restype = ctypes.c_int
+    L.srtm_graph_destroy.argtypes = [_vp]
+    L.srtm_graph_destroy.restype = ctypes.c_int
     L.srtm_loglik.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 9 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_loglik.restype = ctypes.c_int
     L.srtm_loglik_grad.argtypes = [ctypes.POINTER(Shape)] + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
@@ -518,6 +541,124 @@ class Batch:
         bad = [(j, int(x)) for j, x in enumerate(v.tolist()) if x]
         if bad:
             raise SrtmError(f"srtm_smooth_batch: numerical failure in sequences {bad[:8]}")
+
+
+class BatchEx:
+    """A planned mixed batch (srtm_batch_plan_ex / srtm_smooth_batch_ex): sequences of any
+    supported (nx, ny), each with a time-invariant model, with known inputs (problem tuples
+    (F, Q, H, R, L, m0, P0, y, B, u)) or with a per-window model (F, Q, H, R of shape [N, ...]),
+    smoothed by one set of six launches. Same members as Batch."""
+
+    LAUNCHES = 6
+
+    def __init__(self, problems, *, fast: bool = True, slow: bool = True, outputs=None, alloc=None):
+        problems = list(problems)
+        if not problems:
+            raise SrtmError("empty batch")
+        arr = (SeqExC * len(problems))()
+        self.inputs, self.outputs = [], []
+        dev, dt = problems[0][7].device, problems[0][7].dtype
+        for j, pr in enumerate(problems):
+            if len(pr) not in (8, 10):
+                raise SrtmError(f"sequence {j}: expected (F, Q, H, R, L, m0, P0, y[, B, u])")
+            F, Q, H, R, L, m0, P0, y = pr[:8]
+            ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
+            if ts["y"].device != dev or ts["y"].dtype != dt:
+                raise SrtmError("all sequences of a batch share device and dtype")
+            tv = F.dim() == 3
+            inp = _prep_inputs(pr[8], pr[9], nx, int(L), N, ts["y"]) if len(pr) == 10 else None
+            if tv and inp is not None:
+                raise SrtmError(f"sequence {j}: a per-window model takes no inputs")
+            if inp is not None:
+                ts["B"], ts["u"] = inp[0], inp[1]
+            self.inputs.append(ts)
+            out = {} if outputs is None else outputs[j]
+            if outputs is None:
+                if fast:
+                    out["ms_fast"] = torch.empty((N, L, nx), device=dev, dtype=dt)
+                    out["Ps_fast"] = torch.empty((N, L, nx, nx), device=dev, dtype=dt)
+                if slow:
+                    out["ms_slow"] = torch.empty((N, nx), device=dev, dtype=dt)
+                    out["Ps_slow"] = torch.empty((N, nx, nx), device=dev, dtype=dt)
+            else:
+                for k, shp in (("ms_fast", (N, L, nx)), ("Ps_fast", (N, L, nx, nx)), ("ms_slow", (N, nx)),
+                               ("Ps_slow", (N, nx, nx))):
+                    t = out.get(k)
+                    if t is not None and (tuple(t.shape) != shp or t.dtype != dt or t.device != dev or
+                                          not t.is_contiguous()):
+                        raise SrtmError(f"sequence {j}: output {k} must be a contiguous {shp} tensor")
+            self.outputs.append(out)
+            e = arr[j]
+            e.nx, e.ny, e.L, e.per_window, e.N = nx, ny, int(L), int(tv), N
+            for k in ("F", "Q", "H", "R", "m0", "P0", "y", "B", "u"):
+                setattr(e, k, ts[k].data_ptr() if k in ts else None)
+            e.nu, e.reserved = (inp[2].nu if inp is not None else 0), 0
+            for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+                setattr(e, k, out[k].data_ptr() if k in out else None)
+        self.nseq, self.dtype, self.device = len(problems), dt, dev
+        tsz, wsz = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        ntiles, max_L = ctypes.c_int64(0), ctypes.c_int32(0)
+        code = _dtype_code(dt)
+        refs = (ctypes.byref(tsz), ctypes.byref(wsz), ctypes.byref(ntiles), ctypes.byref(max_L))
+        _check(lib().srtm_batch_plan_ex(code, arr, self.nseq, None, 0, *refs), "srtm_batch_plan_ex")
+        self.table_host = torch.empty(tsz.value, dtype=torch.uint8, pin_memory=True)
+        _check(lib().srtm_batch_plan_ex(code, arr, self.nseq, _ptr(self.table_host), tsz.value, *refs),
+               "srtm_batch_plan_ex")
+        get = alloc if alloc is not None else (lambda n: torch.empty(n, device=dev, dtype=torch.uint8))
+        self.table_dev = get(tsz.value)
+        self.table_dev.copy_(self.table_host, non_blocking=True)
+        self.workspace = get(max(wsz.value, 256))
+        self.info = get(4 * self.nseq).view(torch.int32)
+        self.info.zero_()
+        self.ntiles, self.max_L = int(ntiles.value), int(max_L.value)
+
+    def launch(self, stream=None):
+        """Enqueue the six launches on `stream` (default: the current stream); no allocation, no sync."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().srtm_smooth_batch_ex(_dtype_code(self.dtype), self.nseq, _ptr(self.table_host),
+                                          _ptr(self.table_dev), _ptr(self.workspace), self.workspace.numel(),
+                                          _ptr(self.info), ctypes.c_void_p(stream)), "srtm_smooth_batch_ex")
+
+    def check(self):
+        v = self.info.cpu()
+        bad = [(j, int(x)) for j, x in enumerate(v.tolist()) if x]
+        if bad:
+            raise SrtmError(f"srtm_smooth_batch_ex: numerical failure in sequences {bad[:8]}")
+
+
+class Graph:
+    """A HIP graph recorded from calls enqueued on one capture stream (and streams joined to it by
+    events) through srtm_graph_begin / srtm_graph_end; `replay` enqueues it on a stream."""
+
+    def __init__(self, device):
+        self.device = device
+        self.stream = torch.cuda.Stream(device)
+        self.exec = None
+
+    def record(self, enqueue):
+        """Runs enqueue() with the capture stream current, capturing what it enqueues."""
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.stream(self.stream):
+            _check(lib().srtm_graph_begin(ctypes.c_void_p(self.stream.cuda_stream)), "srtm_graph_begin")
+            try:
+                enqueue()
+            finally:
+                h = ctypes.c_void_p()
+                code = lib().srtm_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(code, "srtm_graph_end")
+        self.exec = h
+        torch.cuda.synchronize(self.device)
+
+    def replay(self, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().srtm_graph_launch(self.exec, ctypes.c_void_p(stream)), "srtm_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "exec", None) is not None and _lib is not None:
+            _lib.srtm_graph_destroy(self.exec)
+            self.exec = None
 
 
 def smooth_batch(problems, *, fast: bool = True, slow: bool = True, check: bool = True):

@@ -286,7 +286,8 @@ def test_smooth_batch_rejects_small_workspace_and_bad_table(L):
 
 
 def test_smooth_batch_rejects_descriptors_with_inputs(L):
-    """Batch descriptors carry no inputs: a table whose descriptor names inputs is refused."""
+    """The per-pair batch entry point takes no inputs (srtm_smooth_batch_ex does): a table whose
+    descriptor names inputs is refused."""
     _no_gpu()
     arr = _seqs([(300, 5)])
     _, tsz, wsz, nt, _ = _plan(arr)
@@ -383,3 +384,111 @@ def test_lag1_entry_point_validates(L):
     assert call(sh, 0x9000, need, nulled=0) == 1          # null model array
     assert call(sh, 0x9000, need - 256) == 6              # workspace too small
     assert call(srtm.Shape(5, 1, 10, 1, 5), 0x9000, need) == 4   # pair not compiled
+
+
+# ----------------------------------------------------------------------------- mixed batches (host only)
+DESC_BYTES = 192   # srtm::SeqDesc: 15 pointers, N, tile0, ws_off, L, smoother, B, u, nu, tv, Cs_fast, nx, ny
+OFF_NX = 184
+
+
+def _seqs_ex(specs, base=0x200000):
+    """srtm_seq_ex entries (nx, ny, L, N, kind) with fake, 16-byte aligned addresses."""
+    arr = (srtm.SeqExC * len(specs))()
+    a = base
+    for j, (nx, ny, Lw, N, kind) in enumerate(specs):
+        e = arr[j]
+        for k in ("F", "Q", "H", "R", "m0", "P0", "y", "ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+            setattr(e, k, a)
+            a += 4096
+        e.nx, e.ny, e.L, e.N, e.reserved = nx, ny, Lw, N, 0
+        e.per_window = 1 if kind == "tv" else 0
+        if kind == "inputs":
+            e.B, e.u, e.nu = a, a + 4096, 2
+            a += 8192
+    return arr
+
+
+def _plan_ex(arr, dtype=1, table=None, nbytes=0):
+    t, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    nt, ml = ctypes.c_int64(0), ctypes.c_int32(0)
+    code = srtm.lib().srtm_batch_plan_ex(dtype, arr, len(arr), table, nbytes, ctypes.byref(t), ctypes.byref(w),
+                                         ctypes.byref(nt), ctypes.byref(ml))
+    return code, t.value, w.value, nt.value, ml.value
+
+
+MIXED = [(2, 1, 5, 300, "plain"), (4, 2, 10, 700, "inputs"), (6, 1, 20, 1, "plain"), (3, 2, 7, 257, "tv"),
+         (1, 1, 3, 5000, "plain")]
+
+
+def test_batch_plan_ex_sizes_descriptors_and_tile_map(L):
+    arr = _seqs_ex(MIXED)
+    code, tsz, wsz, nt, ml = _plan_ex(arr)
+    assert code == 0 and ml == 20
+    assert nt == sum((N + 255) // 256 for *_, N, _ in MIXED)
+    want = 0
+    for nx, ny, Lw, N, kind in MIXED:
+        sh = srtm.Shape(nx, ny, Lw, 1, N)
+        b = ctypes.c_size_t(0)
+        fn = {"plain": L.srtm_workspace_size, "inputs": L.srtm_workspace_size_inputs,
+              "tv": L.srtm_workspace_size_tv}[kind]
+        assert fn(ctypes.byref(sh), 1, ctypes.byref(b)) == 0
+        want += (b.value + 255) // 256 * 256
+    assert wsz == want
+    assert tsz == (len(MIXED) * DESC_BYTES + 15) // 16 * 16 + 4 * nt
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan_ex(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    for j, (nx, ny, *_rest) in enumerate(MIXED):
+        assert ctypes.c_int32.from_buffer(buf, j * DESC_BYTES + OFF_NX).value == nx
+        assert ctypes.c_int32.from_buffer(buf, j * DESC_BYTES + OFF_NX + 4).value == ny
+    tile_map = (ctypes.c_int32 * nt).from_buffer(buf, tsz - 4 * nt)
+    assert list(tile_map) == [j for j, (*_, N, _) in enumerate(MIXED) for _ in range((N + 255) // 256)]
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda a: setattr(a[2], "per_window", 1), 4),                # per-window models: nx <= 4
+    (lambda a: setattr(a[1], "per_window", 1), 2),                # per-window model with inputs
+    (lambda a: setattr(a[1], "nu", 0), 2),
+    (lambda a: setattr(a[1], "nu", 5), 2),
+    (lambda a: setattr(a[1], "u", None), 1),
+    (lambda a: setattr(a[0], "nx", 5), 4),                        # pair not compiled
+    (lambda a: setattr(a[0], "reserved", 3), 2),
+    (lambda a: setattr(a[3], "per_window", 2), 2),
+    (lambda a: setattr(a[4], "N", 0), 2),
+    (lambda a: setattr(a[1], "B", 0x200008), 5),
+    (lambda a: setattr(a[0], "F", None), 1),
+])
+def test_batch_plan_ex_errors(L, mutate, code):
+    arr = _seqs_ex(MIXED)
+    mutate(arr)
+    assert _plan_ex(arr)[0] == code
+    assert _plan_ex(_seqs_ex(MIXED), dtype=7)[0] == 3
+
+
+def test_smooth_batch_ex_host_validation(L):
+    _no_gpu()
+    arr = _seqs_ex(MIXED)
+    _, tsz, wsz, nt, _ = _plan_ex(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan_ex(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    host = ctypes.cast(buf, ctypes.c_void_p)
+    dev, ws = ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x8000000)
+    n = len(MIXED)
+    assert L.srtm_smooth_batch_ex(1, n, host, dev, ws, wsz - 256, None, None) == 6
+    assert L.srtm_smooth_batch_ex(1, n, None, dev, ws, wsz, None, None) == 1
+    assert L.srtm_smooth_batch_ex(1, n, host, ctypes.c_void_p(0x4000008), ws, wsz, None, None) == 5
+    assert L.srtm_smooth_batch_ex(5, n, host, dev, ws, wsz, None, None) == 3
+    # a per-window descriptor whose nx the per-window path does not take
+    ctypes.c_int32.from_buffer(buf, 3 * DESC_BYTES + OFF_NX).value = 6
+    assert L.srtm_smooth_batch_ex(1, n, host, dev, ws, wsz, None, None) in (2, 4, 6)
+    ctypes.c_int32.from_buffer(buf, 3 * DESC_BYTES + OFF_NX).value = 3
+    tile_map = (ctypes.c_int32 * nt).from_buffer(buf, tsz - 4 * nt)
+    tile_map[0] = 2
+    assert L.srtm_smooth_batch_ex(1, n, host, dev, ws, wsz, None, None) == 2
+
+
+def test_graph_entry_points_validate(L):
+    h = ctypes.c_void_p()
+    assert L.srtm_graph_begin(None) == 1
+    assert L.srtm_graph_end(None, ctypes.byref(h)) == 1
+    assert L.srtm_graph_launch(None, None) == 1
+    assert L.srtm_graph_destroy(None) == 1

@@ -158,3 +158,124 @@ def test_autotune_picks_a_configuration_with_identical_results():
         alone = srtm.smooth(*pr)
         for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
             assert torch.equal(r.outputs[j][k], alone[k])
+
+
+def _mixed_problems(srtm, dtype):
+    """Sequences of six (nx, ny) pairs and all three kinds: time-invariant, known inputs and
+    per-window models, with one-window, ragged and multi-tile lengths."""
+    specs = [  # nx, ny, L, N, seed, kind
+        (2, 1, 5, 300, 71, "plain"), (4, 2, 10, 700, 72, "plain"), (6, 1, 5, 120, 73, "plain"),
+        (1, 1, 20, 90, 74, "plain"), (3, 2, 7, 257, 75, "plain"), (4, 2, 20, 1, 76, "plain"),
+        (4, 1, 10, 400, 77, "inputs"), (2, 2, 3, 530, 78, "inputs"),
+        (2, 1, 5, 300, 79, "tv"), (4, 2, 10, 260, 80, "tv"), (3, 1, 4, 1100, 81, "plain")]
+    conv = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64)).to("cuda", dtype).contiguous()  # noqa: E731
+    probs, refs = [], []
+    for nx, ny, L, N, seed, kind in specs:
+        if kind == "tv":
+            m = wl.time_varying_model(nx, ny, L, N, seed)
+            y = wl.simulate_tv(m, seed + 1)
+            probs.append((conv(m.A), conv(m.Q), conv(m.C), conv(m.R), L, conv(m.m0), conv(m.P0), conv(y)))
+            refs.append((kind, m, y, None, None))
+        else:
+            m = wl.random_stable_model(nx, ny, L, seed)
+            B = u = None
+            if kind == "inputs":
+                B, u = wl.random_inputs(nx, 2, L, N, seed + 2)
+            y = wl.simulate(m, N, seed + 1, B=B, u=u)
+            pr = (conv(m.A), conv(m.Q), conv(m.C), conv(m.R), L, conv(m.m0), conv(m.P0), conv(y))
+            probs.append(pr + ((conv(B), conv(u)) if kind == "inputs" else ()))
+            refs.append((kind, m, y, B, u))
+    return probs, refs
+
+
+def _alone_any(srtm, pr):
+    if len(pr) == 10:
+        return srtm.smooth(*pr[:8], B=pr[8], u=pr[9])
+    return srtm.smooth(*pr)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_mixed_batch_one_launch_set(dtype):
+    """Six (nx, ny) pairs, inputs and per-window models in ONE srtm_smooth_batch_ex call (six
+    launches): every sequence bitwise equal to its own single call, and equal to the float64
+    reference (on the rounded inputs) within 1e-8 / 1e-3."""
+    srtm = _srtm()
+    probs, refs = _mixed_problems(srtm, dtype)
+    b = srtm.BatchEx(probs)
+    print(f"[gpu] mixed batch of {b.nseq} sequences, {b.ntiles} tiles, {dtype}", flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    b.check()
+    r = (lambda a: a) if dtype == torch.float64 else (
+        lambda a: None if a is None else np.asarray(a, dtype=np.float32).astype(np.float64))
+    for j, (pr, (kind, m, y, B, u)) in enumerate(zip(probs, refs)):
+        alone = _alone_any(srtm, pr)
+        torch.cuda.synchronize()
+        for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+            assert torch.equal(b.outputs[j][k], alone[k]), f"sequence {j} ({kind}): {k} differs from the single call"
+        if kind == "tv":
+            ref = oracle.srtm_smoother_tv(r(m.A), r(m.Q), r(m.C), r(m.R), m.L, r(m.m0), r(m.P0), r(y))
+        else:
+            ref = oracle.srtm_smoother(r(m.A), r(m.Q), r(m.C), r(m.R), m.L, r(m.m0), r(m.P0), r(y), B=r(B), u=r(u))
+        got = {k: v.double().cpu().numpy() for k, v in b.outputs[j].items()}
+        assert_close_states(got["ms_fast"], got["Ps_fast"], ref["ms_fast"], ref["Ps_fast"], TOL[dtype],
+                            f"mixed seq {j} ({kind}) fast")
+        assert_close_states(got["ms_slow"], got["Ps_slow"], ref["ms_slow"], ref["Ps_slow"], TOL[dtype],
+                            f"mixed seq {j} ({kind}) slow")
+
+
+def test_mixed_runner_graph_replays_match_eager():
+    """BatchRunner(mixed=True): two segments on two streams recorded once as a HIP graph through
+    the library's graph entry points and replayed three times (eager work between replays):
+    bitwise the eager results every time; the grouped runner gives the same results."""
+    srtm = _srtm()
+    from paper_2410_00627_amd import batching
+    probs, _ = _mixed_problems(srtm, torch.float64)
+    eager = batching.BatchRunner(probs, segments=2, multi_stream=True, mixed=True)
+    eager.run()
+    torch.cuda.synchronize()
+    eager.check()
+    assert eager.describe()["launches"] == 12
+    ref = [{k: v.clone() for k, v in o.items()} for o in eager.outputs]
+    grouped = batching.BatchRunner(probs)
+    grouped.run()
+    torch.cuda.synchronize()
+    for j, o in enumerate(grouped.outputs):
+        for k in ref[j]:
+            assert torch.equal(o[k], ref[j][k]), f"grouped runner, sequence {j}, {k}"
+    g = batching.BatchRunner(probs, segments=2, multi_stream=True, graph=True, mixed=True)
+    for rep in range(3):
+        for o in g.outputs:
+            for v in o.values():
+                v.fill_(float("nan"))
+        x = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (x @ x).sum().item()
+        print(f"[gpu] mixed graph replay {rep}", flush=True)
+        g.run()
+        torch.cuda.synchronize()
+        for j, o in enumerate(g.outputs):
+            for k in ref[j]:
+                assert torch.equal(o[k], ref[j][k]), f"replay {rep}, sequence {j}, {k}"
+    g.check()
+
+
+def test_mixed_batch_nan_sequence_fails_alone():
+    """A NaN measurement in one sequence of a mixed batch sets only that sequence's info word
+    (non-finite bit) and leaves every other sequence bitwise equal to its single call."""
+    srtm = _srtm()
+    probs, _ = _mixed_problems(srtm, torch.float64)
+    bad = 3
+    y = probs[bad][7].clone()
+    y[y.shape[0] // 2, 0] = float("nan")
+    probs[bad] = probs[bad][:7] + (y,) + probs[bad][8:]
+    b = srtm.BatchEx(probs)
+    b.launch()
+    torch.cuda.synchronize()
+    info = b.info.cpu().tolist()
+    assert info[bad] & 8 and all(v == 0 for j, v in enumerate(info) if j != bad), info
+    for j, pr in enumerate(probs):
+        if j == bad:
+            continue
+        alone = _alone_any(srtm, pr)
+        for k in ("ms_fast", "Ps_fast", "ms_slow", "Ps_slow"):
+            assert torch.equal(b.outputs[j][k], alone[k]), f"sequence {j}: {k} changed by the NaN sequence"
