@@ -790,6 +790,66 @@ SRTM_DEV void ld_selem(const Slots<T>& S, int s, SElem<T, NX>& a) {
   }
 }
 
+// x <- x (x) b under eq. op-smoother, where b is the element of lane l + d (DOWN) or l - d of the
+// same wave, when `take`; otherwise x is left as it is. Every lane takes part in the exchange.
+// The partner's E and S arrive column by column and are consumed at once, so that only a few
+// exchanged values are live (the products are those of selem_combine, in its order).
+template <bool DOWN, typename T, int NX>
+SRTM_DEV void selem_merge_lane(SElem<T, NX>& x, int d, bool take) {
+  auto mv = [&](T v) { return DOWN ? __shfl_down(v, (unsigned)d, 64) : __shfl_up(v, (unsigned)d, 64); };
+  T tE[NX][NX], ES[NX][NX], tg[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) {
+    T be[NX], bs[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      be[k] = mv(x.E[k][c]);
+      bs[k] = mv(x.S[k][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      T e = x.E[r][0] * be[0], q = x.E[r][0] * bs[0];
+#pragma unroll
+      for (int k = 1; k < NX; ++k) {
+        e = my_fma(x.E[r][k], be[k], e);
+        q = my_fma(x.E[r][k], bs[k], q);
+      }
+      tE[r][c] = e;
+      ES[r][c] = q;
+    }
+  }
+  {
+    T bg[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) bg[k] = mv(x.g[k]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      T t = x.g[r];
+#pragma unroll
+      for (int k = 0; k < NX; ++k) t = my_fma(x.E[r][k], bg[k], t);
+      tg[r] = t;
+    }
+  }
+  if (take) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int c = r; c < NX; ++c) {
+        T q = x.S[r][c];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) q = my_fma(ES[r][k], x.E[c][k], q);
+        x.S[r][c] = q;
+        x.S[c][r] = q;
+      }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      x.g[r] = tg[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) x.E[r][c] = tE[r][c];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- per-window quantities
 // Window k with prior (m, P) = (m^f_{k-1,l}, P^f_{k-1,l}) and measurement y_k. With
 // V = P C_bar^T, S = C_bar V + R_x, U_i = A^i V + c_i = Cov(x_{k,i}, y_k | y_{1:k-1}):
@@ -1617,10 +1677,10 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   if (flag && info) atomicOr(info, flag);
 }
 
-// K5 (Kogge-Stone form): reverse tile-level scan in one workgroup of KS threads. Thread r
-// holds the aggregate of its chunk of 2^lchunk consecutive tiles, counted from the end
-// (thread 0 holds the last tiles), folded under eq. op-smoother (earlier (x) later). Step s:
-// thread r merges its run with the later run held by thread r - s. Every run reaching the
+// K5: reverse tile-level scan in one workgroup of KS threads. Thread r holds the aggregate of
+// its chunk of 2^lchunk consecutive tiles, counted from the end (thread 0 holds the last tiles),
+// folded under eq. op-smoother (earlier (x) later), and merges it with all later runs (lane
+// shuffles inside a wave, then the later waves' aggregates). Every run reaching the
 // last window has E = 0, i.e. is the smoothed state at its first window; thread r then walks
 // its chunk backwards from the state after it, writing per tile the smoothed state of the
 // first window after the tile (zero after the last tile).
@@ -1680,15 +1740,25 @@ SRTM_DEV void bwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
   } else {
     selem_identity(x);
   }
+  // Thread r ends with its run merged with every later run (threads r - 1 .. 0): within each
+  // wave by lane shuffles (distances below 64), then each wave with the aggregates of the waves
+  // before it (later tiles; lane 63 holds its wave's), through LDS.
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lim = steps < 6 ? steps : 6;
 #pragma unroll 1
-  for (int q = 0; q < steps; ++q) {
-    const int s = 1 << q;
-    st_selem(S, tid, x);
-    __syncthreads();
-    SElem<T, NX> later;
-    if (tid >= s) ld_selem(S, tid - s, later);
-    __syncthreads();
-    if (tid >= s) selem_combine(x, later, x);
+    for (int q = 0; q < lim; ++q) selem_merge_lane<false>(x, 1 << q, lane >= (1 << q));
+    if (steps > 6) {
+      if (lane == 63) st_selem(S, wv, x);
+      __syncthreads();
+#pragma unroll 1
+      for (int v = wv - 1; v >= 0; --v) {  // x (x) A_{wv-1} (x) ... (x) A_0, left to right
+        SElem<T, NX> a;
+        ld_selem(S, v, a);
+        selem_combine(x, a, x);
+      }
+      __syncthreads();  // the aggregates are read before the slots take the results
+    }
   }
   st_selem(S, tid, x);
   __syncthreads();
@@ -2041,16 +2111,25 @@ SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int
       }
     }
   }
-  __syncthreads();  // the slots switch from forward states to smoother elements
-  // lane j ends with a_j (x) a_{j+1} (x) ... (x) a_{TILE-1}
+  // Lane j ends with a_j (x) a_{j+1} (x) ... (x) a_{TILE-1}. Within each wave first, by lane
+  // shuffles at distances 1 .. 32: lane l then holds its wave's elements l .. 63 merged, and lane
+  // 0 the whole wave's. Then each wave merges with the aggregates of the waves after it, which
+  // pass through LDS (runs of any length merge: eq. op-smoother carries whole matrices).
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = TILE / 64;
 #pragma unroll 1
-  for (int s = 1; s < TILE; s *= 2) {
-    st_selem(S, tid, x);
+    for (int s = 1; s < 64; s *= 2) selem_merge_lane<true>(x, s, lane + s < 64);
+    __syncthreads();  // the slots switch from forward states to smoother elements
+    if (lane == 0) st_selem(S, wv, x);
     __syncthreads();
-    SElem<T, NX> later;
-    if (tid + s < TILE) ld_selem(S, tid + s, later);
-    __syncthreads();
-    if (tid + s < TILE) selem_combine(x, later, x);
+#pragma unroll 1
+    for (int v = wv + 1; v < NW; ++v) {  // x (x) A_{wv+1} (x) ... (x) A_{NW-1}, left to right
+      SElem<T, NX> a;
+      ld_selem(S, v, a);
+      selem_combine(x, a, x);
+    }
+    __syncthreads();  // the aggregates are read before the slots take the suffixes
   }
   st_selem(S, tid, x);
   __syncthreads();
