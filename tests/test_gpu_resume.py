@@ -40,8 +40,10 @@ def test_filter_resumes_from_slow_carry(nx, ny, L, N, n, seed, dtype):
     yt = torch.as_tensor(y, dtype=torch.float64).to("cuda", dtype)
     print(f"[gpu] resume nx={nx} ny={ny} L={L} N={N} at n={n} {dtype}", flush=True)
     full = srtm.filter(F, Q, H, R, L, m0, P0, yt)
-    mc, Pc = full["m_slow"][n - 1].contiguous(), full["P_slow"][n - 1].contiguous()
-    tail = srtm.filter(F, Q, H, R, L, mc, Pc, yt[n:].contiguous())
+    # fresh buffers: the library requires 16-byte aligned arrays, which row slices need not be
+    mc, Pc = full["m_slow"][n - 1].clone(), full["P_slow"][n - 1].clone()
+    head, rest = yt[:n].clone(), yt[n:].clone()
+    tail = srtm.filter(F, Q, H, R, L, mc, Pc, rest)
     torch.cuda.synchronize()
     tol = 1e-9 if dtype == torch.float64 else 1e-3
     g = {k: v.double().cpu().numpy() for k, v in full.items() if k != "info"}
@@ -49,7 +51,7 @@ def test_filter_resumes_from_slow_carry(nx, ny, L, N, n, seed, dtype):
     assert_close_states(t["m_fast"], t["P_fast"], g["m_fast"][n:], g["P_fast"][n:], tol, "resumed fast")
     assert_close_states(t["m_slow"], t["P_slow"], g["m_slow"][n:], g["P_slow"][n:], tol, "resumed slow")
     ll_full = float(srtm.loglik(F, Q, H, R, L, m0, P0, yt))
-    ll_head = float(srtm.loglik(F, Q, H, R, L, m0, P0, yt[:n].contiguous()))
-    ll_tail = float(srtm.loglik(F, Q, H, R, L, mc, Pc, yt[n:].contiguous()))
+    ll_head = float(srtm.loglik(F, Q, H, R, L, m0, P0, head))
+    ll_tail = float(srtm.loglik(F, Q, H, R, L, mc, Pc, rest))
     ltol = 1e-10 if dtype == torch.float64 else 1e-4
     assert abs(ll_head + ll_tail - ll_full) <= ltol * max(1.0, abs(ll_full)), (ll_head, ll_tail, ll_full)
