@@ -1826,39 +1826,82 @@ SRTM_DEV void put_chunk(char* p, const V& v) {
 }
 
 
-// Copies records w = 0..nvalid-1 of RB bytes (stride SB bytes in LDS) to dst + w * gstride
-// bytes in chunks of CH bytes. When a record holds a power-of-two number of chunks, lane l
-// always moves chunk (l mod PER) of windows l / PER + r * 64 / PER: every store address is
-// a wave-uniform base plus one loop-invariant 32-bit lane offset.
-template <int RB, int SB, bool NT = false>
-SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, char* __restrict__ dst,
-                            int64_t gstride) {
-  constexpr int CH = (RB % 16 == 0 && SB % 16 == 0) ? 16 : ((RB % 8 == 0 && SB % 8 == 0) ? 8 : 4);
+// Copies records w = 0..nvalid-1 (nvalid <= 64) of RB bytes (stride SB bytes in LDS) to
+// dst + w * gstride bytes in chunks of CH bytes. A record is PER = RB / CH chunks; one store
+// instruction moves WPI = 64 / PER whole records (lane l: chunk l mod PER of record
+// l / PER + r WPI; the last 64 mod PER lanes idle), so every store address is a wave-uniform base
+// plus one loop-invariant 32-bit lane offset.
+template <int RB, int SB, int CH, bool NT>
+SRTM_DEV void flush_chunks(int lane, int nvalid, const char* __restrict__ lds, char* __restrict__ dst,
+                           int64_t gstride) {
   constexpr int PER = RB / CH;
+  static_assert(RB % CH == 0 && SB % CH == 0 && PER <= 64, "whole chunks, at most one per lane");
+  constexpr int WPI = 64 / PER;
+  constexpr int NIT = (64 + WPI - 1) / WPI;
   using V = typename Chunk<CH>::type;
-  if (((reinterpret_cast<uintptr_t>(dst) | (uintptr_t)gstride) % CH) != 0 || (64 % PER) != 0) {
-    for (int c = lane; c < nvalid * (RB / 4); c += 64) {  // generic: 4-byte words
-      const int w = c / (RB / 4), e = c - w * (RB / 4);
-      put_global(reinterpret_cast<unsigned int*>(dst + w * gstride) + e,
-                 reinterpret_cast<const unsigned int*>(lds + w * SB)[e]);
-    }
-    return;
-  }
-  constexpr int WPI = (64 % PER == 0) ? 64 / PER : 1;  // windows per store instruction
   const int wl = lane / PER, pl = lane - wl * PER;
   const unsigned int lo = (unsigned int)(wl * gstride) + (unsigned int)(pl * CH);
   const char* lsrc = lds + wl * SB + pl * CH;
-  // all LDS reads first, so that the stores leave back to back
-  V v[PER];
+  if constexpr (64 % PER == 0) {  // every lane busy: all LDS reads first, then the stores back to back
+    V v[NIT];
 #pragma unroll
-  for (int r = 0; r < PER; ++r) v[r] = *reinterpret_cast<const V*>(lsrc + r * WPI * SB);
-  if (nvalid == 64) {
+    for (int r = 0; r < NIT; ++r) v[r] = *reinterpret_cast<const V*>(lsrc + r * WPI * SB);
+    if (nvalid == 64) {
 #pragma unroll
-    for (int r = 0; r < PER; ++r) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
-  } else {
+      for (int r = 0; r < NIT; ++r) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < PER; ++r)
-      if (wl + r * WPI < nvalid) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
+      for (int r = 0; r < NIT; ++r)
+        if (wl + r * WPI < nvalid) put_chunk<NT>(dst + (int64_t)r * WPI * gstride + lo, v[r]);
+    }
+  } else {  // groups of four instructions (reads, then stores), to bound the registers held
+    constexpr int G = 4;
+    const bool act = wl < WPI;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NIT; r0 += G) {
+      V v[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (r0 + j < NIT && act && wl + (r0 + j) * WPI < 64)
+          v[j] = *reinterpret_cast<const V*>(lsrc + (r0 + j) * WPI * SB);
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (r0 + j < NIT && act && wl + (r0 + j) * WPI < nvalid)
+          put_chunk<NT>(dst + (int64_t)(r0 + j) * WPI * gstride + lo, v[j]);
+    }
+  }
+}
+
+// Chunks of 16 bytes when the record length and LDS stride allow them and the destination and
+// record stride are 16-byte aligned, 8 bytes for records that are 8- but not 16-byte multiples,
+// 4-byte words otherwise. Without GENERAL only records that divide the wave (64 mod PER = 0) go
+// in chunks. GENERAL (4-byte element types) also chunks the others, e.g. the 144-byte records of
+// a 6 x 6 float covariance; the float64 recovery of the mixed-pair kernels, which spills heavily,
+// returned wrong results for unchanged cases with it, so float64 keeps 4-byte words for them.
+template <int RB, int SB, bool NT = false, bool GENERAL = false>
+SRTM_DEV void flush_records(int lane, int nvalid, const char* __restrict__ lds, char* __restrict__ dst,
+                            int64_t gstride) {
+  const uintptr_t al = reinterpret_cast<uintptr_t>(dst) | (uintptr_t)gstride;
+  if constexpr (RB % 16 == 0 && SB % 16 == 0 && RB / 16 <= 64 && (GENERAL || 64 % (RB / 16) == 0)) {
+    if (al % 16 == 0) {
+      flush_chunks<RB, SB, 16, NT>(lane, nvalid, lds, dst, gstride);
+      return;
+    }
+  }
+  if constexpr (RB % 16 != 0 && RB % 8 == 0 && SB % 8 == 0 && RB / 8 <= 64 && (GENERAL || 64 % (RB / 8) == 0)) {
+    if (al % 8 == 0) {
+      flush_chunks<RB, SB, 8, NT>(lane, nvalid, lds, dst, gstride);
+      return;
+    }
+  }
+  if constexpr (RB % 8 != 0 && 64 % (RB / 4) == 0) {  // whole records of 4-byte words per lane
+    flush_chunks<RB, SB, 4, NT>(lane, nvalid, lds, dst, gstride);
+    return;
+  }
+  for (int c = lane; c < nvalid * (RB / 4); c += 64) {  // 4-byte words
+    const int w = c / (RB / 4), e = c - w * (RB / 4);
+    put_global(reinterpret_cast<unsigned int*>(dst + w * gstride) + e,
+               reinterpret_cast<const unsigned int*>(lds + w * SB)[e]);
   }
 }
 
@@ -1910,7 +1953,7 @@ struct OutStage {
     if (P_out && (sp == GP - 1 || i == ilim)) {
       T* dst = P_out + (w0 * L + (i - sp - 1)) * NN;
       if (sp == GP - 1)
-        flush_records<RBP, SBP, RBP % 128 == 0>(lane, nvalid, pbuf, reinterpret_cast<char*>(dst),
+        flush_records<RBP, SBP, RBP % 128 == 0, sizeof(T) == 4>(lane, nvalid, pbuf, reinterpret_cast<char*>(dst),
                                                 (int64_t)L * NN * sizeof(T));
       else
         flush_records_rt<T>(lane, nvalid, pbuf, SBP, dst, (int64_t)L * NN, (sp + 1) * NN);
@@ -1918,7 +1961,7 @@ struct OutStage {
     if (m_out && (sm == GM - 1 || i == ilim)) {
       T* dst = m_out + (w0 * L + (i - sm - 1)) * NX;
       if (sm == GM - 1)
-        flush_records<RBM, SBM, RBM % 128 == 0>(lane, nvalid, mbuf, reinterpret_cast<char*>(dst),
+        flush_records<RBM, SBM, RBM % 128 == 0, sizeof(T) == 4>(lane, nvalid, mbuf, reinterpret_cast<char*>(dst),
                                                 (int64_t)L * NX * sizeof(T));
       else
         flush_records_rt<T>(lane, nvalid, mbuf, SBM, dst, (int64_t)L * NX, (sm + 1) * NX);
@@ -1927,10 +1970,10 @@ struct OutStage {
   // slow-rate output: the blocks of fast step 1 (call right after put(1)), contiguous windows
   SRTM_DEV void flush_slow(int lane, int nvalid, T* m_out, T* P_out, int64_t w0) const {
     if (m_out)
-      flush_records<NX * (int)sizeof(T), SBM>(lane, nvalid, mbuf, reinterpret_cast<char*>(m_out + w0 * NX),
+      flush_records<NX * (int)sizeof(T), SBM, false, sizeof(T) == 4>(lane, nvalid, mbuf, reinterpret_cast<char*>(m_out + w0 * NX),
                                               (int64_t)NX * sizeof(T));
     if (P_out)
-      flush_records<NN * (int)sizeof(T), SBP>(lane, nvalid, pbuf, reinterpret_cast<char*>(P_out + w0 * NN),
+      flush_records<NN * (int)sizeof(T), SBP, false, sizeof(T) == 4>(lane, nvalid, pbuf, reinterpret_cast<char*>(P_out + w0 * NN),
                                               (int64_t)NN * sizeof(T));
   }
 };
