@@ -277,6 +277,17 @@ srtm_status srtm_loglik_grad(const srtm_shape* shape,
                              void* ll, void* dF, void* dQ, void* dR,
                              void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
+/* srtm_loglik_grad with known inputs (srtm_inputs; the same outputs, errors and centred noise
+ * form). The fast-step smoothed means then carry the input response z_{k,i} of the input
+ * section; the noise w = x_t - F x_{t-1} - B u_{t-1} and the measurement residual keep their
+ * statistics, with the innovations taken against y_k minus the inputs' part. The gradient is with
+ * respect to F, Q and R (B and u are given). Workspace: srtm_workspace_size_inputs(shape, 1). */
+srtm_status srtm_loglik_grad_inputs(const srtm_shape* shape, const srtm_inputs* inputs,
+                                    const void* F, const void* Q, const void* H, const void* R,
+                                    const void* m0, const void* P0, const void* y,
+                                    void* ll, void* dF, void* dQ, void* dR,
+                                    void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
+
 /* ------------------------------------------------------------------ many sequences
  * One sequence of a batch: its own model (F, Q, H, R, m0, P0), measurements y [N][ny],
  * window length L and output arrays (each may be NULL), all DEVICE pointers of the batch's

@@ -290,16 +290,17 @@ def slow_rate_smoother(A, Q, C, R, L, m0, P0, y):
     return ms, Ps
 
 
-def loglik_grad_fd(A, Q, C, R, L, m0, P0, y, h=1e-6):
+def loglik_grad_fd(A, Q, C, R, L, m0, P0, y, h=1e-6, B=None, u=None):
     """Central finite differences of the IMKF log-likelihood (imkf) with respect to the model.
 
     Returns (dA, dQ, dR): dA[i, j] = d loglik / d A[i, j]; Q and R are perturbed as symmetric
     matrices (entries (i, j) and (j, i) together), and the returned dQ, dR are the symmetric
     gradients G with d loglik = tr(G E) for a small symmetric change E, i.e. half the paired
-    difference off the diagonal. Step h is relative to max(1, |entry|).
+    difference off the diagonal. Step h is relative to max(1, |entry|). Known inputs (B, u) are
+    passed through to imkf unchanged.
     """
     def ll(a, q, r):
-        return imkf(a, q, C, r, L, m0, P0, y)[2]
+        return imkf(a, q, C, r, L, m0, P0, y, B=B, u=u)[2]
 
     A, Q, R = (np.array(x, dtype=float) for x in (A, Q, R))
     nx, ny = A.shape[0], R.shape[0]

@@ -565,6 +565,15 @@ srtm_status srtm_loglik_grad(const srtm_shape* shape, const void* F, const void*
   return lik_common(shape, F, Q, H, R, m0, P0, y, ll, dF, dQ, dR, workspace, workspace_bytes, info, stream, true);
 }
 
+srtm_status srtm_loglik_grad_inputs(const srtm_shape* shape, const srtm_inputs* inputs, const void* F, const void* Q,
+                                    const void* H, const void* R, const void* m0, const void* P0, const void* y,
+                                    void* ll, void* dF, void* dQ, void* dR, void* workspace, size_t workspace_bytes,
+                                    int32_t* info, void* stream) {
+  if (!inputs) return SRTM_E_NULL;
+  return lik_common(shape, F, Q, H, R, m0, P0, y, ll, dF, dQ, dR, workspace, workspace_bytes, info, stream, true,
+                    inputs);
+}
+
 int32_t srtm_kernel_count(int32_t smoother) {
   return smoother ? (int32_t)(sizeof(kSmoothKernels) / sizeof(kSmoothKernels[0]))
                   : (int32_t)(sizeof(kFilterKernels) / sizeof(kFilterKernels[0]));

@@ -3338,13 +3338,15 @@ SRTM_DEV void gloadv_f64(double (&a)[R], const T* __restrict__ p) {
 }
 
 // Gradient statistics of window k (float64), added to Sw, Swx, Sy; the window's log-likelihood
-// term in *ll. (m, P): its prior; yk: its measurement; sfx, tin: its smoother-correction record
-// and its tile's incoming smoothed state (element type T).
+// term in *ll. (m, P): its prior; yk: its measurement (y_k - mu_k with known inputs); sfx, tin: its
+// smoother-correction record and its tile's incoming smoothed state (element type T); with known
+// inputs Bm [nx][nu] and uk, the window's inputs [L][nu].
 template <typename T, int NX, int NY>
 SRTM_DEV bool grad_window(const Model<double, NX, NY>& M, int L, const double (&m)[NX], const double (&P)[NX][NX],
                           const double (&yk)[NY], const double (&R)[NY][NY], const T* __restrict__ src,
                           const T* __restrict__ ti, double& ll, double (&Sw)[NX][NX], double (&Swx)[NX][NX],
-                          double (&Sy)[NY][NY]) {
+                          double (&Sy)[NY][NY], const T* __restrict__ Bm = nullptr, const T* __restrict__ uk = nullptr,
+                          int nu = 0) {
   constexpr int NN = NX * NX;
   Window<double, NX, NY> w;
   const bool ok = window_setup(M, L, m, P, yk, w);
@@ -3393,10 +3395,11 @@ SRTM_DEV bool grad_window(const Model<double, NX, NY>& M, int L, const double (&
   double A[NX][NX], Qm[NX][NX];
   M.get(A, M.lay.A);
   M.get(Qm, M.lay.Q);
-  // step i-1 quantities: U_{i-1}, P^f_{k,i-1,l}, m^f_{k,i-1}, c_{i-1}
-  double Up[NX][NY], PLp[NX][NX], mfp[NX], cp[NX][NY];
+  // step i-1 quantities: U_{i-1}, P^f_{k,i-1,l}, m^f_{k,i-1}, c_{i-1}; zin: input response z_{i-1}
+  double Up[NX][NY], PLp[NX][NX], mfp[NX], cp[NX][NY], zin[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
+    zin[r] = 0.0;
     mfp[r] = w.mp[r];
 #pragma unroll
     for (int c = 0; c < NY; ++c) {
@@ -3481,11 +3484,30 @@ SRTM_DEV bool grad_window(const Model<double, NX, NY>& M, int L, const double (&
         Sw[r][c] += sw;
         Swx[r][c] += sx;
       }
-    // step i's own blocks for the next step
+    // step i's own blocks for the next step; with known inputs the fast-step means also carry the
+    // input response z_i = A z_{i-1} + B u_{k,i-1} (z_0 = 0), the noise statistics do not change
     if (i < L) {
       double Pii[NX][NX];
       window_step<double, NX, NY, true>(M, w, i, mfp, Pii, PLp);
       window_U(M, w, i, Up);
+      if (uk) {
+        double nz[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int j = 0; j < NU_MAX; ++j)
+            if (j < nu) t = fma((double)gld(Bm + r * nu + j), (double)gld(uk + (i - 1) * nu + j), t);
+#pragma unroll
+          for (int q = 0; q < NX; ++q) t = fma(A[r][q], zin[q], t);
+          nz[r] = t;
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          zin[r] = nz[r];
+          mfp[r] += zin[r];
+        }
+      }
 #pragma unroll
       for (int r = 0; r < NX; ++r)
 #pragma unroll
@@ -3534,7 +3556,6 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
                          int32_t* info, int64_t tile) {
   using SL = StatLayout<NX, NY>;
   constexpr int NN = NX * NX, ST = NX + NN, SF = sfx_stride(NX), NC = SL::SIZE;
-  static_assert(!(GRAD && INP), "the gradient is built without inputs");
   __shared__ double red[TILE / 64][NC];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t k = tile * TILE + tid;
@@ -3562,9 +3583,15 @@ SRTM_DEV void stats_body(const T* __restrict__ y, int64_t N, int L, const T* __r
       gloadv_f64(m, carry + (kc - 1) * ST);
       gload_f64(P, carry + (kc - 1) * ST + NX);
     }
-    gloadv_f64(yk, y + kc * NY);
+    if constexpr (INP) {  // y_k - mu_k from the tile reductions' per-window record
+      gloadv_f64(yk, in.rec + kc * (NY + NX));
+    } else {
+      gloadv_f64(yk, y + kc * NY);
+    }
     gload_f64(R, Rm);
-    if (!grad_window<T, NX, NY>(M, L, m, P, yk, R, sfx + kc * SF, tin + tile * ST, ll, Sw, Swx, Sy) && valid)
+    if (!grad_window<T, NX, NY>(M, L, m, P, yk, R, sfx + kc * SF, tin + tile * ST, ll, Sw, Swx, Sy,
+                                INP ? in.B : nullptr, INP ? in.u + kc * L * in.nu : nullptr, INP ? in.nu : 0) &&
+        valid)
       flag |= SRTM_INFO_INNOVATION_NOT_PD;
   } else {
     const Model<T, NX, NY> M{cst, make_const_layout(NX, NY, L), in};
@@ -4041,15 +4068,11 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
 
   SRTM_EV(ev.pre(st));
   if (rec_mode == REC_GRAD) {
-    if constexpr (INP) {
-      return SRTM_E_UNSUPPORTED;  // the gradient is built without inputs
-    } else {
-      hipLaunchKernelGGL((k_stats<T, NX, NY, true, false>), dim3(g.ntiles), dim3(TILE), 0, st, b);
-      SRTM_CHECK_LAUNCH();
-      hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
-                         lo.dR);
-      SRTM_CHECK_LAUNCH();
-    }
+    hipLaunchKernelGGL((k_stats<T, NX, NY, true, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+    SRTM_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
+                       lo.dR);
+    SRTM_CHECK_LAUNCH();
   } else if (rec_mode == 2) {
     if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds_rec)) return SRTM_E_HIP;
     hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);

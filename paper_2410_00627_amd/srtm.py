@@ -124,6 +124,8 @@ def lib():
     L.srtm_smooth_inputs.restype = ctypes.c_int
     L.srtm_loglik_inputs.argtypes = _si + [_vp] * 9 + [ctypes.c_size_t, _vp, _vp]
     L.srtm_loglik_inputs.restype = ctypes.c_int
+    L.srtm_loglik_grad_inputs.argtypes = _si + [_vp] * 12 + [ctypes.c_size_t, _vp, _vp]
+    L.srtm_loglik_grad_inputs.restype = ctypes.c_int
     L.srtm_kernel_count.argtypes = [ctypes.c_int32]
     L.srtm_kernel_count.restype = ctypes.c_int32
     L.srtm_kernel_name.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -392,8 +394,6 @@ def smooth_noalloc(F, Q, H, R, L: int, m0, P0, y, out: Dict[str, torch.Tensor], 
 def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):
     ts, nx, ny, N = _prep(F, Q, H, R, L, m0, P0, y)
     inp = _prep_inputs(B, u, nx, L, N, y)
-    if inp is not None and grad:
-        raise SrtmError("the log-likelihood gradient takes no inputs")
     if F.dim() == 3:
         raise SrtmError("the log-likelihood entry points take a time-invariant model")
     dev, dt = y.device, y.dtype
@@ -406,7 +406,11 @@ def _lik(F, Q, H, R, L, m0, P0, y, grad: bool, check: bool, B=None, u=None):
     sh = shape_of(nx, ny, L, N, dt)
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     ins = [_ptr(ts[k]) for k in ("F", "Q", "H", "R", "m0", "P0", "y")]
-    if grad:
+    if grad and inp is not None:
+        code = lib().srtm_loglik_grad_inputs(ctypes.byref(sh), ctypes.byref(inp[2]), *ins, _ptr(ll), _ptr(dF),
+                                             _ptr(dQ), _ptr(dR), _ptr(ws), ws.numel(), _ptr(info), stream)
+        _check(code, "srtm_loglik_grad_inputs")
+    elif grad:
         code = lib().srtm_loglik_grad(ctypes.byref(sh), *ins, _ptr(ll), _ptr(dF), _ptr(dQ), _ptr(dR), _ptr(ws),
                                       ws.numel(), _ptr(info), stream)
         _check(code, "srtm_loglik_grad")
@@ -427,9 +431,10 @@ def loglik(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True, B=None, u=None)
     return _lik(F, Q, H, R, L, m0, P0, y, False, check, B, u)[0]
 
 
-def loglik_grad(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True):
-    """(log p(y_{1:N}), d/dF, d/dQ, d/dR); the Q and R gradients are symmetric-matrix gradients."""
-    return _lik(F, Q, H, R, L, m0, P0, y, True, check)
+def loglik_grad(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True, B=None, u=None):
+    """(log p(y_{1:N}), d/dF, d/dQ, d/dR); the Q and R gradients are symmetric-matrix gradients.
+    B, u: optional known inputs as in filter() (the gradient stays with respect to F, Q, R)."""
+    return _lik(F, Q, H, R, L, m0, P0, y, True, check, B, u)
 
 
 class LogLikelihood(torch.autograd.Function):

@@ -492,3 +492,14 @@ def test_graph_entry_points_validate(L):
     assert L.srtm_graph_end(None, ctypes.byref(h)) == 1
     assert L.srtm_graph_launch(None, None) == 1
     assert L.srtm_graph_destroy(None) == 1
+
+
+def test_loglik_grad_inputs_requires_inputs(L):
+    _no_gpu()
+    sh = srtm.Shape(4, 2, 5, 1, 100)
+    fake = [ctypes.c_void_p(0x100000 + 4096 * j) for j in range(11)]
+    assert L.srtm_loglik_grad_inputs(ctypes.byref(sh), None, *fake, ctypes.c_void_p(0x800000), 1 << 30, None,
+                                     None) == 1
+    bad = srtm.InputsC(0x300000, 0x310000, 0, 0)  # nu = 0
+    assert L.srtm_loglik_grad_inputs(ctypes.byref(sh), ctypes.byref(bad), *fake, ctypes.c_void_p(0x800000),
+                                     1 << 30, None, None) == 2

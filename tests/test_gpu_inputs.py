@@ -144,9 +144,13 @@ def test_inputs_full_size_slow_filter():
                         "smoother tail with inputs")
 
 
-def test_gradient_refuses_inputs():
+def test_gradient_pass_log_likelihood_with_inputs_equals_loglik():
+    """The gradient pass with inputs (both scans, then the statistics kernel) returns the same
+    log-likelihood as the filter-only srtm_loglik_inputs, to rounding (the gradient itself is
+    checked against finite differences in test_gpu_loglik.py)."""
     srtm = _srtm()
     m, B, u, y, *_ = _case(2, 1, 4, 50, 1, 41, torch.float64)
     F, Q, H, R, m0, P0, yt, Bt, ut = _gpu(srtm, m, B, u, y, torch.float64)
-    with pytest.raises(srtm.SrtmError):
-        srtm._lik(F, Q, H, R, m.L, m0, P0, yt, True, True, Bt, ut)
+    ll_g = float(srtm.loglik_grad(F, Q, H, R, m.L, m0, P0, yt, B=Bt, u=ut)[0])
+    ll = float(srtm.loglik(F, Q, H, R, m.L, m0, P0, yt, B=Bt, u=ut))
+    assert abs(ll_g - ll) <= 1e-11 * max(1.0, abs(ll))

@@ -113,3 +113,49 @@ def test_batched_gradient_equals_single_calls(dtype):
         o = b.outputs[j]
         for got, want in ((o["ll"][0], ll), (o["dF"], dF), (o["dQ"], dQ), (o["dR"], dR)):
             assert torch.equal(got, want), f"sequence {j}"
+
+
+IN_CASES = [(4, 2, 5, 150, 2, 131), (2, 1, 10, 300, 1, 132), (3, 1, 4, 90, 3, 133)]
+
+
+@pytest.mark.parametrize("nx,ny,L,N,nu,seed", IN_CASES, ids=[f"nx{c[0]}ny{c[1]}L{c[2]}N{c[3]}nu{c[4]}" for c in IN_CASES])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_gradient_with_inputs_against_finite_differences(nx, ny, L, N, nu, seed, dtype):
+    """srtm_loglik_grad_inputs: the log-likelihood against the IMKF with inputs and the gradient
+    against central differences of it (h = 1e-6), at the tolerances of the input-free test."""
+    srtm = _srtm()
+    m = wl.random_general_model(nx, ny, L, seed)
+    B, u = wl.random_inputs(nx, nu, L, N, seed + 2)
+    y = wl.simulate(m, N, seed + 1, B=B, u=u)
+    args = [_t(x, dtype) for x in (m.A, m.Q, m.C, m.R)] + [L] + [_t(x, dtype) for x in (m.m0, m.P0, y)]
+    print(f"[gpu] loglik_grad with inputs nx={nx} ny={ny} L={L} N={N} nu={nu} {dtype}", flush=True)
+    ll, dF, dQ, dR = srtm.loglik_grad(*args, B=_t(B, dtype), u=_t(u, dtype))
+    torch.cuda.synchronize()
+    r = {k: _rounded(v, dtype) for k, v in dict(A=m.A, Q=m.Q, C=m.C, R=m.R, m0=m.m0, P0=m.P0, y=y, B=B, u=u).items()}
+    ref_ll = oracle.imkf(r["A"], r["Q"], r["C"], r["R"], L, r["m0"], r["P0"], r["y"], B=r["B"], u=r["u"])[2]
+    tol_ll = 1e-10 if dtype == torch.float64 else 2e-5
+    assert abs(float(ll) - ref_ll) <= tol_ll * max(1.0, abs(ref_ll))
+    gA, gQ, gR = oracle.loglik_grad_fd(r["A"], r["Q"], r["C"], r["R"], L, r["m0"], r["P0"], r["y"], B=r["B"], u=r["u"])
+    tol = 1e-6 if dtype == torch.float64 else 1e-3
+    for name, got, want in (("F", dF, gA), ("Q", dQ, gQ), ("R", dR, gR)):
+        got = got.double().cpu().numpy()
+        scale = max(1.0, np.max(np.abs(want)))
+        err = np.max(np.abs(got - want)) / scale
+        print(f"[gpu]   d/d{name}: max rel err {err:.2e} (scale {scale:.3g})", flush=True)
+        assert err <= tol, f"d/d{name}: {err:.3e}"
+
+
+def test_gradient_with_zero_inputs_equals_gradient_without():
+    """u = 0 makes the input path reproduce the input-free gradient to rounding."""
+    srtm = _srtm()
+    nx, ny, L, N = 4, 2, 5, 400
+    m = wl.random_stable_model(nx, ny, L, 141)
+    y = wl.simulate(m, N, 142)
+    dt = torch.float64
+    args = [_t(x, dt) for x in (m.A, m.Q, m.C, m.R)] + [L] + [_t(x, dt) for x in (m.m0, m.P0, y)]
+    B = torch.randn(nx, 2, dtype=dt, device="cuda")
+    u = torch.zeros(N, L, 2, dtype=dt, device="cuda")
+    a = srtm.loglik_grad(*args)
+    b = srtm.loglik_grad(*args, B=B, u=u)
+    for x, z in zip(a, b):
+        assert torch.allclose(x, z, rtol=1e-12, atol=1e-12)
