@@ -438,27 +438,32 @@ def loglik_grad(F, Q, H, R, L: int, m0, P0, y, *, check: bool = True, B=None, u=
 
 
 class LogLikelihood(torch.autograd.Function):
-    """log p(y_{1:N}) as a differentiable function of F, Q and R. The forward pass runs the
-    filter scan only; the backward pass runs both scans again (nothing from the forward pass is
-    stored) and returns the gradient from the library."""
+    """log p(y_{1:N}) as a differentiable function of F, Q and R (known inputs B, u, if given, are
+    constants). The forward pass runs the filter scan only; the backward pass runs both scans
+    again (nothing from the forward pass is stored) and returns the gradient from the library."""
 
     @staticmethod
-    def forward(ctx, F, Q, R, H, m0, P0, y, L):
+    def forward(ctx, F, Q, R, H, m0, P0, y, L, B=None, u=None):
         ctx.save_for_backward(F, Q, R, H, m0, P0, y)
         ctx.L = int(L)
-        return loglik(F.detach(), Q.detach(), H.detach(), R.detach(), int(L), m0.detach(), P0.detach(), y.detach())
+        ctx.inputs = None if B is None else (B.detach(), u.detach())
+        inp = {} if B is None else dict(B=B.detach(), u=u.detach())
+        return loglik(F.detach(), Q.detach(), H.detach(), R.detach(), int(L), m0.detach(), P0.detach(), y.detach(),
+                      **inp)
 
     @staticmethod
     def backward(ctx, g):
         F, Q, R, H, m0, P0, y = ctx.saved_tensors
+        inp = {} if ctx.inputs is None else dict(B=ctx.inputs[0], u=ctx.inputs[1])
         _, dF, dQ, dR = loglik_grad(F.detach(), Q.detach(), H.detach(), R.detach(), ctx.L, m0.detach(),
-                                    P0.detach(), y.detach())
-        return g * dF, g * dQ, g * dR, None, None, None, None, None
+                                    P0.detach(), y.detach(), **inp)
+        return g * dF, g * dQ, g * dR, None, None, None, None, None, None, None
 
 
-def log_likelihood(F, Q, R, H, L: int, m0, P0, y) -> torch.Tensor:
-    """Differentiable log p(y_{1:N}) with respect to F, Q and R (see LogLikelihood)."""
-    return LogLikelihood.apply(F, Q, R, H, m0, P0, y, L)
+def log_likelihood(F, Q, R, H, L: int, m0, P0, y, B=None, u=None) -> torch.Tensor:
+    """Differentiable log p(y_{1:N}) with respect to F, Q and R (see LogLikelihood); B [nx, nu]
+    and u [N, L, nu] are optional known inputs."""
+    return LogLikelihood.apply(F, Q, R, H, m0, P0, y, L, B, u)
 
 
 class Batch:

@@ -159,3 +159,37 @@ def test_gradient_with_zero_inputs_equals_gradient_without():
     b = srtm.loglik_grad(*args, B=B, u=u)
     for x, z in zip(a, b):
         assert torch.allclose(x, z, rtol=1e-12, atol=1e-12)
+
+
+def test_autograd_with_inputs_matches_finite_differences():
+    """theta = (log q, log r, vec F) through torch.autograd with known inputs as constants."""
+    srtm = _srtm()
+    nx, ny, L, N, nu = 3, 1, 5, 150, 2
+    m = wl.random_stable_model(nx, ny, L, 151, rho=0.99, q=0.01, r=0.1)
+    B, u = wl.random_inputs(nx, nu, L, N, 152)
+    y = wl.simulate(m, N, 153, B=B, u=u)
+    dt = torch.float64
+    logq = torch.tensor(np.log(0.01), dtype=dt, device="cuda", requires_grad=True)
+    logr = torch.tensor(np.log(0.1), dtype=dt, device="cuda", requires_grad=True)
+    F = _t(m.A, dt).requires_grad_(True)
+    ll = srtm.log_likelihood(F, torch.exp(logq) * torch.eye(nx, dtype=dt, device="cuda"),
+                             torch.exp(logr) * torch.eye(ny, dtype=dt, device="cuda"), _t(m.C, dt), L, _t(m.m0, dt),
+                             _t(m.P0, dt), _t(y, dt), B=_t(B, dt), u=_t(u, dt))
+    ll.backward()
+
+    def ref(theta):
+        A = theta[2:].reshape(nx, nx)
+        return oracle.imkf(A, np.exp(theta[0]) * np.eye(nx), m.C, np.exp(theta[1]) * np.eye(ny), L, m.m0, m.P0, y,
+                           B=B, u=u)[2]
+
+    th = np.concatenate([[np.log(0.01), np.log(0.1)], m.A.ravel()])
+    fd = np.zeros_like(th)
+    for i in range(th.size):
+        e = np.zeros_like(th)
+        e[i] = 1e-6
+        fd[i] = (ref(th + e) - ref(th - e)) / 2e-6
+    got = np.concatenate([[logq.grad.item(), logr.grad.item()], F.grad.cpu().numpy().ravel()])
+    assert abs(ll.item() - ref(th)) <= 1e-10 * abs(ref(th))
+    err = np.max(np.abs(got - fd)) / max(1.0, np.max(np.abs(fd)))
+    print(f"[gpu] autograd theta grad with inputs max rel err {err:.2e}", flush=True)
+    assert err <= 1e-6
