@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "srtm_entry.h"
 #include "srtm_layout.h"
@@ -404,12 +405,12 @@ srtm_status srtm_batch_plan_ex(int32_t dtype, const srtm_seq_ex* seqs, int32_t n
   int64_t tiles = 0;
   size_t ws = 0;
   int32_t lmax = 1;
+  std::vector<size_t> block(nseq);  // each sequence's workspace block
   for (int32_t s = 0; s < nseq; ++s) {
-    size_t w = 0;
-    const srtm_status st = check_seq_ex(dtype, seqs[s], &w);
+    const srtm_status st = check_seq_ex(dtype, seqs[s], &block[s]);
     if (st != SRTM_OK) return st;
     tiles += (seqs[s].N + srtm::TILE - 1) / srtm::TILE;
-    ws += w;
+    ws += block[s];
     if (seqs[s].L > lmax) lmax = seqs[s].L;
   }
   if (tiles > INT32_MAX) return SRTM_E_UNSUPPORTED;
@@ -444,9 +445,7 @@ srtm_status srtm_batch_plan_ex(int32_t dtype, const srtm_seq_ex* seqs, int32_t n
     const int64_t nt = (q.N + srtm::TILE - 1) / srtm::TILE;
     for (int64_t t = 0; t < nt; ++t) map[t0 + t] = s;
     t0 += nt;
-    size_t w = 0;
-    check_seq_ex(dtype, q, &w);
-    off += w;
+    off += block[s];
   }
   return SRTM_OK;
 }
