@@ -19,7 +19,9 @@ inline __host__ __device__ int ceil_log2(int64_t x) {
 
 // Tile-level forward scan plan: each of the KS threads folds `chunk` (a power of two)
 // tiles, `active` threads take part in ceil_log2(active) Kogge-Stone steps, and the
-// constants kernel provides scan levels 0 .. nlev-1 (segments of 2^p windows).
+// constants kernel provides scan levels 0 .. nlev-1 (segments of 2^p windows): the in-tile
+// levels below LOG_TILE, the chunk level LOG_TILE + lchunk that the prior is folded with, and
+// one level per step above it (levels LOG_TILE + lchunk .. + steps - 1).
 struct ScanPlan {
   int64_t nt;
   int lchunk, active, steps, nlev;
@@ -31,7 +33,7 @@ inline __host__ __device__ ScanPlan make_scan_plan(int64_t N) {
   s.lchunk = ceil_log2((s.nt + KS - 1) / KS);
   s.active = (int)((s.nt + (int64_t(1) << s.lchunk) - 1) >> s.lchunk);
   s.steps = ceil_log2(s.active);
-  const int need = LOG_TILE + s.lchunk + s.steps + 1;
+  const int need = LOG_TILE + s.lchunk + (s.steps > 0 ? s.steps : 1);
   s.nlev = need > LOG_TILE + 1 ? need : LOG_TILE + 1;
   return s;
 }
