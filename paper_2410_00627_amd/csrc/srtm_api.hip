@@ -324,6 +324,18 @@ srtm_status srtm_batch_plan(int32_t nx, int32_t ny, int32_t dtype, const srtm_se
   return SRTM_OK;
 }
 
+// A batch descriptor's arrays, checked again when the table is launched (it may have been edited
+// since it was planned): the model, prior and measurements present, every array 16-byte aligned.
+static srtm_status check_desc_arrays(const srtm::SeqDesc& d) {
+  if (!d.F || !d.Q || !d.H || !d.R || !d.m0 || !d.P0 || !d.y) return SRTM_E_NULL;
+  const void* all[] = {d.F,       d.Q,       d.H,       d.R,       d.m0,      d.P0,      d.y,      d.ms_fast,
+                       d.Ps_fast, d.ms_slow, d.Ps_slow, d.mf_fast, d.Pf_fast, d.mf_slow, d.Pf_slow, d.B,
+                       d.u};
+  for (const void* q : all)
+    if (!aligned(q, 16)) return SRTM_E_ALIGN;
+  return SRTM_OK;
+}
+
 static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t nseq, const void* table_host,
                                 const void* table_dev, void* workspace, size_t workspace_bytes, int32_t* info,
                                 void* stream, bool grad) {
@@ -343,6 +355,8 @@ static srtm_status batch_common(int32_t nx, int32_t ny, int32_t dtype, int32_t n
     if (d[s].tile0 != tiles || d[s].smoother != 1) return SRTM_E_SHAPE;
     if (d[s].B || d[s].u || d[s].nu || d[s].tv || d[s].Cs_fast)  // batches: time-invariant, no inputs
       return SRTM_E_SHAPE;
+    st = check_desc_arrays(d[s]);
+    if (st != SRTM_OK) return st;
     const int32_t* map = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_host) +
                                                           srtm::batch_tile_map_offset(nseq));
     const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;
@@ -471,6 +485,8 @@ srtm_status srtm_smooth_batch_ex(int32_t dtype, int32_t nseq, const void* table_
     if (inputs != (d[s].u != nullptr) || (inputs ? (d[s].nu < 1 || d[s].nu > SRTM_MAX_NU) : d[s].nu != 0))
       return SRTM_E_SHAPE;
     if (d[s].tv != 0 && (d[s].tv != 1 || inputs || d[s].nx > srtm::TV_NX_MAX)) return SRTM_E_SHAPE;
+    st = check_desc_arrays(d[s]);
+    if (st != SRTM_OK) return st;
     const int64_t nt = (d[s].N + srtm::TILE - 1) / srtm::TILE;
     for (int64_t t = 0; t < nt; ++t)
       if (map[tiles + t] != s) return SRTM_E_SHAPE;

@@ -649,14 +649,20 @@ class Graph:
     def record(self, enqueue):
         """Runs enqueue() with the capture stream current, capturing what it enqueues."""
         torch.cuda.synchronize(self.device)
+        h = ctypes.c_void_p()
         with torch.cuda.stream(self.stream):
             _check(lib().srtm_graph_begin(ctypes.c_void_p(self.stream.cuda_stream)), "srtm_graph_begin")
             try:
                 enqueue()
-            finally:
-                h = ctypes.c_void_p()
-                code = lib().srtm_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+            except BaseException:
+                # end the capture so that the stream is usable again, and drop what it recorded
+                if lib().srtm_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)) == 0 and h.value:
+                    lib().srtm_graph_destroy(h)
+                raise
+            code = lib().srtm_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         _check(code, "srtm_graph_end")
+        if self.exec is not None:
+            lib().srtm_graph_destroy(self.exec)
         self.exec = h
         torch.cuda.synchronize(self.device)
 

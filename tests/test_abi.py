@@ -486,6 +486,31 @@ def test_smooth_batch_ex_host_validation(L):
     assert L.srtm_smooth_batch_ex(1, n, host, dev, ws, wsz, None, None) == 2
 
 
+@pytest.mark.parametrize("field,value,code", [(0, 0, 1), (6, 0, 1), (6, 0x200008, 5), (8, 0x200004, 5)],
+                         ids=["F-null", "y-null", "y-misaligned", "Ps_fast-misaligned"])
+def test_batch_launch_rechecks_descriptor_arrays(L, field, value, code):
+    """Both batch entry points check each descriptor's arrays again at launch: a table edited
+    after planning (a required array removed, an array moved off 16-byte alignment) is refused
+    before anything is enqueued. Descriptor pointer j sits at byte 8 j (F, Q, H, R, m0, P0, y, then
+    the outputs)."""
+    _no_gpu()
+    dev, ws = ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x8000000)
+    # per-pair batch
+    arr = _seqs([(300, 5), (600, 7)])
+    _, tsz, wsz, _, _ = _plan(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    ctypes.c_uint64.from_buffer(buf, 8 * field).value = value
+    assert L.srtm_smooth_batch(4, 2, 1, 2, ctypes.cast(buf, ctypes.c_void_p), dev, ws, wsz, None, None) == code
+    # mixed batch: the second descriptor
+    arr = _seqs_ex(MIXED)
+    _, tsz, wsz, _, _ = _plan_ex(arr)
+    buf = (ctypes.c_uint8 * tsz)()
+    assert _plan_ex(arr, table=ctypes.cast(buf, ctypes.c_void_p), nbytes=tsz)[0] == 0
+    ctypes.c_uint64.from_buffer(buf, DESC_BYTES + 8 * field).value = value
+    assert L.srtm_smooth_batch_ex(1, len(MIXED), ctypes.cast(buf, ctypes.c_void_p), dev, ws, wsz, None, None) == code
+
+
 def test_graph_entry_points_validate(L):
     h = ctypes.c_void_p()
     assert L.srtm_graph_begin(None) == 1

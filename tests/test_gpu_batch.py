@@ -143,6 +143,37 @@ def test_batch_runner_graph_replays_match_eager():
     g.check()
 
 
+def test_graph_record_error_leaves_the_stream_usable():
+    """An exception raised while a graph is being recorded ends the capture: the same Graph then
+    records the batch normally, and its replay matches the eager call bitwise."""
+    srtm = _srtm()
+    specs = [(4, 1, 10, 300, 61), (4, 1, 5, 40, 62)]
+    probs, _, _ = _problems(srtm, specs, torch.float64)
+    b = srtm.Batch(probs)
+    b.launch()
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in o.items()} for o in b.outputs]
+    g = srtm.Graph(torch.device("cuda"))
+
+    def failing():
+        b.launch()
+        raise RuntimeError("planted failure while recording")
+
+    with pytest.raises(RuntimeError, match="planted failure"):
+        g.record(failing)
+    assert g.exec is None
+    print("[gpu] capture ended after the planted failure; recording again", flush=True)
+    g.record(b.launch)
+    for o in b.outputs:
+        for v in o.values():
+            v.fill_(float("nan"))
+    g.replay()
+    torch.cuda.synchronize()
+    for j, o in enumerate(b.outputs):
+        for k in ref[j]:
+            assert torch.equal(o[k], ref[j][k]), f"sequence {j}, {k}"
+
+
 def test_autotune_picks_a_configuration_with_identical_results():
     srtm = _srtm()
     from paper_2410_00627_amd import batching
