@@ -92,15 +92,55 @@ def cpu_baseline(model, y, n_windows):
                 host=host_record())
 
 
+def _oracle_sequence(job):
+    """Worker of cpu_baseline_batched: the oracle's smoother on one sequence, one BLAS thread;
+    returns (fast states, seconds)."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    m, y = job
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.srtm_smoother(m.A, m.Q, m.C, m.R, m.L, m.m0, m.P0, y)
+        return y.shape[0] * m.L, time.perf_counter() - t0
+
+
+def cpu_baseline_batched(specs, stride):
+    """The oracle on one sequence in `stride` of the batched workload, one sequence per worker
+    process on the usable host cores, at most 16 (largest sequences first). Run before the process
+    touches the GPU: the workers are forked."""
+    import multiprocessing as mp
+    from paper_2410_00627_amd import workloads as wl
+    sample = specs[::stride]
+    jobs = []
+    for nx, L, N, seed in sorted(sample, key=lambda s: -s[2] * s[1] * s[0] ** 3):
+        m = wl.batched_model(nx, L, seed)
+        jobs.append((m, wl.simulate(m, N, seed + 1)))
+    host = host_record()
+    cores = max(1, min(int(host["nproc"] or 1), 16, len(jobs)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = list(pool.imap_unordered(_oracle_sequence, jobs, chunksize=1))
+    wall = time.perf_counter() - t0
+    states = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    return dict(value=states / wall, unit="fast-rate smoothed states/s", cores=cores, kind="oracle",
+                sample=f"one sequence in {stride} of the {len(specs)} ({len(jobs)} sequences, {states} fast "
+                       f"states), one sequence per worker process on {cores} processes: {wall:.2f} s wall, "
+                       f"{busy:.1f} s of smoothing; the oracle as it stands (float64, dense window filter, "
+                       f"numpy, one BLAS thread per process)",
+                host=host)
+
+
 def run_batched(args):
     """256 independent sequences (nx in {2,4,6}, L in {5,10,20}, N log-uniform in [2^8, 2^14],
     ny = 1): the autotuned batched path against one srtm_smooth call per sequence."""
     import torch
     from paper_2410_00627_amd import batching, srtm, workloads as wl
     dt = torch.float64 if (args.dtype or "f32") == "f64" else torch.float32
+    specs = wl.batched_specs()
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batched(specs, args.cpu_stride)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    specs = wl.batched_specs()
     problems = []
     for nx, L, N, seed in specs:
         m = wl.batched_model(nx, L, seed)
@@ -187,6 +227,8 @@ def run_batched(args):
             "plain_per_sequence": {"ms_per_pass": round(t_plain * 1e3, 4),
                                    "value": round(fast_states / t_plain), "bitwise_equal_to_batched": same},
             "speedup_vs_plain": round(t_plain / t_batch, 2), "fp64_check": check64}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line))
 
 
@@ -563,6 +605,8 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override the number of windows")
     ap.add_argument("--cpu-windows", type=int, default=None, help="windows timed on the CPU (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=4,
+                    help="batched: the CPU baseline smooths one sequence in cpu-stride")
     ap.add_argument("--no-profile-events", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="headline: skip the sequential GPU comparator")
     ap.add_argument("--no-other-precision", action="store_true",
