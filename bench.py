@@ -41,9 +41,9 @@ def algorithmic_bytes(nx, ny, L, N, esz):
     return N * (ny + 2 * st + st + L * st) * esz
 
 
-def profiled_traffic(kernel, dtype):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when that summary was taken on a different kernel source (its sha must match)."""
+def profiled_record(dtype):
+    """The machine-readable record of the committed rocprofv3 summary for `dtype`, or None when
+    that summary was taken on a different kernel source (its sha must match)."""
     import hashlib
     src = os.path.join(ROOT, "paper_2410_00627_amd", "csrc", "srtm_kernels.hip")
     prof = os.path.join(ROOT, "profiles", f"srtm_smooth_kernels_headline_{dtype}.md")
@@ -53,10 +53,24 @@ def profiled_traffic(kernel, dtype):
     for line in open(prof):
         if line.startswith("machine-readable: "):
             d = json.loads(line[len("machine-readable: "):])
-            t = d.get("traffic", {}).get(kernel)
-            if d.get("sha") == sha and t:
-                return int(round(t["read_bytes"] + t["write_bytes"]))
+            return d if d.get("sha") == sha else None
     return None
+
+
+def profiled_traffic(kernel, dtype):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy calibration), or None."""
+    d = profiled_record(dtype)
+    t = (d or {}).get("traffic", {}).get(kernel)
+    return int(round(t["read_bytes"] + t["write_bytes"])) if t else None
+
+
+def profiled_avg_ms(kernel, dtype):
+    """Average duration of `kernel` in the committed kernel trace (rocprofv3 --kernel-trace
+    --stats of the same bench command), or None."""
+    d = profiled_record(dtype)
+    v = (d or {}).get("trace_avg_us", {}).get(kernel)
+    return None if v is None else round(v / 1e3, 5)
 
 
 def host_record():
@@ -772,7 +786,8 @@ def measure_headline(model, y, dtype, args):
         ach = alg / (dom_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(dom, tag),
-                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(dom_ms, 5)}
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(dom_ms, 5),
+                "profiled_avg_ms": profiled_avg_ms(dom, tag)}
     whole = alg / (ms_per_step * 1e-3) / 1e9
     return {
         "ms_per_step": ms_per_step,

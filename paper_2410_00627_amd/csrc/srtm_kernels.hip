@@ -54,6 +54,26 @@ SRTM_DEV void put_global(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// Staged copy of n scalars with the nthr threads of a workgroup: value q = ld(q) is handed to
+// st(q, value). Each thread issues up to B loads before its first store.
+template <int B, typename T, class LD, class ST>
+SRTM_DEV void staged_copy(int n, int tid, int nthr, LD ld, ST st) {
+#pragma unroll 1
+  for (int base = 0; base < n; base += B * nthr) {
+    T v[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int q = base + i * nthr + tid;
+      v[i] = (q < n) ? ld(q) : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int q = base + i * nthr + tid;
+      if (q < n) st(q, v[i]);
+    }
+  }
+}
+
 // ============================================================================ constants
 // Cofactor (r, c) of the NX x NX row-major matrix M: (-1)^{r+c} times the determinant of M
 // without row r and column c.
@@ -2318,6 +2338,9 @@ SRTM_DEV auto recover_model(const T* __restrict__ cst, int L, const InputView<T>
 
 struct NoSteps {};
 
+// Fast steps whose tables the time-invariant recovery holds in LDS at a time.
+constexpr int RSTEPS = 32;
+
 // K7: fast-rate recovery, one window per lane and a loop over the window's fast steps.
 // MODE bit 1: filter blocks p(x_{k,i} | y_{1:k}); bit 2: smoothed blocks p(x_{k,i} | y_{1:N})
 // (and the smoother's slow state, block i = 1) from the correction (v, W) that K3s left as
@@ -2406,10 +2429,29 @@ SRTM_DEV void recover_body(const T* __restrict__ y, int64_t N, int L, int ilim, 
 #pragma unroll 1
   for (int i = 1; i <= ilim; ++i) {
     T mf[NX], Pii[NX][NX], PiL[NX][NX];
-    if constexpr (TV)
+    if constexpr (!TV) {
+      // The per-step tables go to LDS, RSTEPS steps at a time: read per step as wave-uniform
+      // scalar loads they outgrow the scalar registers (spilled to vector-register lanes and
+      // read back every step).
+      if ((i - 1) % RSTEPS == 0) {
+        const int n = (ilim - i + 1 < RSTEPS ? ilim - i + 1 : RSTEPS) * M.lay.per_i_stride;
+        const T* src = M.per_i(i);
+        __syncthreads();  // every wave is done with the previous steps' tables
+        staged_copy<8, T>(n, tid, TILE, [&](int q) { return gld(src + q); }, [&](int q, T v) { mdl[q] = v; });
+        __syncthreads();
+      }
+    }
+    if constexpr (TV) {
       steps.template next<SMOOTH, true>(M, L, w, mf, Pii, PiL);
-    else
-      window_step<T, NX, NY, SMOOTH>(M, w, i, mf, Pii, PiL);
+    } else {  // step i's A^i, c_i, Q_ii and Q_il from the LDS copy
+      const T* ps = mdl + ((i - 1) % RSTEPS) * M.lay.per_i_stride;
+      T Ai[NX][NX], ci[NX][NY];
+      load(Ai, ps + M.lay.o_Ai);
+      load(ci, ps + M.lay.o_ci);
+      step_blocks<SMOOTH>(
+          w, Ai, ci, [&](int r, int c) { return ps[M.lay.o_Qii + r * NX + c]; },
+          [&](int r, int c) { return ps[M.lay.o_QiL + r * NX + c]; }, mf, Pii, PiL);
+    }
     if constexpr (INP) {  // z_i = A z_{i-1} + B u_{k,i-1}, the loads of step i+1 issued first
       T uc[NU_MAX];
 #pragma unroll
@@ -4028,7 +4070,10 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   SRTM_CHECK_LAUNCH();
   SRTM_EV(ev.post(st));
 
-  const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES * ((rec_mode == 3) ? 2 : 1);
+  // output staging, then the per-step tables of up to RSTEPS fast steps
+  const size_t ptab = sizeof(T) * (size_t)(g.max_L < RSTEPS ? g.max_L : RSTEPS) *
+                      make_const_layout(NX, NY, g.max_L).per_i_stride;
+  const size_t lds_rec = (size_t)4 * OutStage<T, NX>::BYTES * ((rec_mode == 3) ? 2 : 1) + ptab;
   if (!smoother) {
     const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
     if (!allow_lds((const void*)k_fwd_final<T, NX, NY, INP>, lds_ff)) return SRTM_E_HIP;
@@ -4082,7 +4127,7 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
     hipLaunchKernelGGL((k_recover<T, NX, NY, 3, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
     SRTM_CHECK_LAUNCH();
   } else if (rec_mode == 3) {  // filter and smoother staging do not fit together: two passes
-    const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES;
+    const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES + ptab;
     if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds1)) return SRTM_E_HIP;
     if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds1)) return SRTM_E_HIP;
     hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
@@ -4340,7 +4385,8 @@ void stage_lds(bool tv, int max_L, int nlev_max, size_t (&o)[6]) {
     up(1, fwd_reduce_lds_bytes<T, NX>());
     up(2, sizeof(T) * ((size_t)KS * (NX + NN) + (size_t)(nlev_max - LOG_TILE) * make_const_layout(NX, NY, 1).lev_stride));
     up(3, sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN));
-    up(5, (size_t)4 * OutStage<T, NX>::BYTES);
+    up(5, (size_t)4 * OutStage<T, NX>::BYTES +
+              sizeof(T) * (size_t)(max_L < RSTEPS ? max_L : RSTEPS) * make_const_layout(NX, NY, max_L).per_i_stride);
   } else {
     if constexpr (NX <= TV_NX_MAX) {
       constexpr int FA = 3 * NN + 2 * NX;
