@@ -27,6 +27,8 @@
 //  * Models given per window (time varying) share nothing between elements: their kernels
 //    (k_tv_*) build each window's constants and element in one lane and scan whole elements.
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "srtm_device.h"
@@ -4015,6 +4017,22 @@ struct Events {
     if (_e != hipSuccess) return SRTM_E_HIP;   \
   } while (0)
 
+// One launch that is a stage of its own. In a profiled call (per-stage events given) the stage's
+// two events are taken by the dispatch itself (hipExtLaunchKernelGGL), so that they time the
+// kernel alone rather than also the gap before it; otherwise a plain launch (calls recorded into a
+// graph carry no events).
+#define SRTM_STAGE(kernel, grid, block, lds, st, ...)                                               \
+  do {                                                                                             \
+    if (ev.ev && 2 * ev.j + 1 < ev.n) {                                                            \
+      hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)(lds), st, ev.ev[2 * ev.j],         \
+                            ev.ev[2 * ev.j + 1], 0u, __VA_ARGS__);                                 \
+    } else {                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                               \
+    }                                                                                              \
+    ++ev.j;                                                                                        \
+    SRTM_CHECK_LAUNCH();                                                                           \
+  } while (0)
+
 #define SRTM_EV(call)                          \
   do {                                         \
     if ((call) != hipSuccess) return SRTM_E_HIP; \
@@ -4049,26 +4067,17 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   constexpr int NN = NX * NX;
   const size_t lds0 = constants_lds_bytes(NX, NY, g.max_L);
   if (!allow_lds((const void*)k_constants<T, NX, NY>, lds0)) return SRTM_E_HIP;
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_constants<T, NX, NY>), dim3(g.nseq), dim3(256), lds0, st, b);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
+  SRTM_STAGE((k_constants<T, NX, NY>), dim3(g.nseq), dim3(256), lds0, st, b);
 
-  SRTM_EV(ev.pre(st));
   constexpr size_t lds_red = fwd_reduce_lds_bytes<T, NX>();
-  hipLaunchKernelGGL((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles + g.nseq), dim3(TILE), lds_red, st, b, (int)g.nseq);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
+  SRTM_STAGE((k_fwd_reduce<T, NX, NY, INP>), dim3(g.ntiles + g.nseq), dim3(TILE), lds_red, st, b, (int)g.nseq);
 
   // slots, then the level records LOG_TILE .. nlev-1 of the longest sequence of the call
   const int nlev_max = make_scan_plan((int64_t)g.ntiles * TILE).nlev;
   const size_t lds_ft = sizeof(T) * ((size_t)KS * (NX + NN) +
                                      (size_t)(nlev_max - LOG_TILE) * make_const_layout(NX, NY, 1).lev_stride);
   if (!allow_lds((const void*)k_fwd_tiles<T, NX, NY>, lds_ft)) return SRTM_E_HIP;
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ft, st, b);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
+  SRTM_STAGE((k_fwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_ft, st, b);
 
   // output staging, then the per-step tables of up to RSTEPS fast steps
   const size_t ptab = sizeof(T) * (size_t)(g.max_L < RSTEPS ? g.max_L : RSTEPS) *
@@ -4077,65 +4086,57 @@ srtm_status launch_all(const Batch& b, const Launch& g, bool smoother, int rec_m
   if (!smoother) {
     const size_t lds_ff = sizeof(T) * (size_t)TILE * ((2 * NX > NX + NN) ? 2 * NX : NX + NN);
     if (!allow_lds((const void*)k_fwd_final<T, NX, NY, INP>, lds_ff)) return SRTM_E_HIP;
-    SRTM_EV(ev.pre(st));
-    hipLaunchKernelGGL((k_fwd_final<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_ff, st, b);
-    SRTM_CHECK_LAUNCH();
-    SRTM_EV(ev.post(st));
-    SRTM_EV(ev.pre(st));
+    SRTM_STAGE((k_fwd_final<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_ff, st, b);
     if (rec_mode == 1) {
       if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds_rec)) return SRTM_E_HIP;
-      hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
-      SRTM_CHECK_LAUNCH();
-    } else if (rec_mode == REC_LL) {
-      hipLaunchKernelGGL((k_stats<T, NX, NY, false, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
-      SRTM_CHECK_LAUNCH();
-      hipLaunchKernelGGL((k_stats_final<T, NX, NY, false>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
-                         lo.dR);
-      SRTM_CHECK_LAUNCH();
+      SRTM_STAGE((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+    } else {
+      SRTM_EV(ev.pre(st));
+      if (rec_mode == REC_LL) {
+        hipLaunchKernelGGL((k_stats<T, NX, NY, false, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+        SRTM_CHECK_LAUNCH();
+        hipLaunchKernelGGL((k_stats_final<T, NX, NY, false>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF,
+                           lo.dQ, lo.dR);
+        SRTM_CHECK_LAUNCH();
+      }
+      SRTM_EV(ev.post(st));
     }
-    SRTM_EV(ev.post(st));
     return SRTM_OK;
   }
 
   const size_t lds_fb = sizeof(T) * (size_t)TILE * ((2 * NN + NX > NX + NN) ? 2 * NN + NX : NX + NN);
   if (!allow_lds((const void*)k_fwd_bwd<T, NX, NY, INP>, lds_fb)) return SRTM_E_HIP;
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_fwd_bwd<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_fb, st, b);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
+  SRTM_STAGE((k_fwd_bwd<T, NX, NY, INP>), dim3(g.ntiles), dim3(TILE), lds_fb, st, b);
 
   const size_t lds_bk = sizeof(T) * (size_t)KS * (2 * NN + NX);
   if (!allow_lds((const void*)k_bwd_tiles<T, NX, NY>, lds_bk)) return SRTM_E_HIP;
-  SRTM_EV(ev.pre(st));
-  hipLaunchKernelGGL((k_bwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_bk, st, b);
-  SRTM_CHECK_LAUNCH();
-  SRTM_EV(ev.post(st));
+  SRTM_STAGE((k_bwd_tiles<T, NX, NY>), dim3(g.nseq), dim3(KS), lds_bk, st, b);
 
-  SRTM_EV(ev.pre(st));
-  if (rec_mode == REC_GRAD) {
-    hipLaunchKernelGGL((k_stats<T, NX, NY, true, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
-    SRTM_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
-                       lo.dR);
-    SRTM_CHECK_LAUNCH();
-  } else if (rec_mode == 2) {
+  if (rec_mode == 2) {
     if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds_rec)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
-    SRTM_CHECK_LAUNCH();
+    SRTM_STAGE((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
   } else if (rec_mode == 3 && lds_rec <= kMaxLdsBytes) {
     if (!allow_lds((const void*)k_recover<T, NX, NY, 3, INP>, lds_rec)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 3, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
-    SRTM_CHECK_LAUNCH();
-  } else if (rec_mode == 3) {  // filter and smoother staging do not fit together: two passes
-    const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES + ptab;
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds1)) return SRTM_E_HIP;
-    if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds1)) return SRTM_E_HIP;
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
-    SRTM_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
-    SRTM_CHECK_LAUNCH();
+    SRTM_STAGE((k_recover<T, NX, NY, 3, INP>), dim3(g.ntiles), dim3(TILE), lds_rec, st, b);
+  } else {
+    SRTM_EV(ev.pre(st));
+    if (rec_mode == REC_GRAD) {
+      hipLaunchKernelGGL((k_stats<T, NX, NY, true, INP>), dim3(g.ntiles), dim3(TILE), 0, st, b);
+      SRTM_CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_stats_final<T, NX, NY, true>), dim3(g.nseq), dim3(256), 0, st, b, lo.ll, lo.dF, lo.dQ,
+                         lo.dR);
+      SRTM_CHECK_LAUNCH();
+    } else if (rec_mode == 3) {  // filter and smoother staging do not fit together: two passes
+      const size_t lds1 = (size_t)4 * OutStage<T, NX>::BYTES + ptab;
+      if (!allow_lds((const void*)k_recover<T, NX, NY, 1, INP>, lds1)) return SRTM_E_HIP;
+      if (!allow_lds((const void*)k_recover<T, NX, NY, 2, INP>, lds1)) return SRTM_E_HIP;
+      hipLaunchKernelGGL((k_recover<T, NX, NY, 1, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+      SRTM_CHECK_LAUNCH();
+      hipLaunchKernelGGL((k_recover<T, NX, NY, 2, INP>), dim3(g.ntiles), dim3(TILE), lds1, st, b);
+      SRTM_CHECK_LAUNCH();
+    }
+    SRTM_EV(ev.post(st));
   }
-  SRTM_EV(ev.post(st));
   return SRTM_OK;
 }
 

@@ -138,6 +138,36 @@ def test_bitwise_deterministic(dtype):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_profiled_call_times_each_kernel_and_keeps_the_outputs(dtype):
+    """srtm_smooth with per-kernel events (the profiled entry point bench.py times with) gives
+    bitwise the outputs of the plain call; every stage's interval is positive, each starts no
+    earlier than the previous one ends, and the call's span covers their sum."""
+    srtm = _need_gpu()
+    from paper_2410_00627_amd.hip_events import EventArray
+    import ctypes
+    m = wl.random_stable_model(4, 2, 20, 77)
+    y = wl.simulate(m, 2000, 78)
+    F, Q, H, R, m0, P0 = srtm.model_tensors(m, "cuda", dtype)
+    yt = torch.as_tensor(y, dtype=torch.float64).to("cuda", dtype)
+    plain = srtm.smooth(F, Q, H, R, 20, m0, P0, yt)
+    names = srtm.kernel_names(True)
+    ev = EventArray(2 * len(names))
+    print(f"[gpu] profiled call, {len(names)} stages, dtype={dtype}", flush=True)
+    prof = srtm.smooth(F, Q, H, R, 20, m0, P0, yt, events=(ctypes.c_void_p * len(ev))(*ev.arr))
+    torch.cuda.synchronize()
+    for k in plain:
+        assert torch.equal(plain[k], prof[k]), k
+    dur = [ev.elapsed_ms(2 * j, 2 * j + 1) for j in range(len(names))]
+    gaps = [ev.elapsed_ms(2 * j - 1, 2 * j) for j in range(1, len(names))]
+    span = ev.elapsed_ms(0, 2 * len(names) - 1)
+    ev.close()
+    print(f"[gpu]   stages (ms) {dict(zip(names, [round(d, 4) for d in dur]))}, span {span:.4f}", flush=True)
+    assert all(d > 0 for d in dur)
+    assert all(g >= -1e-3 for g in gaps)
+    assert span >= sum(dur) - 1e-3
+
+
 def test_info_flags_forced_from_host():
     """Conditions forced through the inputs (kernels still exit normally)."""
     srtm = _need_gpu()
