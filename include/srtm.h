@@ -147,10 +147,11 @@ srtm_status srtm_smooth_sequential(const srtm_shape* shape,
                                    void* ms_fast, void* Ps_fast, void* ms_slow, void* Ps_slow,
                                    void* workspace, size_t workspace_bytes, int32_t* info, void* stream);
 
-/* Profiling variant of srtm_smooth: identical work, and additionally records
- * events[2j] before and events[2j+1] after the j-th kernel it enqueues, j = 0 ..
- * srtm_kernel_count(1) - 1. `events` holds caller-created hipEvent_t handles and
- * n_events must be at least 2 * srtm_kernel_count(1). For measurement only. */
+/* Profiling variant of srtm_smooth: identical work, and additionally sets events[2j] to the
+ * start and events[2j+1] to the end of the j-th kernel it enqueues, j = 0 ..
+ * srtm_kernel_count(1) - 1 (taken by the kernel's dispatch, so each interval is that kernel's
+ * execution). `events` holds caller-created hipEvent_t handles and n_events must be at least
+ * 2 * srtm_kernel_count(1). For measurement only; not for graph capture. */
 srtm_status srtm_smooth_profiled(const srtm_shape* shape,
                                  const void* F, const void* Q, const void* H, const void* R,
                                  const void* m0, const void* P0, const void* y,
