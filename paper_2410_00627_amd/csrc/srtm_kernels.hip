@@ -248,7 +248,7 @@ SRTM_DEV void chain_tail_body(T* __restrict__ cst, const double* __restrict__ ha
 }
 
 // One workgroup, float64 throughout. Per-step tables are built in LDS by parallel
-// loops; the slow-rate constants and the level tables by one lane in registers.
+// loops; the slow-rate constants and the level tables by the lanes of wave 0.
 //
 // With Q_ij = Cov(x_{k,i}, x_{k,j} | x_{k-1,l}) = sum_{t=1..min(i,j)} A^{i-t} Q A^{(j-t)T}:
 //   Q_ii = sum_{t=0}^{i-1} A^t Q A^{tT},   Q_il = Q_ii (A^{l-i})^T,
@@ -296,169 +296,204 @@ SRTM_DEV void constants_body(const T* __restrict__ Fm, const T* __restrict__ Qm,
     }
     __syncthreads();
   }
-  // W1[t] = A^t Q, W2[t] = A^t Q A^tT, t = 0..L-1
+  // W2[t] = A^t Q A^tT, t = 0..L-1: one entry of the upper triangle per item, mirrored, so that
+  // every sum of these blocks is exactly symmetric.
   for (int e = tid; e < L * NN; e += nthr) {
     const int t = e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
+    if (c < r) continue;
+    const double* At = Apow + t * NN;
     double acc = 0.0;
-    for (int k = 0; k < NX; ++k) acc += Apow[t * NN + r * NX + k] * sQ[k * NX + c];
-    W1[t * NN + rc] = acc;
-  }
-  __syncthreads();
-  for (int e = tid; e < L * NN; e += nthr) {
-    const int t = e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
-    double acc = 0.0;
-    for (int k = 0; k < NX; ++k) acc += W1[t * NN + r * NX + k] * Apow[t * NN + c * NX + k];
-    W2[t * NN + rc] = acc;
-  }
-  __syncthreads();
-  // Q_ii = sum_{t<i} W2[t]  (running sum, symmetrised afterwards)
-  for (int e = tid; e < NN; e += nthr) {
-    double acc = 0.0;
-    Qii[e] = 0.0;
-    for (int t = 0; t < L; ++t) {
-      acc += W2[t * NN + e];
-      Qii[(t + 1) * NN + e] = acc;
+    for (int k = 0; k < NX; ++k) {
+      double aq = 0.0;
+      for (int j = 0; j < NX; ++j) aq += At[r * NX + j] * sQ[j * NX + k];
+      acc += aq * At[c * NX + k];
     }
+    W2[t * NN + r * NX + c] = acc;
+    W2[t * NN + c * NX + r] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < L * NN; e += nthr) {
-    const int i = 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
-    if (c > r) {
-      const double s = 0.5 * (Qii[i * NN + r * NX + c] + Qii[i * NN + c * NX + r]);
-      Qii[i * NN + r * NX + c] = s;
-      Qii[i * NN + c * NX + r] = s;
+  // Q_ii = sum_{t<i} W2[t] (Qii[0] = 0) and W1[s] = Sig_s = sum_{u=0}^{s} A^u. Item (i, rc) forms
+  // entry rc of Q_{i+1,i+1} (i < l) and of Sig_i, each as four independent partial sums (a
+  // running sum would chain one LDS round trip per term).
+  auto sum_blocks = [&](const double* src, int n, int rc) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = 0;
+    for (; t + 4 <= n; t += 4) {
+      a0 += src[t * NN + rc];
+      a1 += src[(t + 1) * NN + rc];
+      a2 += src[(t + 2) * NN + rc];
+      a3 += src[(t + 3) * NN + rc];
     }
+    for (; t < n; ++t) a0 += src[t * NN + rc];
+    return (a0 + a1) + (a2 + a3);
+  };
+  for (int e = tid; e < (L + 1) * NN; e += nthr) {
+    const int i = e / NN, rc = e % NN;
+    if (i < L) Qii[(i + 1) * NN + rc] = sum_blocks(W2, i + 1, rc);
+    if (i == 0) Qii[rc] = 0.0;
+    W1[i * NN + rc] = sum_blocks(Apow, i + 1, rc);
   }
   __syncthreads();
-  // W1[s] = Sig_s = sum_{u=0}^{s} A^u, s = 0..L
-  for (int e = tid; e < NN; e += nthr) {
-    double acc = 0.0;
-    for (int s = 0; s <= L; ++s) {
-      acc += Apow[s * NN + e];
-      W1[s * NN + e] = acc;
-    }
-  }
-  __syncthreads();
-  // CS[s] = C Sig_s (NY x NX) in W2[0 ..], QC[j] = Q_jj C^T (NX x NY) in W2[(L+1) NXY ..]
+  // CS[s] = C Sig_s (NY x NX) in W2[0 ..], QC[j] = Q_jj C^T (NX x NY) in W2[(L+1) NXY ..]; beside
+  // them the per-step tables go to the constants block: A^i, Q_ii, Q_il = Q_ii (A^{l-i})^T, and
+  // A, Q. Every entry of the model part (below the level tables) also goes, unrounded, to the
+  // float64 copy.
   double* CS = W2;
   double* QC = W2 + (L + 1) * NXY;
-  for (int e = tid; e < (L + 1) * NXY; e += nthr) {
-    const int s = e / NXY, rc = e % NXY;
-    {
-      const int r = rc / NX, c = rc % NX;   // CS: NY x NX
-      double acc = 0.0;
-      for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * W1[s * NN + k * NX + c];
-      CS[s * NXY + rc] = acc;
-    }
-    {
-      const int r = rc / NY, c = rc % NY;   // QC: NX x NY
-      double acc = 0.0;
-      for (int k = 0; k < NX; ++k) acc += Qii[s * NN + r * NX + k] * sC[c * NX + k];
-      QC[s * NXY + rc] = acc;
-    }
-  }
-  __syncthreads();
-  // c_i = (1/l) [ sum_{j<i} A^{i-j} Q_jj C^T + Q_ii (C Sig_{l-i})^T ]
-  for (int e = tid; e < L * NXY; e += nthr) {
-    const int i = 1 + e / NXY, rc = e % NXY, r = rc / NY, c = rc % NY;
-    double acc = 0.0;
-    for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * CS[(L - i) * NXY + c * NX + k];
-    for (int j = 1; j < i; ++j)
-      for (int k = 0; k < NX; ++k) acc += Apow[(i - j) * NN + r * NX + k] * QC[j * NXY + k * NY + c];
-    ci[i * NXY + rc] = acc / (double)L;
-  }
-  __syncthreads();
-
-  // Per-step tables to the constants block: A^i, Q_ii, Q_il = Q_ii (A^{l-i})^T, c_i. Every entry of
-  // the model part (below the level tables) also goes, unrounded, to the float64 copy.
   auto put = [&](int off, double v) {
     cst[off] = (T)v;
     cst64[off] = v;
   };
-  for (int e = tid; e < L * NN; e += nthr) {
-    const int i = 1 + e / NN, rc = e % NN, r = rc / NX, c = rc % NX;
-    const int base = lay.per_i + (i - 1) * lay.per_i_stride;
-    put(base + lay.o_Ai + rc, Apow[i * NN + rc]);
-    put(base + lay.o_Qii + rc, Qii[i * NN + rc]);
-    double acc = 0.0;
-    for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * Apow[(L - i) * NN + c * NX + k];
-    put(base + lay.o_QiL + rc, acc);
+  for (int e = tid; e < (L + 1) * NXY + (L + 1) * NN; e += nthr) {
+    if (e < (L + 1) * NXY) {
+      const int s = e / NXY, rc = e % NXY;
+      {
+        const int r = rc / NX, c = rc % NX;  // CS: NY x NX
+        double acc = 0.0;
+        for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * W1[s * NN + k * NX + c];
+        CS[s * NXY + rc] = acc;
+      }
+      {
+        const int r = rc / NY, c = rc % NY;  // QC: NX x NY
+        double acc = 0.0;
+        for (int k = 0; k < NX; ++k) acc += Qii[s * NN + r * NX + k] * sC[c * NX + k];
+        QC[s * NXY + rc] = acc;
+      }
+    } else if (e < (L + 1) * NXY + L * NN) {
+      const int e2 = e - (L + 1) * NXY;
+      const int i = 1 + e2 / NN, rc = e2 % NN, r = rc / NX, c = rc % NX;
+      const int base = lay.per_i + (i - 1) * lay.per_i_stride;
+      put(base + lay.o_Ai + rc, Apow[i * NN + rc]);
+      put(base + lay.o_Qii + rc, Qii[i * NN + rc]);
+      double acc = 0.0;
+      for (int k = 0; k < NX; ++k) acc += Qii[i * NN + r * NX + k] * Apow[(L - i) * NN + c * NX + k];
+      put(base + lay.o_QiL + rc, acc);
+    } else {
+      const int q = e - (L + 1) * NXY - L * NN;
+      put(lay.A + q, sA[q]);
+      put(lay.Q + q, sQ[q]);
+    }
   }
-  for (int e = tid; e < L * NXY; e += nthr) {
-    const int i = 1 + e / NXY, rc = e % NXY;
-    put(lay.per_i + (i - 1) * lay.per_i_stride + lay.o_ci + rc, ci[i * NXY + rc]);
-  }
-  for (int e = tid; e < NN; e += nthr) {
-    put(lay.A + e, sA[e]);
-    put(lay.Q + e, sQ[e]);
-  }
-
-  // C_bar = (C/l)(Sig_l - I) and R_x = (1/l) sum_i C c_i + R, into LDS (W2 is free again)
   __syncthreads();
+  // c_i = (1/l) [ sum_{j<i} A^{i-j} Q_jj C^T + Q_ii (C Sig_{l-i})^T ], the sum over j as four
+  // independent partial sums.
+  for (int e = tid; e < L * NXY; e += nthr) {
+    const int i = 1 + e / NXY, rc = e % NXY, r = rc / NY, c = rc % NY;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int k = 0; k < NX; ++k) a0 += Qii[i * NN + r * NX + k] * CS[(L - i) * NXY + c * NX + k];
+    int j = 1;
+    for (; j + 4 <= i; j += 4)
+      for (int k = 0; k < NX; ++k) {
+        a0 += Apow[(i - j) * NN + r * NX + k] * QC[j * NXY + k * NY + c];
+        a1 += Apow[(i - j - 1) * NN + r * NX + k] * QC[(j + 1) * NXY + k * NY + c];
+        a2 += Apow[(i - j - 2) * NN + r * NX + k] * QC[(j + 2) * NXY + k * NY + c];
+        a3 += Apow[(i - j - 3) * NN + r * NX + k] * QC[(j + 3) * NXY + k * NY + c];
+      }
+    for (; j < i; ++j)
+      for (int k = 0; k < NX; ++k) a0 += Apow[(i - j) * NN + r * NX + k] * QC[j * NXY + k * NY + c];
+    ci[i * NXY + rc] = ((a0 + a1) + (a2 + a3)) / (double)L;
+  }
+  __syncthreads();
+
+  // c_i to the constants block; C_bar = (C/l)(Sig_l - I) and R_x = (1/l) sum_i C c_i + R into LDS
+  // (W2 is free again).
   double* sCbar = W2;
   double* sRx = W2 + NXY;
-  for (int e = tid; e < NXY + NY * NY; e += nthr) {
-    if (e < NXY) {
-      const int r = e / NX, c = e % NX;
+  for (int e = tid; e < L * NXY + NXY + NY * NY; e += nthr) {
+    if (e < L * NXY) {
+      const int i = 1 + e / NXY, rc = e % NXY;
+      put(lay.per_i + (i - 1) * lay.per_i_stride + lay.o_ci + rc, ci[i * NXY + rc]);
+    } else if (e < L * NXY + NXY) {
+      const int q = e - L * NXY, r = q / NX, c = q % NX;
       double acc = 0.0;
       for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * (W1[L * NN + k * NX + c] - (k == c ? 1.0 : 0.0));
-      sCbar[e] = acc / (double)L;
+      sCbar[q] = acc / (double)L;
     } else {
-      const int q = e - NXY, r = q / NY, c = q % NY;
-      double acc = 0.0;
-      for (int i = 1; i <= L; ++i)
-        for (int k = 0; k < NX; ++k) acc += sC[r * NX + k] * ci[i * NXY + k * NY + c];
-      sRx[q] = acc / (double)L + sR[r * NY + c];
+      const int q = e - L * NXY - NXY, r = q / NY, c = q % NY;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = 1;
+      for (; i + 4 <= L + 1; i += 4)
+        for (int k = 0; k < NX; ++k) {
+          a0 += sC[r * NX + k] * ci[i * NXY + k * NY + c];
+          a1 += sC[r * NX + k] * ci[(i + 1) * NXY + k * NY + c];
+          a2 += sC[r * NX + k] * ci[(i + 2) * NXY + k * NY + c];
+          a3 += sC[r * NX + k] * ci[(i + 3) * NXY + k * NY + c];
+        }
+      for (; i <= L; ++i)
+        for (int k = 0; k < NX; ++k) a0 += sC[r * NX + k] * ci[i * NXY + k * NY + c];
+      sRx[q] = ((a0 + a1) + (a2 + a3)) / (double)L + sR[r * NY + c];
     }
   }
   __syncthreads();
   if (tid >= 64) return;  // the rest is done by wave 0
   int lflag = 0;
   double* rec = chain;  // the chain's F, D, J of Theta(1): the generic element
-  if (tid == 0) {
-    // ------------------------------------------------------------ generic element (one lane)
-    double Rx[NY][NY], Sxy[NX][NY], Cbar[NY][NX];
-    for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NX; ++c) Cbar[r][c] = sCbar[r * NX + c];
+  {
+    // ------------------------------------------------------------ generic element (wave 0)
+    // Every lane inverts R_x itself; lane e < nx^2 forms entry e of F, D and J (D and J from
+    // both halves, symmetrised), and the first lanes write C_bar, R_x, K and H_eta.
+    //   K = S_xy R_x^{-1},  H_eta = C_bar^T R_x^{-1},  F = A^l - K C_bar,
+    //   D = Q_ll - K S_xy^T,  J = H_eta C_bar,  with S_xy = c_l.
+    double Rx[NY][NY], Rxi[NY][NY];
     for (int r = 0; r < NY; ++r)
       for (int c = 0; c < NY; ++c) Rx[r][c] = sRx[r * NY + c];
     symmetrize(Rx);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NY; ++c) Sxy[r][c] = ci[L * NXY + r * NY + c];
-    double Rxi[NY][NY];
-    if (!spd_inv(Rx, Rxi)) lflag |= SRTM_INFO_INNOVATION_NOT_PD;
-    double K[NX][NY], Heta[NX][NY];
-    mm(Sxy, Rxi, K);
-    mm_tn(Cbar, Rxi, Heta);
-    double F[NX][NX], D[NX][NX], J[NX][NX];
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) {
-        double f = Apow[L * NN + r * NX + c], d = Qii[L * NN + r * NX + c];
-        for (int k = 0; k < NY; ++k) {
-          f -= K[r][k] * Cbar[k][c];
-          d -= K[r][k] * Sxy[c][k];
-        }
-        F[r][c] = f;
-        D[r][c] = d;
+    if (!spd_inv(Rx, Rxi) && tid == 0) lflag |= SRTM_INFO_INNOVATION_NOT_PD;
+    const double* Sxy = ci + L * NXY;  // NX x NY
+    auto krow = [&](int r, double (&o)[NY]) {  // row r of K
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NY; ++j) s += Sxy[r * NY + j] * Rxi[j][k];
+        o[k] = s;
       }
-    mm(Heta, Cbar, J);
-    symmetrize(D);
-    symmetrize(J);
-    for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NX; ++c) put(lay.Cbar + r * NX + c, Cbar[r][c]);
-    for (int r = 0; r < NY; ++r)
-      for (int c = 0; c < NY; ++c) put(lay.Rx + r * NY + c, Rx[r][c]);
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NY; ++c) {
-        put(lay.K + r * NY + c, K[r][c]);
-        put(lay.Heta + r * NY + c, Heta[r][c]);
+    };
+    auto hrow = [&](int r, double (&o)[NY]) {  // row r of H_eta
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NY; ++j) s += sCbar[j * NX + r] * Rxi[j][k];
+        o[k] = s;
       }
-    for (int r = 0; r < NX; ++r)
-      for (int c = 0; c < NX; ++c) {
-        rec[r * NX + c] = F[r][c];
-        rec[NN + r * NX + c] = D[r][c];
-        rec[2 * NN + r * NX + c] = J[r][c];
+    };
+    if (tid < NN) {
+      const int r = tid / NX, c = tid % NX;
+      double Kr[NY], Kc[NY], Hr[NY], Hc[NY];
+      krow(r, Kr);
+      krow(c, Kc);
+      hrow(r, Hr);
+      hrow(c, Hc);
+      double f = Apow[L * NN + tid], drc = Qii[L * NN + r * NX + c], dcr = Qii[L * NN + c * NX + r];
+      double jrc = 0.0, jcr = 0.0;
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        f -= Kr[k] * sCbar[k * NX + c];
+        drc -= Kr[k] * Sxy[c * NY + k];
+        dcr -= Kc[k] * Sxy[r * NY + k];
+        jrc += Hr[k] * sCbar[k * NX + c];
+        jcr += Hc[k] * sCbar[k * NX + r];
       }
+      rec[tid] = f;
+      rec[NN + tid] = (r == c) ? drc : 0.5 * (drc + dcr);
+      rec[2 * NN + tid] = (r == c) ? jrc : 0.5 * (jrc + jcr);
+    }
+    if (tid < NX) {
+      double Kr[NY], Hr[NY];
+      krow(tid, Kr);
+      hrow(tid, Hr);
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        put(lay.K + tid * NY + k, Kr[k]);
+        put(lay.Heta + tid * NY + k, Hr[k]);
+      }
+    }
+    for (int q = tid; q < NXY; q += 64) put(lay.Cbar + q, sCbar[q]);
+    for (int q = tid; q < NY * NY; q += 64) {
+      const int r = q / NY, c = q % NY;
+      put(lay.Rx + q, (r == c) ? sRx[q] : 0.5 * (sRx[r * NY + c] + sRx[c * NY + r]));
+    }
   }
   wave_sync();
   // Levels below CHAIN_SPLIT; the others continue in the tile-reduction launch.
@@ -1436,20 +1471,24 @@ SRTM_DEV void fwd_upsweep(const T* __restrict__ G, const Slots<T>& S, int tid) {
 #pragma unroll 1
   for (int p = 0; p < LOG_TILE; ++p) {
     const int s = 1 << p;
-    if (((tid + 1) & (2 * s - 1)) == 0) {
+    // Pair j (slots j 2^{p+1} + s - 1 and j 2^{p+1} + 2s - 1) goes to thread j, so that the active
+    // threads fill the first waves: every active wave reads the level's coefficients from LDS,
+    // and those broadcast reads, not the arithmetic, set the time of a level.
+    if (tid < (TILE >> (p + 1))) {
+      const int dst = (tid << (p + 1)) + 2 * s - 1;
       T di[NX], ei[NX], dj[NX], ej[NX];
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
-        di[r] = S.at(r, tid - s);
-        ei[r] = S.at(NX + r, tid - s);
-        dj[r] = S.at(r, tid);
-        ej[r] = S.at(NX + r, tid);
+        di[r] = S.at(r, dst - s);
+        ei[r] = S.at(NX + r, dst - s);
+        dj[r] = S.at(r, dst);
+        ej[r] = S.at(NX + r, dst);
       }
       level_vec_combine_g<T, NX>(G + p * 4 * NN, di, ei, dj, ej);
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
-        S.at(r, tid) = dj[r];
-        S.at(NX + r, tid) = ej[r];
+        S.at(r, dst) = dj[r];
+        S.at(NX + r, dst) = ej[r];
       }
     }
     __syncthreads();
@@ -2917,12 +2956,13 @@ SRTM_DEV void tv_reduce_body(const T* __restrict__ Fa, const T* __restrict__ Qa,
 #pragma unroll 1
   for (int p = 0; p < LOG_TILE; ++p) {
     const int sp = 1 << p;
-    if (((tid + 1) & (2 * sp - 1)) == 0) {
+    if (tid < (TILE >> (p + 1))) {  // pair j to thread j: the active threads fill the first waves
+      const int dst = (tid << (p + 1)) + 2 * sp - 1;
       FElem<T, NX> lft, rgt, o;
-      ld_felem(S, tid - sp, lft);
-      ld_felem(S, tid, rgt);
+      ld_felem(S, dst - sp, lft);
+      ld_felem(S, dst, rgt);
       if (!elem_combine(lft, rgt, o)) flag |= SRTM_INFO_COMBINE_SINGULAR;
-      st_felem(S, tid, o);
+      st_felem(S, dst, o);
     }
     __syncthreads();
   }
