@@ -86,6 +86,7 @@ CASES = [
     (2, 2, 1, 700, 6),      # l = 1: Kalman filter + RTS smoother
     (3, 1, 16, 257, 7),
     (6, 1, 5, 300, 8),      # nx > 4: Gaussian elimination instead of the adjugate
+    (4, 2, 2, 400, 9),      # l = 2: one power of A and one cross term per window
 ]
 
 
