@@ -2060,7 +2060,8 @@ SRTM_DEV bool finite_state(const T (&m)[NX], const T (&P)[NX][NX]) {
 // its own element: the same combines as a tree down-sweep, with no exchange between lanes.
 // S needs TILE * 2 nx scalars; (yt, zL): window k's measurement and input response (window_meas);
 // `tree`: the tile's up-sweep tree as the tile reduction left it (2 nx rows of TILE slots).
-template <bool INP, typename T, int NX, int NY>
+// INCL false: the exclusive state only ((m, P) untouched).
+template <bool INP, typename T, int NX, int NY, bool INCL = true>
 SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const T (&yt)[NY], const T (&zL)[NX],
                              int64_t k, const T* __restrict__ m0, const T* __restrict__ P0,
                              const T* __restrict__ tile_state, const T* __restrict__ tree, T (&mprev)[NX],
@@ -2098,14 +2099,13 @@ SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const
       if (!state_combine(mprev, Pprev, F, dl, D, el, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
     }
   }
-  // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
+  if constexpr (INCL) {  // exclusive state -> inclusive: X_k = X_{k-1} (x) a_k
 #pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    m[r] = mprev[r];
+    for (int r = 0; r < NX; ++r) {
+      m[r] = mprev[r];
 #pragma unroll
-    for (int c = 0; c < NX; ++c) P[r][c] = Pprev[r][c];
-  }
-  {
+      for (int c = 0; c < NX; ++c) P[r][c] = Pprev[r][c];
+    }
     const T* lv = M.level(0);
     T F[NX][NX], D[NX][NX], J[NX][NX];
     load(F, lv + M.lay.o_F);
@@ -2114,6 +2114,40 @@ SRTM_DEV int fwd_tile_states(const Model<T, NX, NY>& M, const Slots<T>& S, const
     if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
   return flag;
+}
+
+// Window k's filtered slow state (m^f_{k,l}, P^f_{k,l}) from its window quantities (window_setup
+// on the exclusive state): the recovery's blocks at fast step l, m = A^l m' + c_l S^{-1} e (+ z_{k,l}
+// with inputs) and P = A^l Y1 + Q_ll - c_l Y2 (upper triangle, mirrored). Equal to the inclusive
+// combine X_{k-1} (x) a_k in exact arithmetic, at a fraction of its cost.
+template <bool INP, typename T, int NX, int NY>
+SRTM_DEV void window_slow_state(const Model<T, NX, NY>& M, int L, const Window<T, NX, NY>& w, const T (&zL)[NX],
+                                T (&m)[NX], T (&P)[NX][NX]) {
+  T AL[NX][NX], cL[NX][NY];
+  M.get(AL, M.AL_off(L));
+  M.get(cL, M.cL_off(L));
+  const int oq = M.per_i_off(L) + M.lay.o_Qii;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    T t = INP ? zL[r] : T(0);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) t = my_fma(AL[r][k], w.mp[k], t);
+#pragma unroll
+    for (int k = 0; k < NY; ++k) t = my_fma(cL[r][k], w.Se[k], t);
+    m[r] = t;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int c = r; c < NX; ++c) {
+      T t = M.at(oq + r * NX + c);
+#pragma unroll
+      for (int k = 0; k < NX; ++k) t = my_fma(AL[r][k], w.Y1[k][c], t);
+#pragma unroll
+      for (int k = 0; k < NY; ++k) t = my_fma(-cL[r][k], w.Y2[k][c], t);
+      P[r][c] = t;
+      P[c][r] = t;
+    }
 }
 
 // Writes the slow-rate carry (m^f_{k,l}, P^f_{k,l}) and, when requested, the slow-rate
@@ -2161,15 +2195,15 @@ SRTM_DEV void fwd_final_body(const T* __restrict__ y, int64_t N, int L, const T*
 
 // ============================================================================ backward
 // The smoother half of the fused forward/backward kernel for window k of tile `tile`, given the
-// window's exclusive and inclusive filter states and (An, Qn), the model of the step into
-// x_{k+1,1}: its smoother element (eq. parallel-ak-smoothing), the in-tile reverse Kogge-Stone
-// scan under eq. op-smoother, the tile aggregate and the per-window correction record (see
-// fwd_bwd_body). Returns numerical status bits.
+// window quantities w (window_setup on the exclusive filter state), the inclusive filter state
+// (m, P) and (An, Qn), the model of the step into x_{k+1,1}: its smoother element (eq.
+// parallel-ak-smoothing), the in-tile reverse Kogge-Stone scan under eq. op-smoother, the tile
+// aggregate and the per-window correction record (see fwd_bwd_body). Returns numerical status bits.
 template <bool INP, typename T, int NX, int NY, class MV>
 SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int64_t N,
-                           const T (&yt)[NY], const T (&mprev)[NX], const T (&Pprev)[NX][NX], const T (&m)[NX],
-                           const T (&P)[NX][NX], const T (&An)[NX][NX], const T (&Qn)[NX][NX],
-                           T* __restrict__ btagg, T* __restrict__ sfx, int64_t tile) {
+                           const Window<T, NX, NY>& w, const T (&m)[NX], const T (&P)[NX][NX],
+                           const T (&An)[NX][NX], const T (&Qn)[NX][NX], T* __restrict__ btagg,
+                           T* __restrict__ sfx, int64_t tile) {
   constexpr int NN = NX * NX, SE = 2 * NN + NX, SF = sfx_stride(NX);
   const int tid = threadIdx.x;
   const bool valid = k < N;
@@ -2177,8 +2211,6 @@ SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int
   SElem<T, NX> x;
   T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T (predicted mean), B^T P^- B
   {
-    Window<T, NX, NY> w;
-    if (!window_setup(M, L, mprev, Pprev, yt, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
     T z1[NX], bnext[NX];  // B u_{k,0} and B u_{k+1,0}
 #pragma unroll
     for (int r = 0; r < NX; ++r) z1[r] = bnext[r] = T(0);
@@ -2329,14 +2361,19 @@ SRTM_DEV void fwd_bwd_body(const T* __restrict__ y, int64_t N, int L, const T* _
   T yt[NY], zL[NX];
   window_meas<INP>(M, y, k, N, yt, zL);
   T mprev[NX], Pprev[NX][NX], m[NX], P[NX][NX];
-  int flag = fwd_tile_states<INP>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST, utree + tile * (2 * NX * TILE),
-                                  mprev, Pprev, m, P);
+  int flag = fwd_tile_states<INP, T, NX, NY, false>(M, S, yt, zL, k, m0, P0, ftstate + tile * ST,
+                                                    utree + tile * (2 * NX * TILE), mprev, Pprev, m, P);
+  // The smoother element needs the window quantities of the exclusive state; the inclusive state
+  // (the carry) follows from them.
+  Window<T, NX, NY> w;
+  if (!window_setup(M, L, mprev, Pprev, yt, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+  window_slow_state<INP>(M, L, w, zL, m, P);
   if (valid) flag |= store_carry(k, m, P, carry, m_slow, P_slow);
 
   T An[NX][NX], Qn[NX][NX];  // time-invariant: the step into x_{k+1,1} has the model's A and Q
   load(An, M.cst + M.lay.A);
   load(Qn, M.cst + M.lay.Q);
-  flag |= smoother_part<INP>(M, S, L, k, N, yt, mprev, Pprev, m, P, An, Qn, btagg, sfx, tile);
+  flag |= smoother_part<INP>(M, S, L, k, N, w, m, P, An, Qn, btagg, sfx, tile);
   if (flag && info) atomicOr(info, flag);
 }
 
@@ -3161,7 +3198,9 @@ SRTM_DEV void tv_fwd_body(const T* __restrict__ Fa, const T* __restrict__ Qa, co
     const int64_t kn = (k + 1 < N) ? k + 1 : kc;  // the last window's element ignores them
     gload(An, Fa + kn * NN);
     gload(Qn, Qa + kn * NN);
-    flag |= smoother_part<false>(M, S, L, k, N, yt, mprev, Pprev, m, P, An, Qn, btagg, sfx, tile);
+    Window<T, NX, NY> w;
+    if (!window_setup(M, L, mprev, Pprev, yt, w) && valid) flag |= SRTM_INFO_INNOVATION_NOT_PD;
+    flag |= smoother_part<false>(M, S, L, k, N, w, m, P, An, Qn, btagg, sfx, tile);
   }
   if (flag && info) atomicOr(info, flag);
 }
