@@ -1401,21 +1401,19 @@ SRTM_DEV int smoother_element(const MV& M, int L, const Window<T, NX, NY>& w, bo
 #pragma unroll
     for (int r = 0; r < NX; ++r) mpred[r] += bnext[r];
   }
-  T PA[NX][NX];
+  T PA[NX][NX];  // P^f_{1,l} A^T, which is also E P^-
   mm_nt(Pf1L, A, PA);
   mm(PA, Pmi, el.E);
   T Em[NX];
   mv(el.E, mpred, Em);
-  T EPm[NX][NX];
-  mm(el.E, Pm, EPm);
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     el.g[r] = mf1[r] - Em[r];
 #pragma unroll
-    for (int c = r; c < NX; ++c) {
+    for (int c = r; c < NX; ++c) {  // S = P^f_{1,1} - E P^- E^T = P^f_{1,1} - (P^f_{1,l} A^T) E^T
       T s = Pf11[r][c];
 #pragma unroll
-      for (int k = 0; k < NX; ++k) s = my_fma(-EPm[r][k], el.E[c][k], s);
+      for (int k = 0; k < NX; ++k) s = my_fma(-PA[r][k], el.E[c][k], s);
       el.S[r][c] = s;
       el.S[c][r] = s;
     }
@@ -2209,7 +2207,7 @@ SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int
   const bool valid = k < N;
   int flag = 0;
   SElem<T, NX> x;
-  T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T (predicted mean), B^T P^- B
+  T B[NX][NX], Bm[NX], BPB[NX][NX];  // B = (P^-)^{-1} A, B^T (predicted mean), B^T P^- B = A^T B
   {
     T z1[NX], bnext[NX];  // B u_{k,0} and B u_{k+1,0}
 #pragma unroll
@@ -2223,15 +2221,13 @@ SRTM_DEV int smoother_part(const MV& M, const Slots<T>& S, int L, int64_t k, int
     if (valid) flag |= f;
     mm(Pmi, An, B);
     mtv(B, mpred, Bm);
-    T PB[NX][NX];
-    mm(Pm, B, PB);
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
       for (int c = r; c < NX; ++c) {
         T t = T(0);
 #pragma unroll
-        for (int q = 0; q < NX; ++q) t = my_fma(B[q][r], PB[q][c], t);
+        for (int q = 0; q < NX; ++q) t = my_fma(An[q][r], B[q][c], t);
         BPB[r][c] = t;
         BPB[c][r] = t;
       }
