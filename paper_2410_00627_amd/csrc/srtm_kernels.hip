@@ -1650,28 +1650,65 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
     load(J, lv + M.lay.o_J);
     if (!state_combine(m, P, F, d, D, e, J)) flag |= SRTM_INFO_COMBINE_SINGULAR;
   }
+  // While 2s < 64, wave 0 holds both the lanes [s, 2s) that form states and lanes [2s, 64) that
+  // merge vector runs, and would run both combines one after the other. The vector runs of those
+  // lanes are kept by lane tid - 64 of wave 1 instead (its second vector combine of the step):
+  // the helper writes the run into the slot at the next step's start, and the owner reads it back
+  // from there when it becomes a state. Barriers are unchanged.
+  const bool helper = tid >= 64 && tid < 128;
+  const int hl = tid - 64;  // the chunk a helper keeps
+  T hd[NX], he[NX];         // its run
 #pragma unroll 1
   for (int q = 0; q < steps; ++q) {
     const int s = 1 << q;
+    const bool kept_prev = q >= 1 && s <= 32;  // the previous step kept the runs of [s, 64)
+    const bool keep_now = 2 * s < 64;          // this step keeps the runs of [2s, 64)
     if (tid < s) {
       st_state<T, NX>(S, tid, m, P);
-    } else {
+    } else if (!(tid < 64 && kept_prev)) {
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         S.at(r, tid) = d[r];
         S.at(NX + r, tid) = e[r];
       }
     }
+    if (helper && kept_prev && hl >= s) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        S.at(r, hl) = hd[r];
+        S.at(NX + r, hl) = he[r];
+      }
+    }
     __syncthreads();
     const bool gets_state = tid >= s && tid < 2 * s;
-    T mo[NX], Po[NX][NX], dl[NX], el[NX];
+    const bool own_vec = tid >= 2 * s && !(tid < 64 && keep_now);
+    const bool helps = helper && keep_now && hl >= 2 * s;
+    T mo[NX], Po[NX][NX], dl[NX], el[NX], hdl[NX], hel[NX];
     if (gets_state) {
       ld_state<T, NX>(S, tid - s, mo, Po);
-    } else if (tid >= 2 * s) {
+      if (tid < 64 && kept_prev) {  // the run its helper kept
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          d[r] = S.at(r, tid);
+          e[r] = S.at(NX + r, tid);
+        }
+      }
+    } else if (own_vec) {
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         dl[r] = S.at(r, tid - s);
         el[r] = S.at(NX + r, tid - s);
+      }
+    }
+    if (helps) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        hdl[r] = S.at(r, hl - s);
+        hel[r] = S.at(NX + r, hl - s);
+        if (q == 0) {  // the owner's own run, stored above
+          hd[r] = S.at(r, hl);
+          he[r] = S.at(NX + r, hl);
+        }
       }
     }
     __syncthreads();
@@ -1688,9 +1725,10 @@ SRTM_DEV void fwd_tiles_body(const T* __restrict__ tagg, int64_t nt, int lchunk,
 #pragma unroll
         for (int cc = 0; cc < NX; ++cc) P[r][cc] = Po[r][cc];
       }
-    } else if (tid >= 2 * s) {
+    } else if (own_vec) {
       level_vec_combine(lv, M.lay, dl, el, d, e);
     }
+    if (helps) level_vec_combine(lv, M.lay, hdl, hel, hd, he);
   }
   // every active thread now holds the inclusive state through its chunk
   st_state<T, NX>(S, tid, m, P);
