@@ -216,7 +216,8 @@ SRTM_DEV int level_chain(double* chain, T* __restrict__ cst, const ConstLayout& 
 // Levels 0 .. CHAIN_SPLIT-1 come from the constants kernel (the in-tile scans need the levels
 // below LOG_TILE); the rest, which only the tile-level scan uses, from one workgroup of the
 // tile-reduction launch, so that they are computed while the tiles are reduced (for 2^17 windows
-// ten levels, about 11 us, against the reduction's 16 us).
+// nine levels, about 12 us in float64, beside reductions of about 10 us; a level costs about 0.9 us
+// more in the constants kernel, so a higher split does not pay).
 constexpr int CHAIN_SPLIT = LOG_TILE;
 static_assert(CHAIN_SPLIT >= LOG_TILE, "the tile reductions read levels below LOG_TILE");
 
