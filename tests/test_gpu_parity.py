@@ -98,6 +98,16 @@ def test_parity_shapes(nx, ny, L, N, seed, dtype):
     check_smoother(m, y, dtype, f"nx{nx} ny{ny} L{L} N{N}")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_parity_one_tile_per_scan_lane(dtype):
+    """201 tiles (the last one ragged): one tile per lane of the tile-level scans and all eight of
+    their steps, the early ones with wave 0's vector runs kept by wave 1; every window against the
+    reference."""
+    m = wl.random_stable_model(2, 1, 2, 11)
+    y = wl.simulate(m, 200 * 256 + 37, 12)
+    check_smoother(m, y, dtype, "201 tiles")
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 255, 256, 257, 512, 513])
 def test_edge_lengths(N):
     m = wl.random_general_model(3, 2, 4, 11)
