@@ -108,6 +108,15 @@ def test_parity_one_tile_per_scan_lane(dtype):
     check_smoother(m, y, dtype, "201 tiles")
 
 
+def test_parity_chunk_fold_float32():
+    """514 tiles in float32: past 512 tiles each lane of the tile-level scans first folds a chunk of
+    four tiles with full element combines; every window against the reference (float64 reaches
+    this path in test_largest_sequence)."""
+    m = wl.random_stable_model(1, 1, 1, 13)
+    y = wl.simulate(m, 512 * 256 + 300, 14)
+    check_smoother(m, y, torch.float32, "514 tiles")
+
+
 @pytest.mark.parametrize("N", [1, 2, 3, 255, 256, 257, 512, 513])
 def test_edge_lengths(N):
     m = wl.random_general_model(3, 2, 4, 11)
