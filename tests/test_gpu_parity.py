@@ -110,8 +110,8 @@ def test_parity_one_tile_per_scan_lane(dtype):
 
 def test_parity_chunk_fold_float32():
     """514 tiles in float32: past 512 tiles each lane of the tile-level scans first folds a chunk of
-    four tiles with full element combines; every window against the reference (float64 reaches
-    this path in test_largest_sequence)."""
+    four tiles with full element combines; every window against the reference (float64:
+    test_many_tiles_general_paths)."""
     m = wl.random_stable_model(1, 1, 1, 13)
     y = wl.simulate(m, 512 * 256 + 300, 14)
     check_smoother(m, y, torch.float32, "514 tiles")
@@ -125,8 +125,8 @@ def test_edge_lengths(N):
 
 
 def test_many_tiles_general_paths():
-    """N = 140000 windows (547 tiles of 256): the forward tile scan folds two tiles per thread
-    and the reverse tile scan takes its tree form."""
+    """N = 140000 windows (547 tiles of 256): each lane of the tile-level scans folds a chunk of
+    four tiles with full element combines first (float64)."""
     m = wl.random_stable_model(2, 1, 3, 61)
     y = wl.simulate(m, 140000, 62)
     check_smoother(m, y, torch.float64, "N=140000")
